@@ -1,0 +1,88 @@
+/*
+ * FP64 CPU oracle of the EasyPBR deferred screen-space shading pass.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this code; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark use it.  It shares no code, header, table or constant
+ * generator with the HIP implementation.
+ *
+ * Every routine is the plain, slow reading of the method in double precision:
+ * no blocking, fusion or reordering beyond what the method states.  The paper
+ * names the methods and cites them; the formulas below follow those published
+ * methods, and every point the paper leaves open is read the same way as in the
+ * design notes (conventions, constants, tie-breaks).
+ *
+ * Decisions taken by a floating-point comparison (an SSAO depth test, a PCF
+ * depth test, a nearest-texel floor, a cube-face choice) may legitimately come
+ * out differently in a float32 implementation when the operands are within
+ * rounding distance of the threshold.  Where an operand lies within the tie
+ * margin the oracle evaluates every outcome and reports the smallest and the
+ * largest result ("lo" and "hi").  All later steps are monotone in these values,
+ * so the interval propagates exactly.  Away from ties lo == hi.
+ *
+ * Layouts (all row-major, y down):
+ *   planar image   [c][H][W]
+ *   cube map       [face][S][S][4]   faces +X,-X,+Y,-Y,+Z,-Z, RGBA (A unused)
+ *   mip chain      levels concatenated, level m of size base >> m
+ *   BRDF LUT       [size][size][2]   row = roughness, column = N.V, (A, B)
+ */
+#ifndef EPB_ORACLE_H
+#define EPB_ORACLE_H
+#include <stdint.h>
+
+typedef struct {
+    double world_to_cam[12]; /* row-major 3x4 [R | t] */
+    double fx, fy, cx, cy;
+    int32_t width, height;
+} orc_camera;
+
+typedef struct {
+    double pix; /* half-width of the ambiguous band around an integer, in texels */
+    double rel; /* relative half-width of the ambiguous band of a comparison     */
+} orc_tie;
+
+typedef struct {
+    double pos[3], color[3], intensity;
+    const double *shadow_map; /* [h][w] linear depth, +inf = empty; NULL = no shadow */
+    orc_camera shadow_cam;
+    double shadow_bias;
+} orc_light;
+
+/* conventions */
+void orc_cube_texel_dir(int face, int i, int j, int S, double d[3]);
+double orc_texel_solid_angle(int i, int j, int S);
+
+/* building blocks exported for the pin tests */
+double orc_ggx_D(double NoH, double alpha);
+void orc_brdf_lut_point(double NoV, double rough, int samples, double AB[2]);
+double orc_aces(double x);
+int orc_encode_u8(double x, double exposure, double gamma);
+
+/* a1 image-based-lighting precompute */
+void orc_env_downsample(const double *src, int S, double *dst);
+void orc_irradiance(const double *src, int S_src, double *out, int S_out);
+void orc_prefilter(const double *env, int S, double *out, int base, int levels, int samples);
+void orc_brdf_lut(double *out, int size, int samples);
+
+/* a2 / a3 screen-space ambient occlusion */
+void orc_ssao_raw(const double *depth, const double *normal, const orc_camera *cam,
+                  const double *kernel, int n_samples, const double *noise, double radius,
+                  double bias, const orc_tie *tie, double *lo, double *hi);
+void orc_ssao_blur(const double *raw_lo, const double *raw_hi, const double *depth, int W,
+                   int H, double tau, double *lo, double *hi);
+
+/* a4 shading */
+void orc_shade(const double *depth, const double *normal, const double *albedo,
+               const double *rough, const double *metal, const orc_camera *cam,
+               const double *ao_lo, const double *ao_hi, const orc_light *lights, int n_lights,
+               const double *irradiance, int irr_size, const double *prefiltered, int pref_base,
+               int pref_levels, const double *lut, int lut_size, const double *env, int env_size,
+               const orc_tie *tie, double *hdr_lo, double *hdr_hi);
+
+/* a5 / a6 bloom, composite, tonemap.  pyramid (optional) receives the blurred
+ * levels 1..levels-1 as planar [3][H_l][W_l] blocks one after another. */
+void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double threshold,
+                       double strength, double exposure, double gamma, uint8_t *ldr,
+                       double *composite, double *pyramid);
+
+#endif

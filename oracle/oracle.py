@@ -1,0 +1,318 @@
+"""ctypes front-end of the FP64 CPU oracle (``epb_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY: imported by the tests, the smoke check and the CPU
+baseline of the benchmark.  The product package never imports this module.
+
+Every function takes the same float32 arrays the GPU path receives (or float64
+intermediates), widens them to float64 and calls the C oracle.  Functions that
+involve floating-point decisions return a pair ``(lo, hi)``: the smallest and
+largest result over the outcomes of every decision within the tie margin.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "epb_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+# Decisions whose operands lie this close to the threshold count as ties.
+# ``pix``: texel units of a floor / in-range test; ``rel``: relative to the
+# compared magnitude (depth tests, cube-face choice, signs).
+DEFAULT_TIE = (5e-3, 1e-5)
+
+
+def build() -> str:
+    """Compile the oracle with gcc (IEEE double, no fast-math, OpenMP)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+           "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
+    return _LIB_PATH
+
+
+_lib = None
+
+
+class OrcCamera(C.Structure):
+    _fields_ = [("world_to_cam", C.c_double * 12), ("fx", C.c_double), ("fy", C.c_double),
+                ("cx", C.c_double), ("cy", C.c_double), ("width", C.c_int32),
+                ("height", C.c_int32)]
+
+
+class OrcTie(C.Structure):
+    _fields_ = [("pix", C.c_double), ("rel", C.c_double)]
+
+
+class OrcLight(C.Structure):
+    _fields_ = [("pos", C.c_double * 3), ("color", C.c_double * 3), ("intensity", C.c_double),
+                ("shadow_map", C.POINTER(C.c_double)), ("shadow_cam", OrcCamera),
+                ("shadow_bias", C.c_double)]
+
+
+_D = C.POINTER(C.c_double)
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB_PATH)
+        L.orc_cube_texel_dir.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _D]
+        L.orc_texel_solid_angle.argtypes = [C.c_int, C.c_int, C.c_int]
+        L.orc_texel_solid_angle.restype = C.c_double
+        L.orc_ggx_D.argtypes = [C.c_double, C.c_double]
+        L.orc_ggx_D.restype = C.c_double
+        L.orc_brdf_lut_point.argtypes = [C.c_double, C.c_double, C.c_int, _D]
+        L.orc_aces.argtypes = [C.c_double]
+        L.orc_aces.restype = C.c_double
+        L.orc_encode_u8.argtypes = [C.c_double, C.c_double, C.c_double]
+        L.orc_encode_u8.restype = C.c_int
+        L.orc_env_downsample.argtypes = [_D, C.c_int, _D]
+        L.orc_irradiance.argtypes = [_D, C.c_int, _D, C.c_int]
+        L.orc_prefilter.argtypes = [_D, C.c_int, _D, C.c_int, C.c_int, C.c_int]
+        L.orc_brdf_lut.argtypes = [_D, C.c_int, C.c_int]
+        L.orc_ssao_raw.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, C.c_int, _D, C.c_double,
+                                   C.c_double, C.POINTER(OrcTie), _D, _D]
+        L.orc_ssao_blur.argtypes = [_D, _D, _D, C.c_int, C.c_int, C.c_double, _D, _D]
+        L.orc_shade.argtypes = [_D, _D, _D, _D, _D, C.POINTER(OrcCamera), _D, _D,
+                                C.POINTER(OrcLight), C.c_int, _D, C.c_int, _D, C.c_int, C.c_int,
+                                _D, C.c_int, _D, C.c_int, C.POINTER(OrcTie), _D, _D]
+        L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                        C.c_double, C.c_double, C.POINTER(C.c_uint8), _D, _D]
+        _lib = L
+    return _lib
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(_D)
+
+
+def _cam(cam) -> OrcCamera:
+    c = OrcCamera()
+    for k, v in enumerate(np.asarray(cam.world_to_cam, np.float64).reshape(-1)):
+        c.world_to_cam[k] = float(v)
+    c.fx, c.fy, c.cx, c.cy = float(cam.fx), float(cam.fy), float(cam.cx), float(cam.cy)
+    c.width, c.height = int(cam.width), int(cam.height)
+    return c
+
+
+def _tie(tie) -> OrcTie:
+    t = OrcTie()
+    t.pix, t.rel = tie
+    return t
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+# ---------------------------------------------------------------------------
+def cube_texel_dir(face: int, i: int, j: int, S: int) -> np.ndarray:
+    d = np.zeros(3)
+    lib().orc_cube_texel_dir(face, i, j, S, _p(d))
+    return d
+
+
+def texel_solid_angle(i: int, j: int, S: int) -> float:
+    return lib().orc_texel_solid_angle(i, j, S)
+
+
+def ggx_D(NoH: float, alpha: float) -> float:
+    return lib().orc_ggx_D(NoH, alpha)
+
+
+def brdf_lut_point(NoV: float, rough: float, samples: int = 1024) -> Tuple[float, float]:
+    ab = np.zeros(2)
+    lib().orc_brdf_lut_point(NoV, rough, samples, _p(ab))
+    return float(ab[0]), float(ab[1])
+
+
+def aces(x: float) -> float:
+    return lib().orc_aces(x)
+
+
+def encode_u8(x: float, exposure: float = 1.0, gamma: float = 2.2) -> int:
+    return lib().orc_encode_u8(x, exposure, gamma)
+
+
+# ---------------------------------------------------------------------------
+# a1: image-based-lighting precompute
+# ---------------------------------------------------------------------------
+def env_downsample(src) -> np.ndarray:
+    src = _d(src)
+    S = src.shape[1]
+    out = np.zeros((6, S // 2, S // 2, 4))
+    lib().orc_env_downsample(_p(src), S, _p(out))
+    return out
+
+
+def irradiance_source(env, size: int) -> np.ndarray:
+    """Repeated solid-angle-weighted 2x2 means down to ``min(S, size)``."""
+    src = _d(env)
+    while src.shape[1] > size:
+        src = env_downsample(src)
+    return src
+
+
+def irradiance(src, out_size: int) -> np.ndarray:
+    src = _d(src)
+    out = np.zeros((6, out_size, out_size, 4))
+    lib().orc_irradiance(_p(src), src.shape[1], _p(out), out_size)
+    return out
+
+
+def prefilter(env, base: int, levels: int, samples: int) -> List[np.ndarray]:
+    env = _d(env)
+    total = sum(6 * (base >> m) ** 2 * 4 for m in range(levels))
+    out = np.zeros(total)
+    lib().orc_prefilter(_p(env), env.shape[1], _p(out), base, levels, samples)
+    res, off = [], 0
+    for m in range(levels):
+        s = base >> m
+        n = 6 * s * s * 4
+        res.append(out[off:off + n].reshape(6, s, s, 4))
+        off += n
+    return res
+
+
+def brdf_lut(size: int, samples: int) -> np.ndarray:
+    out = np.zeros((size, size, 2))
+    lib().orc_brdf_lut(_p(out), size, samples)
+    return out
+
+
+def precompute_ibl(env, irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5,
+                   pref_samples=1024, lut_size=256, lut_samples=1024, **_unused) -> dict:
+    """The whole per-environment precompute (Sec. 3.1)."""
+    env = _d(env)
+    S = env.shape[1]
+    src = irradiance_source(env, min(S, irr_src_size))
+    base = min(S, pref_size)
+    return dict(irradiance=irradiance(src, irr_size),
+                prefiltered=prefilter(env, base, pref_levels, pref_samples),
+                lut=brdf_lut(lut_size, lut_samples))
+
+
+# ---------------------------------------------------------------------------
+# a2 / a3: SSAO
+# ---------------------------------------------------------------------------
+def ssao_raw(depth, normal, cam, kernel, noise, radius=0.5, bias=0.025,
+             tie=DEFAULT_TIE) -> Tuple[np.ndarray, np.ndarray]:
+    depth, normal, kernel, noise = _d(depth), _d(normal), _d(kernel), _d(noise)
+    H, W = depth.shape
+    Wh, Hh = (W + 1) // 2, (H + 1) // 2
+    lo = np.zeros((Hh, Wh))
+    hi = np.zeros((Hh, Wh))
+    c, t = _cam(cam), _tie(tie)
+    lib().orc_ssao_raw(_p(depth), _p(normal), C.byref(c), _p(kernel), kernel.shape[0], _p(noise),
+                       radius, bias, C.byref(t), _p(lo), _p(hi))
+    return lo, hi
+
+
+def ssao_blur(raw_lo, raw_hi, depth, tau=0.1) -> Tuple[np.ndarray, np.ndarray]:
+    raw_lo, raw_hi, depth = _d(raw_lo), _d(raw_hi), _d(depth)
+    H, W = depth.shape
+    lo = np.zeros_like(raw_lo)
+    hi = np.zeros_like(raw_hi)
+    lib().orc_ssao_blur(_p(raw_lo), _p(raw_hi), _p(depth), W, H, tau, _p(lo), _p(hi))
+    return lo, hi
+
+
+# ---------------------------------------------------------------------------
+# a4: shading
+# ---------------------------------------------------------------------------
+def shade(gbuf: dict, cam, ao_lo, ao_hi, lights: Sequence, ibl: dict, env,
+          tie=DEFAULT_TIE) -> Tuple[np.ndarray, np.ndarray]:
+    depth, normal, albedo = _d(gbuf["depth"]), _d(gbuf["normal"]), _d(gbuf["albedo"])
+    rough, metal = _d(gbuf["roughness"]), _d(gbuf["metalness"])
+    ao_lo, ao_hi = _d(ao_lo), _d(ao_hi)
+    H, W = depth.shape
+    keep = []
+    arr = (OrcLight * max(1, len(lights)))()
+    for k, L in enumerate(lights):
+        o = arr[k]
+        for c in range(3):
+            o.pos[c] = float(L.pos[c])
+            o.color[c] = float(L.color[c])
+        o.intensity = float(L.intensity)
+        if L.shadow_map is not None:
+            sm = _d(L.shadow_map)
+            keep.append(sm)
+            o.shadow_map = _p(sm)
+            o.shadow_cam = _cam(L.shadow_cam)
+            o.shadow_bias = float(L.shadow_bias)
+        else:
+            o.shadow_map = C.cast(None, _D)
+    irr = _d(ibl["irradiance"])
+    pref = _d(np.concatenate([np.asarray(m, np.float64).reshape(-1) for m in ibl["prefiltered"]]))
+    lut = _d(ibl["lut"])
+    env = _d(env)
+    lo = np.zeros((3, H, W))
+    hi = np.zeros((3, H, W))
+    c, t = _cam(cam), _tie(tie)
+    lib().orc_shade(_p(depth), _p(normal), _p(albedo), _p(rough), _p(metal), C.byref(c),
+                    _p(ao_lo), _p(ao_hi), arr, len(lights), _p(irr), irr.shape[1], _p(pref),
+                    ibl["prefiltered"][0].shape[1], len(ibl["prefiltered"]), _p(lut), lut.shape[0],
+                    _p(env), env.shape[1], C.byref(t), _p(lo), _p(hi))
+    return lo, hi
+
+
+# ---------------------------------------------------------------------------
+# a5 / a6: bloom + tonemap (monotone, so an interval maps end to end)
+# ---------------------------------------------------------------------------
+def bloom_tonemap(hdr, levels=6, threshold=1.0, strength=0.04, exposure=1.0, gamma=2.2,
+                  want_composite=False, want_pyramid=False):
+    hdr = _d(hdr)
+    _, H, W = hdr.shape
+    ldr = np.zeros((H, W, 4), np.uint8)
+    comp = np.zeros((3, H, W)) if want_composite else None
+    sizes = []
+    w, h = W, H
+    for _ in range(1, levels):
+        w, h = (w + 1) // 2, (h + 1) // 2
+        sizes.append((h, w))
+    pyr = np.zeros(sum(3 * a * b for a, b in sizes)) if want_pyramid else None
+    lib().orc_bloom_tonemap(_p(hdr), W, H, levels, threshold, strength, exposure, gamma,
+                            ldr.ctypes.data_as(C.POINTER(C.c_uint8)),
+                            _p(comp) if comp is not None else C.cast(None, _D),
+                            _p(pyr) if pyr is not None else C.cast(None, _D))
+    out = {"ldr": ldr}
+    if comp is not None:
+        out["composite"] = comp
+    if pyr is not None:
+        lv, off = [], 0
+        for (h, w) in sizes:
+            lv.append(pyr[off:off + 3 * h * w].reshape(3, h, w))
+            off += 3 * h * w
+        out["pyramid"] = lv
+    return out
+
+
+# ---------------------------------------------------------------------------
+# the whole pass on one view
+# ---------------------------------------------------------------------------
+def render(view, tie=DEFAULT_TIE, ibl: Optional[dict] = None) -> dict:
+    """Oracle of the full per-frame path on a :class:`synth.ViewInputs`:
+    SSAO (raw + blur), shading, bloom and tonemap, with intervals."""
+    g = view.gbuf
+    if ibl is None:
+        ibl = precompute_ibl(view.env, **view.ibl)
+    raw_lo, raw_hi = ssao_raw(g["depth"], g["normal"], view.cam, view.ssao_kernel,
+                              view.ssao_noise, view.ssao_radius, view.ssao_bias, tie)
+    ao_lo, ao_hi = ssao_blur(raw_lo, raw_hi, g["depth"], view.blur_tau)
+    hdr_lo, hdr_hi = shade(g, view.cam, ao_lo, ao_hi, view.lights, ibl, view.env, tie)
+    post = dict(threshold=view.bloom_threshold, strength=view.bloom_strength,
+                exposure=view.exposure, gamma=view.gamma)
+    lo = bloom_tonemap(hdr_lo, **post)["ldr"]
+    hi = bloom_tonemap(hdr_hi, **post)["ldr"]
+    return dict(ibl=ibl, ao_raw=(raw_lo, raw_hi), ao=(ao_lo, ao_hi), hdr=(hdr_lo, hdr_hi),
+                ldr=(lo, hi))

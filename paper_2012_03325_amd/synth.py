@@ -1,0 +1,424 @@
+"""Seeded synthetic inputs for the deferred shading pass.
+
+This module builds *inputs only*: G-buffers and light-space depth maps ray-cast
+from seeded sphere scenes, environment cube maps, cameras, lights, and the SSAO
+sample kernel and rotation noise.  It contains none of the shading arithmetic
+(no BRDF, no SSAO test, no filtering), so it can feed both the FP64 oracle and
+the HIP path without coupling them.
+
+The G-buffer stands in for the rasterised geometry pass of the paper (Sec. 4,
+Tab. 1): per pixel a linear view depth (``+inf`` for background), a world-space
+unit normal, a linear albedo, a roughness and a metalness (Sec. 3).  Shadow maps
+are depth renders from each point light "as a normal camera" (Sec. 5.1).  The
+paper's scenes (scanned meshes, drone environments) are not available, so seeded
+sphere fields stand in for them.
+
+Conventions shared with the shading code are *definitions of the data*:
+
+* pinhole camera, image y down, pixel centres at (x + 0.5, y + 0.5); a view-space
+  point at linear depth d of pixel (x, y) is
+  ((x + 0.5 - cx) / fx * d, -(y + 0.5 - cy) / fy * d, -d);
+* ``world_to_cam`` is a row-major 3x4 rigid transform [R | t];
+* cube faces in the order +X, -X, +Y, -Y, +Z, -Z; texel (i, j) of a face of size
+  S has s = 2 (i + 0.5) / S - 1, t = 2 (j + 0.5) / S - 1 and points along
+  +X (1, -t, -s), -X (-1, -t, s), +Y (s, 1, t), -Y (s, -1, -t), +Z (s, -t, 1),
+  -Z (-s, -t, -1); texels are stored as RGBA float (A unused).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import List, Optional
+
+import numpy as np
+
+
+# ----------------------------------------------------------------------------
+# cameras
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Camera:
+    world_to_cam: np.ndarray  # (3, 4) float64, rows of [R | t]
+    fx: float
+    fy: float
+    cx: float
+    cy: float
+    width: int
+    height: int
+
+    @property
+    def R(self) -> np.ndarray:
+        return self.world_to_cam[:, :3]
+
+    @property
+    def t(self) -> np.ndarray:
+        return self.world_to_cam[:, 3]
+
+    @property
+    def position(self) -> np.ndarray:
+        return -self.R.T @ self.t
+
+    def as_f32(self) -> "Camera":
+        """The same camera with every float rounded to float32 (what the GPU gets)."""
+        return Camera(self.world_to_cam.astype(np.float32).astype(np.float64),
+                      float(np.float32(self.fx)), float(np.float32(self.fy)),
+                      float(np.float32(self.cx)), float(np.float32(self.cy)),
+                      self.width, self.height)
+
+
+def look_at(eye, target, up, vfov_deg: float, width: int, height: int) -> Camera:
+    """Camera at ``eye`` looking at ``target``; vertical field of view in degrees."""
+    eye = np.asarray(eye, np.float64)
+    target = np.asarray(target, np.float64)
+    up = np.asarray(up, np.float64)
+    f = target - eye
+    f /= np.linalg.norm(f)
+    x = np.cross(f, up)
+    x /= np.linalg.norm(x)
+    y = np.cross(x, f)
+    R = np.stack([x, y, -f])
+    t = -R @ eye
+    fy = (height / 2.0) / math.tan(math.radians(vfov_deg) / 2.0)
+    # round the intrinsics to float32 once so that every consumer sees the same numbers
+    cam = Camera(np.concatenate([R, t[:, None]], axis=1), fy, fy, width / 2.0, height / 2.0,
+                 width, height)
+    return cam.as_f32()
+
+
+# ----------------------------------------------------------------------------
+# scenes
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class SphereScene:
+    centers: np.ndarray      # (n, 3)
+    radii: np.ndarray        # (n,)
+    albedo: np.ndarray       # (n, 3)
+    roughness: np.ndarray    # (n,)
+    metalness: np.ndarray    # (n,)
+    plane: bool = False      # the plane y = 0
+    plane_albedo: tuple = (0.5, 0.5, 0.5)
+    plane_roughness: float = 0.6
+    plane_metalness: float = 0.0
+
+
+def make_spheres(rng: np.random.Generator, n: int, plane: bool) -> SphereScene:
+    """Spheres drawn in order: centre x, z ~ U[-3, 3] on y = 0, radius ~ U[0.1, 0.5],
+    albedo ~ U[0, 1]^3, roughness ~ U[0.05, 1], metalness ~ Bernoulli(0.3)."""
+    cx = rng.uniform(-3.0, 3.0, n)
+    cz = rng.uniform(-3.0, 3.0, n)
+    radii = rng.uniform(0.1, 0.5, n)
+    albedo = rng.uniform(0.0, 1.0, (n, 3))
+    rough = rng.uniform(0.05, 1.0, n)
+    metal = (rng.uniform(0.0, 1.0, n) < 0.3).astype(np.float64)
+    centers = np.stack([cx, np.zeros(n), cz], axis=1)
+    return SphereScene(centers, radii, albedo, rough, metal, plane)
+
+
+def _pixel_rays(cam: Camera, xs: np.ndarray, ys: np.ndarray) -> np.ndarray:
+    """World-space ray directions scaled so that the view-space z component is -1
+    (the ray parameter then equals the linear view depth)."""
+    dv = np.stack([(xs + 0.5 - cam.cx) / cam.fx,
+                   -(ys + 0.5 - cam.cy) / cam.fy,
+                   -np.ones_like(xs, dtype=np.float64)], axis=-1)
+    return dv @ cam.R  # == (R^T dv^T)^T
+
+
+def _sphere_bbox(cam: Camera, c: np.ndarray, r: float):
+    """Conservative pixel bounding box of a sphere, or None for the whole image."""
+    cv = cam.R @ c + cam.t
+    if -(cv[2] + r) <= 1e-3 and -(cv[2] - r) <= 1e-3:
+        return (0, 0, 0, 0)  # entirely behind the camera
+    if -(cv[2] + r) <= 1e-3:
+        return None  # crosses the camera plane
+    corners = cv[None, :] + r * np.array([[sx, sy, sz] for sx in (-1, 1) for sy in (-1, 1)
+                                         for sz in (-1, 1)], np.float64)
+    z = -corners[:, 2]
+    px = cam.cx + cam.fx * corners[:, 0] / z - 0.5
+    py = cam.cy - cam.fy * corners[:, 1] / z - 0.5
+    x0 = max(int(math.floor(px.min())) - 1, 0)
+    x1 = min(int(math.ceil(px.max())) + 2, cam.width)
+    y0 = max(int(math.floor(py.min())) - 1, 0)
+    y1 = min(int(math.ceil(py.max())) + 2, cam.height)
+    return (x0, x1, y0, y1)
+
+
+def raycast(scene: SphereScene, cam: Camera, depth_only: bool = False) -> dict:
+    """Nearest-hit ray cast of the scene through every pixel of ``cam``.
+
+    Returns float32 planes: ``depth`` (H, W) linear view depth or +inf; unless
+    ``depth_only``, also ``normal`` and ``albedo`` (3, H, W) and ``roughness``,
+    ``metalness`` (H, W).  Spheres are tested in index order and the plane last;
+    an exactly equal hit distance keeps the earlier object."""
+    W, H = cam.width, cam.height
+    depth = np.full((H, W), np.inf, np.float64)
+    ident = np.full((H, W), -1, np.int32)
+    o = cam.position
+    n = len(scene.radii)
+    for k in range(n):
+        c = scene.centers[k]
+        r = scene.radii[k]
+        bb = _sphere_bbox(cam, c, r)
+        if bb is None:
+            bb = (0, W, 0, H)
+        x0, x1, y0, y1 = bb
+        if x1 <= x0 or y1 <= y0:
+            continue
+        ys, xs = np.meshgrid(np.arange(y0, y1, dtype=np.float64),
+                             np.arange(x0, x1, dtype=np.float64), indexing="ij")
+        d = _pixel_rays(cam, xs, ys)
+        oc = o - c
+        a = np.einsum("...i,...i->...", d, d)
+        b = d @ oc
+        cc = oc @ oc - r * r
+        disc = b * b - a * cc
+        hit = disc >= 0.0
+        tt = np.where(hit, (-b - np.sqrt(np.where(hit, disc, 0.0))) / a, np.inf)
+        tt = np.where(tt > 0.0, tt, np.inf)
+        sub = depth[y0:y1, x0:x1]
+        closer = tt < sub
+        sub[closer] = tt[closer]
+        ident[y0:y1, x0:x1][closer] = k
+    if scene.plane:
+        ys, xs = np.meshgrid(np.arange(H, dtype=np.float64), np.arange(W, dtype=np.float64),
+                             indexing="ij")
+        d = _pixel_rays(cam, xs, ys)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            tt = np.where(d[..., 1] < 0.0, -o[1] / d[..., 1], np.inf)
+        tt = np.where(tt > 0.0, tt, np.inf)
+        closer = tt < depth
+        depth[closer] = tt[closer]
+        ident[closer] = n
+    out = {"depth": depth.astype(np.float32)}
+    if depth_only:
+        return out
+    normal = np.zeros((3, H, W), np.float64)
+    albedo = np.zeros((3, H, W), np.float64)
+    rough = np.zeros((H, W), np.float64)
+    metal = np.zeros((H, W), np.float64)
+    ys, xs = np.nonzero(ident >= 0)
+    ids = ident[ys, xs]
+    d = _pixel_rays(cam, xs.astype(np.float64), ys.astype(np.float64))
+    p = o[None, :] + depth[ys, xs][:, None] * d
+    sph = ids < n
+    nrm = np.zeros_like(p)
+    nrm[sph] = (p[sph] - scene.centers[ids[sph]]) / scene.radii[ids[sph]][:, None]
+    nrm[~sph] = np.array([0.0, 1.0, 0.0])
+    nrm /= np.linalg.norm(nrm, axis=1, keepdims=True)
+    alb = np.empty_like(p)
+    alb[sph] = scene.albedo[ids[sph]]
+    alb[~sph] = np.asarray(scene.plane_albedo)
+    rgh = np.where(sph, scene.roughness[np.minimum(ids, n - 1)], scene.plane_roughness)
+    mtl = np.where(sph, scene.metalness[np.minimum(ids, n - 1)], scene.plane_metalness)
+    normal[:, ys, xs] = nrm.T
+    albedo[:, ys, xs] = alb.T
+    rough[ys, xs] = rgh
+    metal[ys, xs] = mtl
+    out.update(normal=normal.astype(np.float32), albedo=albedo.astype(np.float32),
+               roughness=rough.astype(np.float32), metalness=metal.astype(np.float32))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# environment cube maps
+# ----------------------------------------------------------------------------
+def cube_texel_dirs(S: int) -> np.ndarray:
+    """Unnormalised texel-centre directions, shape (6, S, S, 3) indexed [face][j][i]."""
+    c = 2.0 * (np.arange(S, dtype=np.float64) + 0.5) / S - 1.0
+    t, s = np.meshgrid(c, c, indexing="ij")  # t varies with row j, s with column i
+    one = np.ones_like(s)
+    faces = [
+        np.stack([one, -t, -s], -1),
+        np.stack([-one, -t, s], -1),
+        np.stack([s, one, t], -1),
+        np.stack([s, -one, -t], -1),
+        np.stack([s, -t, one], -1),
+        np.stack([-s, -t, -one], -1),
+    ]
+    return np.stack(faces)
+
+
+def _rgba(rgb: np.ndarray) -> np.ndarray:
+    out = np.zeros(rgb.shape[:-1] + (4,), np.float32)
+    out[..., :3] = rgb
+    return out
+
+
+def env_sky_gradient(S: int) -> np.ndarray:
+    """Procedural sky gradient: zenith (0.25, 0.45, 1.0), horizon white, ground
+    (0.3, 0.25, 0.2), blended linearly in the y component of the direction."""
+    d = cube_texel_dirs(S)
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    wy = d[..., 1:2]
+    cz = np.array([0.25, 0.45, 1.0])
+    ch = np.array([1.0, 1.0, 1.0])
+    cg = np.array([0.3, 0.25, 0.2])
+    rgb = ch + (cz - ch) * np.maximum(wy, 0.0) + (cg - ch) * np.maximum(-wy, 0.0)
+    return _rgba(rgb)
+
+
+def env_sky_sun(S: int, sun_dir=(0.3, 0.8, 0.5), sun_radius_deg: float = 2.0,
+                sky_tint=(0.7, 0.85, 1.0), sun_tint=(1.0, 0.95, 0.85)) -> np.ndarray:
+    """HDR sky: log10 radiance rising linearly from -2 (nadir) to 2 (zenith), times
+    a tint, plus a sun disc of radiance 1e4 (times a tint) around ``sun_dir``."""
+    d = cube_texel_dirs(S)
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    wy = d[..., 1:2]
+    sky = 10.0 ** (-2.0 + 4.0 * (0.5 + 0.5 * wy)) * np.asarray(sky_tint)
+    sd = np.asarray(sun_dir, np.float64)
+    sd /= np.linalg.norm(sd)
+    in_sun = (d @ sd) >= math.cos(math.radians(sun_radius_deg))
+    rgb = np.where(in_sun[..., None], 1e4 * np.asarray(sun_tint), sky)
+    return _rgba(rgb)
+
+
+def env_constant(S: int, value=1.0) -> np.ndarray:
+    return _rgba(np.full((6, S, S, 3), value, np.float64))
+
+
+def env_linear(S: int, c: float, b) -> np.ndarray:
+    """Radiance c + b . w (same in all three channels), w the unit texel direction."""
+    d = cube_texel_dirs(S)
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    v = c + d @ np.asarray(b, np.float64)
+    return _rgba(np.repeat(v[..., None], 3, axis=-1))
+
+
+# ----------------------------------------------------------------------------
+# SSAO sample kernel and rotation noise (random draws of the method, as inputs)
+# ----------------------------------------------------------------------------
+def ssao_kernel(rng: np.random.Generator, n: int) -> np.ndarray:
+    """n tangent-space hemisphere vectors (z > 0), lengths in (0, 1], denser near
+    the origin: a uniform length scaled by lerp(0.1, 1, (k / n)^2)."""
+    out = np.empty((n, 3), np.float64)
+    for k in range(n):
+        while True:
+            v = np.array([rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0, 1)])
+            ln = np.linalg.norm(v)
+            if 1e-3 < ln <= 1.0 and v[2] > 1e-3:
+                break
+        v /= ln
+        s = k / n
+        v *= rng.uniform(0.05, 1.0) * (0.1 + 0.9 * s * s)
+        out[k] = v
+    return out.astype(np.float32)
+
+
+def ssao_noise(rng: np.random.Generator) -> np.ndarray:
+    """4x4 unit vectors in the view-space xy plane, shape (4, 4, 2) [row][col]."""
+    ang = rng.uniform(0.0, 2.0 * math.pi, (4, 4))
+    return np.stack([np.cos(ang), np.sin(ang)], -1).astype(np.float32)
+
+
+# ----------------------------------------------------------------------------
+# lights
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class Light:
+    pos: np.ndarray
+    color: np.ndarray
+    intensity: float
+    shadow_cam: Optional[Camera] = None
+    shadow_map: Optional[np.ndarray] = None  # (h, w) float32 linear depth / +inf
+    shadow_bias: float = 0.02
+
+
+# ----------------------------------------------------------------------------
+# whole inputs of one view
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class ViewInputs:
+    name: str
+    cam: Camera
+    gbuf: dict
+    lights: List[Light]
+    env: np.ndarray          # (6, S, S, 4) float32
+    ssao_kernel: np.ndarray  # (N, 3) float32
+    ssao_noise: np.ndarray   # (4, 4, 2) float32
+    ssao_radius: float = 0.5
+    ssao_bias: float = 0.025
+    blur_tau: float = 0.1
+    bloom_threshold: float = 1.0
+    bloom_strength: float = 0.04
+    exposure: float = 1.0
+    gamma: float = 2.2
+    ibl: dict = dataclasses.field(default_factory=lambda: dict(
+        irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=1024,
+        lut_size=256, lut_samples=1024))
+
+    @property
+    def width(self) -> int:
+        return self.cam.width
+
+    @property
+    def height(self) -> int:
+        return self.cam.height
+
+
+def _f32(x) -> float:
+    return float(np.float32(x))
+
+
+def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, seed: int,
+              n_lights: int, shadow_size: int, env_size: int, env_kind: str, ssao_n: int,
+              ibl: Optional[dict] = None) -> ViewInputs:
+    """One seeded view.  ``n_lights == 1`` puts a white light of intensity 40 at
+    (3, 5, 4); otherwise lights sit at azimuth 45 + 90 k degrees, radius 6,
+    height 6.  ``shadow_size > 0`` renders a square depth map per light with a
+    90 degree camera looking at the origin."""
+    rng = np.random.default_rng(seed)
+    scene = make_spheres(rng, n_spheres, plane)
+    cam = look_at((0.0, 3.5, 8.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, width, height)
+    gbuf = raycast(scene, cam)
+    lights = []
+    if n_lights == 1:
+        positions = [np.array([3.0, 5.0, 4.0])]
+    else:
+        positions = [np.array([6.0 * math.cos(math.radians(45 + 90 * k)), 6.0,
+                               6.0 * math.sin(math.radians(45 + 90 * k))])
+                     for k in range(n_lights)]
+    for p in positions:
+        p = p.astype(np.float32).astype(np.float64)
+        light = Light(p, np.array([1.0, 1.0, 1.0]), 40.0)
+        if shadow_size > 0:
+            lc = look_at(p, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 90.0, shadow_size, shadow_size)
+            light.shadow_cam = lc
+            light.shadow_map = raycast(scene, lc, depth_only=True)["depth"]
+        lights.append(light)
+    if env_kind == "gradient":
+        env = env_sky_gradient(env_size)
+    elif env_kind == "sun":
+        env = env_sky_sun(env_size)
+    elif env_kind == "white":
+        env = env_constant(env_size, 1.0)
+    else:
+        raise ValueError(env_kind)
+    krng = np.random.default_rng(seed + 10000)
+    kern = ssao_kernel(krng, ssao_n)
+    noise = ssao_noise(krng)
+    v = ViewInputs(name, cam, gbuf, lights, env, kern, noise)
+    if ibl is not None:
+        v.ibl = dict(v.ibl, **ibl)
+    return v
+
+
+def config_small(seed: int = 1) -> ViewInputs:
+    """256x256 single view: 64 spheres, no plane, one light without shadows, a
+    6x64x64 sky-gradient cube, SSAO with 16 samples of radius 0.5."""
+    return make_view("plain-256x256", 256, 256, 64, False, seed, 1, 0, 64, "gradient", 16)
+
+
+def config_1080p(seed: int = 2) -> ViewInputs:
+    """1920x1080 single view: 512 spheres plus the plane, four lights each with a
+    2048x2048 depth map, SSAO with 64 samples, a 6x512x512 HDR sky-and-sun cube."""
+    return make_view("plain-1920x1080", 1920, 1080, 512, True, seed, 4, 2048, 512, "sun", 64)
+
+
+def config_reduced(width: int, height: int, seed: int = 5, shadow_size: int = 256,
+                   env_size: int = 32, ssao_n: int = 16, n_spheres: int = 48,
+                   n_lights: int = 4) -> ViewInputs:
+    """A reduced copy of the 1080p workload (plane, shadowed lights, sun sky) at a
+    size the FP64 oracle finishes in seconds; used for parity tests."""
+    ibl = dict(irr_src_size=min(64, env_size), pref_size=min(128, env_size), pref_samples=256,
+               lut_size=32, lut_samples=256)
+    return make_view(f"reduced-{width}x{height}", width, height, n_spheres, True, seed, n_lights,
+                     shadow_size, env_size, "sun", ssao_n, ibl)

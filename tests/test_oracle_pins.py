@@ -1,0 +1,505 @@
+"""Pins of the FP64 oracle against what the mathematics and the paper fix.
+
+Each test checks the oracle against something other than itself: closed forms,
+invariants, hand-worked special cases, or an independent numerical quadrature
+of the integral an estimator approximates.  They are chosen so that a plausible
+slip (a dropped term, a wrong sign or index, a transposed operand, a wrong
+normalisation) fails at least one of them.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import oracle as O
+from paper_2012_03325_amd import synth
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ---------------------------------------------------------------------------
+# cube-map conventions
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("S", [1, 2, 7, 64])
+def test_texel_solid_angles_cover_the_sphere(S):
+    """The texel solid angles of the six faces add up to 4 pi (closed form)."""
+    tot = 6 * sum(O.texel_solid_angle(i, j, S) for i in range(S) for j in range(S))
+    assert abs(tot - 4 * math.pi) < 1e-12
+
+
+def test_texel_solid_angle_single_face_and_symmetry():
+    # one texel per face: each face subtends a sixth of the sphere
+    assert abs(O.texel_solid_angle(0, 0, 1) - 4 * math.pi / 6) < 1e-14
+    # a centre texel of an odd face is the largest; mirror texels agree
+    S = 9
+    w = np.array([[O.texel_solid_angle(i, j, S) for i in range(S)] for j in range(S)])
+    assert w.argmax() == (S // 2) * S + S // 2
+    assert np.allclose(w, w[::-1, :], rtol=0, atol=1e-15)
+    assert np.allclose(w, w.T, rtol=0, atol=1e-15)
+    # small texels approach the differential solid angle dA / r^3
+    S = 512
+    i = j = 100
+    x = 2 * (i + 0.5) / S - 1
+    y = 2 * (j + 0.5) / S - 1
+    approx = (2 / S) ** 2 / (1 + x * x + y * y) ** 1.5
+    assert abs(O.texel_solid_angle(i, j, S) / approx - 1) < 1e-5
+
+
+def test_cube_face_orientation_is_consistent():
+    """Every face is seen from inside with the same handedness, and the face
+    centres are the six axis directions in the order +X -X +Y -Y +Z -Z."""
+    S = 3
+    axes = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+    for f in range(6):
+        c = O.cube_texel_dir(f, 1, 1, S)
+        assert np.allclose(c, axes[f])
+        ds = O.cube_texel_dir(f, 2, 1, S) - c
+        dt = O.cube_texel_dir(f, 1, 2, S) - c
+        # s x t points back to the cube centre on every face (OpenGL layout)
+        assert np.dot(np.cross(ds, dt), c) < 0
+
+
+# ---------------------------------------------------------------------------
+# a1: irradiance
+# ---------------------------------------------------------------------------
+def test_irradiance_white_furnace():
+    env = synth.env_constant(16, 1.0)
+    E = O.irradiance(env, 8)
+    assert np.abs(E[..., :3] - 1.0).max() < 1e-12
+
+
+def test_irradiance_linear_radiance_closed_form():
+    """For L(w) = c + b.w the cosine-weighted mean over the hemisphere around n
+    is c + (2/3) b.n.  The texel-sum error falls about 4x per doubling."""
+    b = np.array([0.3, -0.5, 0.2])
+    d = synth.cube_texel_dirs(8)
+    d /= np.linalg.norm(d, axis=-1, keepdims=True)
+    ref = 1.0 + (2.0 / 3.0) * (d @ b)
+    errs = []
+    for S in (16, 32, 64):
+        E = O.irradiance(synth.env_linear(S, 1.0, b), 8)
+        for c in range(3):
+            assert np.allclose(E[..., c], E[..., 0])
+        errs.append(np.abs(E[..., 0] - ref).max())
+    assert errs[-1] < 2e-5
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+
+
+def test_downsample_conserves_radiant_integral_and_constants():
+    rng = np.random.default_rng(0)
+    S = 16
+    env = np.zeros((6, S, S, 4))
+    env[..., :3] = rng.uniform(0, 5, (6, S, S, 3))
+    half = O.env_downsample(env)
+    w0 = np.array([[O.texel_solid_angle(i, j, S) for i in range(S)] for j in range(S)])
+    w1 = np.array([[O.texel_solid_angle(i, j, S // 2) for i in range(S // 2)]
+                   for j in range(S // 2)])
+    tot0 = (env[..., :3] * w0[None, :, :, None]).sum(axis=(0, 1, 2))
+    tot1 = (half[..., :3] * w1[None, :, :, None]).sum(axis=(0, 1, 2))
+    assert np.allclose(tot0, tot1, rtol=1e-12)
+    const = O.env_downsample(synth.env_constant(S, 2.5))
+    assert np.abs(const[..., :3] - 2.5).max() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# a1: prefiltered specular
+# ---------------------------------------------------------------------------
+def test_prefilter_white_furnace_and_mirror_level():
+    pref = O.prefilter(synth.env_constant(16, 1.0), 16, 5, 256)
+    for m in pref:
+        assert np.abs(m[..., :3] - 1.0).max() < 1e-12
+    # roughness 0: every GGX half vector is the normal, so the level-0 texel is the
+    # environment seen along its own direction (texel centre => exact texel value)
+    rng = np.random.default_rng(1)
+    env = np.zeros((6, 8, 8, 4))
+    env[..., :3] = rng.uniform(0, 1, (6, 8, 8, 3))
+    p0 = O.prefilter(env, 8, 3, 64)[0]
+    assert np.abs(p0[..., :3] - env[..., :3]).max() < 1e-12
+
+
+def _quad_prefilter(n, alpha, L):
+    """Independent quadrature of the quantity the prefilter estimates: with
+    V = N = n, the N.L-weighted mean of L over reflection directions whose half
+    vector is GGX distributed, int L(l) NoL D(h) (n.h) dh / int NoL D(h) (n.h) dh
+    over half vectors with NoL > 0 (theta_h < pi/4)."""
+    up = np.array([0.0, 0.0, 1.0]) if abs(n[2]) < 0.999 else np.array([1.0, 0.0, 0.0])
+    T = np.cross(up, n)
+    T /= np.linalg.norm(T)
+    B = np.cross(n, T)
+    phis = np.linspace(0, 2 * np.pi, 256, endpoint=False)
+
+    def ring(th, weighted):
+        ct, st = math.cos(th), math.sin(th)
+        h = np.outer(np.cos(phis) * st, T) + np.outer(np.sin(phis) * st, B) + ct * n
+        l = 2 * ct * h - n
+        nl = 2 * ct * ct - 1
+        D = alpha ** 2 / (math.pi * (ct * ct * (alpha ** 2 - 1) + 1) ** 2)
+        v = L(l).mean() if weighted else 1.0
+        return nl * D * ct * st * v
+
+    pts = [min(alpha, 0.7)]
+    num = integrate.quad(lambda t: ring(t, True), 0, math.pi / 4, limit=200, points=pts)[0]
+    den = integrate.quad(lambda t: ring(t, False), 0, math.pi / 4, limit=200, points=pts)[0]
+    return num / den
+
+
+def test_prefilter_matches_quadrature_of_the_ggx_lobe():
+    b = np.array([0.3, -0.5, 0.2])
+    S = 64
+    pref = O.prefilter(synth.env_linear(S, 1.0, b), S, 5, 1024)
+    for m in range(1, 5):
+        s = S >> m
+        alpha = (m / 4) ** 2
+        for (f, i, j) in [(0, 0, 0), (2, s // 2, s // 3), (5, s - 1, 1), (3, s // 2, s // 2)]:
+            n = O.cube_texel_dir(f, i, j, s)
+            n /= np.linalg.norm(n)
+            q = _quad_prefilter(n, alpha, lambda l: 1.0 + l @ b)
+            assert abs(pref[m][f, j, i, 0] - q) < 1e-3, (m, f, i, j)
+
+
+# ---------------------------------------------------------------------------
+# GGX distribution and the environment BRDF table
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("alpha", [0.0025, 0.0625, 0.25, 1.0])
+def test_ggx_is_a_normalised_distribution_of_normals(alpha):
+    """int D(h) (n.h) dw_h = 1 over the hemisphere."""
+    f = lambda mu: O.ggx_D(mu, alpha) * mu * 2 * math.pi
+    pts = [1 - 10 * alpha * alpha] if alpha < 0.1 else None
+    val = integrate.quad(f, 0, 1, points=pts, limit=500, epsabs=1e-12, epsrel=1e-10)[0]
+    assert abs(val - 1.0) < 1e-6
+
+
+def test_ggx_peak_hand_value():
+    # alpha = 0.25 at N.H = 1: D = 1 / (pi alpha^2) = 5.0929582
+    assert abs(O.ggx_D(1.0, 0.25) - 5.092958178940651) < 1e-12
+
+
+def test_brdf_lut_bounds_and_normal_incidence():
+    lut = O.brdf_lut(32, 256)
+    A, B = lut[..., 0], lut[..., 1]
+    assert (A >= 0).all() and (B >= 0).all()
+    assert (A + B <= 1 + 1e-6).all()
+    # roughness 0 at normal incidence: every sample reflects straight back,
+    # Fc = 0, G_vis = 1, so (A, B) = (1, 0) and F0 A + B = F0
+    a, b = O.brdf_lut_point(1.0, 0.0, 1024)
+    assert abs(a - 1.0) < 1e-12 and abs(b) < 1e-12
+    # scale + bias decreases with roughness at fixed N.V (energy lost by single scattering)
+    s = [sum(O.brdf_lut_point(0.6, r, 1024)) for r in (0.2, 0.5, 0.8, 1.0)]
+    assert s == sorted(s, reverse=True)
+
+
+def _quad_lut(NoV, r):
+    """A + B and B of the split-sum BRDF by direct quadrature over half vectors:
+    int D G F / (4 NoL NoV) NoL dl with dl = 4 (V.h) dh, F = 1 or (1 - V.h)^5."""
+    a = r * r
+    k = a / 2
+    V = np.array([math.sqrt(1 - NoV * NoV), 0, NoV])
+    g1 = lambda x: x / (x * (1 - k) + k)
+
+    def integrand(ph, th, bias):
+        h = np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph), math.cos(th)])
+        vh = V @ h
+        nl = (2 * vh * h - V)[2]
+        if nl <= 0:
+            return 0.0
+        D = a * a / (math.pi * (h[2] ** 2 * (a * a - 1) + 1) ** 2)
+        F = (1 - vh) ** 5 if bias else 1.0
+        return D * g1(nl) * g1(NoV) * F * vh / NoV * math.sin(th)
+
+    return [integrate.dblquad(lambda ph, th: integrand(ph, th, w), 0, math.pi / 2, 0,
+                              2 * math.pi, epsabs=1e-8, epsrel=1e-7)[0] for w in (0, 1)]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("NoV,r", [(0.9, 0.5), (0.5, 0.7), (0.2, 0.9), (0.1, 0.4)])
+def test_brdf_lut_matches_direct_quadrature(NoV, r):
+    A, B = O.brdf_lut_point(NoV, r, 1 << 20)
+    q = _quad_lut(NoV, r)
+    assert abs((A + B) - q[0]) < 2e-4
+    assert abs(B - q[1]) < 2e-4
+
+
+# ---------------------------------------------------------------------------
+# a4: shading
+# ---------------------------------------------------------------------------
+def _one_pixel_cam(W=1, H=1, fx=1.0, cx=0.5):
+    return synth.Camera(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), fx, fx, cx,
+                        H / 2.0, W, H)
+
+
+def _zero_ibl(irr=4, pref=4, levels=3, lut=8):
+    # a black environment (no ambient light) with a plausible constant BRDF table
+    tab = np.zeros((lut, lut, 2))
+    tab[..., 0], tab[..., 1] = 0.6, 0.1
+    return dict(irradiance=np.zeros((6, irr, irr, 4)),
+                prefiltered=[np.zeros((6, pref >> m, pref >> m, 4)) for m in range(levels)],
+                lut=tab)
+
+
+def _gbuf(depth, normal, albedo, rough, metal):
+    H, W = depth.shape
+    return dict(depth=np.asarray(depth, np.float64),
+                normal=np.broadcast_to(np.asarray(normal, np.float64).reshape(3, 1, 1), (3, H, W)),
+                albedo=np.broadcast_to(np.asarray(albedo, np.float64).reshape(3, 1, 1), (3, H, W)),
+                roughness=np.full((H, W), rough), metalness=np.full((H, W), metal))
+
+
+def test_direct_light_hand_value_at_normal_incidence():
+    """n = l = V, roughness 0.5, dielectric: specular = D F0 / 4 with D = 5.0929582,
+    G = 1 and F = F0 = 0.04, i.e. 0.05092958; the diffuse part is albedo / pi."""
+    cam = _one_pixel_cam()
+    light = synth.Light(np.zeros(3), np.ones(3), 4.0)  # at the camera, radiance 4 / 2^2 = 1
+    ao = np.ones((1, 1))
+    env = np.zeros((6, 2, 2, 4))
+    for albedo, metal, expect in [
+        ((0.0, 0.0, 0.0), 0.0, [0.05092958178940651] * 3),
+        ((0.5, 0.25, 1.0), 0.0, [0.5 / math.pi + 0.05092958178940651,
+                                 0.25 / math.pi + 0.05092958178940651,
+                                 1.0 / math.pi + 0.05092958178940651]),
+        ((0.5, 0.25, 1.0), 1.0, [5.092958178940651 * 0.5 / 4, 5.092958178940651 * 0.25 / 4,
+                                 5.092958178940651 / 4]),
+    ]:
+        g = _gbuf(np.full((1, 1), 2.0), (0, 0, 1), albedo, 0.5, metal)
+        lo, hi = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env)
+        assert np.allclose(lo[:, 0, 0], expect, rtol=0, atol=1e-12)
+        assert np.array_equal(lo, hi)
+
+
+def test_direct_light_reciprocity():
+    """Helmholtz reciprocity of the BRDF: swapping the camera and the light
+    leaves f(l, v) unchanged, so L_o / (E cos) agrees between the two set-ups."""
+    env = np.zeros((6, 2, 2, 4))
+    ao = np.ones((1, 1))
+    p = np.array([0.2, -0.1, -3.0])
+    n = np.array([0.3, 0.4, 0.85])
+    n /= np.linalg.norm(n)
+    a_pos = np.zeros(3)
+    b_pos = np.array([1.5, 0.7, 0.4])
+    vals = []
+    for eye, lpos in [(a_pos, b_pos), (b_pos, a_pos)]:
+        cam = synth.look_at(eye, p, (0, 1, 0), 30.0, 1, 1)
+        cam = synth.Camera(cam.world_to_cam, cam.fx, cam.fy, 0.5, 0.5, 1, 1)
+        # the pixel ray passes through p: depth = distance along the view axis
+        pv = cam.R @ p + cam.t
+        depth = -pv[2]
+        g = _gbuf(np.full((1, 1), depth), n, (0.6, 0.3, 0.9), 0.35, 0.0)
+        light = synth.Light(lpos, np.ones(3), 1.0)
+        lo, _ = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env)
+        l = lpos - p
+        d2 = l @ l
+        l /= np.linalg.norm(l)
+        vals.append(lo[:, 0, 0] * d2 / (n @ l))
+    assert np.allclose(vals[0], vals[1], rtol=1e-9)
+
+
+@pytest.mark.parametrize("metal", [0.0, 1.0])
+def test_ambient_white_furnace(metal):
+    """Albedo 1 in a uniform unit environment reflects exactly 1 for a dielectric
+    and for a metal at any roughness and view angle: the multiple-scattering
+    compensation restores the energy single scattering loses."""
+    ibl = O.precompute_ibl(synth.env_constant(16, 1.0), irr_size=4, irr_src_size=16,
+                           pref_size=16, pref_levels=5, pref_samples=64, lut_size=16,
+                           lut_samples=256)
+    rng = np.random.default_rng(3)
+    H, W = 6, 7
+    cam = synth.look_at((0.5, 1.0, 4.0), (0, 0, 0), (0, 1, 0), 50.0, W, H)
+    nrm = rng.normal(size=(3, H, W))
+    nrm /= np.linalg.norm(nrm, axis=0)
+    nrm[2] = np.abs(nrm[2]) + 0.2  # roughly facing the camera
+    g = dict(depth=rng.uniform(3, 5, (H, W)), normal=nrm, albedo=np.ones((3, H, W)),
+             roughness=rng.uniform(0.05, 1, (H, W)), metalness=np.full((H, W), metal))
+    ao = np.ones(((H + 1) // 2, (W + 1) // 2))
+    lo, hi = O.shade(g, cam, ao, ao, [], ibl, synth.env_constant(16, 1.0))
+    assert np.abs(lo - 1).max() < 1e-12 and np.abs(hi - 1).max() < 1e-12
+
+
+def test_pcf_lit_fraction_by_hand():
+    """A point projecting to texel (4, 4) of an 8x8 map; occluders placed on
+    chosen taps of the 3x3 patch give lit fractions k / 9 exactly."""
+    cam = _one_pixel_cam()
+    g = _gbuf(np.full((1, 1), 2.0), (0, 0, 1), (0.5, 0.5, 0.5), 0.5, 0.0)
+    ao = np.ones((1, 1))
+    env = np.zeros((6, 2, 2, 4))
+    scam = synth.Camera(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 4.0, 4.0, 4.3, 4.3,
+                        8, 8)
+    base = synth.Light(np.zeros(3), np.ones(3), 4.0)
+    ref, _ = O.shade(g, cam, ao, ao, [base], _zero_ibl(), env)
+    cases = []
+    m = np.full((8, 8), np.inf, np.float32)
+    m[:, 5] = 1.0          # right column of the patch in front of the point
+    cases.append((m, 6 / 9))
+    m = np.full((8, 8), np.inf, np.float32)
+    m[3, 3] = 1.0
+    m[5, 5] = 1.0
+    m[2, 2] = 1.0          # outside the patch: no effect
+    cases.append((m, 7 / 9))
+    m = np.full((8, 8), 10.0, np.float32)  # occluder behind the point: lit
+    cases.append((m, 1.0))
+    m = np.full((8, 8), 1.98, np.float32)  # exactly at depth - bias: lit (<=)
+    m[4, 4] = 1.9                            # one tap in shadow
+    cases.append((m, 8 / 9))
+    for sm, frac in cases:
+        light = synth.Light(np.zeros(3), np.ones(3), 4.0, scam, sm, 0.02)
+        lo, hi = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env, tie=(5e-3, 0.0))
+        assert np.allclose(lo, ref * frac, rtol=1e-12, atol=0), frac
+        assert np.allclose(hi, ref * frac, rtol=1e-12, atol=0), frac
+    # a depth within the tie margin of the threshold yields the interval [8/9, 1]
+    sm = np.full((8, 8), np.inf, np.float32)
+    sm[4, 4] = 1.98
+    light = synth.Light(np.zeros(3), np.ones(3), 4.0, scam, sm, 0.02)
+    lo, hi = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env, tie=(5e-3, 1e-5))
+    assert np.allclose(lo, ref * 8 / 9) and np.allclose(hi, ref)
+
+
+# ---------------------------------------------------------------------------
+# a2 / a3: SSAO
+# ---------------------------------------------------------------------------
+def test_ssao_unoccluded_fronto_parallel_plane():
+    """Every hemisphere sample above a plane facing the camera is in front of
+    the depth buffer, so AO = 1 everywhere (invariant)."""
+    W, H = 40, 30
+    cam = synth.Camera(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 35.0, 35.0, W / 2,
+                       H / 2, W, H)
+    depth = np.full((H, W), 7.0)
+    normal = np.zeros((3, H, W))
+    normal[2] = 1.0
+    rng = np.random.default_rng(4)
+    kern = synth.ssao_kernel(rng, 32)
+    noise = synth.ssao_noise(rng)
+    lo, hi = O.ssao_raw(depth, normal, cam, kern, noise, 0.5, 0.025)
+    assert (lo == 1).all() and (hi == 1).all()
+    blo, bhi = O.ssao_blur(lo, hi, depth, 0.1)
+    assert (blo == 1).all() and (bhi == 1).all()
+
+
+def test_ssao_step_by_hand():
+    """4x4 image, identity camera (f = 2, c = 2), left half at depth 10, right
+    half at depth 5; noise (1, 0) gives the frame t = x, b = y, n = z; one sample
+    (0.5, 0, 1/6) at radius 12 offsets points by (6, 0, 2).
+    Half-res texel (0, 0) at P = (-7.5, 7.5, -10) moves to Q = (-1.5, 7.5, -8),
+    projects to u = 1.625, v = 0.125 -> half-res (1, 0), depth 5 <= 8 - bias:
+    occluded with smoothstep(12 / 5) = 1, so AO = 0.  Likewise texel (0, 1).
+    The right-half texels project past the right border: AO = 1."""
+    W = H = 4
+    cam = synth.Camera(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 2.0, 2.0, 2.0, 2.0,
+                       W, H)
+    depth = np.full((H, W), 10.0)
+    depth[:, 2:] = 5.0
+    normal = np.zeros((3, H, W))
+    normal[2] = 1.0
+    noise = np.zeros((4, 4, 2))
+    noise[..., 0] = 1.0
+    kern = np.array([[0.5, 0.0, 1.0 / 6.0]])
+    lo, hi = O.ssao_raw(depth, normal, cam, kern, noise, 12.0, 0.025)
+    assert np.array_equal(lo, [[0.0, 1.0], [0.0, 1.0]]) and np.array_equal(lo, hi)
+    # the same sample with the near wall moved behind the point is not occluded
+    depth2 = np.full((H, W), 10.0)
+    depth2[:, 2:] = 20.0
+    lo2, _ = O.ssao_raw(depth2, normal, cam, kern, noise, 12.0, 0.025)
+    assert (lo2 == 1).all()
+    # noise (0, 1) turns the offset to +y: texel (0, 1) at P = (-7.5, -2.5, -10)
+    # moves to (-7.5, 3.5, -8) -> u = 0.125 -> stays in the far (left) half: AO = 1
+    noise2 = np.zeros((4, 4, 2))
+    noise2[..., 1] = 1.0
+    lo3, _ = O.ssao_raw(depth, normal, cam, kern, noise2, 12.0, 0.025)
+    assert lo3[1, 0] == 1.0
+
+
+def test_ssao_blur_keeps_constants_and_respects_depth_edges():
+    W, H = 16, 12
+    depth = np.full((H, W), 10.0)
+    depth[:, 8:] = 5.0  # half-res columns >= 4 are 50 % nearer: zero weight across the edge
+    raw = np.full(((H + 1) // 2, (W + 1) // 2), 0.2)
+    raw[:, 4:] = 0.8
+    lo, hi = O.ssao_blur(raw, raw, depth, 0.1)
+    assert np.allclose(lo, raw, rtol=0, atol=1e-15) and np.array_equal(lo, hi)
+    depth[0, 0] = np.inf  # an empty texel reads as AO 1
+    lo, _ = O.ssao_blur(raw, raw, depth, 0.1)
+    assert lo[0, 0] == 1.0
+
+
+# ---------------------------------------------------------------------------
+# a5 / a6: bloom, tonemap
+# ---------------------------------------------------------------------------
+def test_aces_and_u8_table():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "aces_u8.txt"))
+            if l.strip() and not l.startswith("#")]
+    for x, f, q in rows:
+        assert abs(O.aces(float(x)) - float(f)) < 1e-8
+        assert O.encode_u8(float(x)) == int(q)
+    # limits and the crossing of 1: 0.08 x^2 - 0.56 x - 0.14 = 0
+    xs = (0.56 + math.sqrt(0.56 ** 2 + 4 * 0.08 * 0.14)) / 0.16
+    assert abs(O.aces(xs) - 1.0) < 1e-12
+    assert abs(O.aces(1e12) - 2.51 / 2.43) < 1e-9
+    grid = np.linspace(0, 50, 5001)
+    assert np.all(np.diff([O.aces(x) for x in grid]) > 0)
+
+
+def test_bloom_adds_nothing_below_threshold():
+    rng = np.random.default_rng(5)
+    hdr = rng.uniform(0, 0.99, (3, 37, 53))
+    out = O.bloom_tonemap(hdr, want_composite=True)
+    assert np.array_equal(out["composite"], hdr)
+    enc = np.vectorize(O.encode_u8)(hdr)
+    assert np.array_equal(out["ldr"][..., :3], enc.transpose(1, 2, 0))
+    assert (out["ldr"][..., 3] == 255).all()
+
+
+def test_bloom_constant_field():
+    """HDR 3 everywhere: Y = 3, bright = 3 (3 - 1) / 3 = 2 on every level and after
+    every blur (means and clamp-to-edge binomials keep constants), so the
+    composite is 3 + 5 * 0.04 * 2 = 3.4."""
+    hdr = np.full((3, 21, 34), 3.0)
+    out = O.bloom_tonemap(hdr, want_composite=True, want_pyramid=True)
+    for lv in out["pyramid"]:
+        assert np.allclose(lv, 2.0, rtol=0, atol=1e-14)
+    assert [lv.shape[1:] for lv in out["pyramid"]] == [(11, 17), (6, 9), (3, 5), (2, 3), (1, 2)]
+    assert np.allclose(out["composite"], 3.4, rtol=0, atol=1e-14)
+
+
+def test_bloom_impulse_by_hand():
+    """One pixel of HDR 10 at (32, 32) of a 64x64 black image: bright value 9 per
+    channel; level 1 holds 9/4 at (16, 16); after the separable binomial the
+    centre keeps (6/16)^2 of it, the 4-neighbour (4/16)(6/16), and the level
+    sum is preserved; level 2 before blurring holds 9/16 at (8, 8)."""
+    hdr = np.zeros((3, 64, 64))
+    hdr[:, 32, 32] = 10.0
+    out = O.bloom_tonemap(hdr, want_pyramid=True, want_composite=True)
+    l1 = out["pyramid"][0]
+    assert abs(l1[0, 16, 16] - 2.25 * 36 / 256) < 1e-15
+    assert abs(l1[1, 16, 17] - 2.25 * 24 / 256) < 1e-15
+    assert abs(l1[2, 14, 14] - 2.25 / 256) < 1e-15
+    assert abs(l1[0].sum() - 2.25) < 1e-13
+    l2 = out["pyramid"][1]
+    assert abs(l2[0].sum() - 9 / 16) < 1e-13
+    assert abs(l2[0, 8, 8] - 9 / 16 * 36 / 256) < 1e-15
+
+
+def test_bloom_ragged_levels_average_in_range_children():
+    """A 5x1 image: level 1 has 3 texels, the last one the mean of one child."""
+    hdr = np.zeros((3, 1, 5))
+    hdr[:, 0, :] = np.array([2.0, 4.0, 2.0, 2.0, 11.0])  # bright = x - 1 for gray
+    out = O.bloom_tonemap(hdr, levels=2, want_pyramid=True)
+    lv = out["pyramid"][0][0, 0]  # blurred level 1 (3 texels)
+    unblurred = np.array([(1 + 3) / 2, (1 + 1) / 2, 10.0])
+    k = np.array([1, 4, 6, 4, 1]) / 16
+    pad = np.concatenate([[unblurred[0]] * 2, unblurred, [unblurred[-1]] * 2])
+    expect = np.array([pad[i:i + 5] @ k for i in range(3)])
+    assert np.allclose(lv, expect, rtol=0, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
+# interval bookkeeping
+# ---------------------------------------------------------------------------
+def test_intervals_are_ordered_on_a_full_scene():
+    v = synth.config_reduced(96, 64)
+    r = O.render(v)
+    for key in ("ao_raw", "ao", "hdr", "ldr"):
+        lo, hi = r[key]
+        assert (np.asarray(lo, np.float64) <= np.asarray(hi, np.float64)).all(), key
+    lo, hi = r["hdr"]
+    assert np.isfinite(lo).all() and np.isfinite(hi).all()
+    # the ambiguous share stays small
+    assert (hi > lo).mean() < 0.5
