@@ -1,0 +1,273 @@
+/*
+ * epb.h -- C ABI of an MI355X (gfx950) implementation of the deferred
+ * screen-space shading pass of EasyPBR (Rosu and Behnke, "EasyPBR: A
+ * Lightweight Physically-Based Renderer", GRAPP 2021).
+ *
+ * The paper's renderer writes a G-buffer (Sec. 4, Tab. 1), runs effect passes
+ * on it (shadows, SSAO, bloom; Sec. 4.2, Sec. 5) and composes everything with
+ * PBR and image-based lighting (Sec. 3, 3.1, 4.2) before tone mapping (Sec. 5.4).
+ * This library implements that shading pass as four stream-ordered calls:
+ *
+ *   epb_precompute_ibl  -- once per environment map (Sec. 3.1)
+ *   epb_ssao            -- half-resolution SSAO + bilateral blur (Sec. 5.2)
+ *   epb_shade           -- position from depth, direct light with PCF shadows,
+ *                          split-sum IBL with multiple scattering, AO (Sec. 3,
+ *                          3.1, 4, 5.1)
+ *   epb_bloom_tonemap   -- bright-map pyramid bloom, ACES, gamma, 8 bit
+ *                          (Sec. 5.3, 5.4)
+ *
+ * Conventions (the paper leaves them open; every call uses the same ones):
+ *  - Images are row-major, y down.  Multi-channel images are planar [c][H][W].
+ *  - Pinhole cameras: pixel centres at (x + 0.5, y + 0.5); the view-space point
+ *    of pixel (x, y) at linear depth d is
+ *      ((x + 0.5 - cx) / fx * d, -(y + 0.5 - cy) / fy * d, -d);
+ *    world_to_cam is a row-major 3x4 rigid transform [R | t].
+ *  - Depth is the linear view depth d > 0; +inf marks background (Sec. 4 keeps
+ *    only depth and reconstructs positions from it).
+ *  - Normals are world-space (renormalised on read), albedo is linear.
+ *  - Cube maps are [level][face][S][S][4] float RGBA (A unused), faces ordered
+ *    +X, -X, +Y, -Y, +Z, -Z; texel (i, j) has s = 2 (i + .5) / S - 1,
+ *    t = 2 (j + .5) / S - 1 and points along +X (1,-t,-s), -X (-1,-t,s),
+ *    +Y (s,1,t), -Y (s,-1,-t), +Z (s,-t,1), -Z (-s,-t,-1).  Lookups pick the
+ *    major axis (ties x, then y, then z) and filter bilinearly with
+ *    clamp-to-edge inside the face.
+ *  - Half resolution is Wh = ceil(W / 2), Hh = ceil(H / 2); half-resolution
+ *    texel (i, j) is the full-resolution pixel (2 i, 2 j).
+ *
+ * Memory and ownership: every data pointer is a device pointer owned by the
+ * caller and must be 16-byte aligned.  The library allocates nothing: calls
+ * that need temporary device memory take a caller-provided scratch buffer of
+ * at least epb_scratch_bytes() bytes.  Struct arguments are read on the host
+ * during the call; device buffers are read or written by the enqueued work
+ * until the stream reaches it.  Nothing is retained after the call returns.
+ *
+ * Errors: arguments are validated on the host before anything is enqueued; a
+ * validation failure returns a negative epb_status and enqueues nothing (the
+ * outputs are untouched).  A failed launch returns EPB_ERR_HIP and
+ * epb_last_hip_error() gives the HIP error code of the calling thread.
+ * Faults inside kernels surface at the caller's next stream synchronisation.
+ * No call aborts, exits or throws.
+ *
+ * Concurrency: all work is enqueued on the given stream, with no device-wide
+ * synchronisation.  Calls are reentrant; calls on different streams must use
+ * different scratch buffers.  Results are deterministic for fixed inputs (no
+ * floating-point atomics).
+ */
+#ifndef EPB_H
+#define EPB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    EPB_OK = 0,
+    EPB_ERR_NULL = -1,    /* a required pointer is NULL                      */
+    EPB_ERR_SIZE = -2,    /* an image / cube / table size is out of range     */
+    EPB_ERR_DTYPE = -3,   /* unsupported storage type                         */
+    EPB_ERR_ALIGN = -4,   /* a device pointer is not 16-byte aligned          */
+    EPB_ERR_SCRATCH = -5, /* scratch buffer missing or smaller than required  */
+    EPB_ERR_PARAM = -6,   /* a scalar parameter is out of range               */
+    EPB_ERR_HIP = -7      /* a HIP launch failed; see epb_last_hip_error()    */
+} epb_status;
+
+/* Storage type of G-buffer attribute planes, AO and HDR images.  Arithmetic
+ * is always float32; EPB_F16 stores IEEE half (HDR saturates at 65504). */
+typedef enum { EPB_F32 = 0, EPB_F16 = 1 } epb_dtype;
+
+#define EPB_MAX_LIGHTS 8
+#define EPB_MAX_SSAO_SAMPLES 256
+#define EPB_MAX_BLOOM_LEVELS 6 /* "up to six levels" (Sec. 5.3) */
+#define EPB_MAX_IMAGE_SIZE 16384
+
+/* Pinhole camera (see conventions above). */
+typedef struct {
+    float world_to_cam[12]; /* row-major 3x4 [R | t], R orthonormal */
+    float fx, fy, cx, cy;   /* focal lengths and principal point, pixels */
+    int32_t width, height;
+} epb_camera;
+
+/* G-buffer (Sec. 4, Tab. 1): depth is always float32 (the paper's R32 target);
+ * the attribute planes use `dtype`. */
+typedef struct {
+    int32_t width, height;
+    epb_dtype dtype;      /* of normal, albedo, roughness, metalness        */
+    const float *depth;   /* [H][W] linear view depth, +inf = background    */
+    const void *normal;   /* [3][H][W] world-space normal                   */
+    const void *albedo;   /* [3][H][W] linear base colour in [0, 1]         */
+    const void *roughness;/* [H][W] perceptual roughness in (0, 1]          */
+    const void *metalness;/* [H][W] in [0, 1]                               */
+} epb_gbuffer;
+
+/* A float32 cube map with `levels` mip levels of sizes size >> m. */
+typedef struct {
+    int32_t size;
+    int32_t levels;
+    float *data; /* [level][6][s][s][4]; read-only where the call only reads */
+} epb_cube;
+
+/* Image-based-lighting precompute sizes (Sec. 3.1). */
+typedef struct {
+    int32_t irr_size;     /* irradiance map face size (e.g. 32)                    */
+    int32_t irr_src_size; /* irradiance source face size; the environment is
+                             averaged down to min(env size, this) (e.g. 64)         */
+    int32_t pref_size;    /* prefiltered base size cap: base = min(env, this) (128) */
+    int32_t pref_levels;  /* prefiltered mip levels, roughness m / (levels-1) (5)  */
+    int32_t pref_samples; /* GGX samples per prefiltered texel (1024)              */
+    int32_t lut_size;     /* BRDF table size (256)                                 */
+    int32_t lut_samples;  /* GGX samples per table entry (1024)                    */
+} epb_ibl_params;
+
+/* Outputs of epb_precompute_ibl, inputs of epb_shade. */
+typedef struct {
+    epb_cube irradiance;  /* 1 level of irr_size: cosine-weighted mean radiance  */
+    epb_cube prefiltered; /* pref_levels levels from base = min(env, pref_size)  */
+    float *brdf_lut;      /* [lut_size][lut_size][2] = (A, B); row = roughness,
+                             column = N.V, both sampled at texel centres          */
+    int32_t lut_size;
+} epb_ibl_maps;
+
+/* Screen-space ambient occlusion (Sec. 5.2). */
+typedef struct {
+    int32_t n_samples;    /* 1 .. EPB_MAX_SSAO_SAMPLES                         */
+    const float *kernel;  /* device [n][3] tangent-space hemisphere vectors   */
+    const float *noise;   /* device [4][4][2] rotation vectors (view xy)      */
+    float radius;         /* world units (e.g. 0.5)                           */
+    float bias;           /* depth bias, world units (e.g. 0.025)             */
+    float blur_tau;       /* relative depth tolerance of the blur (e.g. 0.1)  */
+    int32_t blur;         /* 1: apply the 4x4 bilateral blur, 0: raw AO       */
+    epb_dtype out_dtype;  /* storage of the AO image                          */
+} epb_ssao_params;
+
+/* Point light (Sec. 5.1) with an optional depth map rendered from the light. */
+typedef struct {
+    float pos[3];
+    float color[3];
+    float intensity;          /* radiance at distance r is color * intensity / r^2 */
+    const float *shadow_map;  /* device [h][w] linear depth (+inf empty), or NULL  */
+    epb_camera shadow_cam;    /* camera the map was rendered with                 */
+    float shadow_bias;        /* depth bias of the shadow test (e.g. 0.02)        */
+} epb_light;
+
+/* Bloom and tone mapping (Sec. 5.3, 5.4). */
+typedef struct {
+    int32_t bloom_levels; /* pyramid levels including the full-resolution bright
+                             map; levels 1 .. bloom_levels-1 are blurred and added
+                             (1 .. EPB_MAX_BLOOM_LEVELS)                      */
+    float threshold;      /* luminance above which light blooms (1.0)           */
+    float strength;       /* weight of each added level (0.04)                  */
+    float exposure;       /* multiplies HDR before the ACES curve (1.0)         */
+    float gamma;          /* display gamma (2.2)                                */
+} epb_post_params;
+
+/* Operation ids for epb_scratch_bytes. */
+typedef enum { EPB_OP_PRECOMPUTE_IBL = 0, EPB_OP_SSAO = 1, EPB_OP_BLOOM_TONEMAP = 2 } epb_op;
+
+/*
+ * epb_precompute_ibl -- image-based-lighting tables of one environment
+ * (Sec. 3.1: blurred cube maps for diffuse light, split-sum prefiltered
+ * specular chain and BRDF table).
+ *
+ *   env      cube with levels >= 1 of size S; S = irr_src * 2^k for some k >= 0
+ *            where irr_src = min(S, params->irr_src_size)
+ *   out      irradiance (size irr_size, 1 level), prefiltered (size
+ *            min(S, pref_size), pref_levels levels), brdf_lut (lut_size^2 x 2),
+ *            all caller-allocated
+ *   scratch  >= epb_scratch_bytes(EPB_OP_PRECOMPUTE_IBL, S, S, params)
+ *
+ * Irradiance: E(n) = sum L max(0, n.w) dW / sum max(0, n.w) dW over the texels
+ * of the solid-angle-weighted average of env at size irr_src.  Prefiltered level
+ * m: the N.L-weighted mean of env level 0 over pref_samples GGX reflection
+ * samples (Hammersley) with N = V = R the texel direction and roughness
+ * m / (pref_levels - 1).  BRDF table: the Karis scale and bias integrals
+ * (k = alpha / 2) at N.V = (i + .5) / lut_size, roughness = (j + .5) / lut_size.
+ * Sums are Kahan-compensated in float32.
+ */
+int epb_precompute_ibl(const epb_cube *env, const epb_ibl_params *params, epb_ibl_maps *out,
+                       void *scratch, size_t scratch_bytes, hipStream_t stream);
+
+/*
+ * epb_ssao -- normal-oriented hemisphere ambient occlusion at half resolution,
+ * bilaterally blurred (Sec. 5.2).
+ *
+ *   gbuf, cam  G-buffer and the camera it was rendered with (same W, H)
+ *   ao_out     [Hh][Wh] of params->out_dtype
+ *   scratch    >= epb_scratch_bytes(EPB_OP_SSAO, W, H, params)
+ *
+ * Per half-resolution texel p (background: AO = 1): view-space position P and
+ * normal n; the noise vector of (i mod 4, j mod 4) Gram-Schmidt-orthogonalised
+ * to n gives t and b = n x t; each kernel vector s gives Q = P + radius (t sx +
+ * b sy + n sz), projected to the nearest half-resolution texel q; the sample is
+ * occluded by smoothstep(0, 1, radius / |d_p - d_q|) when d_q <= -Q.z - bias.
+ * AO = 1 - mean occlusion.  The blur is the mean over offsets -2..1 in x and y
+ * weighted by max(0, 1 - |d_q - d_p| / (blur_tau d_p)).
+ */
+int epb_ssao(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_params *params,
+             void *ao_out, void *scratch, size_t scratch_bytes, hipStream_t stream);
+
+/*
+ * epb_shade -- the compose pass (Sec. 4.2) with PBR (Sec. 3) and IBL (Sec. 3.1).
+ *
+ *   gbuf, cam   G-buffer and camera (same W, H)
+ *   ao, ao_dtype  [Hh][Wh] ambient occlusion (e.g. from epb_ssao), or NULL for 1
+ *   lights      host array of n_lights (0 .. EPB_MAX_LIGHTS) lights
+ *   ibl         tables from epb_precompute_ibl
+ *   env         environment cube (level 0 is shown behind the scene)
+ *   hdr_out     [3][H][W] linear radiance of hdr_dtype
+ *
+ * Per pixel: world position from depth; Cook-Torrance with GGX, Smith-Schlick
+ * (k = (r + 1)^2 / 8) and Schlick Fresnel, F0 = mix(0.04, albedo, metal),
+ * Lambert diffuse albedo (1 - metal) / pi, N.V clamped to [1e-4, 1]; per light
+ * the 3x3 percentage-closer shadow test of the light's depth map (taps outside
+ * the map are lit).  Ambient = split-sum specular and irradiance with the
+ * Fdez-Aguera multiple-scattering terms, times the bilinearly upsampled AO.
+ * Background pixels show the environment along the view ray.
+ */
+int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao,
+              epb_dtype ao_dtype, const epb_light *lights, int32_t n_lights,
+              const epb_ibl_maps *ibl, const epb_cube *env, void *hdr_out, epb_dtype hdr_dtype,
+              hipStream_t stream);
+
+/*
+ * epb_bloom_tonemap -- bloom (Sec. 5.3) and final compositing with ACES tone
+ * mapping and gamma correction (Sec. 5.4).
+ *
+ *   hdr       [3][H][W] of hdr_dtype
+ *   ldr_out   [H][W][4] uint8 RGBA (A = 255)
+ *   scratch   >= epb_scratch_bytes(EPB_OP_BLOOM_TONEMAP, W, H, params); on
+ *             return its first part holds the blurred levels 1 .. L-1, each
+ *             [H_l][W_l][4] float (RGB + unused), level after level
+ *
+ * Bright map b = c max(Y - threshold, 0) / Y (Rec. 709 luminance Y); level l
+ * of size ceil(W / 2^l) x ceil(H / 2^l) is the mean of the in-range children of
+ * level l - 1; levels 1 .. L-1 are blurred with the separable [1 4 6 4 1] / 16
+ * kernel (clamp to edge) and added, times strength, bilinearly upsampled; the
+ * result goes through exposure, the ACES fit x (2.51 x + .03) / (x (2.43 x + .59)
+ * + .14), clamp to [0, 1], x^(1 / gamma) and rounding to 8 bits.
+ */
+int epb_bloom_tonemap(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32_t height,
+                      const epb_post_params *params, uint8_t *ldr_out, void *scratch,
+                      size_t scratch_bytes, hipStream_t stream);
+
+/* Bytes of scratch the operation needs for a W x H image (for
+ * EPB_OP_PRECOMPUTE_IBL pass the environment size as W and H and an
+ * epb_ibl_params; for EPB_OP_SSAO an epb_ssao_params or NULL; for
+ * EPB_OP_BLOOM_TONEMAP an epb_post_params).  Returns 0 for invalid arguments. */
+size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *params);
+
+/* Static description of a status code (never NULL). */
+const char *epb_status_str(int status);
+
+/* HIP error code of the last EPB_ERR_HIP returned on the calling thread. */
+int epb_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EPB_H */

@@ -102,14 +102,6 @@ static void face_coords(const double d[3], int axis, int *face, double *s, doubl
     }
 }
 
-/* Major axis with ties broken x before y before z. */
-static int major_axis(const double d[3]) {
-    double ax = fabs(d[0]), ay = fabs(d[1]), az = fabs(d[2]);
-    if (ax >= ay && ax >= az) return 0;
-    if (ay >= az) return 1;
-    return 2;
-}
-
 /* Bilinear lookup with clamp-to-edge inside one face of a cube level. */
 static void face_bilinear(const double *tex, int S, int face, double s, double t, double out[3]) {
     double x = (s + 1.0) * 0.5 * S - 0.5;
@@ -127,13 +119,6 @@ static void face_bilinear(const double *tex, int S, int face, double s, double t
         double v01 = f[((size_t)yb * S + xa) * 4 + c], v11 = f[((size_t)yb * S + xb) * 4 + c];
         out[c] = (1 - wy) * ((1 - wx) * v00 + wx * v10) + wy * ((1 - wx) * v01 + wx * v11);
     }
-}
-
-/* Cube lookup with the deterministic tie-break (used inside the precompute). */
-static void cube_bilinear(const double *tex, int S, const double d[3], double out[3]) {
-    int face; double s, t;
-    face_coords(d, major_axis(d), &face, &s, &t);
-    face_bilinear(tex, S, face, s, t, out);
 }
 
 /* Candidate major axes: every axis whose magnitude is within the relative tie
@@ -300,14 +285,16 @@ void orc_irradiance(const double *src, int S_src, double *out, int S_out) {
 /* Split-sum prefiltered specular chain (Karis 2013): level m has size base >> m
  * and roughness m / (levels - 1); with N = V = R the texel direction, the value
  * is the N.L-weighted mean of the environment over GGX-sampled reflection
- * directions from a Hammersley sequence, looked up bilinearly in level 0. */
-void orc_prefilter(const double *env, int S, double *out, int base, int levels, int samples) {
+ * directions from a Hammersley sequence, looked up bilinearly in level 0.  A
+ * sample whose cube-face choice is within the tie margin contributes the
+ * smaller face value to lo and the larger to hi. */
+void orc_prefilter(const double *env, int S, double *out_lo, double *out_hi, int base, int levels,
+                   int samples, double tie_rel) {
     size_t off = 0;
     for (int m = 0; m < levels; ++m) {
         int sm = base >> m;
         double rough = levels > 1 ? (double)m / (levels - 1) : 0.0;
         double alpha = rough * rough;
-        double *lvl = out + off;
 #pragma omp parallel for schedule(dynamic)
         for (int o = 0; o < 6 * sm * sm; ++o) {
             int f = o / (sm * sm), j = (o / sm) % sm, i = o % sm;
@@ -315,22 +302,23 @@ void orc_prefilter(const double *env, int S, double *out, int base, int levels, 
             orc_cube_texel_dir(f, i, j, sm, n);
             normalize3(n);
             tangent_frame(n, T, B);
-            double acc[3] = {0, 0, 0}, w = 0;
+            double alo[3] = {0, 0, 0}, ahi[3] = {0, 0, 0}, w = 0;
             for (int k = 0; k < samples; ++k) {
-                double h[3], l[3], L[3];
+                double h[3], l[3], Llo[3], Lhi[3];
                 ggx_half_vector((double)k / samples, radical_inverse2((uint32_t)k), alpha, n, T,
                                 B, h);
                 double vh = dot3(n, h);
                 for (int c = 0; c < 3; ++c) l[c] = 2.0 * vh * h[c] - n[c];
                 double nl = dot3(n, l);
                 if (nl > 0.0) {
-                    cube_bilinear(env, S, l, L);
-                    for (int c = 0; c < 3; ++c) acc[c] += L[c] * nl;
+                    cube_bilinear_iv(env, S, l, tie_rel, Llo, Lhi);
+                    for (int c = 0; c < 3; ++c) { alo[c] += Llo[c] * nl; ahi[c] += Lhi[c] * nl; }
                     w += nl;
                 }
             }
-            double *p = lvl + 4 * (size_t)o;
-            p[0] = acc[0] / w; p[1] = acc[1] / w; p[2] = acc[2] / w; p[3] = 0.0;
+            double *pl = out_lo + off + 4 * (size_t)o, *ph = out_hi + off + 4 * (size_t)o;
+            for (int c = 0; c < 3; ++c) { pl[c] = alo[c] / w; ph[c] = ahi[c] / w; }
+            pl[3] = ph[3] = 0.0;
         }
         off += (size_t)6 * sm * sm * 4;
     }
@@ -574,9 +562,9 @@ static double ao_upsample(const double *ao, int Wh, int Hh, int x, int y) {
 void orc_shade(const double *depth, const double *normal, const double *albedo,
                const double *rough, const double *metal, const orc_camera *cam,
                const double *ao_lo, const double *ao_hi, const orc_light *lights, int n_lights,
-               const double *irradiance, int irr_size, const double *prefiltered, int pref_base,
-               int pref_levels, const double *lut, int lut_size, const double *env, int env_size,
-               const orc_tie *tie, double *hdr_lo, double *hdr_hi) {
+               const double *irradiance, int irr_size, const double *pref_lo, const double *pref_hi,
+               int pref_base, int pref_levels, const double *lut, int lut_size, const double *env,
+               int env_size, const orc_tie *tie, double *hdr_lo, double *hdr_hi) {
     int W = cam->width, H = cam->height;
     int Wh = (W + 1) / 2, Hh = (H + 1) / 2;
     size_t plane = (size_t)W * H;
@@ -650,8 +638,12 @@ void orc_shade(const double *depth, const double *normal, const double *albedo,
                 cube_bilinear_iv(irradiance, irr_size, n, tie->rel, Elo, Ehi);
                 double R[3] = {2.0 * nv_raw * n[0] - V[0], 2.0 * nv_raw * n[1] - V[1],
                                2.0 * nv_raw * n[2] - V[2]};
-                chain_trilinear_iv(prefiltered, pref_base, pref_levels, R, r * (pref_levels - 1),
-                                   tie->rel, Plo, Phi);
+                double Pa[3], Pb[3];
+                chain_trilinear_iv(pref_lo, pref_base, pref_levels, R, r * (pref_levels - 1),
+                                   tie->rel, Plo, Pa);
+                chain_trilinear_iv(pref_hi, pref_base, pref_levels, R, r * (pref_levels - 1),
+                                   tie->rel, Pb, Phi);
+                for (int c = 0; c < 3; ++c) { Plo[c] = mind(Plo[c], Pb[c]); Phi[c] = maxd(Phi[c], Pa[c]); }
                 double aol = ao_upsample(ao_lo, Wh, Hh, x, y);
                 double aoh = ao_upsample(ao_hi, Wh, Hh, x, y);
                 double fc5 = pow5(1.0 - NoV);

@@ -61,7 +61,8 @@ int orc_encode_u8(double x, double exposure, double gamma);
 /* a1 image-based-lighting precompute */
 void orc_env_downsample(const double *src, int S, double *dst);
 void orc_irradiance(const double *src, int S_src, double *out, int S_out);
-void orc_prefilter(const double *env, int S, double *out, int base, int levels, int samples);
+void orc_prefilter(const double *env, int S, double *out_lo, double *out_hi, int base, int levels,
+                   int samples, double tie_rel);
 void orc_brdf_lut(double *out, int size, int samples);
 
 /* a2 / a3 screen-space ambient occlusion */
@@ -75,9 +76,9 @@ void orc_ssao_blur(const double *raw_lo, const double *raw_hi, const double *dep
 void orc_shade(const double *depth, const double *normal, const double *albedo,
                const double *rough, const double *metal, const orc_camera *cam,
                const double *ao_lo, const double *ao_hi, const orc_light *lights, int n_lights,
-               const double *irradiance, int irr_size, const double *prefiltered, int pref_base,
-               int pref_levels, const double *lut, int lut_size, const double *env, int env_size,
-               const orc_tie *tie, double *hdr_lo, double *hdr_hi);
+               const double *irradiance, int irr_size, const double *pref_lo, const double *pref_hi,
+               int pref_base, int pref_levels, const double *lut, int lut_size, const double *env,
+               int env_size, const orc_tie *tie, double *hdr_lo, double *hdr_hi);
 
 /* a5 / a6 bloom, composite, tonemap.  pyramid (optional) receives the blurred
  * levels 1..levels-1 as planar [3][H_l][W_l] blocks one after another. */

@@ -76,13 +76,13 @@ def lib():
         L.orc_encode_u8.restype = C.c_int
         L.orc_env_downsample.argtypes = [_D, C.c_int, _D]
         L.orc_irradiance.argtypes = [_D, C.c_int, _D, C.c_int]
-        L.orc_prefilter.argtypes = [_D, C.c_int, _D, C.c_int, C.c_int, C.c_int]
+        L.orc_prefilter.argtypes = [_D, C.c_int, _D, _D, C.c_int, C.c_int, C.c_int, C.c_double]
         L.orc_brdf_lut.argtypes = [_D, C.c_int, C.c_int]
         L.orc_ssao_raw.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, C.c_int, _D, C.c_double,
                                    C.c_double, C.POINTER(OrcTie), _D, _D]
         L.orc_ssao_blur.argtypes = [_D, _D, _D, C.c_int, C.c_int, C.c_double, _D, _D]
         L.orc_shade.argtypes = [_D, _D, _D, _D, _D, C.POINTER(OrcCamera), _D, _D,
-                                C.POINTER(OrcLight), C.c_int, _D, C.c_int, _D, C.c_int, C.c_int,
+                                C.POINTER(OrcLight), C.c_int, _D, C.c_int, _D, _D, C.c_int, C.c_int,
                                 _D, C.c_int, _D, C.c_int, C.POINTER(OrcTie), _D, _D]
         L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                         C.c_double, C.c_double, C.POINTER(C.c_uint8), _D, _D]
@@ -170,18 +170,26 @@ def irradiance(src, out_size: int) -> np.ndarray:
     return out
 
 
-def prefilter(env, base: int, levels: int, samples: int) -> List[np.ndarray]:
+def prefilter(env, base: int, levels: int, samples: int, tie=DEFAULT_TIE,
+              with_hi: bool = False):
+    """Prefiltered chain as a list of (6, s, s, 4) levels; with ``with_hi`` also
+    the upper ends of the face-tie intervals."""
     env = _d(env)
     total = sum(6 * (base >> m) ** 2 * 4 for m in range(levels))
-    out = np.zeros(total)
-    lib().orc_prefilter(_p(env), env.shape[1], _p(out), base, levels, samples)
-    res, off = [], 0
-    for m in range(levels):
-        s = base >> m
-        n = 6 * s * s * 4
-        res.append(out[off:off + n].reshape(6, s, s, 4))
-        off += n
-    return res
+    lo = np.zeros(total)
+    hi = np.zeros(total)
+    lib().orc_prefilter(_p(env), env.shape[1], _p(lo), _p(hi), base, levels, samples, tie[1])
+
+    def split(out):
+        res, off = [], 0
+        for m in range(levels):
+            s = base >> m
+            n = 6 * s * s * 4
+            res.append(out[off:off + n].reshape(6, s, s, 4))
+            off += n
+        return res
+
+    return (split(lo), split(hi)) if with_hi else split(lo)
 
 
 def brdf_lut(size: int, samples: int) -> np.ndarray:
@@ -197,8 +205,8 @@ def precompute_ibl(env, irr_size=32, irr_src_size=64, pref_size=128, pref_levels
     S = env.shape[1]
     src = irradiance_source(env, min(S, irr_src_size))
     base = min(S, pref_size)
-    return dict(irradiance=irradiance(src, irr_size),
-                prefiltered=prefilter(env, base, pref_levels, pref_samples),
+    plo, phi = prefilter(env, base, pref_levels, pref_samples, with_hi=True)
+    return dict(irradiance=irradiance(src, irr_size), prefiltered=plo, prefiltered_hi=phi,
                 lut=brdf_lut(lut_size, lut_samples))
 
 
@@ -254,6 +262,8 @@ def shade(gbuf: dict, cam, ao_lo, ao_hi, lights: Sequence, ibl: dict, env,
             o.shadow_map = C.cast(None, _D)
     irr = _d(ibl["irradiance"])
     pref = _d(np.concatenate([np.asarray(m, np.float64).reshape(-1) for m in ibl["prefiltered"]]))
+    pref_hi = _d(np.concatenate([np.asarray(m, np.float64).reshape(-1)
+                                 for m in ibl.get("prefiltered_hi", ibl["prefiltered"])]))
     lut = _d(ibl["lut"])
     env = _d(env)
     lo = np.zeros((3, H, W))
@@ -261,7 +271,7 @@ def shade(gbuf: dict, cam, ao_lo, ao_hi, lights: Sequence, ibl: dict, env,
     c, t = _cam(cam), _tie(tie)
     lib().orc_shade(_p(depth), _p(normal), _p(albedo), _p(rough), _p(metal), C.byref(c),
                     _p(ao_lo), _p(ao_hi), arr, len(lights), _p(irr), irr.shape[1], _p(pref),
-                    ibl["prefiltered"][0].shape[1], len(ibl["prefiltered"]), _p(lut), lut.shape[0],
+                    _p(pref_hi), ibl["prefiltered"][0].shape[1], len(ibl["prefiltered"]), _p(lut), lut.shape[0],
                     _p(env), env.shape[1], C.byref(t), _p(lo), _p(hi))
     return lo, hi
 

@@ -1,0 +1,229 @@
+// Device-side helpers shared by the gfx950 kernels of the shading pass:
+// small vector algebra, storage conversions, camera projection, cube-map
+// addressing and filtering, compensated summation and the XCD-aware block
+// order.  Nothing here is host code.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace epb {
+
+constexpr float kPi = 3.14159265358979323846f;
+constexpr int kNumXcd = 8;  // MI355X: 256 CUs in 8 accelerator complex dies
+
+// ---------------------------------------------------------------------------
+// storage
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float ldc(const float *p) { return *p; }
+__device__ __forceinline__ float ldc(const __half *p) { return __half2float(*p); }
+
+__device__ __forceinline__ void st(float *p, float v) { *p = v; }
+__device__ __forceinline__ void st(__half *p, float v) {
+    // saturate instead of overflowing to inf (HDR peaks can exceed 65504)
+    *p = __float2half_rn(fminf(v, 65504.0f));
+}
+
+// ---------------------------------------------------------------------------
+// vectors
+// ---------------------------------------------------------------------------
+struct v3 {
+    float x, y, z;
+};
+__device__ __forceinline__ v3 mk3(float x, float y, float z) { return v3{x, y, z}; }
+__device__ __forceinline__ v3 operator+(v3 a, v3 b) { return mk3(a.x + b.x, a.y + b.y, a.z + b.z); }
+__device__ __forceinline__ v3 operator-(v3 a, v3 b) { return mk3(a.x - b.x, a.y - b.y, a.z - b.z); }
+__device__ __forceinline__ v3 operator*(v3 a, float s) { return mk3(a.x * s, a.y * s, a.z * s); }
+__device__ __forceinline__ float dot(v3 a, v3 b) { return fmaf(a.x, b.x, fmaf(a.y, b.y, a.z * b.z)); }
+__device__ __forceinline__ v3 cross(v3 a, v3 b) {
+    return mk3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
+}
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ v3 normalize(v3 a) { return a * rsq(dot(a, a)); }
+__device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+__device__ __forceinline__ float pow5(float x) {
+    float x2 = x * x;
+    return x2 * x2 * x;
+}
+
+// Rigid transform / camera as kernel argument.
+struct DevCam {
+    float R[9];  // row-major rotation
+    float t[3];
+    float fx, fy, cx, cy;
+    float inv_fx, inv_fy;
+    int w, h;
+};
+__device__ __forceinline__ v3 mul_R(const float *R, v3 v) {
+    return mk3(fmaf(R[0], v.x, fmaf(R[1], v.y, R[2] * v.z)), fmaf(R[3], v.x, fmaf(R[4], v.y, R[5] * v.z)),
+               fmaf(R[6], v.x, fmaf(R[7], v.y, R[8] * v.z)));
+}
+__device__ __forceinline__ v3 mul_Rt(const float *R, v3 v) {
+    return mk3(fmaf(R[0], v.x, fmaf(R[3], v.y, R[6] * v.z)), fmaf(R[1], v.x, fmaf(R[4], v.y, R[7] * v.z)),
+               fmaf(R[2], v.x, fmaf(R[5], v.y, R[8] * v.z)));
+}
+
+// ---------------------------------------------------------------------------
+// cube maps: [face][S][S] float4 texels, faces +X -X +Y -Y +Z -Z
+// ---------------------------------------------------------------------------
+struct FaceST {
+    int face;
+    float s, t;  // in [-1, 1] on the face
+};
+
+// Major axis with ties broken x, then y, then z.
+__device__ __forceinline__ FaceST cube_face(v3 d) {
+    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
+    FaceST r;
+    float ma, sc, tc;
+    if (ax >= ay && ax >= az) {
+        ma = ax;
+        r.face = d.x >= 0.0f ? 0 : 1;
+        sc = d.x >= 0.0f ? -d.z : d.z;
+        tc = -d.y;
+    } else if (ay >= az) {
+        ma = ay;
+        r.face = d.y >= 0.0f ? 2 : 3;
+        sc = d.x;
+        tc = d.y >= 0.0f ? d.z : -d.z;
+    } else {
+        ma = az;
+        r.face = d.z >= 0.0f ? 4 : 5;
+        sc = d.z >= 0.0f ? d.x : -d.x;
+        tc = -d.y;
+    }
+    float inv = rcp(ma);
+    r.s = sc * inv;
+    r.t = tc * inv;
+    return r;
+}
+
+__device__ __forceinline__ float4 ld4(const float4 *p) { return *p; }
+__device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
+    return make_float4(fmaf(w, b.x - a.x, a.x), fmaf(w, b.y - a.y, a.y), fmaf(w, b.z - a.z, a.z), 0.0f);
+}
+
+// Bilinear, clamp-to-edge inside one face of one level.
+__device__ __forceinline__ float4 face_bilinear(const float4 *__restrict__ lvl, int S, FaceST f) {
+    float half = 0.5f * (float)S;
+    float x = fmaf(f.s, half, half - 0.5f);
+    float y = fmaf(f.t, half, half - 0.5f);
+    float x0f = floorf(x), y0f = floorf(y);
+    float wx = x - x0f, wy = y - y0f;
+    int x0 = (int)x0f, y0 = (int)y0f;
+    int xa = min(max(x0, 0), S - 1), xb = min(max(x0 + 1, 0), S - 1);
+    int ya = min(max(y0, 0), S - 1), yb = min(max(y0 + 1, 0), S - 1);
+    const float4 *fp = lvl + (size_t)f.face * S * S;
+    float4 a = ld4(fp + ya * S + xa), b = ld4(fp + ya * S + xb);
+    float4 c = ld4(fp + yb * S + xa), d = ld4(fp + yb * S + xb);
+    return lerp4(lerp4(a, b, wx), lerp4(c, d, wx), wy);
+}
+
+__device__ __forceinline__ float4 cube_bilinear(const float4 *__restrict__ lvl, int S, v3 d) {
+    return face_bilinear(lvl, S, cube_face(d));
+}
+
+// Offset (in texels) of level m of a chain with base size `base`.
+__device__ __forceinline__ size_t chain_offset(int base, int m) {
+    size_t off = 0;
+    for (int k = 0; k < m; ++k) off += (size_t)6 * (base >> k) * (base >> k);
+    return off;
+}
+
+// ---------------------------------------------------------------------------
+// compensated (Kahan) summation; contraction must stay off inside
+// ---------------------------------------------------------------------------
+struct Kahan {
+    float s, c;
+};
+__device__ __forceinline__ void kahan_add(Kahan &k, float x) {
+#pragma clang fp contract(off)
+    float y = x - k.c;
+    float t = k.s + y;
+    k.c = (t - k.s) - y;
+    k.s = t;
+}
+__device__ __forceinline__ float kahan_value(const Kahan &k) {
+#pragma clang fp contract(off)
+    return k.s - k.c;
+}
+
+// Error-free sum of two floats (Knuth): a + b = s + e exactly.
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+#pragma clang fp contract(off)
+    s = a + b;
+    float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// Compensated sum over the 64 lanes of a wavefront; every lane gets the total.
+__device__ __forceinline__ float wave_sum_compensated(float v) {
+    float comp = 0.0f;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+        float o = __shfl_xor(v, off, 64);
+        float oc = __shfl_xor(comp, off, 64);
+        float s, e;
+        two_sum(v, o, s, e);
+        v = s;
+        comp = comp + oc + e;
+    }
+    return v + comp;
+}
+
+// ---------------------------------------------------------------------------
+// launch order: consecutive tiles go to the same XCD (own L2)
+// ---------------------------------------------------------------------------
+// The dispatcher hands workgroup b to XCD b % 8.  Remap so that XCD k
+// processes a contiguous range of tiles (a bijection for any grid size).
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    int q = nb / kNumXcd, r = nb % kNumXcd;
+    int x = b % kNumXcd, local = b / kNumXcd;
+    return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+// GGX half vector for the point (u1, u2) around normal n with tangent frame
+// (T, B): phi = 2 pi u1, cos^2 = (1 - u2) / den, sin^2 = alpha^2 u2 / den,
+// den = (1 - u2) + alpha^2 u2 (both fractions without cancellation).
+__device__ __forceinline__ v3 ggx_half(float u1, float u2, float a2, v3 n, v3 T, v3 B) {
+    float om = 1.0f - u2;
+    float den = fmaf(a2, u2, om);
+    float inv = rcp(den);
+    float ct = sqrtf(om * inv);
+    float st = sqrtf(a2 * u2 * inv);
+    float sp, cp;
+    sincospif(2.0f * u1, &sp, &cp);
+    float hx = st * cp, hy = st * sp;
+    return mk3(fmaf(T.x, hx, fmaf(B.x, hy, n.x * ct)), fmaf(T.y, hx, fmaf(B.y, hy, n.y * ct)),
+               fmaf(T.z, hx, fmaf(B.z, hy, n.z * ct)));
+}
+
+// Tangent frame: up = +z unless |n.z| >= 0.999, then +x; T = norm(up x n), B = n x T.
+__device__ __forceinline__ void tangent_frame(v3 n, v3 &T, v3 &B) {
+    v3 up = fabsf(n.z) < 0.999f ? mk3(0.0f, 0.0f, 1.0f) : mk3(1.0f, 0.0f, 0.0f);
+    T = normalize(cross(up, n));
+    B = cross(n, T);
+}
+
+__device__ __forceinline__ float radical_inverse2(uint32_t k) {
+    return (float)__builtin_bitreverse32(k) * 2.3283064365386963e-10f;  // 2^-32
+}
+
+// Texel-centre direction of cube texel (i, j) on a face of size S (not unit).
+__device__ __forceinline__ v3 cube_texel_dir(int face, int i, int j, int S) {
+    float inv = 1.0f / (float)S;
+    float s = (float)(2 * i + 1 - S) * inv;
+    float t = (float)(2 * j + 1 - S) * inv;
+    switch (face) {
+    case 0: return mk3(1.0f, -t, -s);
+    case 1: return mk3(-1.0f, -t, s);
+    case 2: return mk3(s, 1.0f, t);
+    case 3: return mk3(s, -1.0f, -t);
+    case 4: return mk3(s, -t, 1.0f);
+    default: return mk3(-s, -t, -1.0f);
+    }
+}
+
+}  // namespace epb

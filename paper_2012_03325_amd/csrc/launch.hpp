@@ -1,0 +1,91 @@
+// Internal launch interface between the C ABI (api.cpp) and the kernels.
+// Arguments are already validated when these are called; each returns the
+// hipError_t of its launches.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/epb.h"
+
+namespace epb {
+
+struct HostCam {
+    float R[9], t[3];
+    float fx, fy, cx, cy, inv_fx, inv_fy;
+    int w, h;
+};
+
+// ---- image-based lighting (ibl.hip) ---------------------------------------
+struct IblPlan {
+    int S;          // environment face size
+    int src;        // irradiance source size
+    int irr;        // irradiance output size
+    int pref_base, pref_levels, pref_samples;
+    int lut, lut_samples;
+    int chunks;     // split of the irradiance source sum
+    size_t off_src, off_tab, off_part, bytes;  // scratch layout
+};
+IblPlan ibl_plan(int S, const epb_ibl_params &p);
+hipError_t launch_precompute_ibl(const IblPlan &plan, const float *env, float *irr, float *pref,
+                                 float *lut, void *scratch, hipStream_t s);
+
+// ---- SSAO (ssao.hip) --------------------------------------------------------
+struct SsaoPlan {
+    int W, H, Wh, Hh;
+    size_t off_hdepth, off_raw, bytes;
+};
+SsaoPlan ssao_plan(int W, int H);
+hipError_t launch_ssao(const SsaoPlan &plan, const float *depth, const void *normal,
+                       epb_dtype gdtype, const HostCam &cam, const float *kernel, int n_samples,
+                       const float *noise, float radius, float bias, float tau, int blur,
+                       void *ao_out, epb_dtype ao_dtype, void *scratch, hipStream_t s);
+
+// ---- shading (shade.hip) ----------------------------------------------------
+struct HostLight {
+    float pos[3], rad[3];     // rad = color * intensity
+    const float *map;         // may be null
+    float M[9], o[3];         // light-from-camera-view transform: P_l = M P_v + o
+    float fx, fy, cx, cy;
+    int w, h;
+    float bias;
+};
+struct ShadeArgs {
+    const float *depth;
+    const void *normal, *albedo, *rough, *metal;
+    epb_dtype gdtype;
+    int W, H;
+    HostCam cam;
+    float cam_pos[3];
+    const void *ao;
+    epb_dtype ao_dtype;
+    int n_lights;
+    HostLight lights[EPB_MAX_LIGHTS];
+    const float *irr;
+    int irr_size;
+    const float *pref;
+    int pref_base, pref_levels;
+    const float *lut;
+    int lut_size;
+    const float *env;
+    int env_size;
+    void *hdr;
+    epb_dtype hdr_dtype;
+};
+hipError_t launch_shade(const ShadeArgs &a, hipStream_t s);
+
+// ---- bloom + tonemap (post.hip) ----------------------------------------------
+struct PostPlan {
+    int W, H, levels;
+    int lw[EPB_MAX_BLOOM_LEVELS], lh[EPB_MAX_BLOOM_LEVELS];
+    size_t off_blur[EPB_MAX_BLOOM_LEVELS];  // blurred level l (float4 texels)
+    size_t off_raw[EPB_MAX_BLOOM_LEVELS];   // unblurred level l
+    size_t bytes;
+};
+PostPlan post_plan(int W, int H, int levels);
+hipError_t launch_bloom_tonemap(const PostPlan &plan, const void *hdr, epb_dtype hdr_dtype,
+                                float threshold, float strength, float exposure, float gamma,
+                                uint8_t *ldr, void *scratch, hipStream_t s);
+
+}  // namespace epb

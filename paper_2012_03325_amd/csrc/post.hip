@@ -1,0 +1,272 @@
+// Bloom (paper Sec. 5.3) and final compositing with ACES tone mapping and
+// gamma correction (Sec. 5.4).
+//
+// gfx950 mapping:
+//  * k_bloom_down: one workgroup per 64x64-pixel tile reads the HDR planes
+//    once, forms the bright map and its 2x2 means, and builds pyramid levels
+//    1..5 of that tile in LDS (a level-1 tile of 32x32 texels halves down to
+//    2x2 at level 5), writing every level once.
+//  * k_bloom_blur: all levels in one launch; each workgroup stages a 36x12
+//    texel footprint of its 32x8 tile in LDS and applies the separable
+//    [1 4 6 4 1] / 16 binomial (clamp to edge) horizontally then vertically.
+//  * k_composite: one thread per pixel adds the bilinearly upsampled blurred
+//    levels (float4 texels, L2-resident), applies exposure, the ACES fit,
+//    gamma and 8-bit rounding, and writes one 32-bit RGBA word.
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace epb {
+
+struct PostK {
+    int W, H, nl;  // nl = number of levels >= 1
+    int lw[EPB_MAX_BLOOM_LEVELS], lh[EPB_MAX_BLOOM_LEVELS];
+    float4 *raw[EPB_MAX_BLOOM_LEVELS];
+    float4 *blur[EPB_MAX_BLOOM_LEVELS];
+    int blk_start[EPB_MAX_BLOOM_LEVELS + 1];  // blur launch: first block of each level
+    float threshold, strength, exposure, inv_gamma;
+    int tiles_x, tiles;
+};
+
+__device__ __forceinline__ float4 add4(float4 a, float4 b) {
+    return make_float4(a.x + b.x, a.y + b.y, a.z + b.z, 0.0f);
+}
+__device__ __forceinline__ float4 scale4(float4 a, float s) { return make_float4(a.x * s, a.y * s, a.z * s, 0.0f); }
+
+template <typename TH>
+__global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__restrict__ hdr) {
+    __shared__ float4 s1[32][33];
+    __shared__ float4 s2[16][17];
+    __shared__ float4 s3[8][9];
+    __shared__ float4 s4[4][5];
+    int tile = xcd_tile(blockIdx.x, c.tiles);
+    int bx = tile % c.tiles_x, by = tile / c.tiles_x;
+    int t = threadIdx.x;
+    size_t plane = (size_t)c.W * c.H;
+    // level 1: bright map averaged over the in-range 2x2 children
+    {
+        int lx = t % 32;
+        for (int ly = t / 32; ly < 32; ly += 8) {
+            int X = bx * 32 + lx, Y = by * 32 + ly;
+            float4 v = make_float4(0, 0, 0, 0);
+            if (X < c.lw[1] && Y < c.lh[1]) {
+                float n = 0.0f;
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+#pragma unroll
+                    for (int a = 0; a < 2; ++a) {
+                        int px = 2 * X + a, py = 2 * Y + b;
+                        if (px < c.W && py < c.H) {
+                            size_t p = (size_t)py * c.W + px;
+                            float R = ldc(hdr + p), G = ldc(hdr + plane + p), B = ldc(hdr + 2 * plane + p);
+                            float Yl = fmaf(0.2126f, R, fmaf(0.7152f, G, 0.0722f * B));
+                            float sc = Yl > 0.0f ? fmaxf(Yl - c.threshold, 0.0f) / Yl : 0.0f;
+                            v.x = fmaf(R, sc, v.x);
+                            v.y = fmaf(G, sc, v.y);
+                            v.z = fmaf(B, sc, v.z);
+                            n += 1.0f;
+                        }
+                    }
+                v = scale4(v, 1.0f / n);
+                c.raw[1][(size_t)Y * c.lw[1] + X] = v;
+            }
+            s1[ly][lx] = v;
+        }
+    }
+    __syncthreads();
+    // levels 2..5 inside the tile; a texel averages its in-range children
+#define EPB_LEVEL(L, SRC, DST, N)                                                                   \
+    if (c.nl >= L) {                                                                                \
+        if (t < N * N) {                                                                            \
+            int lx = t % N, ly = t / N;                                                             \
+            int X = bx * N + lx, Y = by * N + ly;                                                   \
+            float4 v = make_float4(0, 0, 0, 0);                                                     \
+            if (X < c.lw[L] && Y < c.lh[L]) {                                                       \
+                float n = 0.0f;                                                                     \
+                for (int b = 0; b < 2; ++b)                                                         \
+                    for (int a = 0; a < 2; ++a)                                                     \
+                        if (2 * X + a < c.lw[L - 1] && 2 * Y + b < c.lh[L - 1]) {                   \
+                            v = add4(v, SRC[2 * ly + b][2 * lx + a]);                               \
+                            n += 1.0f;                                                              \
+                        }                                                                           \
+                v = scale4(v, 1.0f / n);                                                            \
+                c.raw[L][(size_t)Y * c.lw[L] + X] = v;                                              \
+            }                                                                                       \
+            DST[ly][lx] = v;                                                                        \
+        }                                                                                           \
+        __syncthreads();                                                                            \
+    }
+    EPB_LEVEL(2, s1, s2, 16)
+    EPB_LEVEL(3, s2, s3, 8)
+    EPB_LEVEL(4, s3, s4, 4)
+    if (c.nl >= 5 && t < 4) {
+        int lx = t % 2, ly = t / 2;
+        int X = bx * 2 + lx, Y = by * 2 + ly;
+        if (X < c.lw[5] && Y < c.lh[5]) {
+            float4 v = make_float4(0, 0, 0, 0);
+            float n = 0.0f;
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a)
+                    if (2 * X + a < c.lw[4] && 2 * Y + b < c.lh[4]) {
+                        v = add4(v, s4[2 * ly + b][2 * lx + a]);
+                        n += 1.0f;
+                    }
+            c.raw[5][(size_t)Y * c.lw[5] + X] = scale4(v, 1.0f / n);
+        }
+    }
+#undef EPB_LEVEL
+}
+
+__global__ void __launch_bounds__(256) k_bloom_blur(const PostK c) {
+    __shared__ float4 sin_[12][36];
+    __shared__ float4 sh[12][32];
+    int b = blockIdx.x;
+    int L = 1;
+    while (L < c.nl && b >= c.blk_start[L + 1]) ++L;
+    int local = b - c.blk_start[L];
+    int w = c.lw[L], h = c.lh[L];
+    int tx = (w + 31) / 32;
+    int X0 = (local % tx) * 32, Y0 = (local / tx) * 8;
+    const float4 *src = c.raw[L];
+    int t = threadIdx.x;
+    for (int q = t; q < 12 * 36; q += 256) {
+        int r = q / 36, cc = q % 36;
+        int gy = min(max(Y0 + r - 2, 0), h - 1);
+        int gx = min(max(X0 + cc - 2, 0), w - 1);
+        sin_[r][cc] = src[(size_t)gy * w + gx];
+    }
+    __syncthreads();
+    for (int q = t; q < 12 * 32; q += 256) {
+        int r = q / 32, cc = q % 32;
+        float4 a = sin_[r][cc], bb = sin_[r][cc + 1], m = sin_[r][cc + 2], d = sin_[r][cc + 3], e = sin_[r][cc + 4];
+        sh[r][cc] = make_float4((a.x + e.x + 4.0f * (bb.x + d.x) + 6.0f * m.x) * 0.0625f,
+                                (a.y + e.y + 4.0f * (bb.y + d.y) + 6.0f * m.y) * 0.0625f,
+                                (a.z + e.z + 4.0f * (bb.z + d.z) + 6.0f * m.z) * 0.0625f, 0.0f);
+    }
+    __syncthreads();
+    int ox = t % 32, oy = t / 32;
+    int X = X0 + ox, Y = Y0 + oy;
+    if (X < w && Y < h) {
+        float4 a = sh[oy][ox], bb = sh[oy + 1][ox], m = sh[oy + 2][ox], d = sh[oy + 3][ox], e = sh[oy + 4][ox];
+        c.blur[L][(size_t)Y * w + X] =
+            make_float4((a.x + e.x + 4.0f * (bb.x + d.x) + 6.0f * m.x) * 0.0625f,
+                        (a.y + e.y + 4.0f * (bb.y + d.y) + 6.0f * m.y) * 0.0625f,
+                        (a.z + e.z + 4.0f * (bb.z + d.z) + 6.0f * m.z) * 0.0625f, 0.0f);
+    }
+}
+
+__device__ __forceinline__ float aces(float x) {
+    return x * fmaf(2.51f, x, 0.03f) / fmaf(x, fmaf(2.43f, x, 0.59f), 0.14f);
+}
+__device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_gamma) {
+    float y = clamp01(aces(exposure * x));
+    float g = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(y) * inv_gamma);
+    float q = floorf(fmaf(255.0f, g, 0.5f));
+    return (uint32_t)fminf(fmaxf(q, 0.0f), 255.0f);
+}
+
+template <typename TH>
+__global__ void __launch_bounds__(256) k_composite(const PostK c, const TH *__restrict__ hdr,
+                                                   uint32_t *__restrict__ ldr) {
+    int tile = xcd_tile(blockIdx.x, c.tiles);
+    int x = (tile % c.tiles_x) * 32 + (int)(threadIdx.x % 32);
+    int y = (tile / c.tiles_x) * 8 + (int)(threadIdx.x / 32);
+    if (x >= c.W || y >= c.H) return;
+    size_t p = (size_t)y * c.W + x;
+    size_t plane = (size_t)c.W * c.H;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    float sc = 0.5f;
+    for (int L = 1; L <= c.nl; ++L, sc *= 0.5f) {
+        int w = c.lw[L], h = c.lh[L];
+        float fx = fmaf((float)x + 0.5f, sc, -0.5f), fy = fmaf((float)y + 0.5f, sc, -0.5f);
+        float x0f = floorf(fx), y0f = floorf(fy);
+        float wx = fx - x0f, wy = fy - y0f;
+        int x0 = (int)x0f, y0 = (int)y0f;
+        int xa = min(max(x0, 0), w - 1), xb = min(max(x0 + 1, 0), w - 1);
+        int ya = min(max(y0, 0), h - 1), yb = min(max(y0 + 1, 0), h - 1);
+        const float4 *B = c.blur[L];
+        float4 v = lerp4(lerp4(B[(size_t)ya * w + xa], B[(size_t)ya * w + xb], wx),
+                         lerp4(B[(size_t)yb * w + xa], B[(size_t)yb * w + xb], wx), wy);
+        sx += v.x;
+        sy += v.y;
+        sz += v.z;
+    }
+    float R = fmaf(c.strength, sx, ldc(hdr + p));
+    float G = fmaf(c.strength, sy, ldc(hdr + plane + p));
+    float Bc = fmaf(c.strength, sz, ldc(hdr + 2 * plane + p));
+    uint32_t word = encode8(R, c.exposure, c.inv_gamma) | (encode8(G, c.exposure, c.inv_gamma) << 8) |
+                    (encode8(Bc, c.exposure, c.inv_gamma) << 16) | (255u << 24);
+    ldr[p] = word;
+}
+
+PostPlan post_plan(int W, int H, int levels) {
+    PostPlan q{};
+    q.W = W;
+    q.H = H;
+    q.levels = levels;
+    q.lw[0] = W;
+    q.lh[0] = H;
+    for (int l = 1; l < levels; ++l) {
+        q.lw[l] = (q.lw[l - 1] + 1) / 2;
+        q.lh[l] = (q.lh[l - 1] + 1) / 2;
+    }
+    size_t off = 0;
+    for (int l = 1; l < levels; ++l) {  // blurred levels first (documented scratch layout)
+        q.off_blur[l] = off;
+        off += (size_t)q.lw[l] * q.lh[l] * 16;
+    }
+    off = (off + 255) & ~size_t(255);
+    for (int l = 1; l < levels; ++l) {
+        q.off_raw[l] = off;
+        off += (size_t)q.lw[l] * q.lh[l] * 16;
+    }
+    q.bytes = (off + 255) & ~size_t(255);
+    if (q.bytes == 0) q.bytes = 256;
+    return q;
+}
+
+hipError_t launch_bloom_tonemap(const PostPlan &q, const void *hdr, epb_dtype hdr_dtype, float threshold,
+                                float strength, float exposure, float gamma, uint8_t *ldr, void *scratch,
+                                hipStream_t s) {
+    PostK c{};
+    c.W = q.W;
+    c.H = q.H;
+    c.nl = q.levels - 1;
+    char *sc = (char *)scratch;
+    for (int l = 0; l < q.levels; ++l) {
+        c.lw[l] = q.lw[l];
+        c.lh[l] = q.lh[l];
+        if (l >= 1) {
+            c.raw[l] = (float4 *)(sc + q.off_raw[l]);
+            c.blur[l] = (float4 *)(sc + q.off_blur[l]);
+        }
+    }
+    c.threshold = threshold;
+    c.strength = strength;
+    c.exposure = exposure;
+    c.inv_gamma = 1.0f / gamma;
+    if (c.nl >= 1) {
+        c.tiles_x = (c.lw[1] + 31) / 32;
+        c.tiles = c.tiles_x * ((c.lh[1] + 31) / 32);
+        if (hdr_dtype == EPB_F32)
+            hipLaunchKernelGGL(k_bloom_down<float>, dim3(c.tiles), dim3(256), 0, s, c, (const float *)hdr);
+        else
+            hipLaunchKernelGGL(k_bloom_down<__half>, dim3(c.tiles), dim3(256), 0, s, c, (const __half *)hdr);
+        int nb = 0;
+        for (int l = 1; l <= c.nl; ++l) {
+            c.blk_start[l] = nb;
+            nb += ((c.lw[l] + 31) / 32) * ((c.lh[l] + 7) / 8);
+        }
+        c.blk_start[c.nl + 1] = nb;
+        hipLaunchKernelGGL(k_bloom_blur, dim3(nb), dim3(256), 0, s, c);
+    }
+    c.tiles_x = (q.W + 31) / 32;
+    c.tiles = c.tiles_x * ((q.H + 7) / 8);
+    if (hdr_dtype == EPB_F32)
+        hipLaunchKernelGGL(k_composite<float>, dim3(c.tiles), dim3(256), 0, s, c, (const float *)hdr, (uint32_t *)ldr);
+    else
+        hipLaunchKernelGGL(k_composite<__half>, dim3(c.tiles), dim3(256), 0, s, c, (const __half *)hdr,
+                           (uint32_t *)ldr);
+    return hipGetLastError();
+}
+
+}  // namespace epb

@@ -364,7 +364,12 @@ def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, s
     """One seeded view.  ``n_lights == 1`` puts a white light of intensity 40 at
     (3, 5, 4); otherwise lights sit at azimuth 45 + 90 k degrees, radius 6,
     height 6.  ``shadow_size > 0`` renders a square depth map per light with a
-    90 degree camera looking at the origin."""
+    90 degree camera looking at the origin.
+
+    Under the HDR sky-and-sun environment (sky radiance up to 1e2, sun 1e4) the
+    lights get intensity 1500 (about the sky's irradiance at the scene) and the
+    exposure is 0.012, which maps the median shaded radiance (about 24) to the
+    middle of the ACES curve; with exposure 1 that sky saturates every pixel."""
     rng = np.random.default_rng(seed)
     scene = make_spheres(rng, n_spheres, plane)
     cam = look_at((0.0, 3.5, 8.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, width, height)
@@ -378,7 +383,7 @@ def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, s
                      for k in range(n_lights)]
     for p in positions:
         p = p.astype(np.float32).astype(np.float64)
-        light = Light(p, np.array([1.0, 1.0, 1.0]), 40.0)
+        light = Light(p, np.array([1.0, 1.0, 1.0]), 1500.0 if env_kind == "sun" else 40.0)
         if shadow_size > 0:
             lc = look_at(p, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 90.0, shadow_size, shadow_size)
             light.shadow_cam = lc
@@ -396,6 +401,8 @@ def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, s
     kern = ssao_kernel(krng, ssao_n)
     noise = ssao_noise(krng)
     v = ViewInputs(name, cam, gbuf, lights, env, kern, noise)
+    if env_kind == "sun":
+        v.exposure = 0.012
     if ibl is not None:
         v.ibl = dict(v.ibl, **ibl)
     return v
@@ -418,7 +425,8 @@ def config_reduced(width: int, height: int, seed: int = 5, shadow_size: int = 25
                    n_lights: int = 4) -> ViewInputs:
     """A reduced copy of the 1080p workload (plane, shadowed lights, sun sky) at a
     size the FP64 oracle finishes in seconds; used for parity tests."""
-    ibl = dict(irr_src_size=min(64, env_size), pref_size=min(128, env_size), pref_samples=256,
-               lut_size=32, lut_samples=256)
+    base = min(128, env_size)
+    ibl = dict(irr_src_size=min(64, env_size), pref_size=base, pref_samples=256,
+               pref_levels=min(5, base.bit_length()), lut_size=32, lut_samples=256)
     return make_view(f"reduced-{width}x{height}", width, height, n_spheres, True, seed, n_lights,
                      shadow_size, env_size, "sun", ssao_n, ibl)

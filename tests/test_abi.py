@@ -1,0 +1,190 @@
+"""The C ABI on the CPU: the library loads, exports every entry point the
+header declares, its structs have the header's layout, and argument
+validation returns the documented status before anything is enqueued (no
+compute call is made here: every case fails validation)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2012_03325_amd import epb as E
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "epb.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(epb_\w+)\s*\(", text, flags=re.M)))
+
+
+def test_library_exports_every_declared_entry_point():
+    names = _declared_functions()
+    assert set(E.ENTRY_POINTS) <= set(names)
+    lib = C.CDLL(E.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+    assert {"epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap"} <= set(names)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    """Compile a probe against the header with gcc and compare sizes and field
+    offsets with the ctypes mirrors of the binding."""
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "epb.h"', "int main(void){"]
+    for sname, st in E.STRUCTS.items():
+        lines.append(f'printf("{sname} __sizeof__ %zu\\n", sizeof({sname}));')
+        for fname, _ in st._fields_:
+            lines.append(f'printf("{sname} {fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines.append("return 0;}")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-D__HIP_PLATFORM_AMD__", "-I", os.path.join(ROOT, "include"),
+                    "-I", "/opt/rocm/include", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    seen = {}
+    for line in out.splitlines():
+        a, b, v = line.split()
+        seen[(a, b)] = int(v)
+    for sname, st in E.STRUCTS.items():
+        assert seen[(sname, "__sizeof__")] == C.sizeof(st), sname
+        for fname, _ in st._fields_:
+            assert seen[(sname, fname)] == getattr(st, fname).offset, (sname, fname)
+
+
+def test_status_strings():
+    for code in range(0, -8, -1):
+        s = E.epb_status_str(code)
+        assert s and s != "unknown status"
+    assert E.epb_status_str(-99) == "unknown status"
+
+
+def test_scratch_sizes():
+    post = E.epb_post_params(6, 1.0, 0.04, 1.0, 2.2)
+    prev = 0
+    for n in (8, 64, 256, 1080, 2160):
+        b = E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, n, n, post)
+        s = E.epb_scratch_bytes(E.EPB_OP_SSAO, n, n, None)
+        assert b > 0 and s >= 2 * ((n + 1) // 2) ** 2 * 4
+        assert b >= prev
+        prev = b
+    assert E.epb_scratch_bytes(E.EPB_OP_SSAO, 0, 10, None) == 0
+    assert E.epb_scratch_bytes(99, 10, 10, None) == 0
+    bad = E.epb_post_params(7, 1.0, 0.04, 1.0, 2.2)
+    assert E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, 10, 10, bad) == 0
+    ip = E.epb_ibl_params(32, 64, 128, 5, 1024, 256, 1024)
+    assert E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 512, 512, ip) > 0
+    assert E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 96, 96, ip) == 0  # 96 / 64 not a power of 2
+
+
+# A fake but 16-byte-aligned device address: only ever seen by validation,
+# since every call below fails before launching.
+FAKE = 0x7F0000001000
+
+
+def _cam(w=64, h=48):
+    return E.make_camera([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0], 50, 50, w / 2, h / 2, w, h)
+
+
+def _gbuf(w=64, h=48, dt=E.EPB_F32, base=FAKE):
+    return E.epb_gbuffer(w, h, dt, base, base, base, base, base)
+
+
+def test_ssao_validation():
+    cam = _cam()
+    p = E.epb_ssao_params(16, FAKE, FAKE, 0.5, 0.025, 0.1, 1, E.EPB_F32)
+    call = lambda g=_gbuf(), c=cam, pp=p, out=FAKE, sc=FAKE, n=1 << 30: \
+        E.lib.epb_ssao(C.byref(g), C.byref(c), C.byref(pp), out, sc, n, None)
+    assert E.lib.epb_ssao(None, C.byref(cam), C.byref(p), FAKE, FAKE, 1 << 30, None) == E.EPB_ERR_NULL
+    assert call(out=None) == E.EPB_ERR_NULL
+    assert call(g=_gbuf(w=63)) == E.EPB_ERR_SIZE
+    assert call(c=_cam(0, 48), g=_gbuf(0, 48)) == E.EPB_ERR_SIZE
+    assert call(g=_gbuf(dt=7)) == E.EPB_ERR_DTYPE
+    assert call(g=_gbuf(base=FAKE + 4)) == E.EPB_ERR_ALIGN
+    assert call(out=FAKE + 8) == E.EPB_ERR_ALIGN
+    assert call(sc=None) == E.EPB_ERR_SCRATCH
+    assert call(n=16) == E.EPB_ERR_SCRATCH
+    for bad in (dict(n_samples=0), dict(n_samples=257), dict(radius=0.0), dict(radius=float("nan")),
+                dict(blur_tau=0.0)):
+        q = E.epb_ssao_params(16, FAKE, FAKE, 0.5, 0.025, 0.1, 1, E.EPB_F32)
+        for k, v in bad.items():
+            setattr(q, k, v)
+        assert call(pp=q) == E.EPB_ERR_PARAM, bad
+    q = E.epb_ssao_params(16, None, FAKE, 0.5, 0.025, 0.1, 1, E.EPB_F32)
+    assert call(pp=q) == E.EPB_ERR_NULL
+    c2 = _cam()
+    c2.fx = -1.0
+    assert call(c=c2) == E.EPB_ERR_PARAM
+
+
+def test_shade_validation():
+    cam = _cam()
+    cube = E.epb_cube(8, 1, FAKE)
+    maps = E.epb_ibl_maps(E.epb_cube(4, 1, FAKE), E.epb_cube(8, 3, FAKE), FAKE, 16)
+    lights = (E.epb_light * 9)()
+
+    def call(g=None, c=cam, n=0, mp=maps, env=cube, hdr=FAKE, hdt=E.EPB_F32, ao=FAKE):
+        g = g or _gbuf()
+        return E.lib.epb_shade(C.byref(g), C.byref(c), ao, E.EPB_F32, lights, n, C.byref(mp),
+                               C.byref(env), hdr, hdt, None)
+
+    assert call(hdr=None) == E.EPB_ERR_NULL
+    assert call(n=9) == E.EPB_ERR_PARAM
+    assert call(n=-1) == E.EPB_ERR_PARAM
+    assert call(hdt=5) == E.EPB_ERR_DTYPE
+    assert call(ao=FAKE + 2) == E.EPB_ERR_ALIGN
+    assert call(env=E.epb_cube(8, 1, None)) == E.EPB_ERR_NULL
+    assert call(env=E.epb_cube(0, 1, FAKE)) == E.EPB_ERR_SIZE
+    assert call(mp=E.epb_ibl_maps(E.epb_cube(4, 1, FAKE), E.epb_cube(4, 4, FAKE), FAKE, 16)) \
+        == E.EPB_ERR_SIZE  # 4 >> 3 == 0
+    assert call(mp=E.epb_ibl_maps(E.epb_cube(4, 1, FAKE), E.epb_cube(8, 3, FAKE), None, 16)) \
+        == E.EPB_ERR_NULL
+    bad_light = (E.epb_light * 1)()
+    bad_light[0].intensity = float("inf")
+    g = _gbuf()
+    assert E.lib.epb_shade(C.byref(g), C.byref(cam), FAKE, E.EPB_F32, bad_light, 1, C.byref(maps),
+                           C.byref(cube), FAKE, E.EPB_F32, None) == E.EPB_ERR_PARAM
+    unaligned_map = (E.epb_light * 1)()
+    unaligned_map[0].intensity = 1.0
+    unaligned_map[0].shadow_map = FAKE + 4
+    assert E.lib.epb_shade(C.byref(g), C.byref(cam), FAKE, E.EPB_F32, unaligned_map, 1,
+                           C.byref(maps), C.byref(cube), FAKE, E.EPB_F32, None) == E.EPB_ERR_ALIGN
+
+
+def test_bloom_tonemap_validation():
+    p = E.epb_post_params(6, 1.0, 0.04, 1.0, 2.2)
+    need = E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, 64, 48, p)
+
+    def call(hdr=FAKE, dt=E.EPB_F32, w=64, h=48, pp=p, out=FAKE, sc=FAKE, n=need):
+        return E.lib.epb_bloom_tonemap(hdr, dt, w, h, C.byref(pp), out, sc, n, None)
+
+    assert call(hdr=None) == E.EPB_ERR_NULL
+    assert call(w=0) == E.EPB_ERR_SIZE
+    assert call(h=20000) == E.EPB_ERR_SIZE
+    assert call(dt=3) == E.EPB_ERR_DTYPE
+    assert call(pp=E.epb_post_params(0, 1.0, 0.04, 1.0, 2.2)) == E.EPB_ERR_PARAM
+    assert call(pp=E.epb_post_params(6, 1.0, 0.04, 0.0, 2.2)) == E.EPB_ERR_PARAM
+    assert call(pp=E.epb_post_params(6, 1.0, 0.04, 1.0, float("nan"))) == E.EPB_ERR_PARAM
+    assert call(out=FAKE + 1) == E.EPB_ERR_ALIGN
+    assert call(n=need - 1) == E.EPB_ERR_SCRATCH
+
+
+def test_precompute_ibl_validation():
+    ip = E.epb_ibl_params(8, 16, 16, 3, 64, 16, 64)
+    need = E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 32, 32, ip)
+    env = E.epb_cube(32, 1, FAKE)
+    maps = E.epb_ibl_maps(E.epb_cube(8, 1, FAKE), E.epb_cube(16, 3, FAKE), FAKE, 16)
+
+    def call(e=env, p=ip, m=maps, sc=FAKE, n=need):
+        return E.lib.epb_precompute_ibl(C.byref(e), C.byref(p), C.byref(m), sc, n, None)
+
+    assert call(e=E.epb_cube(32, 1, None)) == E.EPB_ERR_NULL
+    assert call(e=E.epb_cube(48, 1, FAKE)) == E.EPB_ERR_SIZE  # 48 / 16 not a power of 2
+    assert call(m=E.epb_ibl_maps(E.epb_cube(8, 1, FAKE), E.epb_cube(32, 3, FAKE), FAKE, 16)) \
+        == E.EPB_ERR_SIZE  # prefiltered base must be min(32, 16)
+    assert call(p=E.epb_ibl_params(8, 16, 16, 3, 0, 16, 64)) == E.EPB_ERR_PARAM
+    assert call(n=need - 1) == E.EPB_ERR_SCRATCH
+    assert call(sc=FAKE + 8) == E.EPB_ERR_ALIGN
