@@ -30,7 +30,8 @@
  *    t = 2 (j + .5) / S - 1 and points along +X (1,-t,-s), -X (-1,-t,s),
  *    +Y (s,1,t), -Y (s,-1,-t), +Z (s,-t,1), -Z (-s,-t,-1).  Lookups pick the
  *    major axis (ties x, then y, then z) and filter bilinearly with
- *    clamp-to-edge inside the face.
+ *    clamp-to-edge inside the face; every filtered level has faces of at
+ *    least 2x2 texels.
  *  - Half resolution is Wh = ceil(W / 2), Hh = ceil(H / 2); half-resolution
  *    texel (i, j) is the full-resolution pixel (2 i, 2 j).
  *
@@ -149,7 +150,8 @@ typedef struct {
     float pos[3];
     float color[3];
     float intensity;          /* radiance at distance r is color * intensity / r^2 */
-    const float *shadow_map;  /* device [h][w] linear depth (+inf empty), or NULL  */
+    const float *shadow_map;  /* device [h][w] linear depth (+inf empty), or NULL;
+                                 at least 3x3 texels                              */
     epb_camera shadow_cam;    /* camera the map was rendered with                 */
     float shadow_bias;        /* depth bias of the shadow test (e.g. 0.02)        */
 } epb_light;

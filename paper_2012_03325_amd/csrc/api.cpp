@@ -58,24 +58,25 @@ int check_gbuffer(const epb_gbuffer *g, const epb_camera *cam) {
     return EPB_OK;
 }
 
-int check_cube(const epb_cube *c, int min_levels) {
+// Cubes that are filtered bilinearly must have faces of at least 2x2 on every level.
+int check_cube(const epb_cube *c, int min_levels, int min_face = 1) {
     if (!c->data) return EPB_ERR_NULL;
     if (c->size < 1 || c->size > 8192 || c->levels < min_levels || c->levels > 16) return EPB_ERR_SIZE;
-    if ((c->size >> (c->levels - 1)) < 1) return EPB_ERR_SIZE;
+    if ((c->size >> (c->levels - 1)) < min_face) return EPB_ERR_SIZE;
     if (!aligned16(c->data)) return EPB_ERR_ALIGN;
     return EPB_OK;
 }
 
 int check_ibl_params(int S, const epb_ibl_params *p) {
-    if (p->irr_size < 1 || p->irr_size > 1024 || p->irr_src_size < 1 || p->pref_size < 1 || p->pref_levels < 1 ||
-        p->pref_levels > 8 || p->lut_size < 1 || p->lut_size > 4096)
+    if (p->irr_size < 2 || p->irr_size > 1024 || p->irr_src_size < 1 || p->pref_size < 2 || p->pref_levels < 1 ||
+        p->pref_levels > 8 || p->lut_size < 2 || p->lut_size > 4096 || S < 2)
         return EPB_ERR_SIZE;
     if (p->pref_samples < 1 || p->pref_samples > (1 << 20) || p->lut_samples < 1 || p->lut_samples > (1 << 20))
         return EPB_ERR_PARAM;
     int src = S < p->irr_src_size ? S : p->irr_src_size;
     if (S % src != 0 || !is_pow2(S / src)) return EPB_ERR_SIZE;
     int base = S < p->pref_size ? S : p->pref_size;
-    if ((base >> (p->pref_levels - 1)) < 1) return EPB_ERR_SIZE;
+    if ((base >> (p->pref_levels - 1)) < 2) return EPB_ERR_SIZE;
     return EPB_OK;
 }
 
@@ -177,12 +178,12 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, ep
     if (st) return st;
     if (!valid_dtype(ao_dtype) || !valid_dtype(hdr_dtype)) return EPB_ERR_DTYPE;
     if ((ao && !aligned16(ao)) || !aligned16(hdr_out)) return EPB_ERR_ALIGN;
-    if ((st = check_cube(&ibl->irradiance, 1)) || (st = check_cube(&ibl->prefiltered, 1)) ||
-        (st = check_cube(env, 1)))
+    if ((st = check_cube(&ibl->irradiance, 1, 2)) || (st = check_cube(&ibl->prefiltered, 1, 2)) ||
+        (st = check_cube(env, 1, 2)))
         return st;
     if (ibl->prefiltered.levels > 8) return EPB_ERR_SIZE;
     if (!ibl->brdf_lut) return EPB_ERR_NULL;
-    if (ibl->lut_size < 1 || ibl->lut_size > 4096) return EPB_ERR_SIZE;
+    if (ibl->lut_size < 2 || ibl->lut_size > 4096) return EPB_ERR_SIZE;
     if (!aligned16(ibl->brdf_lut)) return EPB_ERR_ALIGN;
     epb::ShadeArgs a{};
     a.depth = gbuf->depth;
@@ -213,6 +214,7 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, ep
         if (L.shadow_map) {
             if (!aligned16(L.shadow_map)) return EPB_ERR_ALIGN;
             if ((st = check_camera(&L.shadow_cam))) return st;
+            if (L.shadow_cam.width < 3 || L.shadow_cam.height < 3) return EPB_ERR_SIZE;
             if (!finite(L.shadow_bias)) return EPB_ERR_PARAM;
             // light view from camera view: P_l = R_l (R^T (P_v - t) ) + t_l = M P_v + o
             const float *A = L.shadow_cam.world_to_cam, *B = cam->world_to_cam;

@@ -105,19 +105,21 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
     return make_float4(fmaf(w, b.x - a.x, a.x), fmaf(w, b.y - a.y, a.y), fmaf(w, b.z - a.z, a.z), 0.0f);
 }
 
-// Bilinear, clamp-to-edge inside one face of one level.
+// Bilinear, clamp-to-edge inside one face of one level (S >= 2).  Clamping
+// the coordinate to [0, S-1] and the left tap to S-2 gives the same result as
+// clamping both taps (at an edge one weight is 0 or 1), and keeps the second
+// column at a fixed +1 offset from the first.
 __device__ __forceinline__ float4 face_bilinear(const float4 *__restrict__ lvl, int S, FaceST f) {
     float half = 0.5f * (float)S;
-    float x = fmaf(f.s, half, half - 0.5f);
-    float y = fmaf(f.t, half, half - 0.5f);
-    float x0f = floorf(x), y0f = floorf(y);
-    float wx = x - x0f, wy = y - y0f;
-    int x0 = (int)x0f, y0 = (int)y0f;
-    int xa = min(max(x0, 0), S - 1), xb = min(max(x0 + 1, 0), S - 1);
-    int ya = min(max(y0, 0), S - 1), yb = min(max(y0 + 1, 0), S - 1);
-    const float4 *fp = lvl + (size_t)f.face * S * S;
-    float4 a = ld4(fp + ya * S + xa), b = ld4(fp + ya * S + xb);
-    float4 c = ld4(fp + yb * S + xa), d = ld4(fp + yb * S + xb);
+    float hi = (float)(S - 1);
+    float x = fminf(fmaxf(fmaf(f.s, half, half - 0.5f), 0.0f), hi);
+    float y = fminf(fmaxf(fmaf(f.t, half, half - 0.5f), 0.0f), hi);
+    int x0 = min((int)x, S - 2), y0 = min((int)y, S - 2);
+    float wx = x - (float)x0, wy = y - (float)y0;
+    const float4 *r0 = lvl + ((size_t)f.face * S + y0) * S + x0;
+    const float4 *r1 = r0 + S;
+    float4 a = ld4(r0), b = ld4(r0 + 1);
+    float4 c = ld4(r1), d = ld4(r1 + 1);
     return lerp4(lerp4(a, b, wx), lerp4(c, d, wx), wy);
 }
 

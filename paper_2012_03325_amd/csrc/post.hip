@@ -45,6 +45,7 @@ __global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__r
     // level 1: bright map averaged over the in-range 2x2 children
     {
         int lx = t % 32;
+#pragma unroll
         for (int ly = t / 32; ly < 32; ly += 8) {
             int X = bx * 32 + lx, Y = by * 32 + ly;
             float4 v = make_float4(0, 0, 0, 0);
@@ -155,7 +156,7 @@ __global__ void __launch_bounds__(256) k_bloom_blur(const PostK c) {
 }
 
 __device__ __forceinline__ float aces(float x) {
-    return x * fmaf(2.51f, x, 0.03f) / fmaf(x, fmaf(2.43f, x, 0.59f), 0.14f);
+    return x * fmaf(2.51f, x, 0.03f) * rcp(fmaf(x, fmaf(2.43f, x, 0.59f), 0.14f));
 }
 __device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_gamma) {
     float y = clamp01(aces(exposure * x));
@@ -164,35 +165,71 @@ __device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_g
     return (uint32_t)fminf(fmaxf(q, 0.0f), 255.0f);
 }
 
+// Texel footprint of a 32x8 pixel tile on level l (scale 2^-l): from
+// floor((X0 + .5) 2^-l - .5) to floor((X0 + 31.5) 2^-l - .5) + 1, i.e. at most
+// 32 / 2^l + 2 columns and 8 / 2^l + 2 rows (+1 for rounding).
+constexpr int kCompLds = (19 * 7) + (11 * 5) + (7 * 4) + (5 * 4) + (4 * 4);
+
 template <typename TH>
 __global__ void __launch_bounds__(256) k_composite(const PostK c, const TH *__restrict__ hdr,
                                                    uint32_t *__restrict__ ldr) {
+    __shared__ float4 sb[kCompLds];
     int tile = xcd_tile(blockIdx.x, c.tiles);
-    int x = (tile % c.tiles_x) * 32 + (int)(threadIdx.x % 32);
-    int y = (tile / c.tiles_x) * 8 + (int)(threadIdx.x / 32);
-    if (x >= c.W || y >= c.H) return;
-    size_t p = (size_t)y * c.W + x;
+    int X0 = (tile % c.tiles_x) * 32, Y0 = (tile / c.tiles_x) * 8;
+    int x = X0 + (int)(threadIdx.x % 32);
+    int y = Y0 + (int)(threadIdx.x / 32);
+    bool live = x < c.W && y < c.H;
+    size_t p = live ? (size_t)y * c.W + x : 0;
     size_t plane = (size_t)c.W * c.H;
-    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
-    float sc = 0.5f;
-    for (int L = 1; L <= c.nl; ++L, sc *= 0.5f) {
+    // the pixel's HDR first (in flight while the pyramid footprint is staged)
+    float R0 = ldc(hdr + p), G0 = ldc(hdr + plane + p), B0 = ldc(hdr + 2 * plane + p);
+    // stage the clamped footprint of every blurred level; a footprint is at
+    // most 19 x 7 texels, one texel per thread (row = thread / 32, col = thread % 32)
+    int base[EPB_MAX_BLOOM_LEVELS], sx0[EPB_MAX_BLOOM_LEVELS], sy0[EPB_MAX_BLOOM_LEVELS],
+        cols[EPB_MAX_BLOOM_LEVELS];
+    int off = 0;
+    int tr = threadIdx.x / 32, tc = threadIdx.x % 32;
+#pragma unroll
+    for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
+        if (L > c.nl) break;
+        const float sc = 1.0f / (float)(1 << L);
         int w = c.lw[L], h = c.lh[L];
+        int ax = (int)floorf(fmaf((float)X0 + 0.5f, sc, -0.5f));
+        int ay = (int)floorf(fmaf((float)Y0 + 0.5f, sc, -0.5f));
+        int bx = (int)floorf(fmaf((float)X0 + 31.5f, sc, -0.5f)) + 1;
+        int by = (int)floorf(fmaf((float)Y0 + 7.5f, sc, -0.5f)) + 1;
+        int nc = bx - ax + 1, nr = by - ay + 1;
+        if (tc < nc && tr < nr) {
+            int gx = min(max(ax + tc, 0), w - 1), gy = min(max(ay + tr, 0), h - 1);
+            sb[off + tr * nc + tc] = c.blur[L][(size_t)gy * w + gx];
+        }
+        base[L] = off;
+        sx0[L] = ax;
+        sy0[L] = ay;
+        cols[L] = nc;
+        off += nc * nr;
+    }
+    __syncthreads();
+    if (!live) return;
+    float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+#pragma unroll
+    for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
+        if (L > c.nl) break;
+        const float sc = 1.0f / (float)(1 << L);
         float fx = fmaf((float)x + 0.5f, sc, -0.5f), fy = fmaf((float)y + 0.5f, sc, -0.5f);
         float x0f = floorf(fx), y0f = floorf(fy);
         float wx = fx - x0f, wy = fy - y0f;
-        int x0 = (int)x0f, y0 = (int)y0f;
-        int xa = min(max(x0, 0), w - 1), xb = min(max(x0 + 1, 0), w - 1);
-        int ya = min(max(y0, 0), h - 1), yb = min(max(y0 + 1, 0), h - 1);
-        const float4 *B = c.blur[L];
-        float4 v = lerp4(lerp4(B[(size_t)ya * w + xa], B[(size_t)ya * w + xb], wx),
-                         lerp4(B[(size_t)yb * w + xa], B[(size_t)yb * w + xb], wx), wy);
+        int lx = (int)x0f - sx0[L], ly = (int)y0f - sy0[L];
+        const float4 *r0 = sb + base[L] + ly * cols[L] + lx;
+        const float4 *r1 = r0 + cols[L];
+        float4 v = lerp4(lerp4(r0[0], r0[1], wx), lerp4(r1[0], r1[1], wx), wy);
         sx += v.x;
         sy += v.y;
         sz += v.z;
     }
-    float R = fmaf(c.strength, sx, ldc(hdr + p));
-    float G = fmaf(c.strength, sy, ldc(hdr + plane + p));
-    float Bc = fmaf(c.strength, sz, ldc(hdr + 2 * plane + p));
+    float R = fmaf(c.strength, sx, R0);
+    float G = fmaf(c.strength, sy, G0);
+    float Bc = fmaf(c.strength, sz, B0);
     uint32_t word = encode8(R, c.exposure, c.inv_gamma) | (encode8(G, c.exposure, c.inv_gamma) << 8) |
                     (encode8(Bc, c.exposure, c.inv_gamma) << 16) | (255u << 24);
     ldr[p] = word;

@@ -31,6 +31,7 @@ struct DevLight {
     float M[9], o[3];  // light view from camera view: P_l = M P_v + o
     float fx, fy, cx, cy;
     int w, h;
+    float fw, fh;      // w, h as floats
     float bias;
 };
 
@@ -52,46 +53,57 @@ struct ShadeK {
     DevLight lights[EPB_MAX_LIGHTS];
 };
 
+// Bilinear lookup of the (size >= 2) BRDF table, clamp to edge.
 __device__ __forceinline__ float2 lut_bilinear(const float2 *__restrict__ lut, int size, float u, float v) {
-    float fx = fmaf(u, (float)size, -0.5f), fy = fmaf(v, (float)size, -0.5f);
-    float x0f = floorf(fx), y0f = floorf(fy);
-    float wx = fx - x0f, wy = fy - y0f;
-    int x0 = (int)x0f, y0 = (int)y0f;
-    int xa = min(max(x0, 0), size - 1), xb = min(max(x0 + 1, 0), size - 1);
-    int ya = min(max(y0, 0), size - 1), yb = min(max(y0 + 1, 0), size - 1);
-    float2 a = lut[ya * size + xa], b = lut[ya * size + xb];
-    float2 c = lut[yb * size + xa], d = lut[yb * size + xb];
+    float hi = (float)(size - 1);
+    float fx = fminf(fmaxf(fmaf(u, (float)size, -0.5f), 0.0f), hi);
+    float fy = fminf(fmaxf(fmaf(v, (float)size, -0.5f), 0.0f), hi);
+    int x0 = min((int)fx, size - 2), y0 = min((int)fy, size - 2);
+    float wx = fx - (float)x0, wy = fy - (float)y0;
+    const float2 *r0 = lut + y0 * size + x0;
+    const float2 *r1 = r0 + size;
+    float2 a = r0[0], b = r0[1], c = r1[0], d = r1[1];
     float ax = fmaf(wx, b.x - a.x, a.x), ay = fmaf(wx, b.y - a.y, a.y);
     float cx = fmaf(wx, d.x - c.x, c.x), cy = fmaf(wx, d.y - c.y, c.y);
     return make_float2(fmaf(wy, cx - ax, ax), fmaf(wy, cy - ay, ay));
 }
 
-// Lit fraction of the 3x3 patch around the projection of view point Pv.
-// The nine taps are fetched at clamped (always valid) addresses with no
-// branch between them, so they are in flight together; taps outside the map
-// and points outside the light frustum are lit.
-__device__ __forceinline__ float pcf(const DevLight &L, v3 Pv) {
-    v3 Pl = mul_R(L.M, Pv) + mk3(L.o[0], L.o[1], L.o[2]);
+// Lit fraction of the 3x3 patch around the projection of view point Pv
+// (maps of at least 3x3).  One 3x3 block that lies wholly inside the map is
+// fetched through three row pointers (fixed +1/+2 column offsets, all nine
+// loads in flight together); when the true patch sticks out of the map the
+// block is shifted inwards by one texel and the columns/rows that do not belong
+// to the patch are dropped, the missing taps counting as lit.  Points outside
+// the light's frustum are lit.
+__device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, float d) {
+    // P_l = M P_v + o with P_v = d (dvx, dvy, -1)
+    v3 Md = mk3(fmaf(L.M[0], dvx, fmaf(L.M[1], dvy, -L.M[2])), fmaf(L.M[3], dvx, fmaf(L.M[4], dvy, -L.M[5])),
+                fmaf(L.M[6], dvx, fmaf(L.M[7], dvy, -L.M[8])));
+    v3 Pl = mk3(fmaf(Md.x, d, L.o[0]), fmaf(Md.y, d, L.o[1]), fmaf(Md.z, d, L.o[2]));
     float dl = -Pl.z;
     float idl = rcp(dl);
     float u = fmaf(L.fx * Pl.x, idl, L.cx);
     float v = fmaf(-L.fy * Pl.y, idl, L.cy);
-    bool inside = dl > 0.0f && u >= 0.0f && u < (float)L.w && v >= 0.0f && v < (float)L.h;
-    int i0 = (int)fminf(fmaxf(u, 0.0f), (float)(L.w - 1));  // == floor(u) when inside
-    int j0 = (int)fminf(fmaxf(v, 0.0f), (float)(L.h - 1));
+    bool inside = dl > 0.0f && u >= 0.0f && u < L.fw && v >= 0.0f && v < L.fh;
+    int i0 = inside ? (int)u : 1, j0 = inside ? (int)v : 1;  // truncation == floor when inside
+    int bi = min(max(i0, 1), L.w - 2), bj = min(max(j0, 1), L.h - 2);
+    const float *r0 = L.map + (unsigned)((bj - 1) * L.w + (bi - 1));
+    const float *r1 = r0 + L.w;
+    const float *r2 = r1 + L.w;
+    float t[9] = {r0[0], r0[1], r0[2], r1[0], r1[1], r1[2], r2[0], r2[1], r2[2]};
     float ref = dl - L.bias;
-    float tap[9];
-    bool in[9];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        int ti = i0 + k % 3 - 1, tj = j0 + k / 3 - 1;
-        in[k] = ti >= 0 && ti < L.w && tj >= 0 && tj < L.h;
-        int ci = min(max(ti, 0), L.w - 1), cj = min(max(tj, 0), L.h - 1);
-        tap[k] = L.map[(size_t)cj * L.w + ci];
-    }
     int lit = 0;
 #pragma unroll
-    for (int k = 0; k < 9; ++k) lit += (!in[k] || ref <= tap[k]) ? 1 : 0;
+    for (int k = 0; k < 9; ++k) lit += ref <= t[k] ? 1 : 0;
+    int si = i0 - bi, sj = j0 - bj;  // -1, 0 or +1; non-zero only next to the map border
+    if (si | sj) {
+        bool kc[3] = {si <= 0, true, si >= 0};
+        bool kr[3] = {sj <= 0, true, sj >= 0};
+        int nc = 1 + (si <= 0) + (si >= 0), nr = 1 + (sj <= 0) + (sj >= 0);
+        lit = 9 - nc * nr;  // taps outside the map
+#pragma unroll
+        for (int k = 0; k < 9; ++k) lit += (kr[k / 3] && kc[k % 3] && ref <= t[k]) ? 1 : 0;
+    }
     return inside ? (float)lit * (1.0f / 9.0f) : 1.0f;
 }
 
@@ -123,11 +135,13 @@ __global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
         float mt = ldc((const TG *)c.metal + p);
         float nv_raw = dot(n, V);
         float NoV = fminf(fmaxf(nv_raw, 1e-4f), 1.0f);
-        float F0[3], cd[3];
+        float F0[3], cd[3], omF0[3], cdpi[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             F0[ch] = fmaf(mt, a[ch] - 0.04f, 0.04f);
             cd[ch] = a[ch] * (1.0f - mt);
+            omF0[ch] = 1.0f - F0[ch];
+            cdpi[ch] = cd[ch] * (1.0f / kPi);
         }
         float alpha = r * r, a2 = alpha * alpha;
         float kd = (r + 1.0f) * (r + 1.0f) * 0.125f;
@@ -164,21 +178,20 @@ __global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
             v3 l = lv * il;
             float NoL = dot(n, l);
             if (!(NoL > 0.0f)) continue;
-            float sh = L.map ? pcf(L, Pv) : 1.0f;
+            float sh = L.map ? pcf(L, dvx, dvy, d) : 1.0f;
             v3 h = normalize(V + l);
             float NoH = dot(n, h);
             float VoH = fmaxf(dot(V, h), 0.0f);
             v3 nxh = cross(n, h);
             float q = fmaf(NoH * NoH, a2, dot(nxh, nxh));
-            float D = a2 * rcp(kPi * q * q);
-            float vis = 0.25f * rcp(fmaf(NoL, 1.0f - kd, kd) * gv);
-            float spec = D * vis;
+            // D * G / (4 NoL NoV) = alpha^2 / (pi q^2) * 1 / (4 (NoL(1-k)+k)(NoV(1-k)+k))
+            float spec = (0.25f / kPi) * a2 * rcp(q * q * fmaf(NoL, 1.0f - kd, kd) * gv);
             float fc = pow5(1.0f - VoH);
             float e = il * il * NoL * sh;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                float F = fmaf(1.0f - F0[ch], fc, F0[ch]);
-                float f = fmaf(spec, F, cd[ch] * (1.0f / kPi));
+                float F = fmaf(omF0[ch], fc, F0[ch]);
+                float f = fmaf(spec, F, cdpi[ch]);
                 Lo[ch] = fmaf(f, L.rad[ch] * e, Lo[ch]);
             }
         }
@@ -251,6 +264,7 @@ hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
         d.map = h.map;
         d.fx = h.fx; d.fy = h.fy; d.cx = h.cx; d.cy = h.cy;
         d.w = h.w; d.h = h.h;
+        d.fw = (float)h.w; d.fh = (float)h.h;
         d.bias = h.bias;
     }
     if (a.gdtype == EPB_F32) go_a<float>(k, a.ao_dtype, a.hdr_dtype, s);

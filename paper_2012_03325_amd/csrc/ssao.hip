@@ -68,15 +68,21 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
     v3 r = mk3(rn[0], rn[1], 0.0f);
     v3 t = normalize(r - nv * dot(nv, r));
     v3 bb = cross(nv, t);
-    t = t * c.radius;
-    bb = bb * c.radius;
-    v3 nn = nv * c.radius;
-    // projection to half-resolution texel space: hx = u / 2 + 1/4 with
-    // u = cx + fx Q.x / zq (v analogous with the sign flip)
+    // Sample s of the kernel lands at Q = P + radius (t sx + b sy + n sz).  Its
+    // depth zq = -Q.z and the numerators of its half-resolution texel
+    // coordinates hx = u / 2 + 1/4 = (fx/2 Q.x + (cx/2 + 1/4) zq) / zq (hy alike,
+    // y flipped) are affine in s: three plane equations per pixel.
     float ax = 0.5f * c.cam.fx, bx = 0.5f * c.cam.cx + 0.25f;
     float ay = -0.5f * c.cam.fy, by = 0.5f * c.cam.cy + 0.25f;
-    // samples in batches of 8: every gather of a batch is issued at a valid
-    // (clamped) address before any is consumed
+    v3 Mx = mk3(t.x, bb.x, nv.x) * c.radius, My = mk3(t.y, bb.y, nv.y) * c.radius,
+       Mz = mk3(t.z, bb.z, nv.z) * c.radius;
+    v3 Zv = mk3(-Mz.x, -Mz.y, -Mz.z);
+    float Z0 = -P.z;
+    v3 Xv = Mx * ax + Zv * bx, Yv = My * ay + Zv * by;
+    float X0 = fmaf(ax, P.x, bx * Z0), Y0 = fmaf(ay, P.y, by * Z0);
+    float fWh = (float)c.Wh, fHh = (float)c.Hh;
+    // samples in batches of 8: every gather of a batch is issued (at index 0
+    // for samples that miss the image) before any is consumed
     constexpr int kB = 8;
     float occ = 0.0f;
     for (int k0 = 0; k0 < c.n; k0 += kB) {
@@ -86,24 +92,22 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
         for (int b = 0; b < kB; ++b) {
             int k = min(k0 + b, c.n - 1);
             float sx = sk[3 * k], sy = sk[3 * k + 1], sz = sk[3 * k + 2];
-            float qx = fmaf(t.x, sx, fmaf(bb.x, sy, fmaf(nn.x, sz, P.x)));
-            float qy = fmaf(t.y, sx, fmaf(bb.y, sy, fmaf(nn.y, sz, P.y)));
-            float qz = fmaf(t.z, sx, fmaf(bb.z, sy, fmaf(nn.z, sz, P.z)));
-            float zq = -qz;
+            float zq = fmaf(Zv.x, sx, fmaf(Zv.y, sy, fmaf(Zv.z, sz, Z0)));
+            float nx = fmaf(Xv.x, sx, fmaf(Xv.y, sy, fmaf(Xv.z, sz, X0)));
+            float ny = fmaf(Yv.x, sx, fmaf(Yv.y, sy, fmaf(Yv.z, sz, Y0)));
             float iz = rcp(zq);
-            float hx = fminf(fmaxf(fmaf(ax * qx, iz, bx), -1.0f), (float)c.Wh);
-            float hy = fminf(fmaxf(fmaf(ay * qy, iz, by), -1.0f), (float)c.Hh);
-            int ix = (int)floorf(hx), iy = (int)floorf(hy);
-            ok[b] = (k0 + b < c.n) && zq > 0.0f && ix >= 0 && ix < c.Wh && iy >= 0 && iy < c.Hh;
-            ds[b] = hdepth[ok[b] ? (size_t)iy * c.Wh + ix : 0];
+            float hx = nx * iz, hy = ny * iz;
+            ok[b] = (k0 + b < c.n) && zq > 0.0f && hx >= 0.0f && hx < fWh && hy >= 0.0f && hy < fHh;
+            // truncation is floor on the accepted (non-negative) range
+            unsigned idx = ok[b] ? (unsigned)(int)hy * (unsigned)c.Wh + (unsigned)(int)hx : 0u;
+            ds[b] = hdepth[idx];
             zqs[b] = zq;
         }
 #pragma unroll
         for (int b = 0; b < kB; ++b) {
-            if (ok[b] && ds[b] <= zqs[b] - c.bias) {
-                float u = clamp01(c.radius * rcp(fabsf(d - ds[b])));
-                occ += u * u * (3.0f - 2.0f * u);
-            }
+            float u = clamp01(c.radius * rcp(fabsf(d - ds[b])));
+            float sm = u * u * (3.0f - 2.0f * u);
+            occ += (ok[b] && ds[b] <= zqs[b] - c.bias) ? sm : 0.0f;
         }
     }
     st(out + o, 1.0f - occ / (float)c.n);

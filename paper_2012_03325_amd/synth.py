@@ -427,6 +427,6 @@ def config_reduced(width: int, height: int, seed: int = 5, shadow_size: int = 25
     size the FP64 oracle finishes in seconds; used for parity tests."""
     base = min(128, env_size)
     ibl = dict(irr_src_size=min(64, env_size), pref_size=base, pref_samples=256,
-               pref_levels=min(5, base.bit_length()), lut_size=32, lut_samples=256)
+               pref_levels=min(5, base.bit_length() - 1), lut_size=32, lut_samples=256)
     return make_view(f"reduced-{width}x{height}", width, height, n_spheres, True, seed, n_lights,
                      shadow_size, env_size, "sun", ssao_n, ibl)

@@ -74,7 +74,7 @@ def _oracle_ibl_small(view):
         S = view.env.shape[1]
         base = min(32, S)
         p = dict(irr_size=8, irr_src_size=min(16, S), pref_size=base,
-                 pref_levels=min(5, base.bit_length()), pref_samples=64, lut_size=32, lut_samples=64)
+                 pref_levels=min(5, base.bit_length() - 1), pref_samples=64, lut_size=32, lut_samples=64)
         _cache[key] = (p, O.precompute_ibl(view.env, **p))
     return _cache[key]
 
