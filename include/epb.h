@@ -105,7 +105,7 @@ typedef struct {
     const void *metalness;/* [H][W] in [0, 1]                               */
 } epb_gbuffer;
 
-/* A float32 cube map with `levels` mip levels of sizes size >> m. */
+/* A float32 cube map with `levels` mip levels of sizes size >> m (size <= 4096). */
 typedef struct {
     int32_t size;
     int32_t levels;

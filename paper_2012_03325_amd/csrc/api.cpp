@@ -61,7 +61,7 @@ int check_gbuffer(const epb_gbuffer *g, const epb_camera *cam) {
 // Cubes that are filtered bilinearly must have faces of at least 2x2 on every level.
 int check_cube(const epb_cube *c, int min_levels, int min_face = 1) {
     if (!c->data) return EPB_ERR_NULL;
-    if (c->size < 1 || c->size > 8192 || c->levels < min_levels || c->levels > 16) return EPB_ERR_SIZE;
+    if (c->size < 1 || c->size > 4096 || c->levels < min_levels || c->levels > 16) return EPB_ERR_SIZE;
     if ((c->size >> (c->levels - 1)) < min_face) return EPB_ERR_SIZE;
     if (!aligned16(c->data)) return EPB_ERR_ALIGN;
     return EPB_OK;

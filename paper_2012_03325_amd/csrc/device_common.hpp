@@ -16,6 +16,26 @@ constexpr int kNumXcd = 8;  // MI355X: 256 CUs in 8 accelerator complex dies
 // ---------------------------------------------------------------------------
 // storage
 // ---------------------------------------------------------------------------
+// Loads and stores at a 32-bit byte offset from a wave-uniform base: the
+// compiler then emits the scalar-base + 32-bit vector-offset form (with the
+// constant part folded into the immediate) instead of 64-bit address
+// arithmetic per lane.  Callers keep every offset below 2^32 (sizes are
+// validated on the host).
+template <typename T>
+__device__ __forceinline__ T ldo(const T *base, unsigned byte_off) {
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+}
+template <typename T>
+__device__ __forceinline__ void sto(T *base, unsigned byte_off, T v) {
+    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+}
+__device__ __forceinline__ float ldf(const float *base, unsigned i) { return ldo(base, i * 4u); }
+__device__ __forceinline__ float ldf(const __half *base, unsigned i) { return __half2float(ldo(base, i * 2u)); }
+__device__ __forceinline__ void stf(float *base, unsigned i, float v) { sto(base, i * 4u, v); }
+__device__ __forceinline__ void stf(__half *base, unsigned i, float v) {
+    sto(base, i * 2u, __float2half_rn(fminf(v, 65504.0f)));  // saturate (HDR peaks can exceed 65504)
+}
+
 __device__ __forceinline__ float ldc(const float *p) { return *p; }
 __device__ __forceinline__ float ldc(const __half *p) { return __half2float(*p); }
 
@@ -108,23 +128,26 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
 // Bilinear, clamp-to-edge inside one face of one level (S >= 2).  Clamping
 // the coordinate to [0, S-1] and the left tap to S-2 gives the same result as
 // clamping both taps (at an edge one weight is 0 or 1), and keeps the second
-// column at a fixed +1 offset from the first.
-__device__ __forceinline__ float4 face_bilinear(const float4 *__restrict__ lvl, int S, FaceST f) {
-    float half = 0.5f * (float)S;
-    float hi = (float)(S - 1);
+// column at a fixed +1 offset from the first.  `lvl` is wave-uniform and the
+// texel index a 32-bit offset (24-bit multiplies; S <= 8192).
+__device__ __forceinline__ float4 face_bilinear(const float4 *__restrict__ lvl, unsigned off, int S, float fS,
+                                                FaceST f) {
+    float half = 0.5f * fS;
+    float hi = fS - 1.0f;
     float x = fminf(fmaxf(fmaf(f.s, half, half - 0.5f), 0.0f), hi);
     float y = fminf(fmaxf(fmaf(f.t, half, half - 0.5f), 0.0f), hi);
-    int x0 = min((int)x, S - 2), y0 = min((int)y, S - 2);
-    float wx = x - (float)x0, wy = y - (float)y0;
-    const float4 *r0 = lvl + ((size_t)f.face * S + y0) * S + x0;
-    const float4 *r1 = r0 + S;
-    float4 a = ld4(r0), b = ld4(r0 + 1);
-    float4 c = ld4(r1), d = ld4(r1 + 1);
+    float x0f = fminf(floorf(x), hi - 1.0f), y0f = fminf(floorf(y), hi - 1.0f);
+    float wx = x - x0f, wy = y - y0f;
+    unsigned idx = off + __umul24(__umul24((unsigned)f.face, (unsigned)S) + (unsigned)y0f, (unsigned)S) +
+                   (unsigned)x0f;
+    unsigned o0 = idx * 16u, o1 = o0 + (unsigned)S * 16u;
+    float4 a = ldo(lvl, o0), b = ldo(lvl, o0 + 16u);
+    float4 c = ldo(lvl, o1), d = ldo(lvl, o1 + 16u);
     return lerp4(lerp4(a, b, wx), lerp4(c, d, wx), wy);
 }
 
-__device__ __forceinline__ float4 cube_bilinear(const float4 *__restrict__ lvl, int S, v3 d) {
-    return face_bilinear(lvl, S, cube_face(d));
+__device__ __forceinline__ float4 cube_bilinear(const float4 *__restrict__ lvl, int S, float fS, v3 d) {
+    return face_bilinear(lvl, 0u, S, fS, cube_face(d));
 }
 
 // Offset (in texels) of level m of a chain with base size `base`.

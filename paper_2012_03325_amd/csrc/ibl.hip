@@ -134,7 +134,7 @@ __global__ void __launch_bounds__(256) k_prefilter_mirror(const float4 *__restri
     if (o >= 6 * sm * sm) return;
     int f = o / (sm * sm), j = (o / sm) % sm, i = o % sm;
     v3 n = normalize(cube_texel_dir(f, i, j, sm));
-    out[o] = cube_bilinear(env, S, n);
+    out[o] = cube_bilinear(env, S, (float)S, n);
 }
 
 // One wavefront per prefiltered texel of a level with roughness^2 = alpha > 0.
@@ -149,6 +149,7 @@ __global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ en
     tangent_frame(n, T, B);
     float a2 = alpha * alpha;
     float inv_n = 1.0f / (float)samples;
+    float fS = (float)S;
     Kahan r{0, 0}, g{0, 0}, b{0, 0}, w{0, 0};
     for (int k = lane; k < samples; k += 64) {
         v3 h = ggx_half((float)k * inv_n, radical_inverse2((uint32_t)k), a2, n, T, B);
@@ -156,7 +157,7 @@ __global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ en
         v3 l = h * (2.0f * vh) - n;
         float nl = dot(n, l);
         if (nl > 0.0f) {
-            float4 L = cube_bilinear(env, S, l);
+            float4 L = cube_bilinear(env, S, fS, l);
             kahan_add(r, L.x * nl);
             kahan_add(g, L.y * nl);
             kahan_add(b, L.z * nl);

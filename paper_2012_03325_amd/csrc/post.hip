@@ -41,7 +41,7 @@ __global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__r
     int tile = xcd_tile(blockIdx.x, c.tiles);
     int bx = tile % c.tiles_x, by = tile / c.tiles_x;
     int t = threadIdx.x;
-    size_t plane = (size_t)c.W * c.H;
+    unsigned plane = (unsigned)c.W * (unsigned)c.H;
     // level 1: bright map averaged over the in-range 2x2 children
     {
         int lx = t % 32;
@@ -57,8 +57,8 @@ __global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__r
                     for (int a = 0; a < 2; ++a) {
                         int px = 2 * X + a, py = 2 * Y + b;
                         if (px < c.W && py < c.H) {
-                            size_t p = (size_t)py * c.W + px;
-                            float R = ldc(hdr + p), G = ldc(hdr + plane + p), B = ldc(hdr + 2 * plane + p);
+                            unsigned p = __umul24((unsigned)py, (unsigned)c.W) + (unsigned)px;
+                            float R = ldf(hdr, p), G = ldf(hdr, plane + p), B = ldf(hdr, 2 * plane + p);
                             float Yl = fmaf(0.2126f, R, fmaf(0.7152f, G, 0.0722f * B));
                             float sc = Yl > 0.0f ? fmaxf(Yl - c.threshold, 0.0f) / Yl : 0.0f;
                             v.x = fmaf(R, sc, v.x);
@@ -179,10 +179,10 @@ __global__ void __launch_bounds__(256) k_composite(const PostK c, const TH *__re
     int x = X0 + (int)(threadIdx.x % 32);
     int y = Y0 + (int)(threadIdx.x / 32);
     bool live = x < c.W && y < c.H;
-    size_t p = live ? (size_t)y * c.W + x : 0;
-    size_t plane = (size_t)c.W * c.H;
+    unsigned p = live ? __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x : 0u;
+    unsigned plane = (unsigned)c.W * (unsigned)c.H;
     // the pixel's HDR first (in flight while the pyramid footprint is staged)
-    float R0 = ldc(hdr + p), G0 = ldc(hdr + plane + p), B0 = ldc(hdr + 2 * plane + p);
+    float R0 = ldf(hdr, p), G0 = ldf(hdr, plane + p), B0 = ldf(hdr, 2 * plane + p);
     // stage the clamped footprint of every blurred level; a footprint is at
     // most 19 x 7 texels, one texel per thread (row = thread / 32, col = thread % 32)
     int base[EPB_MAX_BLOOM_LEVELS], sx0[EPB_MAX_BLOOM_LEVELS], sy0[EPB_MAX_BLOOM_LEVELS],
@@ -232,7 +232,7 @@ __global__ void __launch_bounds__(256) k_composite(const PostK c, const TH *__re
     float Bc = fmaf(c.strength, sz, B0);
     uint32_t word = encode8(R, c.exposure, c.inv_gamma) | (encode8(G, c.exposure, c.inv_gamma) << 8) |
                     (encode8(Bc, c.exposure, c.inv_gamma) << 16) | (255u << 24);
-    ldr[p] = word;
+    sto(ldr, p * 4u, word);
 }
 
 PostPlan post_plan(int W, int H, int levels) {

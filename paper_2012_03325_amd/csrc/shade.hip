@@ -25,6 +25,10 @@ namespace epb {
 
 constexpr int kShTx = 32, kShTy = 8;
 
+struct Row3 {
+    float v[3];
+};
+
 struct DevLight {
     float pos[3], rad[3];
     const float *map;
@@ -48,21 +52,23 @@ struct ShadeK {
     int W, H, Wh, Hh;
     int tiles_x, tiles;
     int irr_size, pref_base, pref_levels, lut_size, env_size;
+    float f_irr, f_lut, f_env, f_levels1;  // sizes as floats; f_levels1 = levels - 1
     int pref_off[8];
     int n_lights;
     DevLight lights[EPB_MAX_LIGHTS];
 };
 
 // Bilinear lookup of the (size >= 2) BRDF table, clamp to edge.
-__device__ __forceinline__ float2 lut_bilinear(const float2 *__restrict__ lut, int size, float u, float v) {
-    float hi = (float)(size - 1);
-    float fx = fminf(fmaxf(fmaf(u, (float)size, -0.5f), 0.0f), hi);
-    float fy = fminf(fmaxf(fmaf(v, (float)size, -0.5f), 0.0f), hi);
-    int x0 = min((int)fx, size - 2), y0 = min((int)fy, size - 2);
-    float wx = fx - (float)x0, wy = fy - (float)y0;
-    const float2 *r0 = lut + y0 * size + x0;
-    const float2 *r1 = r0 + size;
-    float2 a = r0[0], b = r0[1], c = r1[0], d = r1[1];
+__device__ __forceinline__ float2 lut_bilinear(const float2 *__restrict__ lut, int size, float fsize, float u,
+                                               float v) {
+    float hi = fsize - 1.0f;
+    float fx = fminf(fmaxf(fmaf(u, fsize, -0.5f), 0.0f), hi);
+    float fy = fminf(fmaxf(fmaf(v, fsize, -0.5f), 0.0f), hi);
+    float x0f = fminf(floorf(fx), hi - 1.0f), y0f = fminf(floorf(fy), hi - 1.0f);
+    float wx = fx - x0f, wy = fy - y0f;
+    unsigned o0 = (__umul24((unsigned)y0f, (unsigned)size) + (unsigned)x0f) * 8u;
+    unsigned o1 = o0 + (unsigned)size * 8u;
+    float2 a = ldo(lut, o0), b = ldo(lut, o0 + 8u), c = ldo(lut, o1), d = ldo(lut, o1 + 8u);
     float ax = fmaf(wx, b.x - a.x, a.x), ay = fmaf(wx, b.y - a.y, a.y);
     float cx = fmaf(wx, d.x - c.x, c.x), cy = fmaf(wx, d.y - c.y, c.y);
     return make_float2(fmaf(wy, cx - ax, ax), fmaf(wy, cy - ay, ay));
@@ -87,10 +93,13 @@ __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, fl
     bool inside = dl > 0.0f && u >= 0.0f && u < L.fw && v >= 0.0f && v < L.fh;
     int i0 = inside ? (int)u : 1, j0 = inside ? (int)v : 1;  // truncation == floor when inside
     int bi = min(max(i0, 1), L.w - 2), bj = min(max(j0, 1), L.h - 2);
-    const float *r0 = L.map + (unsigned)((bj - 1) * L.w + (bi - 1));
-    const float *r1 = r0 + L.w;
-    const float *r2 = r1 + L.w;
-    float t[9] = {r0[0], r0[1], r0[2], r1[0], r1[1], r1[2], r2[0], r2[1], r2[2]};
+    // three 12-byte row loads (dword aligned) cover the 3x3 block
+    unsigned q0 = (__umul24((unsigned)(bj - 1), (unsigned)L.w) + (unsigned)(bi - 1)) * 4u;
+    unsigned row = (unsigned)L.w * 4u;
+    Row3 a = ldo(reinterpret_cast<const Row3 *>(L.map), q0);
+    Row3 b = ldo(reinterpret_cast<const Row3 *>(L.map), q0 + row);
+    Row3 e = ldo(reinterpret_cast<const Row3 *>(L.map), q0 + 2u * row);
+    float t[9] = {a.v[0], a.v[1], a.v[2], b.v[0], b.v[1], b.v[2], e.v[0], e.v[1], e.v[2]};
     float ref = dl - L.bias;
     int lit = 0;
 #pragma unroll
@@ -113,15 +122,15 @@ __global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
     int x = (tile % c.tiles_x) * kShTx + (int)(threadIdx.x % kShTx);
     int y = (tile / c.tiles_x) * kShTy + (int)(threadIdx.x / kShTx);
     if (x >= c.W || y >= c.H) return;
-    size_t p = (size_t)y * c.W + x;
-    size_t plane = (size_t)c.W * c.H;
-    float d = c.depth[p];
+    unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
+    unsigned plane = (unsigned)c.W * (unsigned)c.H;
+    float d = ldf(c.depth, p);
     float dvx = ((float)x + 0.5f - c.cx) * c.inv_fx;
     float dvy = -((float)y + 0.5f - c.cy) * c.inv_fy;
     float out[3];
     if (__builtin_isinf(d)) {
         v3 dw = mul_Rt(c.R, mk3(dvx, dvy, -1.0f));
-        float4 e = cube_bilinear(c.env, c.env_size, dw);
+        float4 e = cube_bilinear(c.env, c.env_size, c.f_env, dw);
         out[0] = e.x; out[1] = e.y; out[2] = e.z;
     } else {
         const TG *nrm = (const TG *)c.normal, *alb = (const TG *)c.albedo;
@@ -129,10 +138,10 @@ __global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
         v3 Pr = mul_Rt(c.R, Pv);  // world position relative to the camera
         v3 Pw = Pr + mk3(c.cam_pos[0], c.cam_pos[1], c.cam_pos[2]);
         v3 V = normalize(mk3(-Pr.x, -Pr.y, -Pr.z));
-        v3 n = normalize(mk3(ldc(nrm + p), ldc(nrm + plane + p), ldc(nrm + 2 * plane + p)));
-        float a[3] = {ldc(alb + p), ldc(alb + plane + p), ldc(alb + 2 * plane + p)};
-        float r = ldc((const TG *)c.rough + p);
-        float mt = ldc((const TG *)c.metal + p);
+        v3 n = normalize(mk3(ldf(nrm, p), ldf(nrm, plane + p), ldf(nrm, 2 * plane + p)));
+        float a[3] = {ldf(alb, p), ldf(alb, plane + p), ldf(alb, 2 * plane + p)};
+        float r = ldf((const TG *)c.rough, p);
+        float mt = ldf((const TG *)c.metal, p);
         float nv_raw = dot(n, V);
         float NoV = fminf(fmaxf(nv_raw, 1e-4f), 1.0f);
         float F0[3], cd[3], omF0[3], cdpi[3];
@@ -147,24 +156,26 @@ __global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
         float kd = (r + 1.0f) * (r + 1.0f) * 0.125f;
         float gv = fmaf(NoV, 1.0f - kd, kd);
         // ambient inputs first: their gathers overlap the direct-light math
-        float2 AB = lut_bilinear(c.lut, c.lut_size, NoV, r);
-        float4 E = cube_bilinear(c.irr, c.irr_size, n);
+        float2 AB = lut_bilinear(c.lut, c.lut_size, c.f_lut, NoV, r);
+        float4 E = cube_bilinear(c.irr, c.irr_size, c.f_irr, n);
         v3 Rf = n * (2.0f * nv_raw) - V;
-        float lod = fminf(fmaxf(r * (float)(c.pref_levels - 1), 0.0f), (float)(c.pref_levels - 1));
+        float lod = fminf(fmaxf(r * c.f_levels1, 0.0f), c.f_levels1);
         int l0 = (int)lod;
         int l1 = min(l0 + 1, c.pref_levels - 1);
         float fl = lod - (float)l0;
         FaceST fs = cube_face(Rf);
-        float4 P0 = face_bilinear(c.pref + c.pref_off[l0], c.pref_base >> l0, fs);
-        float4 P1 = face_bilinear(c.pref + c.pref_off[l1], c.pref_base >> l1, fs);
+        int s0 = c.pref_base >> l0, s1 = c.pref_base >> l1;
+        float4 P0 = face_bilinear(c.pref, c.pref_off[l0], s0, (float)s0, fs);
+        float4 P1 = face_bilinear(c.pref, c.pref_off[l1], s1, (float)s1, fs);
         float ao = 1.0f;
         if (c.ao) {
             const TA *aop = (const TA *)c.ao;
-            int x0 = x >> 1, y0 = y >> 1;
-            int x1 = min(x0 + 1, c.Wh - 1), y1 = min(y0 + 1, c.Hh - 1);
+            unsigned x0 = x >> 1, y0 = y >> 1;
+            unsigned dx = (x & 1) && (int)x0 + 1 < c.Wh ? 1u : 0u;
+            unsigned dy = (y & 1) && (int)y0 + 1 < c.Hh ? (unsigned)c.Wh : 0u;
+            unsigned q = __umul24(y0, (unsigned)c.Wh) + x0;
+            float a00 = ldf(aop, q), a10 = ldf(aop, q + dx), a01 = ldf(aop, q + dy), a11 = ldf(aop, q + dy + dx);
             float wx = (x & 1) ? 0.5f : 0.0f, wy = (y & 1) ? 0.5f : 0.0f;
-            float a00 = ldc(aop + (size_t)y0 * c.Wh + x0), a10 = ldc(aop + (size_t)y0 * c.Wh + x1);
-            float a01 = ldc(aop + (size_t)y1 * c.Wh + x0), a11 = ldc(aop + (size_t)y1 * c.Wh + x1);
             float top = fmaf(wx, a10 - a00, a00), bot = fmaf(wx, a11 - a01, a01);
             ao = fmaf(wy, bot - top, top);
         }
@@ -212,9 +223,9 @@ __global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
         }
     }
     TH *hdr = (TH *)c.hdr;
-    st(hdr + p, out[0]);
-    st(hdr + plane + p, out[1]);
-    st(hdr + 2 * plane + p, out[2]);
+    stf(hdr, p, out[0]);
+    stf(hdr, plane + p, out[1]);
+    stf(hdr, 2 * plane + p, out[2]);
 }
 
 template <typename TG, typename TA, typename TH>
@@ -250,10 +261,13 @@ hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
     k.tiles = k.tiles_x * ((a.H + kShTy - 1) / kShTy);
     k.irr_size = a.irr_size; k.pref_base = a.pref_base; k.pref_levels = a.pref_levels;
     k.lut_size = a.lut_size; k.env_size = a.env_size;
+    k.f_irr = (float)a.irr_size; k.f_lut = (float)a.lut_size; k.f_env = (float)a.env_size;
+    k.f_levels1 = (float)(a.pref_levels - 1);
     int off = 0;
     for (int m = 0; m < 8; ++m) {
+        int sm = m < a.pref_levels ? a.pref_base >> m : 2;
         k.pref_off[m] = off;
-        if (m < a.pref_levels) off += 6 * (a.pref_base >> m) * (a.pref_base >> m);
+        if (m < a.pref_levels) off += 6 * sm * sm;
     }
     k.n_lights = a.n_lights;
     for (int i = 0; i < a.n_lights; ++i) {

@@ -32,6 +32,7 @@ struct SsaoConst {
     DevCam cam;
     float radius, bias;
     int n;
+    float inv_n;
     int W, H, Wh, Hh;
     int tiles_x, tiles;
 };
@@ -51,17 +52,17 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
     int j = (tile / c.tiles_x) * kTy + tj;
     if (i >= c.Wh || j >= c.Hh) return;
     int x = 2 * i, y = 2 * j;
-    size_t p = (size_t)y * c.W + x;
-    float d = depth[p];
-    size_t o = (size_t)j * c.Wh + i;
+    unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
+    float d = ldf(depth, p);
+    unsigned o = __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i;
     if (__builtin_isinf(d)) {
-        st(out + o, 1.0f);
+        stf(out, o, 1.0f);
         return;
     }
-    size_t plane = (size_t)c.W * c.H;
+    unsigned plane = (unsigned)c.W * (unsigned)c.H;
     // view-space position and normal
     v3 P = mk3(((float)x + 0.5f - c.cam.cx) * c.cam.inv_fx * d, -((float)y + 0.5f - c.cam.cy) * c.cam.inv_fy * d, -d);
-    v3 nw = mk3(ldc(normal + p), ldc(normal + plane + p), ldc(normal + 2 * plane + p));
+    v3 nw = mk3(ldf(normal, p), ldf(normal, plane + p), ldf(normal, 2 * plane + p));
     v3 nv = normalize(mul_R(c.cam.R, nw));
     // rotation noise, Gram-Schmidt against the normal
     const float *rn = noise + 2 * ((j & 3) * 4 + (i & 3));
@@ -99,8 +100,8 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
             float hx = nx * iz, hy = ny * iz;
             ok[b] = (k0 + b < c.n) && zq > 0.0f && hx >= 0.0f && hx < fWh && hy >= 0.0f && hy < fHh;
             // truncation is floor on the accepted (non-negative) range
-            unsigned idx = ok[b] ? (unsigned)(int)hy * (unsigned)c.Wh + (unsigned)(int)hx : 0u;
-            ds[b] = hdepth[idx];
+            unsigned idx = ok[b] ? __umul24((unsigned)(int)hy, (unsigned)c.Wh) + (unsigned)(int)hx : 0u;
+            ds[b] = ldf(hdepth, idx);
             zqs[b] = zq;
         }
 #pragma unroll
@@ -110,7 +111,7 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
             occ += (ok[b] && ds[b] <= zqs[b] - c.bias) ? sm : 0.0f;
         }
     }
-    st(out + o, 1.0f - occ / (float)c.n);
+    stf(out, o, 1.0f - occ * c.inv_n);
 }
 
 template <typename TA>
@@ -191,6 +192,7 @@ hipError_t launch_ssao(const SsaoPlan &q, const float *depth, const void *normal
     c.radius = radius;
     c.bias = bias;
     c.n = n_samples;
+    c.inv_n = 1.0f / (float)n_samples;
     c.W = q.W; c.H = q.H; c.Wh = q.Wh; c.Hh = q.Hh;
     c.tiles_x = (q.Wh + kTx - 1) / kTx;
     c.tiles = c.tiles_x * ((q.Hh + kTy - 1) / kTy);
