@@ -73,18 +73,21 @@ def shadow_texels_touched(view) -> int:
     return total
 
 
-def shade_algorithmic_bytes(view, ibl) -> dict:
+def shade_algorithmic_bytes(view, ibl, half: bool = False, shadow=None) -> dict:
     """Bytes epb_shade must move per launch: the G-buffer of foreground pixels
-    (36 B) and the depth of background pixels (4 B), the half-resolution AO
-    (1 B per pixel), the HDR output (12 B), the shadow-map texels the PCF tests
+    (depth 4 B + 8 attribute values of 4 B, or 2 B in the FP16 form) and the
+    depth of background pixels, the half-resolution AO (4 or 2 B per 4 pixels),
+    the HDR output (3 values of 4 or 2 B), the shadow-map texels the PCF tests
     touch (4 B each) and the IBL tables once."""
     d = view.gbuf["depth"]
     fg = int(np.isfinite(d).sum())
     px = d.size
-    shadow = shadow_texels_touched(view)
+    vb = 2 if half else 4
+    if shadow is None:
+        shadow = shadow_texels_touched(view)
     tables = 4 * (ibl.irr.numel() + ibl.pref.numel() + ibl.lut.numel())
-    total = 36 * fg + 4 * (px - fg) + px * 1 + 12 * px + 4 * shadow + tables
-    return dict(total=total, per_px=total / px, shadow_texels=shadow, tables=tables)
+    total = (4 + 8 * vb) * fg + 4 * (px - fg) + px * vb / 4 + 3 * vb * px + 4 * shadow + tables
+    return dict(total=int(total), per_px=total / px, shadow_texels=shadow, tables=tables)
 
 
 def hbm_copy_gbps(torch, nbytes=1 << 30, reps=10) -> float:
@@ -147,6 +150,7 @@ def main():
         sys.exit(2)
 
     import torch
+    from paper_2012_03325_amd import epb as E
     from paper_2012_03325_amd import frame, synth
 
     torch.cuda.set_device(0)
@@ -154,11 +158,6 @@ def main():
     view = synth.config_1080p()
     log(f"inputs generated in {time.time() - t0:.1f} s")
     ibl = frame.DeviceIBL(view.env, **view.ibl)
-    views = [frame.DeviceView(view, ibl) for _ in range(args.copies)]
-    # shared scene-static shadow maps: point every copy at the first copy's maps
-    for dv in views[1:]:
-        dv.shadow_maps = views[0].shadow_maps
-        dv.lights = views[0].lights
     stream = torch.cuda.current_stream()
 
     # per-environment precompute, timed alone
@@ -173,41 +172,64 @@ def main():
     torch.cuda.synchronize()
     ibl_ms = ev[0].elapsed_time(ev[1]) / reps
 
-    for k in range(args.warmup):
-        views[k % args.copies].render()
-    torch.cuda.synchronize()
+    def measure(dt):
+        """Time K frames of one storage form over rotated copies of every
+        per-frame buffer; HIP events around epb_shade on the launch stream."""
+        views = [frame.DeviceView(view, ibl, gdtype=dt, ao_dtype=dt, hdr_dtype=dt)
+                 for _ in range(args.copies)]
+        for dv in views[1:]:  # the scene-static shadow maps are shared
+            dv.shadow_maps = views[0].shadow_maps
+            dv.lights = views[0].lights
+        for k in range(args.warmup):
+            views[k % args.copies].render()
+        torch.cuda.synchronize()
+        K = args.steps
+        marks = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
+        sh0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        sh1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        marks[0].record(stream)
+        for k in range(K):
+            dv = views[k % args.copies]
+            dv.ssao()
+            sh0[k].record(stream)
+            dv.shade()
+            sh1[k].record(stream)
+            dv.bloom_tonemap()
+            marks[k + 1].record(stream)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        step_ms = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(K)])
+        shade_ms = np.array([sh0[k].elapsed_time(sh1[k]) for k in range(K)])
+        del views
+        torch.cuda.empty_cache()
+        return dict(ms_per_step=marks[0].elapsed_time(marks[K]) / K, wall_ms=1e3 * wall / K,
+                    p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99)),
+                    shade_ms=float(shade_ms.mean()))
 
     K = args.steps
-    marks = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-    sh0 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    sh1 = [torch.cuda.Event(enable_timing=True) for _ in range(K)]
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    marks[0].record(stream)
-    for k in range(K):
-        dv = views[k % args.copies]
-        dv.ssao()
-        sh0[k].record(stream)
-        dv.shade()
-        sh1[k].record(stream)
-        dv.bloom_tonemap()
-        marks[k + 1].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    step_ms = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(K)])
-    shade_ms = np.array([sh0[k].elapsed_time(sh1[k]) for k in range(K)])
-    total_ms = marks[0].elapsed_time(marks[K])
-    ms_per_step = total_ms / K
     px = view.width * view.height
-    value = px / (ms_per_step / 1e3) / 1e6
-
-    acc = shade_algorithmic_bytes(view, ibl)
-    shade_avg_s = float(shade_ms.mean()) / 1e3
-    achieved = acc["total"] / shade_avg_s / 1e9
+    shadow = shadow_texels_touched(view)
+    res = {}
+    for name, dt in (("fp32", E.EPB_F32), ("fp16", E.EPB_F16)):
+        m = measure(dt)
+        acc = shade_algorithmic_bytes(view, ibl, half=(dt == E.EPB_F16), shadow=shadow)
+        m["shade_GBps"] = acc["total"] / (m["shade_ms"] / 1e3) / 1e9
+        m["shade_bytes"] = acc["total"]
+        m["shade_bytes_per_px"] = acc["per_px"]
+        m["Mpix_s"] = px / (m["ms_per_step"] / 1e3) / 1e6
+        res[name] = m
+        log(f"{name}: ms/step {m['ms_per_step']:.4f} (wall {m['wall_ms']:.4f}); shade {m['shade_ms']:.4f} ms, "
+            f"{m['shade_GBps']:.0f} GB/s")
+    plain = res["fp32"]
+    ms_per_step = plain["ms_per_step"]
+    value = plain["Mpix_s"]
+    achieved = plain["shade_GBps"]
     copy_gbps = hbm_copy_gbps(torch)
-    log(f"ms/step {ms_per_step:.4f} (wall {1e3 * wall / K:.4f}); shade {1e3 * shade_avg_s:.4f} ms, "
-        f"{achieved:.0f} GB/s; copy {copy_gbps:.0f} GB/s")
-
+    log(f"copy {copy_gbps:.0f} GB/s")
+    acc = dict(total=plain["shade_bytes"], per_px=plain["shade_bytes_per_px"])
+    shade_avg_s = plain["shade_ms"] / 1e3
     out = {
         "metric": METRIC,
         "value": round(value, 2),
@@ -230,8 +252,8 @@ def main():
             "width": view.width, "height": view.height, "form": "plain",
             "rotated_copies": args.copies,
         },
-        "p50_ms": round(float(np.percentile(step_ms, 50)), 5),
-        "p99_ms": round(float(np.percentile(step_ms, 99)), 5),
+        "p50_ms": round(plain["p50"], 5),
+        "p99_ms": round(plain["p99"], 5),
         "ibl_precompute_ms": round(ibl_ms, 4),
         "value_incl_ibl": round(px / ((ms_per_step + ibl_ms) / 1e3) / 1e6, 2),
         "roofline": {
@@ -246,6 +268,14 @@ def main():
             "algorithmic_bytes_per_px": round(acc["per_px"], 2),
             "avg_launch_ms": round(1e3 * shade_avg_s, 5),
             "measured_copy_GBps": round(copy_gbps, 1),
+            "frac_of_measured_copy": round(achieved / copy_gbps, 4),
+        },
+        "forms": {
+            name: {"Mpix_s": round(m["Mpix_s"], 2), "ms_per_step": round(m["ms_per_step"], 5),
+                   "p50_ms": round(m["p50"], 5), "p99_ms": round(m["p99"], 5),
+                   "shade_ms": round(m["shade_ms"], 5), "shade_GBps": round(m["shade_GBps"], 1),
+                   "shade_bytes_per_px": round(m["shade_bytes_per_px"], 2)}
+            for name, m in res.items()
         },
     }
     if not args.no_cpu:

@@ -165,6 +165,7 @@ typedef struct {
     float strength;       /* weight of each added level (0.04)                  */
     float exposure;       /* multiplies HDR before the ACES curve (1.0)         */
     float gamma;          /* display gamma (2.2)                                */
+    epb_dtype pyr_dtype;  /* storage of the bloom pyramid in scratch            */
 } epb_post_params;
 
 /* Operation ids for epb_scratch_bytes. */
@@ -243,7 +244,7 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao,
  *   ldr_out   [H][W][4] uint8 RGBA (A = 255)
  *   scratch   >= epb_scratch_bytes(EPB_OP_BLOOM_TONEMAP, W, H, params); on
  *             return its first part holds the blurred levels 1 .. L-1, each
- *             [H_l][W_l][4] float (RGB + unused), level after level
+ *             [H_l][W_l][4] of params->pyr_dtype (RGB + unused), level after level
  *
  * Bright map b = c max(Y - threshold, 0) / Y (Rec. 709 luminance Y); level l
  * of size ceil(W / 2^l) x ceil(H / 2^l) is the mean of the in-range children of

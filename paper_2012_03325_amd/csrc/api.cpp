@@ -114,8 +114,8 @@ size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *
     case EPB_OP_BLOOM_TONEMAP: {
         if (!params) return 0;
         const epb_post_params *p = (const epb_post_params *)params;
-        if (p->bloom_levels < 1 || p->bloom_levels > EPB_MAX_BLOOM_LEVELS) return 0;
-        return epb::post_plan(width, height, p->bloom_levels).bytes;
+        if (p->bloom_levels < 1 || p->bloom_levels > EPB_MAX_BLOOM_LEVELS || !valid_dtype(p->pyr_dtype)) return 0;
+        return epb::post_plan(width, height, p->bloom_levels, p->pyr_dtype).bytes;
     }
     default:
         return 0;
@@ -252,8 +252,9 @@ int epb_bloom_tonemap(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32
     if (!finite(params->threshold) || !finite(params->strength) || !(params->exposure > 0) ||
         !finite(params->exposure) || !(params->gamma > 0) || !finite(params->gamma))
         return EPB_ERR_PARAM;
+    if (!valid_dtype(params->pyr_dtype)) return EPB_ERR_DTYPE;
     if (!aligned16(hdr) || !aligned16(ldr_out)) return EPB_ERR_ALIGN;
-    epb::PostPlan plan = epb::post_plan(width, height, params->bloom_levels);
+    epb::PostPlan plan = epb::post_plan(width, height, params->bloom_levels, params->pyr_dtype);
     if (!scratch || scratch_bytes < plan.bytes) return EPB_ERR_SCRATCH;
     if (!aligned16(scratch)) return EPB_ERR_ALIGN;
     return hip_status(epb::launch_bloom_tonemap(plan, hdr, hdr_dtype, params->threshold, params->strength,

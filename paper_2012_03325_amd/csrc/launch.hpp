@@ -78,12 +78,13 @@ hipError_t launch_shade(const ShadeArgs &a, hipStream_t s);
 // ---- bloom + tonemap (post.hip) ----------------------------------------------
 struct PostPlan {
     int W, H, levels;
+    int texel_bytes;  // 16 (float4) or 8 (half4) per pyramid texel
     int lw[EPB_MAX_BLOOM_LEVELS], lh[EPB_MAX_BLOOM_LEVELS];
-    size_t off_blur[EPB_MAX_BLOOM_LEVELS];  // blurred level l (float4 texels)
+    size_t off_blur[EPB_MAX_BLOOM_LEVELS];  // blurred level l
     size_t off_raw[EPB_MAX_BLOOM_LEVELS];   // unblurred level l
     size_t bytes;
 };
-PostPlan post_plan(int W, int H, int levels);
+PostPlan post_plan(int W, int H, int levels, epb_dtype pyr_dtype);
 hipError_t launch_bloom_tonemap(const PostPlan &plan, const void *hdr, epb_dtype hdr_dtype,
                                 float threshold, float strength, float exposure, float gamma,
                                 uint8_t *ldr, void *scratch, hipStream_t s);

@@ -20,8 +20,8 @@ namespace epb {
 struct PostK {
     int W, H, nl;  // nl = number of levels >= 1
     int lw[EPB_MAX_BLOOM_LEVELS], lh[EPB_MAX_BLOOM_LEVELS];
-    float4 *raw[EPB_MAX_BLOOM_LEVELS];
-    float4 *blur[EPB_MAX_BLOOM_LEVELS];
+    void *raw[EPB_MAX_BLOOM_LEVELS];   // level texels of the pyramid storage type
+    void *blur[EPB_MAX_BLOOM_LEVELS];
     int blk_start[EPB_MAX_BLOOM_LEVELS + 1];  // blur launch: first block of each level
     float threshold, strength, exposure, inv_gamma;
     int tiles_x, tiles;
@@ -32,7 +32,26 @@ __device__ __forceinline__ float4 add4(float4 a, float4 b) {
 }
 __device__ __forceinline__ float4 scale4(float4 a, float s) { return make_float4(a.x * s, a.y * s, a.z * s, 0.0f); }
 
-template <typename TH>
+// Pyramid texel storage: float4, or four halves (saturating at 65504).
+struct alignas(8) Half4 {
+    __half x, y, z, w;
+};
+__device__ __forceinline__ float4 unpack(float4 v) { return v; }
+__device__ __forceinline__ float4 unpack(Half4 v) {
+    return make_float4(__half2float(v.x), __half2float(v.y), __half2float(v.z), 0.0f);
+}
+template <typename TP> __device__ __forceinline__ TP pack(float4 v);
+template <> __device__ __forceinline__ float4 pack<float4>(float4 v) { return v; }
+template <> __device__ __forceinline__ Half4 pack<Half4>(float4 v) {
+    Half4 h;
+    h.x = __float2half_rn(fminf(v.x, 65504.0f));
+    h.y = __float2half_rn(fminf(v.y, 65504.0f));
+    h.z = __float2half_rn(fminf(v.z, 65504.0f));
+    h.w = __float2half_rn(0.0f);
+    return h;
+}
+
+template <typename TH, typename TP>
 __global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__restrict__ hdr) {
     __shared__ float4 s1[32][33];
     __shared__ float4 s2[16][17];
@@ -68,7 +87,7 @@ __global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__r
                         }
                     }
                 v = scale4(v, 1.0f / n);
-                c.raw[1][(size_t)Y * c.lw[1] + X] = v;
+                ((TP *)c.raw[1])[(size_t)Y * c.lw[1] + X] = pack<TP>(v);
             }
             s1[ly][lx] = v;
         }
@@ -90,7 +109,7 @@ __global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__r
                             n += 1.0f;                                                              \
                         }                                                                           \
                 v = scale4(v, 1.0f / n);                                                            \
-                c.raw[L][(size_t)Y * c.lw[L] + X] = v;                                              \
+                ((TP *)c.raw[L])[(size_t)Y * c.lw[L] + X] = pack<TP>(v);                            \
             }                                                                                       \
             DST[ly][lx] = v;                                                                        \
         }                                                                                           \
@@ -111,12 +130,13 @@ __global__ void __launch_bounds__(256) k_bloom_down(const PostK c, const TH *__r
                         v = add4(v, s4[2 * ly + b][2 * lx + a]);
                         n += 1.0f;
                     }
-            c.raw[5][(size_t)Y * c.lw[5] + X] = scale4(v, 1.0f / n);
+            ((TP *)c.raw[5])[(size_t)Y * c.lw[5] + X] = pack<TP>(scale4(v, 1.0f / n));
         }
     }
 #undef EPB_LEVEL
 }
 
+template <typename TP>
 __global__ void __launch_bounds__(256) k_bloom_blur(const PostK c) {
     __shared__ float4 sin_[12][36];
     __shared__ float4 sh[12][32];
@@ -127,13 +147,13 @@ __global__ void __launch_bounds__(256) k_bloom_blur(const PostK c) {
     int w = c.lw[L], h = c.lh[L];
     int tx = (w + 31) / 32;
     int X0 = (local % tx) * 32, Y0 = (local / tx) * 8;
-    const float4 *src = c.raw[L];
+    const TP *src = (const TP *)c.raw[L];
     int t = threadIdx.x;
     for (int q = t; q < 12 * 36; q += 256) {
         int r = q / 36, cc = q % 36;
         int gy = min(max(Y0 + r - 2, 0), h - 1);
         int gx = min(max(X0 + cc - 2, 0), w - 1);
-        sin_[r][cc] = src[(size_t)gy * w + gx];
+        sin_[r][cc] = unpack(src[(size_t)gy * w + gx]);
     }
     __syncthreads();
     for (int q = t; q < 12 * 32; q += 256) {
@@ -148,10 +168,10 @@ __global__ void __launch_bounds__(256) k_bloom_blur(const PostK c) {
     int X = X0 + ox, Y = Y0 + oy;
     if (X < w && Y < h) {
         float4 a = sh[oy][ox], bb = sh[oy + 1][ox], m = sh[oy + 2][ox], d = sh[oy + 3][ox], e = sh[oy + 4][ox];
-        c.blur[L][(size_t)Y * w + X] =
+        ((TP *)c.blur[L])[(size_t)Y * w + X] = pack<TP>(
             make_float4((a.x + e.x + 4.0f * (bb.x + d.x) + 6.0f * m.x) * 0.0625f,
                         (a.y + e.y + 4.0f * (bb.y + d.y) + 6.0f * m.y) * 0.0625f,
-                        (a.z + e.z + 4.0f * (bb.z + d.z) + 6.0f * m.z) * 0.0625f, 0.0f);
+                        (a.z + e.z + 4.0f * (bb.z + d.z) + 6.0f * m.z) * 0.0625f, 0.0f));
     }
 }
 
@@ -170,7 +190,7 @@ __device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_g
 // 32 / 2^l + 2 columns and 8 / 2^l + 2 rows (+1 for rounding).
 constexpr int kCompLds = (19 * 7) + (11 * 5) + (7 * 4) + (5 * 4) + (4 * 4);
 
-template <typename TH>
+template <typename TH, typename TP>
 __global__ void __launch_bounds__(256) k_composite(const PostK c, const TH *__restrict__ hdr,
                                                    uint32_t *__restrict__ ldr) {
     __shared__ float4 sb[kCompLds];
@@ -201,7 +221,7 @@ __global__ void __launch_bounds__(256) k_composite(const PostK c, const TH *__re
         int nc = bx - ax + 1, nr = by - ay + 1;
         if (tc < nc && tr < nr) {
             int gx = min(max(ax + tc, 0), w - 1), gy = min(max(ay + tr, 0), h - 1);
-            sb[off + tr * nc + tc] = c.blur[L][(size_t)gy * w + gx];
+            sb[off + tr * nc + tc] = unpack(((const TP *)c.blur[L])[(size_t)gy * w + gx]);
         }
         base[L] = off;
         sx0[L] = ax;
@@ -235,11 +255,12 @@ __global__ void __launch_bounds__(256) k_composite(const PostK c, const TH *__re
     sto(ldr, p * 4u, word);
 }
 
-PostPlan post_plan(int W, int H, int levels) {
+PostPlan post_plan(int W, int H, int levels, epb_dtype pyr_dtype) {
     PostPlan q{};
     q.W = W;
     q.H = H;
     q.levels = levels;
+    q.texel_bytes = pyr_dtype == EPB_F16 ? 8 : 16;
     q.lw[0] = W;
     q.lh[0] = H;
     for (int l = 1; l < levels; ++l) {
@@ -249,16 +270,36 @@ PostPlan post_plan(int W, int H, int levels) {
     size_t off = 0;
     for (int l = 1; l < levels; ++l) {  // blurred levels first (documented scratch layout)
         q.off_blur[l] = off;
-        off += (size_t)q.lw[l] * q.lh[l] * 16;
+        off += (size_t)q.lw[l] * q.lh[l] * q.texel_bytes;
     }
     off = (off + 255) & ~size_t(255);
     for (int l = 1; l < levels; ++l) {
         q.off_raw[l] = off;
-        off += (size_t)q.lw[l] * q.lh[l] * 16;
+        off += (size_t)q.lw[l] * q.lh[l] * q.texel_bytes;
     }
     q.bytes = (off + 255) & ~size_t(255);
     if (q.bytes == 0) q.bytes = 256;
     return q;
+}
+
+template <typename TH, typename TP>
+static void launch_post(const PostK &c0, const void *hdr, uint8_t *ldr, hipStream_t s) {
+    PostK c = c0;
+    if (c.nl >= 1) {
+        c.tiles_x = (c.lw[1] + 31) / 32;
+        c.tiles = c.tiles_x * ((c.lh[1] + 31) / 32);
+        hipLaunchKernelGGL((k_bloom_down<TH, TP>), dim3(c.tiles), dim3(256), 0, s, c, (const TH *)hdr);
+        int nb = 0;
+        for (int l = 1; l <= c.nl; ++l) {
+            c.blk_start[l] = nb;
+            nb += ((c.lw[l] + 31) / 32) * ((c.lh[l] + 7) / 8);
+        }
+        c.blk_start[c.nl + 1] = nb;
+        hipLaunchKernelGGL(k_bloom_blur<TP>, dim3(nb), dim3(256), 0, s, c);
+    }
+    c.tiles_x = (c.W + 31) / 32;
+    c.tiles = c.tiles_x * ((c.H + 7) / 8);
+    hipLaunchKernelGGL((k_composite<TH, TP>), dim3(c.tiles), dim3(256), 0, s, c, (const TH *)hdr, (uint32_t *)ldr);
 }
 
 hipError_t launch_bloom_tonemap(const PostPlan &q, const void *hdr, epb_dtype hdr_dtype, float threshold,
@@ -273,36 +314,19 @@ hipError_t launch_bloom_tonemap(const PostPlan &q, const void *hdr, epb_dtype hd
         c.lw[l] = q.lw[l];
         c.lh[l] = q.lh[l];
         if (l >= 1) {
-            c.raw[l] = (float4 *)(sc + q.off_raw[l]);
-            c.blur[l] = (float4 *)(sc + q.off_blur[l]);
+            c.raw[l] = sc + q.off_raw[l];
+            c.blur[l] = sc + q.off_blur[l];
         }
     }
     c.threshold = threshold;
     c.strength = strength;
     c.exposure = exposure;
     c.inv_gamma = 1.0f / gamma;
-    if (c.nl >= 1) {
-        c.tiles_x = (c.lw[1] + 31) / 32;
-        c.tiles = c.tiles_x * ((c.lh[1] + 31) / 32);
-        if (hdr_dtype == EPB_F32)
-            hipLaunchKernelGGL(k_bloom_down<float>, dim3(c.tiles), dim3(256), 0, s, c, (const float *)hdr);
-        else
-            hipLaunchKernelGGL(k_bloom_down<__half>, dim3(c.tiles), dim3(256), 0, s, c, (const __half *)hdr);
-        int nb = 0;
-        for (int l = 1; l <= c.nl; ++l) {
-            c.blk_start[l] = nb;
-            nb += ((c.lw[l] + 31) / 32) * ((c.lh[l] + 7) / 8);
-        }
-        c.blk_start[c.nl + 1] = nb;
-        hipLaunchKernelGGL(k_bloom_blur, dim3(nb), dim3(256), 0, s, c);
-    }
-    c.tiles_x = (q.W + 31) / 32;
-    c.tiles = c.tiles_x * ((q.H + 7) / 8);
-    if (hdr_dtype == EPB_F32)
-        hipLaunchKernelGGL(k_composite<float>, dim3(c.tiles), dim3(256), 0, s, c, (const float *)hdr, (uint32_t *)ldr);
-    else
-        hipLaunchKernelGGL(k_composite<__half>, dim3(c.tiles), dim3(256), 0, s, c, (const __half *)hdr,
-                           (uint32_t *)ldr);
+    bool h16 = hdr_dtype == EPB_F16, p16 = q.texel_bytes == 8;
+    if (!h16 && !p16) launch_post<float, float4>(c, hdr, ldr, s);
+    else if (!h16 && p16) launch_post<float, Half4>(c, hdr, ldr, s);
+    else if (h16 && !p16) launch_post<__half, float4>(c, hdr, ldr, s);
+    else launch_post<__half, Half4>(c, hdr, ldr, s);
     return hipGetLastError();
 }
 

@@ -87,7 +87,7 @@ class epb_light(C.Structure):
 
 class epb_post_params(C.Structure):
     _fields_ = [("bloom_levels", C.c_int32), ("threshold", C.c_float), ("strength", C.c_float),
-                ("exposure", C.c_float), ("gamma", C.c_float)]
+                ("exposure", C.c_float), ("gamma", C.c_float), ("pyr_dtype", C.c_int)]
 
 
 STRUCTS = dict(epb_camera=epb_camera, epb_gbuffer=epb_gbuffer, epb_cube=epb_cube,

@@ -77,9 +77,9 @@ class DevicePost:
     """Bloom and tone-mapping outputs and scratch for a W x H frame."""
 
     def __init__(self, W: int, H: int, bloom_levels=6, threshold=1.0, strength=0.04,
-                 exposure=1.0, gamma=2.2, device="cuda"):
+                 exposure=1.0, gamma=2.2, device="cuda", pyr_dtype=E.EPB_F32):
         self.W, self.H = W, H
-        self.post = E.epb_post_params(bloom_levels, threshold, strength, exposure, gamma)
+        self.post = E.epb_post_params(bloom_levels, threshold, strength, exposure, gamma, pyr_dtype)
         self.ldr = torch.empty((H, W, 4), dtype=torch.uint8, device=device)
         self.scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, W, H, self.post)
         self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
@@ -93,7 +93,7 @@ class DevicePost:
         """Blurred bloom levels 1.. from the head of the scratch buffer."""
         out, off = [], 0
         w, h = self.W, self.H
-        f = self.scratch.view(torch.float32)
+        f = self.scratch.view(_TORCH_DT[self.post.pyr_dtype])
         for _ in range(1, self.post.bloom_levels):
             w, h = (w + 1) // 2, (h + 1) // 2
             out.append(f[off:off + h * w * 4].view(h, w, 4))
@@ -146,7 +146,7 @@ class DeviceView:
                 s.shadow_bias = float(L.shadow_bias)
             self.lights.append(s)
         self.postp = DevicePost(W, H, bloom_levels, view.bloom_threshold, view.bloom_strength,
-                                view.exposure, view.gamma, device)
+                                view.exposure, view.gamma, device, pyr_dtype=hdr_dtype)
         self.post = self.postp.post
         self.ldr = self.postp.ldr
         self.ao = torch.empty((self.Hh, self.Wh), dtype=_TORCH_DT[ao_dtype], device=device)

@@ -282,3 +282,64 @@ def test_validation_leaves_outputs_untouched():
     assert st == E.EPB_ERR_SCRATCH
     torch.cuda.synchronize()
     assert (dv.ldr == 7).all() and (dv.ao == -3.0).all()
+
+
+# ---------------------------------------------------------------------------
+# precision form: FP16 G-buffer attributes, FP16 AO / HDR / bloom pyramid
+# ---------------------------------------------------------------------------
+HALF_MAX = 65504.0
+# FP16 storage adds at most one half-precision rounding of the stored AO and of the
+# stored HDR (each <= 2^-11 relative) to the float32 arithmetic bar of 1e-3.
+FP16_RTOL = 1e-3 + 2 * 2.0 ** -11
+
+
+def _round_gbuffer_f16(view):
+    for k in ("normal", "albedo", "roughness", "metalness"):
+        view.gbuf[k] = view.gbuf[k].astype(np.float16).astype(np.float32)
+    return view
+
+
+@pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "full-1080p"])
+def test_fp16_form_arithmetic_parity(kind):
+    """FP16 storage against the oracle fed the same FP16-rounded G-buffer: only
+    the arithmetic and the half storage of AO and HDR differ."""
+    from paper_2012_03325_amd import epb as E
+    v = _round_gbuffer_f16(_view(kind))
+    ref = O.render(v)
+    dv = _device_view(v, v.ibl, gdtype=E.EPB_F16, ao_dtype=E.EPB_F16, hdr_dtype=E.EPB_F16)
+    log(f"[fp16] {kind}: {v.width}x{v.height}")
+    dv.render()
+    torch.cuda.synchronize()
+    hdr = dv.hdr.float().cpu().numpy()
+    lo, hi = (np.minimum(x, HALF_MAX) for x in ref["hdr"])  # storage saturates at 65504
+    fh = assert_interval(f"{kind} FP16 HDR", hdr, lo, hi, rtol=FP16_RTOL, min_frac=0.9999)
+    frac, exact = assert_ldr(f"{kind} FP16 LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
+    log(f"[fp16] {kind}: HDR within {100 * fh:.4f}%, LDR +-1 {100 * frac:.4f}% (exact {100 * exact:.3f}%)")
+
+
+def test_fp16_form_error_against_fp32_inputs():
+    """End-to-end error of the FP16 form against the FP64 oracle on the original
+    FP32 inputs, stated per output (rounding the G-buffer to half moves normals
+    by up to ~5e-4, which sharp highlights amplify)."""
+    from paper_2012_03325_amd import epb as E
+    v = _view("full-1080p")
+    ref = O.render(v)
+    dv = _device_view(v, v.ibl, gdtype=E.EPB_F16, ao_dtype=E.EPB_F16, hdr_dtype=E.EPB_F16)
+    log("[fp16-e2e] 1080p")
+    dv.render()
+    torch.cuda.synchronize()
+    hdr = dv.hdr.float().cpu().numpy()
+    mid = 0.5 * (ref["hdr"][0] + ref["hdr"][1])
+    rel = np.abs(hdr - np.minimum(mid, HALF_MAX)) / np.maximum(np.abs(mid), 1e-6 * np.abs(mid).max())
+    ao = dv.ao.float().cpu().numpy()
+    ao_err = np.maximum(ao - ref["ao"][1], ref["ao"][0] - ao).clip(min=0)
+    g = dv.ldr.cpu().numpy()[..., :3].astype(np.int32)
+    lo, hi = (x[..., :3].astype(np.int32) for x in ref["ldr"])
+    dist = np.maximum(g - hi, lo - g).clip(min=0).max(-1)
+    hist = np.bincount(dist.ravel(), minlength=4)
+    log(f"[fp16-e2e] AO max err {ao_err.max():.2e}; HDR rel err p50 {np.percentile(rel, 50):.2e} "
+        f"p99 {np.percentile(rel, 99):.2e} p99.9 {np.percentile(rel, 99.9):.2e} max {rel.max():.2e}; "
+        f"LDR LSB histogram {hist[:4].tolist()} (of {dist.size})")
+    assert ao_err.max() < 2e-3
+    assert np.percentile(rel, 99) < 1e-2
+    assert (dist <= 1).mean() >= 0.999
