@@ -257,6 +257,87 @@ int epb_bloom_tonemap(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32
                       const epb_post_params *params, uint8_t *ldr_out, void *scratch,
                       size_t scratch_bytes, hipStream_t stream);
 
+/* ------------------------------------------------------------------------
+ * Batched form: the whole pass (SSAO, shading, bloom and tone mapping) of many
+ * views of any sizes with one launch per stage (seven launches per batch, not
+ * seven per view).  Every stage walks the work items (tiles) of all views, so
+ * small views do not leave the device idle and a batch is a fixed sequence of
+ * launches that can be captured in a HIP graph and replayed.
+ *
+ * Use: fill one epb_view per view; size the scratch with
+ * epb_batch_scratch_bytes() and the table with epb_batch_table_bytes();
+ * epb_batch_build() validates every view and writes the batch table into host
+ * memory; copy those table bytes to device memory (16-byte aligned); then
+ * epb_render_batch() enqueues the frame.  The table holds the device addresses
+ * of every input, output and scratch buffer and may be reused (and its device
+ * copy replayed) for as long as those buffers stay where they are.
+ * Each view's results are bitwise identical to the single-view calls
+ * epb_ssao -> epb_shade -> epb_bloom_tonemap on the same inputs with the same
+ * schedule choices (tile shapes do not change results; see epb_schedule).
+ * ------------------------------------------------------------------------ */
+
+#define EPB_MAX_BATCH_VIEWS 4096
+
+typedef struct {
+    epb_gbuffer gbuf;             /* the view's G-buffer                        */
+    epb_camera cam;               /* its camera (same W, H)                     */
+    const epb_light *lights;      /* host array of n_lights lights              */
+    int32_t n_lights;             /* 0 .. EPB_MAX_LIGHTS                        */
+    const epb_ibl_maps *ibl;      /* host struct: tables of epb_precompute_ibl  */
+    const epb_cube *env;          /* host struct: environment cube              */
+    const epb_ssao_params *ssao;  /* host struct                                */
+    const epb_post_params *post;  /* host struct                                */
+    epb_dtype hdr_dtype;          /* storage of the HDR image                   */
+    void *ao;                     /* [Hh][Wh] AO output, or NULL: kept in scratch */
+    void *hdr;                    /* [3][H][W] HDR output, or NULL: in scratch  */
+    uint8_t *ldr;                 /* [H][W][4] RGBA8 output (required)          */
+} epb_view;
+
+/* Launch shapes of a batch.  They change the speed, never the results: every
+ * output value is computed by the same arithmetic whatever the shape. */
+typedef struct {
+    int32_t shade_tile;    /* shading pixel tile: 0 = 32x8, 1 = 64x4, 2 = 16x16 */
+    int32_t ssao_tile;     /* SSAO half-resolution tile: 0 = 16x8, 1 = 32x4     */
+    int32_t ssao_batch;    /* SSAO depth gathers in flight: 0 = 8, 1 = 16        */
+    int32_t blocks_per_cu; /* 0: one workgroup per work item; k in 1..64: a
+                              persistent grid of k workgroups per compute unit  */
+} epb_schedule;
+
+/* Bytes of the batch table for n_views views (0 if n_views is out of range). */
+size_t epb_batch_table_bytes(int32_t n_views);
+
+/* Bytes of device scratch a batch of these views needs: per view the SSAO
+ * and bloom scratch of the single-view calls, plus AO and HDR images for the
+ * views that leave them NULL.  0 for invalid arguments. */
+size_t epb_batch_scratch_bytes(const epb_view *views, int32_t n_views);
+
+/*
+ * epb_batch_build -- validate n_views views (1 .. EPB_MAX_BATCH_VIEWS) and
+ * write the batch table into the host buffer `table`.
+ *
+ *   views     host array; each view is checked as the single-view calls check
+ *             their arguments (same status codes)
+ *   schedule  launch shapes, or NULL for all zeros
+ *   scratch   device buffer of >= epb_batch_scratch_bytes(views, n_views)
+ *   table     host buffer of >= epb_batch_table_bytes(n_views)
+ *
+ * All views must share the G-buffer dtype, the AO dtype, the HDR dtype, the
+ * bloom pyramid dtype (else EPB_ERR_DTYPE) and the SSAO blur flag (else
+ * EPB_ERR_PARAM).  Enqueues nothing; returns EPB_OK or a validation status.
+ */
+int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *schedule,
+                    void *scratch, size_t scratch_bytes, void *table, size_t table_bytes);
+
+/*
+ * epb_render_batch -- enqueue the batch described by `table` (host copy, as
+ * written by epb_batch_build) on `stream`; `table_dev` is a device copy of
+ * the same bytes that stays unchanged until the enqueued work has run.
+ * Launches exactly the kernels of one frame: no copies, allocations or
+ * memsets, so the call may be captured into a HIP graph.  Returns
+ * EPB_ERR_PARAM for a table that epb_batch_build did not write.
+ */
+int epb_render_batch(const void *table, const void *table_dev, hipStream_t stream);
+
 /* Bytes of scratch the operation needs for a W x H image (for
  * EPB_OP_PRECOMPUTE_IBL pass the environment size as W and H and an
  * epb_ibl_params; for EPB_OP_SSAO an epb_ssao_params or NULL; for

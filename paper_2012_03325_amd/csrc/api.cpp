@@ -80,71 +80,10 @@ int check_ibl_params(int S, const epb_ibl_params *p) {
     return EPB_OK;
 }
 
-}  // namespace
-
-extern "C" {
-
-const char *epb_status_str(int status) {
-    switch (status) {
-    case EPB_OK: return "ok";
-    case EPB_ERR_NULL: return "a required pointer is NULL";
-    case EPB_ERR_SIZE: return "size out of range";
-    case EPB_ERR_DTYPE: return "unsupported storage type";
-    case EPB_ERR_ALIGN: return "device pointer not 16-byte aligned";
-    case EPB_ERR_SCRATCH: return "scratch buffer missing or too small";
-    case EPB_ERR_PARAM: return "parameter out of range";
-    case EPB_ERR_HIP: return "HIP launch failed";
-    default: return "unknown status";
-    }
-}
-
-int epb_last_hip_error(void) { return g_last_hip_error; }
-
-size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *params) {
-    if (width < 1 || height < 1 || width > EPB_MAX_IMAGE_SIZE || height > EPB_MAX_IMAGE_SIZE) return 0;
-    switch (op) {
-    case EPB_OP_PRECOMPUTE_IBL: {
-        if (!params || width != height) return 0;
-        const epb_ibl_params *p = (const epb_ibl_params *)params;
-        if (check_ibl_params(width, p) != EPB_OK) return 0;
-        return epb::ibl_plan(width, *p).bytes;
-    }
-    case EPB_OP_SSAO:
-        return epb::ssao_plan(width, height).bytes;
-    case EPB_OP_BLOOM_TONEMAP: {
-        if (!params) return 0;
-        const epb_post_params *p = (const epb_post_params *)params;
-        if (p->bloom_levels < 1 || p->bloom_levels > EPB_MAX_BLOOM_LEVELS || !valid_dtype(p->pyr_dtype)) return 0;
-        return epb::post_plan(width, height, p->bloom_levels, p->pyr_dtype).bytes;
-    }
-    default:
-        return 0;
-    }
-}
-
-int epb_precompute_ibl(const epb_cube *env, const epb_ibl_params *params, epb_ibl_maps *out, void *scratch,
-                       size_t scratch_bytes, hipStream_t stream) {
-    if (!env || !params || !out) return EPB_ERR_NULL;
-    int st = check_cube(env, 1);
-    if (st) return st;
-    st = check_ibl_params(env->size, params);
-    if (st) return st;
-    if (!out->irradiance.data || !out->prefiltered.data || !out->brdf_lut) return EPB_ERR_NULL;
-    int base = env->size < params->pref_size ? env->size : params->pref_size;
-    if (out->irradiance.size != params->irr_size || out->irradiance.levels < 1 || out->prefiltered.size != base ||
-        out->prefiltered.levels != params->pref_levels || out->lut_size != params->lut_size)
-        return EPB_ERR_SIZE;
-    if (!aligned16(out->irradiance.data) || !aligned16(out->prefiltered.data) || !aligned16(out->brdf_lut))
-        return EPB_ERR_ALIGN;
-    epb::IblPlan plan = epb::ibl_plan(env->size, *params);
-    if (!scratch || scratch_bytes < plan.bytes) return EPB_ERR_SCRATCH;
-    if (!aligned16(scratch)) return EPB_ERR_ALIGN;
-    return hip_status(epb::launch_precompute_ibl(plan, env->data, out->irradiance.data, out->prefiltered.data,
-                                                 out->brdf_lut, scratch, stream));
-}
-
-int epb_ssao(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_params *params, void *ao_out,
-             void *scratch, size_t scratch_bytes, hipStream_t stream) {
+// ---- per-stage validation and descriptor set-up (shared by the single-view
+// calls and the batch builder) -------------------------------------------------
+int build_ssao(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_params *params, void *ao_out,
+               void *scratch, size_t scratch_bytes, epb::SsaoDesc *out) {
     if (!gbuf || !cam || !params || !ao_out) return EPB_ERR_NULL;
     int st = check_camera(cam);
     if (st) return st;
@@ -160,15 +99,15 @@ int epb_ssao(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_para
     epb::SsaoPlan plan = epb::ssao_plan(cam->width, cam->height);
     if (!scratch || scratch_bytes < plan.bytes) return EPB_ERR_SCRATCH;
     if (!aligned16(scratch)) return EPB_ERR_ALIGN;
-    return hip_status(epb::launch_ssao(plan, gbuf->depth, gbuf->normal, gbuf->dtype, host_cam(cam),
-                                       params->kernel, params->n_samples, params->noise, params->radius,
-                                       params->bias, params->blur_tau, params->blur, ao_out, params->out_dtype,
-                                       scratch, stream));
+    *out = epb::ssao_desc(plan, gbuf->depth, gbuf->normal, host_cam(cam), params->kernel, params->n_samples,
+                          params->noise, params->radius, params->bias, params->blur_tau, params->blur ? 1 : 0,
+                          ao_out, scratch);
+    return EPB_OK;
 }
 
-int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, epb_dtype ao_dtype,
-              const epb_light *lights, int32_t n_lights, const epb_ibl_maps *ibl, const epb_cube *env,
-              void *hdr_out, epb_dtype hdr_dtype, hipStream_t stream) {
+int build_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, epb_dtype ao_dtype,
+                const epb_light *lights, int32_t n_lights, const epb_ibl_maps *ibl, const epb_cube *env,
+                void *hdr_out, epb_dtype hdr_dtype, epb::ShadeArgs *out) {
     if (!gbuf || !cam || !ibl || !env || !hdr_out) return EPB_ERR_NULL;
     if (n_lights < 0 || n_lights > EPB_MAX_LIGHTS) return EPB_ERR_PARAM;
     if (n_lights > 0 && !lights) return EPB_ERR_NULL;
@@ -203,7 +142,7 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, ep
     a.n_lights = n_lights;
     for (int i = 0; i < n_lights; ++i) {
         const epb_light &L = lights[i];
-        epb::HostLight &h = a.lights[i];
+        epb::DevLight &h = a.lights[i];
         for (int c = 0; c < 3; ++c) {
             if (!finite(L.pos[c]) || !finite(L.color[c]) || L.color[c] < 0) return EPB_ERR_PARAM;
             h.pos[c] = L.pos[c];
@@ -230,6 +169,7 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, ep
             }
             h.fx = L.shadow_cam.fx; h.fy = L.shadow_cam.fy; h.cx = L.shadow_cam.cx; h.cy = L.shadow_cam.cy;
             h.w = L.shadow_cam.width; h.h = L.shadow_cam.height;
+            h.fw = (float)h.w; h.fh = (float)h.h;
             h.bias = L.shadow_bias;
         }
     }
@@ -239,26 +179,272 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, ep
     a.env = env->data; a.env_size = env->size;
     a.hdr = hdr_out;
     a.hdr_dtype = hdr_dtype;
+    *out = a;
+    return EPB_OK;
+}
+
+int check_post_params(const epb_post_params *params) {
+    if (params->bloom_levels < 1 || params->bloom_levels > EPB_MAX_BLOOM_LEVELS) return EPB_ERR_PARAM;
+    if (!finite(params->threshold) || !finite(params->strength) || !(params->exposure > 0) ||
+        !finite(params->exposure) || !(params->gamma > 0) || !finite(params->gamma))
+        return EPB_ERR_PARAM;
+    if (!valid_dtype(params->pyr_dtype)) return EPB_ERR_DTYPE;
+    return EPB_OK;
+}
+
+int build_post(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32_t height, const epb_post_params *params,
+               uint8_t *ldr_out, void *scratch, size_t scratch_bytes, epb::PostDesc *out) {
+    if (!hdr || !params || !ldr_out) return EPB_ERR_NULL;
+    if (width < 1 || height < 1 || width > EPB_MAX_IMAGE_SIZE || height > EPB_MAX_IMAGE_SIZE) return EPB_ERR_SIZE;
+    if (!valid_dtype(hdr_dtype)) return EPB_ERR_DTYPE;
+    int st = check_post_params(params);
+    if (st) return st;
+    if (!aligned16(hdr) || !aligned16(ldr_out)) return EPB_ERR_ALIGN;
+    epb::PostPlan plan = epb::post_plan(width, height, params->bloom_levels, params->pyr_dtype);
+    if (!scratch || scratch_bytes < plan.bytes) return EPB_ERR_SCRATCH;
+    if (!aligned16(scratch)) return EPB_ERR_ALIGN;
+    *out = epb::post_desc(plan, hdr, params->threshold, params->strength, params->exposure, params->gamma, ldr_out,
+                          scratch);
+    return EPB_OK;
+}
+
+// ---- batched form ------------------------------------------------------------
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Scratch of one view of a batch: [SSAO][bloom pyramid][AO if not given][HDR if not given].
+struct ViewScratch {
+    size_t ssao, post, ao, hdr, total;
+};
+
+int view_scratch(const epb_view &v, ViewScratch *out) {
+    if (!v.ssao || !v.post) return EPB_ERR_NULL;
+    int W = v.cam.width, H = v.cam.height;
+    if (W < 1 || H < 1 || W > EPB_MAX_IMAGE_SIZE || H > EPB_MAX_IMAGE_SIZE) return EPB_ERR_SIZE;
+    if (!valid_dtype(v.ssao->out_dtype) || !valid_dtype(v.hdr_dtype)) return EPB_ERR_DTYPE;
+    int st = check_post_params(v.post);
+    if (st) return st;
+    ViewScratch s{};
+    s.ssao = align256(epb::ssao_plan(W, H).bytes);
+    s.post = align256(epb::post_plan(W, H, v.post->bloom_levels, v.post->pyr_dtype).bytes);
+    size_t ao_elt = v.ssao->out_dtype == EPB_F16 ? 2 : 4, hdr_elt = v.hdr_dtype == EPB_F16 ? 2 : 4;
+    s.ao = v.ao ? 0 : align256((size_t)((W + 1) / 2) * ((H + 1) / 2) * ao_elt);
+    s.hdr = v.hdr ? 0 : align256((size_t)3 * W * H * hdr_elt);
+    s.total = s.ssao + s.post + s.ao + s.hdr;
+    *out = s;
+    return EPB_OK;
+}
+
+int batch_scratch(const epb_view *views, int32_t n, size_t *bytes) {
+    if (!views) return EPB_ERR_NULL;
+    if (n < 1 || n > EPB_MAX_BATCH_VIEWS) return EPB_ERR_SIZE;
+    size_t total = 0;
+    for (int i = 0; i < n; ++i) {
+        ViewScratch s;
+        int st = view_scratch(views[i], &s);
+        if (st) return st;
+        total += s.total;
+    }
+    *bytes = total;
+    return EPB_OK;
+}
+
+int check_schedule(const epb_schedule &q) {
+    if (q.shade_tile < 0 || q.shade_tile > 2 || q.ssao_tile < 0 || q.ssao_tile > 1 || q.ssao_batch < 0 ||
+        q.ssao_batch > 1 || q.blocks_per_cu < 0 || q.blocks_per_cu > 64)
+        return EPB_ERR_PARAM;
+    return EPB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *epb_status_str(int status) {
+    switch (status) {
+    case EPB_OK: return "ok";
+    case EPB_ERR_NULL: return "a required pointer is NULL";
+    case EPB_ERR_SIZE: return "size out of range";
+    case EPB_ERR_DTYPE: return "unsupported storage type";
+    case EPB_ERR_ALIGN: return "device pointer not 16-byte aligned";
+    case EPB_ERR_SCRATCH: return "scratch buffer missing or too small";
+    case EPB_ERR_PARAM: return "parameter out of range";
+    case EPB_ERR_HIP: return "HIP launch failed";
+    default: return "unknown status";
+    }
+}
+
+int epb_last_hip_error(void) { return g_last_hip_error; }
+
+size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *params) {
+    if (width < 1 || height < 1 || width > EPB_MAX_IMAGE_SIZE || height > EPB_MAX_IMAGE_SIZE) return 0;
+    switch (op) {
+    case EPB_OP_PRECOMPUTE_IBL: {
+        if (!params || width != height) return 0;
+        const epb_ibl_params *p = (const epb_ibl_params *)params;
+        if (check_ibl_params(width, p) != EPB_OK) return 0;
+        return epb::ibl_plan(width, *p).bytes;
+    }
+    case EPB_OP_SSAO:
+        return epb::ssao_plan(width, height).bytes;
+    case EPB_OP_BLOOM_TONEMAP: {
+        if (!params) return 0;
+        const epb_post_params *p = (const epb_post_params *)params;
+        if (check_post_params(p) != EPB_OK) return 0;
+        return epb::post_plan(width, height, p->bloom_levels, p->pyr_dtype).bytes;
+    }
+    default:
+        return 0;
+    }
+}
+
+int epb_precompute_ibl(const epb_cube *env, const epb_ibl_params *params, epb_ibl_maps *out, void *scratch,
+                       size_t scratch_bytes, hipStream_t stream) {
+    if (!env || !params || !out) return EPB_ERR_NULL;
+    int st = check_cube(env, 1);
+    if (st) return st;
+    st = check_ibl_params(env->size, params);
+    if (st) return st;
+    if (!out->irradiance.data || !out->prefiltered.data || !out->brdf_lut) return EPB_ERR_NULL;
+    int base = env->size < params->pref_size ? env->size : params->pref_size;
+    if (out->irradiance.size != params->irr_size || out->irradiance.levels < 1 || out->prefiltered.size != base ||
+        out->prefiltered.levels != params->pref_levels || out->lut_size != params->lut_size)
+        return EPB_ERR_SIZE;
+    if (!aligned16(out->irradiance.data) || !aligned16(out->prefiltered.data) || !aligned16(out->brdf_lut))
+        return EPB_ERR_ALIGN;
+    epb::IblPlan plan = epb::ibl_plan(env->size, *params);
+    if (!scratch || scratch_bytes < plan.bytes) return EPB_ERR_SCRATCH;
+    if (!aligned16(scratch)) return EPB_ERR_ALIGN;
+    return hip_status(epb::launch_precompute_ibl(plan, env->data, out->irradiance.data, out->prefiltered.data,
+                                                 out->brdf_lut, scratch, stream));
+}
+
+int epb_ssao(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_params *params, void *ao_out,
+             void *scratch, size_t scratch_bytes, hipStream_t stream) {
+    epb::SsaoDesc d;
+    int st = build_ssao(gbuf, cam, params, ao_out, scratch, scratch_bytes, &d);
+    if (st) return st;
+    return hip_status(epb::launch_ssao(d, gbuf->dtype, params->out_dtype, stream));
+}
+
+int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, epb_dtype ao_dtype,
+              const epb_light *lights, int32_t n_lights, const epb_ibl_maps *ibl, const epb_cube *env,
+              void *hdr_out, epb_dtype hdr_dtype, hipStream_t stream) {
+    epb::ShadeArgs a;
+    int st = build_shade(gbuf, cam, ao, ao_dtype, lights, n_lights, ibl, env, hdr_out, hdr_dtype, &a);
+    if (st) return st;
     return hip_status(epb::launch_shade(a, stream));
 }
 
 int epb_bloom_tonemap(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32_t height,
                       const epb_post_params *params, uint8_t *ldr_out, void *scratch, size_t scratch_bytes,
                       hipStream_t stream) {
-    if (!hdr || !params || !ldr_out) return EPB_ERR_NULL;
-    if (width < 1 || height < 1 || width > EPB_MAX_IMAGE_SIZE || height > EPB_MAX_IMAGE_SIZE) return EPB_ERR_SIZE;
-    if (!valid_dtype(hdr_dtype)) return EPB_ERR_DTYPE;
-    if (params->bloom_levels < 1 || params->bloom_levels > EPB_MAX_BLOOM_LEVELS) return EPB_ERR_PARAM;
-    if (!finite(params->threshold) || !finite(params->strength) || !(params->exposure > 0) ||
-        !finite(params->exposure) || !(params->gamma > 0) || !finite(params->gamma))
-        return EPB_ERR_PARAM;
-    if (!valid_dtype(params->pyr_dtype)) return EPB_ERR_DTYPE;
-    if (!aligned16(hdr) || !aligned16(ldr_out)) return EPB_ERR_ALIGN;
-    epb::PostPlan plan = epb::post_plan(width, height, params->bloom_levels, params->pyr_dtype);
-    if (!scratch || scratch_bytes < plan.bytes) return EPB_ERR_SCRATCH;
+    epb::PostDesc d;
+    int st = build_post(hdr, hdr_dtype, width, height, params, ldr_out, scratch, scratch_bytes, &d);
+    if (st) return st;
+    return hip_status(epb::launch_bloom_tonemap(d, hdr_dtype, params->pyr_dtype, stream));
+}
+
+size_t epb_batch_table_bytes(int32_t n_views) {
+    if (n_views < 1 || n_views > EPB_MAX_BATCH_VIEWS) return 0;
+    return epb::batch_table_bytes(n_views);
+}
+
+size_t epb_batch_scratch_bytes(const epb_view *views, int32_t n_views) {
+    size_t bytes = 0;
+    return batch_scratch(views, n_views, &bytes) == EPB_OK ? bytes : 0;
+}
+
+int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *schedule, void *scratch,
+                    size_t scratch_bytes, void *table, size_t table_bytes) {
+    if (!views || !table) return EPB_ERR_NULL;
+    if (n_views < 1 || n_views > EPB_MAX_BATCH_VIEWS) return EPB_ERR_SIZE;
+    epb_schedule q{};
+    if (schedule) q = *schedule;
+    int st = check_schedule(q);
+    if (st) return st;
+    if (table_bytes < epb::batch_table_bytes(n_views)) return EPB_ERR_SIZE;
+    size_t need = 0;
+    if ((st = batch_scratch(views, n_views, &need))) return st;
+    if (!scratch || scratch_bytes < need) return EPB_ERR_SCRATCH;
     if (!aligned16(scratch)) return EPB_ERR_ALIGN;
-    return hip_status(epb::launch_bloom_tonemap(plan, hdr, hdr_dtype, params->threshold, params->strength,
-                                                params->exposure, params->gamma, ldr_out, scratch, stream));
+    const epb_view &v0 = views[0];
+    for (int i = 0; i < n_views; ++i) {
+        const epb_view &v = views[i];
+        if (v.gbuf.dtype != v0.gbuf.dtype || v.ssao->out_dtype != v0.ssao->out_dtype ||
+            v.hdr_dtype != v0.hdr_dtype || v.post->pyr_dtype != v0.post->pyr_dtype)
+            return EPB_ERR_DTYPE;
+        if ((v.ssao->blur != 0) != (v0.ssao->blur != 0)) return EPB_ERR_PARAM;
+    }
+    // descriptors first (validating every view), then the header and item prefix sums
+    epb::ViewDesc *vd = (epb::ViewDesc *)((char *)table + epb::batch_views_offset(n_views));
+    char *sc = (char *)scratch;
+    long long total[epb::kStages] = {};
+    int *start = (int *)((char *)table + epb::batch_start_offset());
+    for (int i = 0; i < n_views; ++i) {
+        const epb_view &v = views[i];
+        ViewScratch vs;
+        view_scratch(v, &vs);
+        char *s_ssao = sc, *s_post = sc + vs.ssao;
+        void *ao = v.ao ? v.ao : (void *)(s_post + vs.post);
+        void *hdr = v.hdr ? v.hdr : (void *)(s_post + vs.post + vs.ao);
+        sc += vs.total;
+        epb::ViewDesc d;
+        std::memset(&d, 0, sizeof(d));
+        if ((st = build_ssao(&v.gbuf, &v.cam, v.ssao, ao, s_ssao, vs.ssao, &d.ssao))) return st;
+        epb::ShadeArgs a;
+        if ((st = build_shade(&v.gbuf, &v.cam, ao, v.ssao->out_dtype, v.lights, v.n_lights, v.ibl, v.env, hdr,
+                              v.hdr_dtype, &a)))
+            return st;
+        d.shade = epb::shade_desc(a);
+        if ((st = build_post(hdr, v.hdr_dtype, v.cam.width, v.cam.height, v.post, v.ldr, s_post, vs.post, &d.post)))
+            return st;
+        int items[epb::kStages];
+        items[epb::kStPrep] = epb::ssao_items(d.ssao, epb::kStPrep, q.ssao_tile);
+        items[epb::kStRaw] = epb::ssao_items(d.ssao, epb::kStRaw, q.ssao_tile);
+        items[epb::kStBlur] = d.ssao.blur ? epb::ssao_items(d.ssao, epb::kStBlur, q.ssao_tile) : 0;
+        items[epb::kStShade] = epb::shade_items(d.shade, q.shade_tile);
+        items[epb::kStDown] = epb::post_items(d.post, epb::kStDown);
+        items[epb::kStBloomBlur] = epb::post_items(d.post, epb::kStBloomBlur);
+        items[epb::kStComposite] = epb::post_items(d.post, epb::kStComposite);
+        for (int k = 0; k < epb::kStages; ++k) {
+            if (total[k] + items[k] > 0x7fffffffLL) return EPB_ERR_SIZE;
+            start[k * (n_views + 1) + i] = (int)total[k];
+            total[k] += items[k];
+        }
+        std::memcpy(&vd[i], &d, sizeof(d));
+    }
+    epb::BatchHeader h{};
+    h.magic = epb::kBatchMagic;
+    h.n_views = n_views;
+    h.gdtype = v0.gbuf.dtype;
+    h.ao_dtype = v0.ssao->out_dtype;
+    h.hdr_dtype = v0.hdr_dtype;
+    h.pyr_dtype = v0.post->pyr_dtype;
+    h.blur = v0.ssao->blur ? 1 : 0;
+    h.has_ao = 1;
+    h.shade_tile = q.shade_tile;
+    h.ssao_tile = q.ssao_tile;
+    h.ssao_batch = q.ssao_batch;
+    h.blocks_per_cu = q.blocks_per_cu;
+    for (int k = 0; k < epb::kStages; ++k) {
+        h.total[k] = (int)total[k];
+        start[k * (n_views + 1) + n_views] = (int)total[k];
+    }
+    std::memset(table, 0, epb::batch_start_offset());
+    std::memcpy(table, &h, sizeof(h));
+    return EPB_OK;
+}
+
+int epb_render_batch(const void *table, const void *table_dev, hipStream_t stream) {
+    if (!table || !table_dev) return EPB_ERR_NULL;
+    if (!aligned16(table_dev)) return EPB_ERR_ALIGN;
+    epb::BatchHeader h;
+    std::memcpy(&h, table, sizeof(h));
+    if (h.magic != epb::kBatchMagic || h.n_views < 1 || h.n_views > EPB_MAX_BATCH_VIEWS) return EPB_ERR_PARAM;
+    hipError_t e = epb::launch_ssao_batch(h, table_dev, stream);
+    if (e == hipSuccess) e = epb::launch_shade_batch(h, table_dev, stream);
+    if (e == hipSuccess) e = epb::launch_post_batch(h, table_dev, stream);
+    return hip_status(e);
 }
 
 }  // extern "C"

@@ -1,0 +1,133 @@
+// Plain descriptors shared by host set-up code and kernels: one view's inputs,
+// outputs and scratch for each stage of the shading pass, and the layout of
+// the batch table that carries many views to the batched kernels.
+#pragma once
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime.h>
+
+#include "../../include/epb.h"
+
+namespace epb {
+
+// Rigid camera with precomputed reciprocals.
+struct DevCam {
+    float R[9];  // row-major rotation
+    float t[3];
+    float fx, fy, cx, cy;
+    float inv_fx, inv_fy;
+    int w, h;
+};
+
+// Point light with an optional depth map, transforms composed on the host.
+struct DevLight {
+    float pos[3], rad[3];  // rad = colour * intensity
+    const float *map;      // may be null
+    float M[9], o[3];      // light view from camera view: P_l = M P_v + o
+    float fx, fy, cx, cy;
+    int w, h;
+    float fw, fh;          // w, h as floats
+    float bias;
+};
+
+struct SsaoDesc {
+    DevCam cam;
+    float radius, bias, tau, inv_n;
+    int n, blur;
+    int W, H, Wh, Hh;
+    const float *depth;
+    const void *normal;
+    const float *kernel;  // [n][3]
+    const float *noise;   // [4][4][2]
+    float *hdepth;        // scratch: compact half-resolution depth
+    void *raw;            // raw AO: scratch when blurred, else the output
+    void *out;            // AO output
+};
+
+struct ShadeDesc {
+    const float *depth;
+    const void *normal, *albedo, *rough, *metal;
+    const void *ao;  // may be null
+    void *hdr;
+    const float4 *irr, *pref, *env;
+    const float2 *lut;
+    float R[9];
+    float cam_pos[3];
+    float cx, cy, inv_fx, inv_fy;
+    int W, H, Wh, Hh;
+    int irr_size, pref_base, pref_levels, lut_size, env_size;
+    float f_irr, f_lut, f_env, f_levels1;  // sizes as floats; f_levels1 = levels - 1
+    int pref_off[8];                       // texel offset of each prefiltered level
+    int n_lights;
+    DevLight lights[EPB_MAX_LIGHTS];
+};
+
+struct PostDesc {
+    int W, H, nl;  // nl = number of pyramid levels >= 1
+    int lw[EPB_MAX_BLOOM_LEVELS], lh[EPB_MAX_BLOOM_LEVELS];
+    void *raw[EPB_MAX_BLOOM_LEVELS];   // unblurred level texels (pyramid storage type)
+    void *blur[EPB_MAX_BLOOM_LEVELS];  // blurred level texels
+    int blk_start[EPB_MAX_BLOOM_LEVELS + 1];  // first blur work item of each level
+    float threshold, strength, exposure, inv_gamma;
+    const void *hdr;
+    uint32_t *ldr;
+};
+
+// ---------------------------------------------------------------------------
+// tile shapes
+// ---------------------------------------------------------------------------
+constexpr int kSsaoPrepW = 256;           // half-resolution texels per prep item
+constexpr int kBlurTx = 16, kBlurTy = 8;  // SSAO blur tile
+constexpr int kPostTx = 32, kPostTy = 8;  // composite and bloom-blur tiles
+constexpr int kDownTile = 32;             // bloom_down: 32x32 level-1 texels (64x64 pixels)
+
+// Selectable shapes (the schedule picks one per stage).
+struct TileShape {
+    int tx, ty;
+};
+constexpr TileShape kShadeTiles[3] = {{32, 8}, {64, 4}, {16, 16}};
+constexpr TileShape kSsaoTiles[2] = {{16, 8}, {32, 4}};
+constexpr int kSsaoBatches[2] = {8, 16};
+
+inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
+
+// ---------------------------------------------------------------------------
+// batch table: [BatchHeader][int start[kStages][n + 1]][pad to 16][ViewDesc[n]]
+// ---------------------------------------------------------------------------
+enum Stage { kStPrep = 0, kStRaw, kStBlur, kStShade, kStDown, kStBloomBlur, kStComposite, kStages };
+
+struct ViewDesc {
+    SsaoDesc ssao;
+    ShadeDesc shade;
+    PostDesc post;
+};
+
+struct BatchHeader {
+    uint32_t magic;
+    int n_views;
+    int gdtype, ao_dtype, hdr_dtype, pyr_dtype;
+    int blur, has_ao;
+    int shade_tile, ssao_tile, ssao_batch, blocks_per_cu;
+    int total[kStages];  // work items of each stage over all views
+};
+
+constexpr uint32_t kBatchMagic = 0x45504231u;  // "EPB1"
+
+__host__ __device__ inline size_t batch_start_offset() { return (sizeof(BatchHeader) + 15) & ~size_t(15); }
+__host__ __device__ inline size_t batch_views_offset(int n) {
+    return (batch_start_offset() + sizeof(int) * kStages * (size_t)(n + 1) + 15) & ~size_t(15);
+}
+__host__ __device__ inline size_t batch_table_bytes(int n) { return batch_views_offset(n) + sizeof(ViewDesc) * (size_t)n; }
+
+__host__ __device__ inline const int *batch_start(const void *table, int stage) {
+    const BatchHeader *h = (const BatchHeader *)table;
+    return (const int *)((const char *)table + batch_start_offset()) + stage * (h->n_views + 1);
+}
+__host__ __device__ inline const ViewDesc *batch_views(const void *table) {
+    const BatchHeader *h = (const BatchHeader *)table;
+    return (const ViewDesc *)((const char *)table + batch_views_offset(h->n_views));
+}
+
+}  // namespace epb

@@ -8,6 +8,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "desc.hpp"
+
 namespace epb {
 
 constexpr float kPi = 3.14159265358979323846f;
@@ -68,14 +70,6 @@ __device__ __forceinline__ float pow5(float x) {
     return x2 * x2 * x;
 }
 
-// Rigid transform / camera as kernel argument.
-struct DevCam {
-    float R[9];  // row-major rotation
-    float t[3];
-    float fx, fy, cx, cy;
-    float inv_fx, inv_fy;
-    int w, h;
-};
 __device__ __forceinline__ v3 mul_R(const float *R, v3 v) {
     return mk3(fmaf(R[0], v.x, fmaf(R[1], v.y, R[2] * v.z)), fmaf(R[3], v.x, fmaf(R[4], v.y, R[5] * v.z)),
                fmaf(R[6], v.x, fmaf(R[7], v.y, R[8] * v.z)));
@@ -207,6 +201,36 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     int q = nb / kNumXcd, r = nb % kNumXcd;
     int x = b % kNumXcd, local = b / kNumXcd;
     return x < r ? x * (q + 1) + local : r * (q + 1) + (x - r) * q + local;
+}
+
+// Work distribution of persistent (or one-item-per-block) grids: XCD x (the
+// blocks b with b mod 8 == x) owns a contiguous share of the items, visited by
+// its blocks in turn.  With one block per item this is the bijection above.
+// The trip count depends on blockIdx only, so loops may contain barriers.
+struct XcdRange {
+    int first, count, lb, stride;
+};
+__device__ __forceinline__ XcdRange xcd_range(int total) {
+    int nb = gridDim.x, b = blockIdx.x;
+    int x = b % kNumXcd;
+    int q = total / kNumXcd, r = total % kNumXcd;
+    XcdRange w;
+    w.first = x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q;
+    w.count = q + (x < r ? 1 : 0);
+    w.stride = nb / kNumXcd + (x < nb % kNumXcd ? 1 : 0);
+    w.lb = b / kNumXcd;
+    return w;
+}
+
+// View owning work item g: start[v] <= g < start[v + 1] (binary search; uniform).
+__device__ __forceinline__ int find_view(const int *start, int n, int g) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (start[mid] <= g) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // GGX half vector for the point (u1, u2) around normal n with tangent frame

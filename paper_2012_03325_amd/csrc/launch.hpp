@@ -1,6 +1,6 @@
 // Internal launch interface between the C ABI (api.cpp) and the kernels.
-// Arguments are already validated when these are called; each returns the
-// hipError_t of its launches.
+// Arguments are already validated when these are called; each launcher
+// returns the hipError_t of its launches.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -8,6 +8,7 @@
 #include <stdint.h>
 
 #include "../../include/epb.h"
+#include "desc.hpp"
 
 namespace epb {
 
@@ -16,6 +17,10 @@ struct HostCam {
     float fx, fy, cx, cy, inv_fx, inv_fy;
     int w, h;
 };
+
+// Grid of a batched stage: one block per item, or a persistent grid of
+// blocks_per_cu blocks per CU.
+int batch_grid(int total, int blocks_per_cu);
 
 // ---- image-based lighting (ibl.hip) ---------------------------------------
 struct IblPlan {
@@ -37,20 +42,14 @@ struct SsaoPlan {
     size_t off_hdepth, off_raw, bytes;
 };
 SsaoPlan ssao_plan(int W, int H);
-hipError_t launch_ssao(const SsaoPlan &plan, const float *depth, const void *normal,
-                       epb_dtype gdtype, const HostCam &cam, const float *kernel, int n_samples,
-                       const float *noise, float radius, float bias, float tau, int blur,
-                       void *ao_out, epb_dtype ao_dtype, void *scratch, hipStream_t s);
+SsaoDesc ssao_desc(const SsaoPlan &q, const float *depth, const void *normal, const HostCam &cam,
+                   const float *kernel, int n_samples, const float *noise, float radius, float bias,
+                   float tau, int blur, void *ao_out, void *scratch);
+int ssao_items(const SsaoDesc &c, int stage, int ssao_tile);
+hipError_t launch_ssao(const SsaoDesc &c, epb_dtype gdtype, epb_dtype ao_dtype, hipStream_t s);
+hipError_t launch_ssao_batch(const BatchHeader &h, const void *table, hipStream_t s);
 
 // ---- shading (shade.hip) ----------------------------------------------------
-struct HostLight {
-    float pos[3], rad[3];     // rad = color * intensity
-    const float *map;         // may be null
-    float M[9], o[3];         // light-from-camera-view transform: P_l = M P_v + o
-    float fx, fy, cx, cy;
-    int w, h;
-    float bias;
-};
 struct ShadeArgs {
     const float *depth;
     const void *normal, *albedo, *rough, *metal;
@@ -61,7 +60,7 @@ struct ShadeArgs {
     const void *ao;
     epb_dtype ao_dtype;
     int n_lights;
-    HostLight lights[EPB_MAX_LIGHTS];
+    DevLight lights[EPB_MAX_LIGHTS];
     const float *irr;
     int irr_size;
     const float *pref;
@@ -73,7 +72,10 @@ struct ShadeArgs {
     void *hdr;
     epb_dtype hdr_dtype;
 };
+ShadeDesc shade_desc(const ShadeArgs &a);
+int shade_items(const ShadeDesc &c, int shade_tile);
 hipError_t launch_shade(const ShadeArgs &a, hipStream_t s);
+hipError_t launch_shade_batch(const BatchHeader &h, const void *table, hipStream_t s);
 
 // ---- bloom + tonemap (post.hip) ----------------------------------------------
 struct PostPlan {
@@ -85,8 +87,10 @@ struct PostPlan {
     size_t bytes;
 };
 PostPlan post_plan(int W, int H, int levels, epb_dtype pyr_dtype);
-hipError_t launch_bloom_tonemap(const PostPlan &plan, const void *hdr, epb_dtype hdr_dtype,
-                                float threshold, float strength, float exposure, float gamma,
-                                uint8_t *ldr, void *scratch, hipStream_t s);
+PostDesc post_desc(const PostPlan &q, const void *hdr, float threshold, float strength, float exposure,
+                   float gamma, uint8_t *ldr, void *scratch);
+int post_items(const PostDesc &c, int stage);
+hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s);
+hipError_t launch_post_batch(const BatchHeader &h, const void *table, hipStream_t s);
 
 }  // namespace epb

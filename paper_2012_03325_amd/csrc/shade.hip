@@ -23,39 +23,8 @@
 
 namespace epb {
 
-constexpr int kShTx = 32, kShTy = 8;
-
 struct Row3 {
     float v[3];
-};
-
-struct DevLight {
-    float pos[3], rad[3];
-    const float *map;
-    float M[9], o[3];  // light view from camera view: P_l = M P_v + o
-    float fx, fy, cx, cy;
-    int w, h;
-    float fw, fh;      // w, h as floats
-    float bias;
-};
-
-struct ShadeK {
-    const float *depth;
-    const void *normal, *albedo, *rough, *metal;
-    const void *ao;
-    void *hdr;
-    const float4 *irr, *pref, *env;
-    const float2 *lut;
-    float R[9];
-    float cam_pos[3];
-    float cx, cy, inv_fx, inv_fy;
-    int W, H, Wh, Hh;
-    int tiles_x, tiles;
-    int irr_size, pref_base, pref_levels, lut_size, env_size;
-    float f_irr, f_lut, f_env, f_levels1;  // sizes as floats; f_levels1 = levels - 1
-    int pref_off[8];
-    int n_lights;
-    DevLight lights[EPB_MAX_LIGHTS];
 };
 
 // Bilinear lookup of the (size >= 2) BRDF table, clamp to edge.
@@ -116,11 +85,12 @@ __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, fl
     return inside ? (float)lit * (1.0f / 9.0f) : 1.0f;
 }
 
-template <typename TG, typename TA, typename TH>
-__global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
-    int tile = xcd_tile(blockIdx.x, c.tiles);
-    int x = (tile % c.tiles_x) * kShTx + (int)(threadIdx.x % kShTx);
-    int y = (tile / c.tiles_x) * kShTy + (int)(threadIdx.x / kShTx);
+template <int TX, int TY, typename TG, typename TA, typename TH>
+__device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
+    int tiles_x = (c.W + TX - 1) / TX;
+    int ty = tile / tiles_x;
+    int x = (tile - ty * tiles_x) * TX + (int)(threadIdx.x % TX);
+    int y = ty * TY + (int)(threadIdx.x / TX);
     if (x >= c.W || y >= c.H) return;
     unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
@@ -228,23 +198,32 @@ __global__ void __launch_bounds__(kShTx *kShTy) k_shade(const ShadeK c) {
     stf(hdr, 2 * plane + p, out[2]);
 }
 
-template <typename TG, typename TA, typename TH>
-static void go(const ShadeK &k, hipStream_t s) {
-    hipLaunchKernelGGL((k_shade<TG, TA, TH>), dim3(k.tiles), dim3(kShTx * kShTy), 0, s, k);
-}
-template <typename TG, typename TA>
-static void go_h(const ShadeK &k, epb_dtype hd, hipStream_t s) {
-    if (hd == EPB_F32) go<TG, TA, float>(k, s);
-    else go<TG, TA, __half>(k, s);
-}
-template <typename TG>
-static void go_a(const ShadeK &k, epb_dtype ad, epb_dtype hd, hipStream_t s) {
-    if (ad == EPB_F32) go_h<TG, float>(k, hd, s);
-    else go_h<TG, __half>(k, hd, s);
+// ---------------------------------------------------------------------------
+// kernels
+// ---------------------------------------------------------------------------
+template <int TX, int TY, typename TG, typename TA, typename TH>
+__global__ void __launch_bounds__(TX *TY) k_shade(const ShadeDesc c, int tiles) {
+    shade_tile<TX, TY, TG, TA, TH>(c, xcd_tile(blockIdx.x, tiles));
 }
 
-hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
-    ShadeK k{};
+template <int TX, int TY, typename TG, typename TA, typename TH>
+__global__ void __launch_bounds__(TX *TY) k_shade_batch(const void *__restrict__ table) {
+    const BatchHeader *h = (const BatchHeader *)table;
+    const int *start = batch_start(table, kStShade);
+    const ViewDesc *views = batch_views(table);
+    XcdRange w = xcd_range(h->total[kStShade]);
+    for (int it = w.lb; it < w.count; it += w.stride) {
+        int g = w.first + it;
+        int v = find_view(start, h->n_views, g);
+        shade_tile<TX, TY, TG, TA, TH>(views[v].shade, g - start[v]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+ShadeDesc shade_desc(const ShadeArgs &a) {
+    ShadeDesc k{};
     k.depth = a.depth;
     k.normal = a.normal; k.albedo = a.albedo; k.rough = a.rough; k.metal = a.metal;
     k.ao = a.ao;
@@ -257,8 +236,6 @@ hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
     for (int i = 0; i < 3; ++i) k.cam_pos[i] = a.cam_pos[i];
     k.cx = a.cam.cx; k.cy = a.cam.cy; k.inv_fx = a.cam.inv_fx; k.inv_fy = a.cam.inv_fy;
     k.W = a.W; k.H = a.H; k.Wh = (a.W + 1) / 2; k.Hh = (a.H + 1) / 2;
-    k.tiles_x = (a.W + kShTx - 1) / kShTx;
-    k.tiles = k.tiles_x * ((a.H + kShTy - 1) / kShTy);
     k.irr_size = a.irr_size; k.pref_base = a.pref_base; k.pref_levels = a.pref_levels;
     k.lut_size = a.lut_size; k.env_size = a.env_size;
     k.f_irr = (float)a.irr_size; k.f_lut = (float)a.lut_size; k.f_env = (float)a.env_size;
@@ -270,19 +247,60 @@ hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
         if (m < a.pref_levels) off += 6 * sm * sm;
     }
     k.n_lights = a.n_lights;
-    for (int i = 0; i < a.n_lights; ++i) {
-        const HostLight &h = a.lights[i];
-        DevLight &d = k.lights[i];
-        for (int j = 0; j < 3; ++j) { d.pos[j] = h.pos[j]; d.rad[j] = h.rad[j]; d.o[j] = h.o[j]; }
-        for (int j = 0; j < 9; ++j) d.M[j] = h.M[j];
-        d.map = h.map;
-        d.fx = h.fx; d.fy = h.fy; d.cx = h.cx; d.cy = h.cy;
-        d.w = h.w; d.h = h.h;
-        d.fw = (float)h.w; d.fh = (float)h.h;
-        d.bias = h.bias;
+    for (int i = 0; i < a.n_lights; ++i) k.lights[i] = a.lights[i];
+    return k;
+}
+
+int shade_items(const ShadeDesc &c, int shade_tile) {
+    TileShape t = kShadeTiles[shade_tile];
+    return ceil_div(c.W, t.tx) * ceil_div(c.H, t.ty);
+}
+
+template <typename TG, typename TA, typename TH>
+static void go(const ShadeDesc &k, hipStream_t s) {
+    int tiles = shade_items(k, 0);
+    hipLaunchKernelGGL((k_shade<32, 8, TG, TA, TH>), dim3(tiles), dim3(256), 0, s, k, tiles);
+}
+template <int TX, int TY, typename TG, typename TA, typename TH>
+static void go_batch(const BatchHeader &h, const void *table, hipStream_t s) {
+    hipLaunchKernelGGL((k_shade_batch<TX, TY, TG, TA, TH>), dim3(batch_grid(h.total[kStShade], h.blocks_per_cu)),
+                       dim3(TX * TY), 0, s, table);
+}
+template <typename TG, typename TA, typename TH>
+static void go_shape(const BatchHeader *h, const void *table, const ShadeDesc *k, hipStream_t s) {
+    if (!h) {
+        go<TG, TA, TH>(*k, s);
+        return;
     }
-    if (a.gdtype == EPB_F32) go_a<float>(k, a.ao_dtype, a.hdr_dtype, s);
-    else go_a<__half>(k, a.ao_dtype, a.hdr_dtype, s);
+    switch (h->shade_tile) {
+    case 1: go_batch<64, 4, TG, TA, TH>(*h, table, s); break;
+    case 2: go_batch<16, 16, TG, TA, TH>(*h, table, s); break;
+    default: go_batch<32, 8, TG, TA, TH>(*h, table, s); break;
+    }
+}
+template <typename TG, typename TA>
+static void go_h(const BatchHeader *h, const void *table, const ShadeDesc *k, epb_dtype hd, hipStream_t s) {
+    if (hd == EPB_F32) go_shape<TG, TA, float>(h, table, k, s);
+    else go_shape<TG, TA, __half>(h, table, k, s);
+}
+template <typename TG>
+static void go_a(const BatchHeader *h, const void *table, const ShadeDesc *k, epb_dtype ad, epb_dtype hd,
+                 hipStream_t s) {
+    if (ad == EPB_F32) go_h<TG, float>(h, table, k, hd, s);
+    else go_h<TG, __half>(h, table, k, hd, s);
+}
+
+hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
+    ShadeDesc k = shade_desc(a);
+    if (a.gdtype == EPB_F32) go_a<float>(nullptr, nullptr, &k, a.ao_dtype, a.hdr_dtype, s);
+    else go_a<__half>(nullptr, nullptr, &k, a.ao_dtype, a.hdr_dtype, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_shade_batch(const BatchHeader &h, const void *table, hipStream_t s) {
+    epb_dtype ad = (epb_dtype)h.ao_dtype, hd = (epb_dtype)h.hdr_dtype;
+    if (h.gdtype == EPB_F32) go_a<float>(&h, table, nullptr, ad, hd, s);
+    else go_a<__half>(&h, table, nullptr, ad, hd, s);
     return hipGetLastError();
 }
 

@@ -2,70 +2,64 @@
 // (paper Sec. 5.2: normal-oriented hemisphere, Bavoil and Sainz).
 //
 // gfx950 mapping:
-//  * k_ssao_prep compacts the half-resolution depth (the depth at (2i, 2j))
-//    into a dense Wh x Hh plane: 2 MB at 1080p, resident in one XCD's 4 MB
-//    L2, so the sample gathers hit L2 instead of striding through the
-//    full-resolution plane.
-//  * k_ssao_raw: one thread per half-resolution texel; the sample kernel is
-//    staged once per workgroup in LDS and read as wave-uniform broadcasts; the
-//    per-sample work is a 3x3 frame transform, one reciprocal, a floor and one
-//    gathered depth.
-//  * k_ssao_blur: 4x4 bilateral mean; the 19x11 depth/AO footprint of a 16x8
-//    tile is staged through LDS.
-//  * 16x8 tiles, consecutive tiles on the same XCD.
+//  * prep compacts the half-resolution depth (the depth at (2i, 2j)) into a
+//    dense Wh x Hh plane: 2 MB at 1080p, resident in one XCD's 4 MB L2, so
+//    the sample gathers hit L2 instead of striding the full-resolution plane.
+//  * raw: one thread per half-resolution texel; the sample kernel is staged in
+//    LDS and read as wave-uniform broadcasts.  A sample's depth and projected
+//    texel coordinates are affine in the kernel vector (three plane equations
+//    per pixel), so a sample costs 9 FMA, one reciprocal, two multiplies, a
+//    range test and one gathered depth; gathers are issued a batch at a time
+//    from clamped addresses before any is consumed.
+//  * blur: 4x4 bilateral mean; the 19x11 depth/AO footprint of a 16x8 tile is
+//    staged through LDS.
+//  * every stage has a single-view kernel (one block per tile, XCD-aware
+//    order) and a batched kernel that walks the tiles of many views.
 #include "device_common.hpp"
 #include "launch.hpp"
 
 namespace epb {
 
-constexpr int kTx = 16, kTy = 8;  // 128 threads per workgroup
-
-__global__ void __launch_bounds__(256) k_ssao_prep(const float *__restrict__ depth, int W, int Wh, int Hh,
-                                                   float *__restrict__ hdepth) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    int j = blockIdx.y;
-    if (i >= Wh) return;
-    hdepth[(size_t)j * Wh + i] = depth[(size_t)(2 * j) * W + 2 * i];
+// ---------------------------------------------------------------------------
+// per-item work
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void ssao_prep_item(const SsaoDesc &c, int item) {
+    int chunks = (c.Wh + kSsaoPrepW - 1) / kSsaoPrepW;
+    int j = item / chunks;
+    int i = (item - j * chunks) * kSsaoPrepW + (int)threadIdx.x;
+    if (i >= c.Wh) return;
+    stf(c.hdepth, __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i,
+        ldf(c.depth, __umul24((unsigned)(2 * j), (unsigned)c.W) + (unsigned)(2 * i)));
 }
 
-struct SsaoConst {
-    DevCam cam;
-    float radius, bias;
-    int n;
-    float inv_n;
-    int W, H, Wh, Hh;
-    int tiles_x, tiles;
-};
+__device__ __forceinline__ void stage_kernel(const SsaoDesc &c, float *sk) {
+    for (int q = threadIdx.x; q < c.n * 3; q += blockDim.x) sk[q] = c.kernel[q];
+}
 
-template <typename TG, typename TA>
-__global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float *__restrict__ depth,
-                                                       const TG *__restrict__ normal,
-                                                       const float *__restrict__ hdepth,
-                                                       const float *__restrict__ kern,
-                                                       const float *__restrict__ noise, TA *__restrict__ out) {
-    __shared__ float sk[EPB_MAX_SSAO_SAMPLES * 3];
-    for (int q = threadIdx.x; q < c.n * 3; q += blockDim.x) sk[q] = kern[q];
-    __syncthreads();
-    int tile = xcd_tile(blockIdx.x, c.tiles);
-    int ti = threadIdx.x % kTx, tj = threadIdx.x / kTx;
-    int i = (tile % c.tiles_x) * kTx + ti;
-    int j = (tile / c.tiles_x) * kTy + tj;
+template <int TX, int TY, int KB, typename TG, typename TA>
+__device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile, const float *sk) {
+    int tiles_x = (c.Wh + TX - 1) / TX;
+    int ty = tile / tiles_x;
+    int i = (tile - ty * tiles_x) * TX + (int)(threadIdx.x % TX);
+    int j = ty * TY + (int)(threadIdx.x / TX);
     if (i >= c.Wh || j >= c.Hh) return;
     int x = 2 * i, y = 2 * j;
     unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
-    float d = ldf(depth, p);
+    float d = ldf(c.depth, p);
     unsigned o = __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i;
+    TA *out = (TA *)c.raw;
     if (__builtin_isinf(d)) {
         stf(out, o, 1.0f);
         return;
     }
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
+    const TG *normal = (const TG *)c.normal;
     // view-space position and normal
     v3 P = mk3(((float)x + 0.5f - c.cam.cx) * c.cam.inv_fx * d, -((float)y + 0.5f - c.cam.cy) * c.cam.inv_fy * d, -d);
     v3 nw = mk3(ldf(normal, p), ldf(normal, plane + p), ldf(normal, 2 * plane + p));
     v3 nv = normalize(mul_R(c.cam.R, nw));
     // rotation noise, Gram-Schmidt against the normal
-    const float *rn = noise + 2 * ((j & 3) * 4 + (i & 3));
+    const float *rn = c.noise + 2 * ((j & 3) * 4 + (i & 3));
     v3 r = mk3(rn[0], rn[1], 0.0f);
     v3 t = normalize(r - nv * dot(nv, r));
     v3 bb = cross(nv, t);
@@ -82,15 +76,12 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
     v3 Xv = Mx * ax + Zv * bx, Yv = My * ay + Zv * by;
     float X0 = fmaf(ax, P.x, bx * Z0), Y0 = fmaf(ay, P.y, by * Z0);
     float fWh = (float)c.Wh, fHh = (float)c.Hh;
-    // samples in batches of 8: every gather of a batch is issued (at index 0
-    // for samples that miss the image) before any is consumed
-    constexpr int kB = 8;
     float occ = 0.0f;
-    for (int k0 = 0; k0 < c.n; k0 += kB) {
-        float ds[kB], zqs[kB];
-        bool ok[kB];
+    for (int k0 = 0; k0 < c.n; k0 += KB) {
+        float ds[KB], zqs[KB];
+        bool ok[KB];
 #pragma unroll
-        for (int b = 0; b < kB; ++b) {
+        for (int b = 0; b < KB; ++b) {
             int k = min(k0 + b, c.n - 1);
             float sx = sk[3 * k], sy = sk[3 * k + 1], sz = sk[3 * k + 2];
             float zq = fmaf(Zv.x, sx, fmaf(Zv.y, sy, fmaf(Zv.z, sz, Z0)));
@@ -101,11 +92,11 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
             ok[b] = (k0 + b < c.n) && zq > 0.0f && hx >= 0.0f && hx < fWh && hy >= 0.0f && hy < fHh;
             // truncation is floor on the accepted (non-negative) range
             unsigned idx = ok[b] ? __umul24((unsigned)(int)hy, (unsigned)c.Wh) + (unsigned)(int)hx : 0u;
-            ds[b] = ldf(hdepth, idx);
+            ds[b] = ldf(c.hdepth, idx);
             zqs[b] = zq;
         }
 #pragma unroll
-        for (int b = 0; b < kB; ++b) {
+        for (int b = 0; b < KB; ++b) {
             float u = clamp01(c.radius * rcp(fabsf(d - ds[b])));
             float sm = u * u * (3.0f - 2.0f * u);
             occ += (ok[b] && ds[b] <= zqs[b] - c.bias) ? sm : 0.0f;
@@ -115,45 +106,124 @@ __global__ void __launch_bounds__(kTx *kTy) k_ssao_raw(SsaoConst c, const float 
 }
 
 template <typename TA>
-__global__ void __launch_bounds__(kTx *kTy) k_ssao_blur(const float *__restrict__ hdepth,
-                                                        const float *__restrict__ raw, int Wh, int Hh, float tau,
-                                                        int tiles_x, int tiles, TA *__restrict__ out) {
-    constexpr int LW = kTx + 3, LH = kTy + 3;  // offsets -2 .. +1
-    __shared__ float sd[LH][LW];
-    __shared__ float sa[LH][LW];
-    int tile = xcd_tile(blockIdx.x, tiles);
-    int i0 = (tile % tiles_x) * kTx, j0 = (tile / tiles_x) * kTy;
+__device__ __forceinline__ void ssao_blur_tile(const SsaoDesc &c, int tile, float (*sd)[kBlurTx + 3],
+                                               float (*sa)[kBlurTx + 3]) {
+    constexpr int LW = kBlurTx + 3, LH = kBlurTy + 3;  // offsets -2 .. +1
+    int tiles_x = (c.Wh + kBlurTx - 1) / kBlurTx;
+    int ty = tile / tiles_x;
+    int i0 = (tile - ty * tiles_x) * kBlurTx, j0 = ty * kBlurTy;
+    const float *raw = (const float *)c.raw;
     for (int q = threadIdx.x; q < LW * LH; q += blockDim.x) {
         int li = q % LW, lj = q / LW;
         int gi = i0 + li - 2, gj = j0 + lj - 2;
-        bool in = gi >= 0 && gi < Wh && gj >= 0 && gj < Hh;
-        size_t g = (size_t)gj * Wh + gi;
-        sd[lj][li] = in ? hdepth[g] : __builtin_inff();  // out of range: weight 0
-        sa[lj][li] = in ? raw[g] : 0.0f;
+        bool in = gi >= 0 && gi < c.Wh && gj >= 0 && gj < c.Hh;
+        unsigned g = in ? __umul24((unsigned)gj, (unsigned)c.Wh) + (unsigned)gi : 0u;
+        float dq = ldf(c.hdepth, g), aq = ldf(raw, g);
+        sd[lj][li] = in ? dq : __builtin_inff();  // out of range: weight 0
+        sa[lj][li] = in ? aq : 0.0f;
     }
     __syncthreads();
-    int ti = threadIdx.x % kTx, tj = threadIdx.x / kTx;
+    int ti = threadIdx.x % kBlurTx, tj = threadIdx.x / kBlurTx;
     int i = i0 + ti, j = j0 + tj;
-    if (i >= Wh || j >= Hh) return;
-    float dp = sd[tj + 2][ti + 2];
-    float v = 1.0f;
-    if (!__builtin_isinf(dp)) {
-        float inv = 1.0f / (tau * dp);
-        float s = 0.0f, sw = 0.0f;
+    if (i < c.Wh && j < c.Hh) {
+        float dp = sd[tj + 2][ti + 2];
+        float v = 1.0f;
+        if (!__builtin_isinf(dp)) {
+            float inv = 1.0f / (c.tau * dp);
+            float s = 0.0f, sw = 0.0f;
 #pragma unroll
-        for (int dy = 0; dy < 4; ++dy)
+            for (int dy = 0; dy < 4; ++dy)
 #pragma unroll
-            for (int dx = 0; dx < 4; ++dx) {
-                float dq = sd[tj + dy][ti + dx];
-                float w = __builtin_isinf(dq) ? 0.0f : fmaxf(0.0f, 1.0f - fabsf(dq - dp) * inv);
-                s = fmaf(w, sa[tj + dy][ti + dx], s);
-                sw += w;
-            }
-        v = s / sw;
+                for (int dx = 0; dx < 4; ++dx) {
+                    float dq = sd[tj + dy][ti + dx];
+                    float w = __builtin_isinf(dq) ? 0.0f : fmaxf(0.0f, 1.0f - fabsf(dq - dp) * inv);
+                    s = fmaf(w, sa[tj + dy][ti + dx], s);
+                    sw += w;
+                }
+            v = s / sw;
+        }
+        stf((TA *)c.out, __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i, v);
     }
-    st(out + (size_t)j * Wh + i, v);
+    __syncthreads();  // the tile's LDS may be refilled by the next item
 }
 
+// ---------------------------------------------------------------------------
+// single-view kernels
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kSsaoPrepW) k_ssao_prep(const SsaoDesc c, int items) {
+    ssao_prep_item(c, xcd_tile(blockIdx.x, items));
+}
+
+template <int TX, int TY, int KB, typename TG, typename TA>
+__global__ void __launch_bounds__(TX *TY) k_ssao_raw(const SsaoDesc c, int tiles) {
+    __shared__ float sk[EPB_MAX_SSAO_SAMPLES * 3];
+    stage_kernel(c, sk);
+    __syncthreads();
+    ssao_raw_tile<TX, TY, KB, TG, TA>(c, xcd_tile(blockIdx.x, tiles), sk);
+}
+
+template <typename TA>
+__global__ void __launch_bounds__(kBlurTx *kBlurTy) k_ssao_blur(const SsaoDesc c, int tiles) {
+    __shared__ float sd[kBlurTy + 3][kBlurTx + 3];
+    __shared__ float sa[kBlurTy + 3][kBlurTx + 3];
+    ssao_blur_tile<TA>(c, xcd_tile(blockIdx.x, tiles), sd, sa);
+}
+
+// ---------------------------------------------------------------------------
+// batched kernels: work items of all views, XCD-aware persistent walk
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(kSsaoPrepW) k_ssao_prep_batch(const void *__restrict__ table) {
+    const BatchHeader *h = (const BatchHeader *)table;
+    const int *start = batch_start(table, kStPrep);
+    const ViewDesc *views = batch_views(table);
+    XcdRange w = xcd_range(h->total[kStPrep]);
+    for (int it = w.lb; it < w.count; it += w.stride) {
+        int g = w.first + it;
+        int v = find_view(start, h->n_views, g);
+        ssao_prep_item(views[v].ssao, g - start[v]);
+    }
+}
+
+template <int TX, int TY, int KB, typename TG, typename TA>
+__global__ void __launch_bounds__(TX *TY) k_ssao_raw_batch(const void *__restrict__ table) {
+    __shared__ float sk[EPB_MAX_SSAO_SAMPLES * 3];
+    const BatchHeader *h = (const BatchHeader *)table;
+    const int *start = batch_start(table, kStRaw);
+    const ViewDesc *views = batch_views(table);
+    XcdRange w = xcd_range(h->total[kStRaw]);
+    int staged = -1;
+    for (int it = w.lb; it < w.count; it += w.stride) {
+        int g = w.first + it;
+        int v = find_view(start, h->n_views, g);
+        const SsaoDesc &c = views[v].ssao;
+        if (v != staged) {  // uniform: the block restages the kernel of a new view
+            __syncthreads();
+            stage_kernel(c, sk);
+            __syncthreads();
+            staged = v;
+        }
+        ssao_raw_tile<TX, TY, KB, TG, TA>(c, g - start[v], sk);
+    }
+}
+
+template <typename TA>
+__global__ void __launch_bounds__(kBlurTx *kBlurTy) k_ssao_blur_batch(const void *__restrict__ table) {
+    __shared__ float sd[kBlurTy + 3][kBlurTx + 3];
+    __shared__ float sa[kBlurTy + 3][kBlurTx + 3];
+    const BatchHeader *h = (const BatchHeader *)table;
+    const int *start = batch_start(table, kStBlur);
+    const ViewDesc *views = batch_views(table);
+    XcdRange w = xcd_range(h->total[kStBlur]);
+    for (int it = w.lb; it < w.count; it += w.stride) {
+        int g = w.first + it;
+        int v = find_view(start, h->n_views, g);
+        ssao_blur_tile<TA>(views[v].ssao, g - start[v], sd, sa);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
 SsaoPlan ssao_plan(int W, int H) {
     SsaoPlan q{};
     q.W = W;
@@ -168,22 +238,21 @@ SsaoPlan ssao_plan(int W, int H) {
     return q;
 }
 
-template <typename TG, typename TA>
-static void launch_raw(const SsaoPlan &q, SsaoConst c, const float *depth, const void *normal,
-                       const float *hdepth, const float *kernel, const float *noise, void *out, hipStream_t s) {
-    hipLaunchKernelGGL((k_ssao_raw<TG, TA>), dim3(c.tiles), dim3(kTx * kTy), 0, s, c, depth, (const TG *)normal,
-                       hdepth, kernel, noise, (TA *)out);
+int ssao_items(const SsaoDesc &c, int stage, int ssao_tile) {
+    switch (stage) {
+    case kStPrep: return c.Hh * ceil_div(c.Wh, kSsaoPrepW);
+    case kStRaw: {
+        TileShape t = kSsaoTiles[ssao_tile];
+        return ceil_div(c.Wh, t.tx) * ceil_div(c.Hh, t.ty);
+    }
+    default: return ceil_div(c.Wh, kBlurTx) * ceil_div(c.Hh, kBlurTy);
+    }
 }
 
-hipError_t launch_ssao(const SsaoPlan &q, const float *depth, const void *normal, epb_dtype gdtype,
-                       const HostCam &cam, const float *kernel, int n_samples, const float *noise, float radius,
-                       float bias, float tau, int blur, void *ao_out, epb_dtype ao_dtype, void *scratch,
-                       hipStream_t s) {
-    char *sc = (char *)scratch;
-    float *hdepth = (float *)(sc + q.off_hdepth);
-    float *raw = (float *)(sc + q.off_raw);
-    hipLaunchKernelGGL(k_ssao_prep, dim3((q.Wh + 255) / 256, q.Hh), dim3(256), 0, s, depth, q.W, q.Wh, q.Hh, hdepth);
-    SsaoConst c{};
+SsaoDesc ssao_desc(const SsaoPlan &q, const float *depth, const void *normal, const HostCam &cam, const float *kernel,
+                   int n_samples, const float *noise, float radius, float bias, float tau, int blur, void *ao_out,
+                   void *scratch) {
+    SsaoDesc c{};
     for (int k = 0; k < 9; ++k) c.cam.R[k] = cam.R[k];
     for (int k = 0; k < 3; ++k) c.cam.t[k] = cam.t[k];
     c.cam.fx = cam.fx; c.cam.fy = cam.fy; c.cam.cx = cam.cx; c.cam.cy = cam.cy;
@@ -191,29 +260,92 @@ hipError_t launch_ssao(const SsaoPlan &q, const float *depth, const void *normal
     c.cam.w = cam.w; c.cam.h = cam.h;
     c.radius = radius;
     c.bias = bias;
+    c.tau = tau;
     c.n = n_samples;
     c.inv_n = 1.0f / (float)n_samples;
+    c.blur = blur;
     c.W = q.W; c.H = q.H; c.Wh = q.Wh; c.Hh = q.Hh;
-    c.tiles_x = (q.Wh + kTx - 1) / kTx;
-    c.tiles = c.tiles_x * ((q.Hh + kTy - 1) / kTy);
+    c.depth = depth;
+    c.normal = normal;
+    c.kernel = kernel;
+    c.noise = noise;
+    char *sc = (char *)scratch;
+    c.hdepth = (float *)(sc + q.off_hdepth);
     // raw AO goes to scratch when blurred, straight to the output otherwise
-    bool direct = !blur;
-    void *raw_dst = direct ? ao_out : (void *)raw;
-    epb_dtype raw_dt = direct ? ao_dtype : EPB_F32;
+    c.raw = blur ? (void *)(sc + q.off_raw) : ao_out;
+    c.out = ao_out;
+    return c;
+}
+
+template <int TX, int TY, int KB, typename TG, typename TA>
+static void go_raw(const SsaoDesc &c, hipStream_t s) {
+    int tiles = ceil_div(c.Wh, TX) * ceil_div(c.Hh, TY);
+    hipLaunchKernelGGL((k_ssao_raw<TX, TY, KB, TG, TA>), dim3(tiles), dim3(TX * TY), 0, s, c, tiles);
+}
+
+hipError_t launch_ssao(const SsaoDesc &c, epb_dtype gdtype, epb_dtype ao_dtype, hipStream_t s) {
+    int prep = ssao_items(c, kStPrep, 0);
+    hipLaunchKernelGGL(k_ssao_prep, dim3(prep), dim3(kSsaoPrepW), 0, s, c, prep);
+    // the raw pass writes float32 into scratch when a blur follows
+    epb_dtype raw_dt = c.blur ? EPB_F32 : ao_dtype;
     if (gdtype == EPB_F32) {
-        if (raw_dt == EPB_F32) launch_raw<float, float>(q, c, depth, normal, hdepth, kernel, noise, raw_dst, s);
-        else launch_raw<float, __half>(q, c, depth, normal, hdepth, kernel, noise, raw_dst, s);
+        if (raw_dt == EPB_F32) go_raw<16, 8, 8, float, float>(c, s);
+        else go_raw<16, 8, 8, float, __half>(c, s);
     } else {
-        if (raw_dt == EPB_F32) launch_raw<__half, float>(q, c, depth, normal, hdepth, kernel, noise, raw_dst, s);
-        else launch_raw<__half, __half>(q, c, depth, normal, hdepth, kernel, noise, raw_dst, s);
+        if (raw_dt == EPB_F32) go_raw<16, 8, 8, __half, float>(c, s);
+        else go_raw<16, 8, 8, __half, __half>(c, s);
     }
-    if (!direct) {
+    if (c.blur) {
+        int tiles = ssao_items(c, kStBlur, 0);
         if (ao_dtype == EPB_F32)
-            hipLaunchKernelGGL(k_ssao_blur<float>, dim3(c.tiles), dim3(kTx * kTy), 0, s, hdepth, raw, q.Wh, q.Hh,
-                               tau, c.tiles_x, c.tiles, (float *)ao_out);
+            hipLaunchKernelGGL(k_ssao_blur<float>, dim3(tiles), dim3(kBlurTx * kBlurTy), 0, s, c, tiles);
         else
-            hipLaunchKernelGGL(k_ssao_blur<__half>, dim3(c.tiles), dim3(kTx * kTy), 0, s, hdepth, raw, q.Wh, q.Hh,
-                               tau, c.tiles_x, c.tiles, (__half *)ao_out);
+            hipLaunchKernelGGL(k_ssao_blur<__half>, dim3(tiles), dim3(kBlurTx * kBlurTy), 0, s, c, tiles);
+    }
+    return hipGetLastError();
+}
+
+// Grid of a batched stage: one block per item, or a persistent grid of
+// blocks_per_cu blocks per CU (at least 8, so that every XCD has a block).
+int batch_grid(int total, int blocks_per_cu) {
+    if (blocks_per_cu <= 0) return total;
+    int g = blocks_per_cu * 256;
+    if (g < 8) g = 8;
+    return total < g ? total : g;
+}
+
+template <int TX, int TY, int KB, typename TG, typename TA>
+static void go_raw_batch(const BatchHeader &h, const void *table, hipStream_t s) {
+    int grid = batch_grid(h.total[kStRaw], h.blocks_per_cu);
+    hipLaunchKernelGGL((k_ssao_raw_batch<TX, TY, KB, TG, TA>), dim3(grid), dim3(TX * TY), 0, s, table);
+}
+
+template <typename TG, typename TA>
+static void pick_raw_batch(const BatchHeader &h, const void *table, hipStream_t s) {
+    int shape = h.ssao_tile, kb = h.ssao_batch;
+    if (shape == 0 && kb == 0) go_raw_batch<16, 8, 8, TG, TA>(h, table, s);
+    else if (shape == 0) go_raw_batch<16, 8, 16, TG, TA>(h, table, s);
+    else if (kb == 0) go_raw_batch<32, 4, 8, TG, TA>(h, table, s);
+    else go_raw_batch<32, 4, 16, TG, TA>(h, table, s);
+}
+
+hipError_t launch_ssao_batch(const BatchHeader &h, const void *table, hipStream_t s) {
+    hipLaunchKernelGGL(k_ssao_prep_batch, dim3(batch_grid(h.total[kStPrep], h.blocks_per_cu)), dim3(kSsaoPrepW), 0,
+                       s, table);
+    epb_dtype raw_dt = h.blur ? EPB_F32 : (epb_dtype)h.ao_dtype;
+    if (h.gdtype == EPB_F32) {
+        if (raw_dt == EPB_F32) pick_raw_batch<float, float>(h, table, s);
+        else pick_raw_batch<float, __half>(h, table, s);
+    } else {
+        if (raw_dt == EPB_F32) pick_raw_batch<__half, float>(h, table, s);
+        else pick_raw_batch<__half, __half>(h, table, s);
+    }
+    if (h.blur) {
+        int grid = batch_grid(h.total[kStBlur], h.blocks_per_cu);
+        if (h.ao_dtype == EPB_F32)
+            hipLaunchKernelGGL(k_ssao_blur_batch<float>, dim3(grid), dim3(kBlurTx * kBlurTy), 0, s, table);
+        else
+            hipLaunchKernelGGL(k_ssao_blur_batch<__half>, dim3(grid), dim3(kBlurTx * kBlurTy), 0, s, table);
     }
     return hipGetLastError();
 }

@@ -30,13 +30,16 @@ EPB_F16 = 1
 EPB_MAX_LIGHTS = 8
 EPB_MAX_SSAO_SAMPLES = 256
 EPB_MAX_BLOOM_LEVELS = 6
+EPB_MAX_BATCH_VIEWS = 4096
 
 EPB_OP_PRECOMPUTE_IBL = 0
 EPB_OP_SSAO = 1
 EPB_OP_BLOOM_TONEMAP = 2
 
 ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
-                "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error")
+                "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
+                "epb_batch_table_bytes", "epb_batch_scratch_bytes", "epb_batch_build",
+                "epb_render_batch")
 
 
 class EpbError(RuntimeError):
@@ -90,10 +93,22 @@ class epb_post_params(C.Structure):
                 ("exposure", C.c_float), ("gamma", C.c_float), ("pyr_dtype", C.c_int)]
 
 
+class epb_view(C.Structure):
+    _fields_ = [("gbuf", epb_gbuffer), ("cam", epb_camera), ("lights", C.c_void_p),
+                ("n_lights", C.c_int32), ("ibl", C.c_void_p), ("env", C.c_void_p),
+                ("ssao", C.c_void_p), ("post", C.c_void_p), ("hdr_dtype", C.c_int),
+                ("ao", C.c_void_p), ("hdr", C.c_void_p), ("ldr", C.c_void_p)]
+
+
+class epb_schedule(C.Structure):
+    _fields_ = [("shade_tile", C.c_int32), ("ssao_tile", C.c_int32), ("ssao_batch", C.c_int32),
+                ("blocks_per_cu", C.c_int32)]
+
+
 STRUCTS = dict(epb_camera=epb_camera, epb_gbuffer=epb_gbuffer, epb_cube=epb_cube,
                epb_ibl_params=epb_ibl_params, epb_ibl_maps=epb_ibl_maps,
                epb_ssao_params=epb_ssao_params, epb_light=epb_light,
-               epb_post_params=epb_post_params)
+               epb_post_params=epb_post_params, epb_view=epb_view, epb_schedule=epb_schedule)
 
 
 def _load() -> C.CDLL:
@@ -120,8 +135,14 @@ def _load() -> C.CDLL:
     lib.epb_status_str.argtypes = [C.c_int]
     lib.epb_status_str.restype = C.c_char_p
     lib.epb_last_hip_error.argtypes = []
+    lib.epb_batch_table_bytes.argtypes = [C.c_int32]
+    lib.epb_batch_table_bytes.restype = C.c_size_t
+    lib.epb_batch_scratch_bytes.argtypes = [P, C.c_int32]
+    lib.epb_batch_scratch_bytes.restype = C.c_size_t
+    lib.epb_batch_build.argtypes = [P, C.c_int32, P, P, C.c_size_t, P, C.c_size_t]
+    lib.epb_render_batch.argtypes = [P, P, P]
     for fn in ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
-               "epb_last_hip_error"):
+               "epb_last_hip_error", "epb_batch_build", "epb_render_batch"):
         getattr(lib, fn).restype = C.c_int
     return lib
 
@@ -197,6 +218,36 @@ def epb_bloom_tonemap(hdr, hdr_dtype: int, width: int, height: int, params: epb_
     st = lib.epb_bloom_tonemap(_ptr(hdr), hdr_dtype, width, height, C.byref(params), _ptr(ldr_out),
                                _ptr(scratch), scratch_bytes, _stream(stream))
     return _check("epb_bloom_tonemap", st, check)
+
+
+def epb_batch_table_bytes(n_views: int) -> int:
+    return lib.epb_batch_table_bytes(n_views)
+
+
+def _views(views) -> C.Array:
+    return (epb_view * len(views))(*views)
+
+
+def epb_batch_scratch_bytes(views: Sequence[epb_view]) -> int:
+    arr = _views(views)
+    return lib.epb_batch_scratch_bytes(C.addressof(arr), len(views))
+
+
+def epb_batch_build(views: Sequence[epb_view], schedule: Optional[epb_schedule], scratch,
+                    scratch_bytes: int, table, table_bytes: int, check: bool = True) -> int:
+    """`table` is a host buffer (a ctypes buffer, a pinned CPU tensor or an int address)."""
+    arr = _views(views)
+    tab = C.addressof(table) if isinstance(table, C.Array) else _ptr(table)
+    st = lib.epb_batch_build(C.addressof(arr), len(views),
+                             C.addressof(schedule) if schedule is not None else None,
+                             _ptr(scratch), scratch_bytes, tab, table_bytes)
+    return _check("epb_batch_build", st, check)
+
+
+def epb_render_batch(table, table_dev, stream=None, check: bool = True) -> int:
+    tab = C.addressof(table) if isinstance(table, C.Array) else _ptr(table)
+    st = lib.epb_render_batch(tab, _ptr(table_dev), _stream(stream))
+    return _check("epb_render_batch", st, check)
 
 
 # ---------------------------------------------------------------------------

@@ -8,6 +8,8 @@ from __future__ import annotations
 
 from typing import List, Optional
 
+import ctypes as C
+
 import numpy as np
 import torch
 
@@ -176,3 +178,61 @@ class DeviceView:
 
     def pyramid(self) -> List[torch.Tensor]:
         return self.postp.pyramid()
+
+    # -- batched form ---------------------------------------------------------
+    def batch_view(self, blur: bool = True, keep_ao: bool = True, keep_hdr: bool = True) -> E.epb_view:
+        """This view as an entry of a batch (outputs into this view's AO, HDR and
+        LDR images; AO or HDR left to batch scratch when not kept)."""
+        self.ssao_params.blur = 1 if blur else 0
+        self._light_arr = (E.epb_light * max(1, len(self.lights)))(*self.lights)
+        v = E.epb_view()
+        v.gbuf = self.gbuf
+        v.cam = self.cam
+        v.lights = C.addressof(self._light_arr) if self.lights else None
+        v.n_lights = len(self.lights)
+        v.ibl = C.addressof(self.ibl.maps)
+        v.env = C.addressof(self.ibl.env_c)
+        v.ssao = C.addressof(self.ssao_params)
+        v.post = C.addressof(self.post)
+        v.hdr_dtype = self.hdr_dtype
+        v.ao = self.ao.data_ptr() if keep_ao else None
+        v.hdr = self.hdr.data_ptr() if keep_hdr else None
+        v.ldr = self.ldr.data_ptr()
+        return v
+
+
+def make_schedule(shade_tile=0, ssao_tile=0, ssao_batch=0, blocks_per_cu=0) -> E.epb_schedule:
+    return E.epb_schedule(shade_tile, ssao_tile, ssao_batch, blocks_per_cu)
+
+
+class DeviceBatch:
+    """Many device views rendered together: one launch per stage for the whole
+    batch.  The batch table is written on the host into pinned memory and
+    copied to the device once; `render` then only enqueues kernels (and can be
+    captured into a HIP graph)."""
+
+    def __init__(self, dviews, schedule: Optional[E.epb_schedule] = None, blur: bool = True,
+                 keep_ao: bool = True, keep_hdr: bool = True, device="cuda"):
+        self.dviews = list(dviews)
+        self.views = [dv.batch_view(blur, keep_ao, keep_hdr) for dv in self.dviews]
+        n = len(self.views)
+        self.scratch_bytes = E.epb_batch_scratch_bytes(self.views)
+        if self.scratch_bytes == 0:
+            raise ValueError("invalid batch")
+        self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
+        self.table_bytes = E.epb_batch_table_bytes(n)
+        self.table_host = torch.empty(self.table_bytes, dtype=torch.uint8, pin_memory=True)
+        self.table_dev = torch.empty(self.table_bytes, dtype=torch.uint8, device=device)
+        self.schedule = schedule if schedule is not None else make_schedule()
+        self.build(self.schedule)
+
+    def build(self, schedule: E.epb_schedule):
+        """(Re)write the table for a schedule and upload it (synchronously)."""
+        self.schedule = schedule
+        E.epb_batch_build(self.views, schedule, self.scratch, self.scratch_bytes,
+                          self.table_host.data_ptr(), self.table_bytes)
+        self.table_dev.copy_(self.table_host)
+        torch.cuda.synchronize()
+
+    def render(self, stream=None):
+        E.epb_render_batch(self.table_host.data_ptr(), self.table_dev, stream)

@@ -188,3 +188,125 @@ def test_precompute_ibl_validation():
     assert call(p=E.epb_ibl_params(8, 16, 16, 3, 0, 16, 64)) == E.EPB_ERR_PARAM
     assert call(n=need - 1) == E.EPB_ERR_SCRATCH
     assert call(sc=FAKE + 8) == E.EPB_ERR_ALIGN
+
+
+# ---------------------------------------------------------------------------
+# batched form: building the table is host work, checked here with fake
+# device addresses (nothing is launched)
+# ---------------------------------------------------------------------------
+def _cdiv(a, b):
+    return -(-a // b)
+
+
+class _Batch:
+    """Host structs of a batch of fake-address views, kept alive together."""
+
+    def __init__(self, sizes, gdtypes=None, blurs=None, levels=6, keep=True):
+        self.env = E.epb_cube(8, 1, FAKE)
+        self.maps = E.epb_ibl_maps(E.epb_cube(4, 1, FAKE), E.epb_cube(8, 3, FAKE), FAKE, 16)
+        self.post = E.epb_post_params(levels, 1.0, 0.04, 1.0, 2.2, E.EPB_F32)
+        self.ssao = []
+        self.lights = (E.epb_light * 1)()
+        self.lights[0].intensity = 1.0
+        self.views = []
+        for k, (w, h) in enumerate(sizes):
+            p = E.epb_ssao_params(16, FAKE, FAKE, 0.5, 0.025, 0.1,
+                                  blurs[k] if blurs else 1, E.EPB_F32)
+            self.ssao.append(p)
+            v = E.epb_view()
+            v.gbuf = _gbuf(w, h, gdtypes[k] if gdtypes else E.EPB_F32)
+            v.cam = _cam(w, h)
+            v.lights = C.addressof(self.lights)
+            v.n_lights = 1
+            v.ibl = C.addressof(self.maps)
+            v.env = C.addressof(self.env)
+            v.ssao = C.addressof(p)
+            v.post = C.addressof(self.post)
+            v.hdr_dtype = E.EPB_F32
+            v.ao = FAKE if keep else None
+            v.hdr = FAKE if keep else None
+            v.ldr = FAKE
+            self.views.append(v)
+        self.arr = (E.epb_view * len(self.views))(*self.views)
+
+    def build(self, n=None, sched=None, sc=FAKE, sc_bytes=None, table_bytes=None):
+        n = len(self.views) if n is None else n
+        tb = E.lib.epb_batch_table_bytes(max(n, 1)) if table_bytes is None else table_bytes
+        self.table = (C.c_uint8 * max(tb, 16))()
+        need = E.lib.epb_batch_scratch_bytes(C.addressof(self.arr), len(self.views))
+        return E.lib.epb_batch_build(C.addressof(self.arr), n, C.addressof(sched) if sched else None,
+                                     sc, need if sc_bytes is None else sc_bytes,
+                                     C.addressof(self.table), tb)
+
+
+def _expected_items(w, h, levels=6):
+    wh, hh = (w + 1) // 2, (h + 1) // 2
+    lw, lh, blur_items = w, h, 0
+    dims = []
+    for _ in range(1, levels):
+        lw, lh = (lw + 1) // 2, (lh + 1) // 2
+        dims.append((lw, lh))
+        blur_items += _cdiv(lw, 32) * _cdiv(lh, 8)
+    down = _cdiv(dims[0][0], 32) * _cdiv(dims[0][1], 32) if dims else 0
+    return [hh * _cdiv(wh, 256), _cdiv(wh, 16) * _cdiv(hh, 8), _cdiv(wh, 16) * _cdiv(hh, 8),
+            _cdiv(w, 32) * _cdiv(h, 8), down, blur_items, _cdiv(w, 32) * _cdiv(h, 8)]
+
+
+def test_batch_sizes():
+    assert E.epb_batch_table_bytes(0) == 0
+    assert E.epb_batch_table_bytes(E.EPB_MAX_BATCH_VIEWS + 1) == 0
+    assert 0 < E.epb_batch_table_bytes(1) < E.epb_batch_table_bytes(256)
+    kept = _Batch([(64, 48), (33, 17)])
+    free = _Batch([(64, 48), (33, 17)], keep=False)
+    a = E.lib.epb_batch_scratch_bytes(C.addressof(kept.arr), 2)
+    b = E.lib.epb_batch_scratch_bytes(C.addressof(free.arr), 2)
+    ssao = sum(E.epb_scratch_bytes(E.EPB_OP_SSAO, w, h) for w, h in ((64, 48), (33, 17)))
+    post = sum(E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, w, h, kept.post) for w, h in ((64, 48), (33, 17)))
+    assert a >= ssao + post
+    # AO and HDR images kept in scratch when the view leaves them NULL
+    assert b >= a + 3 * 4 * (64 * 48 + 33 * 17) + 4 * (32 * 24 + 17 * 9)
+    assert E.lib.epb_batch_scratch_bytes(None, 2) == 0
+    assert E.lib.epb_batch_scratch_bytes(C.addressof(kept.arr), 0) == 0
+
+
+def test_batch_build_table():
+    sizes = [(64, 48), (33, 17), (3, 2), (1920, 1080)]
+    b = _Batch(sizes)
+    assert b.build() == E.EPB_OK
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 19)).contents)
+    assert words[0] == 0x45504231 and words[1] == len(sizes)
+    totals = words[12:19]
+    exp = [sum(col) for col in zip(*[_expected_items(w, h) for w, h in sizes])]
+    assert totals == exp
+
+
+def test_batch_build_validation():
+    b = _Batch([(64, 48), (33, 17)])
+    assert b.build(n=0) == E.EPB_ERR_SIZE
+    assert b.build(sc=None) == E.EPB_ERR_SCRATCH
+    assert b.build(sc_bytes=16) == E.EPB_ERR_SCRATCH
+    assert b.build(sc=FAKE + 4) == E.EPB_ERR_ALIGN
+    assert b.build(table_bytes=64) == E.EPB_ERR_SIZE
+    for bad in (E.epb_schedule(3, 0, 0, 0), E.epb_schedule(0, 2, 0, 0), E.epb_schedule(0, 0, 2, 0),
+                E.epb_schedule(0, 0, 0, 65), E.epb_schedule(-1, 0, 0, 0)):
+        assert b.build(sched=bad) == E.EPB_ERR_PARAM
+    assert b.build(sched=E.epb_schedule(2, 1, 1, 4)) == E.EPB_OK
+    assert _Batch([(64, 48), (33, 17)], gdtypes=[E.EPB_F32, E.EPB_F16]).build() == E.EPB_ERR_DTYPE
+    assert _Batch([(64, 48), (33, 17)], blurs=[1, 0]).build() == E.EPB_ERR_PARAM
+    # a view failing the single-view checks fails the batch with the same status
+    bad = _Batch([(64, 48), (33, 17)])
+    bad.arr[1].gbuf.width = 32
+    assert bad.build() == E.EPB_ERR_SIZE
+    bad = _Batch([(64, 48), (33, 17)])
+    bad.arr[0].ldr = None
+    assert bad.build() == E.EPB_ERR_NULL
+
+
+def test_render_batch_rejects_foreign_tables():
+    junk = (C.c_uint8 * 4096)()
+    assert E.lib.epb_render_batch(C.addressof(junk), FAKE, None) == E.EPB_ERR_PARAM
+    assert E.lib.epb_render_batch(None, FAKE, None) == E.EPB_ERR_NULL
+    b = _Batch([(64, 48)])
+    assert b.build() == E.EPB_OK
+    assert E.lib.epb_render_batch(C.addressof(b.table), None, None) == E.EPB_ERR_NULL
+    assert E.lib.epb_render_batch(C.addressof(b.table), FAKE + 8, None) == E.EPB_ERR_ALIGN

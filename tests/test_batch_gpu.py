@@ -1,0 +1,162 @@
+"""Batched form on the GPU, through the C ABI: views of uneven sizes rendered
+with one launch per stage must equal their single-view renders bitwise (the
+arithmetic of every output value is the same), under every launch schedule,
+eagerly and replayed from a captured HIP graph; batched outputs are also
+checked against the FP64 oracle directly."""
+import copy
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import oracle as O
+from paper_2012_03325_amd import synth
+from tests.parity_util import assert_interval, assert_ldr, log
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2012_03325_amd import frame  # noqa: F401  (loads libepb.so, fails loudly)
+    yield
+    torch.cuda.synchronize()
+
+
+_cache = {}
+
+# (width, height, seed, ssao samples): several tiles with ragged tails, a tiny
+# view, a thin strip and views of different SSAO kernel lengths
+SIZES = [(256, 256, 31, 16), (201, 137, 32, 16), (97, 61, 33, 64), (3, 2, 34, 8),
+         (640, 360, 35, 32), (37, 300, 36, 16), (1000, 9, 37, 8)]
+
+
+def _views():
+    if "views" not in _cache:
+        _cache["views"] = [synth.config_reduced(w, h, seed=s, shadow_size=128, env_size=16, ssao_n=n,
+                                                n_spheres=24, n_lights=1 + s % 3)
+                           for w, h, s, n in SIZES]
+    return [copy.deepcopy(v) for v in _cache["views"]]
+
+
+def _device_views(views, **kw):
+    from paper_2012_03325_amd import frame as fr
+    out = []
+    for v in views:
+        ibl = fr.DeviceIBL(v.env, **v.ibl)
+        ibl.precompute()
+        out.append(fr.DeviceView(v, ibl, **kw))
+    return out
+
+
+def _outputs(dvs):
+    torch.cuda.synchronize()
+    return [(dv.ao.clone(), dv.hdr.clone(), dv.ldr.clone()) for dv in dvs]
+
+
+def _solo(dvs, blur=True):
+    for dv in dvs:
+        dv.ssao(blur=blur)
+        dv.shade()
+        dv.bloom_tonemap()
+    return _outputs(dvs)
+
+
+def _assert_same(a, b, what):
+    for k, (x, y) in enumerate(zip(a, b)):
+        for name, p, q in zip(("AO", "HDR", "LDR"), x, y):
+            assert torch.equal(p, q), f"{what}: view {k} ({SIZES[k][:2]}) {name} differs"
+
+
+SCHEDULES = [(0, 0, 0, 0), (1, 1, 1, 2), (2, 0, 1, 4), (0, 1, 0, 1), (1, 0, 0, 8)]
+
+
+@pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "sched-" + "-".join(map(str, s)))
+def test_batch_equals_solo(sched):
+    from paper_2012_03325_amd import frame as fr
+    dvs = _device_views(_views())
+    log(f"[batch] {len(dvs)} views, schedule {sched}: solo renders")
+    solo = _solo(dvs)
+    for dv in dvs:
+        for t in (dv.ao, dv.hdr, dv.ldr):
+            t.zero_()
+    b = fr.DeviceBatch(dvs, fr.make_schedule(*sched))
+    log(f"[batch] schedule {sched}: batched render")
+    b.render()
+    _assert_same(_outputs(dvs), solo, f"schedule {sched}")
+
+
+def test_batch_fp16_and_unblurred_equal_solo():
+    from paper_2012_03325_amd import epb as E
+    from paper_2012_03325_amd import frame as fr
+    dvs = _device_views(_views(), gdtype=E.EPB_F16, ao_dtype=E.EPB_F16, hdr_dtype=E.EPB_F16)
+    for blur in (True, False):
+        log(f"[batch] FP16 form, blur={blur}")
+        solo = _solo(dvs, blur=blur)
+        b = fr.DeviceBatch(dvs, fr.make_schedule(1, 1, 1, 2), blur=blur)
+        b.render()
+        _assert_same(_outputs(dvs), solo, f"fp16 blur={blur}")
+
+
+def test_batch_scratch_outputs():
+    """AO and HDR left to batch scratch: the LDR images are unchanged."""
+    from paper_2012_03325_amd import frame as fr
+    dvs = _device_views(_views())
+    solo = _solo(dvs)
+    for dv in dvs:
+        dv.ldr.zero_()
+        dv.hdr.fill_(-1.0)
+    b = fr.DeviceBatch(dvs, keep_ao=False, keep_hdr=False)
+    log("[batch] AO and HDR in scratch")
+    b.render()
+    torch.cuda.synchronize()
+    for k, dv in enumerate(dvs):
+        assert torch.equal(dv.ldr, solo[k][2]), k
+        assert (dv.hdr == -1.0).all(), k  # not written
+
+
+def test_batch_graph_replay_equals_eager():
+    from paper_2012_03325_amd import frame as fr
+    dvs = _device_views(_views())
+    b = fr.DeviceBatch(dvs, fr.make_schedule(1, 1, 1, 4))
+    b.render()
+    eager = _outputs(dvs)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        b.render()  # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    log("[graph] capture one batched frame")
+    with torch.cuda.graph(g):
+        b.render()
+    for rep in range(3):
+        for dv in dvs:  # eager work between replays
+            dv.ldr.zero_()
+            dv.hdr.fill_(float(rep))
+            dv.ao.fill_(-1.0)
+        torch.cuda.synchronize()
+        log(f"[graph] replay {rep}")
+        g.replay()
+        _assert_same(_outputs(dvs), eager, f"graph replay {rep}")
+
+
+@pytest.mark.parametrize("k", [2, 3, 6])
+def test_batched_view_oracle_parity(k):
+    """A view rendered inside the batch against the FP64 oracle."""
+    from paper_2012_03325_amd import frame as fr
+    views = _views()
+    dvs = _device_views(views)
+    b = fr.DeviceBatch(dvs, fr.make_schedule(2, 1, 1, 2))
+    b.render()
+    torch.cuda.synchronize()
+    v = views[k]
+    log(f"[batch-oracle] view {k} {v.width}x{v.height}")
+    ref = O.render(v)
+    dv = dvs[k]
+    assert_interval(f"batched view {k} HDR", dv.hdr.cpu().numpy(), *ref["hdr"], min_frac=0.9999)
+    assert_ldr(f"batched view {k} LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
