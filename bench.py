@@ -107,6 +107,136 @@ def hbm_copy_gbps(torch, nbytes=1 << 30, reps=10) -> float:
     return 2 * nbytes / sec / 1e9
 
 
+def frame_algorithmic_bytes(view, half: bool = False) -> int:
+    """Bytes the whole per-frame path must move for one view: SSAO reads depth
+    and normal at the half-resolution points, writes AO and shading reads it
+    back; shading reads the G-buffer (foreground pixels all planes, background
+    pixels only depth) and writes HDR, which the bright pass and the composite
+    read again; bloom levels 1..5 are written, read by the blur, written
+    blurred and read by the composite (four passes over the pyramid texels);
+    the composite writes RGBA8.  IBL tables and cube maps are not included
+    (they are per scene)."""
+    d = view.gbuf["depth"]
+    H, W = d.shape
+    px = W * H
+    fg = int(np.isfinite(d).sum())
+    vb = 2 if half else 4
+    wh, hh = (W + 1) // 2, (H + 1) // 2
+    ssao = wh * hh * (4 + 3 * vb)
+    ao = 2 * wh * hh * vb
+    shade = (4 + 8 * vb) * fg + 4 * (px - fg)
+    hdr = 3 * 3 * vb * px
+    texels, w, h = 0, W, H
+    for _ in range(5):
+        w, h = (w + 1) // 2, (h + 1) // 2
+        texels += w * h
+    bloom = 4 * texels * (8 if half else 16)
+    return ssao + ao + shade + hdr + bloom + 4 * px
+
+
+def bench_batched(args, torch, E, frame, synth) -> dict:
+    """The batched form on 16 scenes / 256 views of uneven resolution: the plain
+    single-view calls over every view (eager, and captured in one graph)
+    against the batched path (one launch per stage, autotuned schedule,
+    graph-captured), in FP32 and in the FP16 storage form."""
+    from paper_2012_03325_amd import autotune
+    t0 = time.time()
+    scenes, views = synth.config_batch()
+    px = sum(v.width * v.height for v in views)
+    log(f"batch inputs: {len(scenes)} scenes, {len(views)} views, {px / 1e6:.1f} Mpx in {time.time() - t0:.1f} s")
+    ibls = [frame.DeviceIBL(sc.env, **sc.ibl) for sc in scenes]
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    for ibl in ibls:
+        ibl.precompute()
+    ev[1].record()
+    torch.cuda.synchronize()
+    ibl_ms = ev[0].elapsed_time(ev[1])
+    res = {"workload": f"{len(scenes)} scenes (64-1024 spheres + plane, own 6x256^2 HDR sky+sun cube), "
+                       f"{len(views)} views drawn from 320x240/640x480/1280x720/1920x1080, orbit cameras; "
+                       "1 point light without depth map, SSAO 16 samples + blur, 6-level bloom",
+           "views": len(views), "Mpx": round(px / 1e6, 3), "ibl_precompute_ms_16_envs": round(ibl_ms, 3)}
+    base = None
+    s = torch.cuda.current_stream()
+    for name, dt in (("fp32", E.EPB_F32), ("fp16", E.EPB_F16)):
+        dvs = [frame.DeviceView(v, ibls[v.scene], gdtype=dt, ao_dtype=dt, hdr_dtype=dt,
+                                solo_scratch=False, src=None if base is None else base[k])
+               for k, v in enumerate(views)]
+        if base is None:
+            base = dvs
+        # plain path: the single-view calls in sequence, sharing one scratch of each kind
+        ss = torch.empty(max(dv.ssao_scratch_bytes for dv in dvs), dtype=torch.uint8, device="cuda")
+        ps = torch.empty(max(dv.postp.scratch_bytes for dv in dvs), dtype=torch.uint8, device="cuda")
+        for dv in dvs:
+            dv.ssao_scratch, dv.postp.scratch = ss, ps
+
+        def plain():
+            for dv in dvs:
+                dv.render()
+
+        def timed(fn, reps):
+            fn()
+            torch.cuda.synchronize()
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(reps + 1)]
+            e[0].record(s)
+            for k in range(reps):
+                fn()
+                e[k + 1].record(s)
+            torch.cuda.synchronize()
+            ms = sorted(e[k].elapsed_time(e[k + 1]) for k in range(reps))
+            return ms[len(ms) // 2], e[0].elapsed_time(e[reps]) / reps
+
+        plain_ms, _ = timed(plain, 3)
+        ref_ldr = [dv.ldr.clone() for dv in dvs]
+        g = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream()
+        side.wait_stream(s)
+        with torch.cuda.stream(side):
+            plain()
+        s.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            plain()
+        plain_graph_ms, _ = timed(g.replay, 5)
+        del g
+        # batched path
+        b = frame.DeviceBatch(dvs)
+        default_ms = autotune.time_render(b, 3)
+        sched, trace = autotune.tune(b, reps=3, use_cache=False)
+        tuned = autotune._as_dict(sched)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.stream(side):
+            b.render(side)
+        s.wait_stream(side)
+        torch.cuda.synchronize()
+        with torch.cuda.graph(g):
+            b.render()
+        for dv in dvs:
+            dv.ldr.zero_()
+        med_ms, mean_ms = timed(g.replay, max(5, args.batch_steps))
+        same = all(torch.equal(dv.ldr, r) for dv, r in zip(dvs, ref_ldr))
+        nbytes = sum(frame_algorithmic_bytes(v, half=(dt == E.EPB_F16)) for v in views)
+        res[name] = {
+            "batched_Mpix_s": round(px / (mean_ms / 1e3) / 1e6, 2),
+            "batched_ms": round(mean_ms, 4), "batched_p50_ms": round(med_ms, 4),
+            "batched_default_schedule_ms": round(default_ms, 4),
+            "schedule": tuned, "autotune_tried": len(trace),
+            "plain_eager_Mpix_s": round(px / (plain_ms / 1e3) / 1e6, 2), "plain_eager_ms": round(plain_ms, 4),
+            "plain_graph_Mpix_s": round(px / (plain_graph_ms / 1e3) / 1e6, 2),
+            "plain_graph_ms": round(plain_graph_ms, 4),
+            "batched_equals_plain_bitwise": bool(same),
+            "algorithmic_GB": round(nbytes / 1e9, 3),
+            "achieved_GBps": round(nbytes / (mean_ms / 1e3) / 1e9, 1),
+        }
+        log(f"batched {name}: {res[name]}")
+        del g, b
+        if name == "fp16":
+            del dvs
+        torch.cuda.empty_cache()
+    return res
+
+
 def cpu_baseline(view, budget_s: float) -> dict:
     """The FP64 oracle on the host cores: whole frames (SSAO, blur, shading,
     bloom + tonemap, without the per-environment precompute) until the time
@@ -142,6 +272,8 @@ def main():
     ap.add_argument("--copies", type=int, default=4, help="rotated input/output copies (MALL)")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-view batched form")
+    ap.add_argument("--batch-steps", type=int, default=10, help="timed replays of the batched frame")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -278,6 +410,8 @@ def main():
             for name, m in res.items()
         },
     }
+    if not args.no_batch:
+        out["batched"] = bench_batched(args, torch, E, frame, synth)
     if not args.no_cpu:
         log("timing the FP64 oracle on the host cores ...")
         out["cpu_baseline"] = cpu_baseline(view, args.cpu_budget)

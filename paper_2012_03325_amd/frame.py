@@ -79,12 +79,13 @@ class DevicePost:
     """Bloom and tone-mapping outputs and scratch for a W x H frame."""
 
     def __init__(self, W: int, H: int, bloom_levels=6, threshold=1.0, strength=0.04,
-                 exposure=1.0, gamma=2.2, device="cuda", pyr_dtype=E.EPB_F32):
+                 exposure=1.0, gamma=2.2, device="cuda", pyr_dtype=E.EPB_F32, scratch=True):
         self.W, self.H = W, H
         self.post = E.epb_post_params(bloom_levels, threshold, strength, exposure, gamma, pyr_dtype)
         self.ldr = torch.empty((H, W, 4), dtype=torch.uint8, device=device)
         self.scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, W, H, self.post)
-        self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
+        self.scratch = (torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
+                        if scratch else None)
 
     def run(self, hdr: torch.Tensor, stream=None):
         hdt = E.EPB_F16 if hdr.dtype == torch.float16 else E.EPB_F32
@@ -105,10 +106,17 @@ class DevicePost:
 
 class DeviceView:
     """One view (G-buffer, camera, lights, SSAO kernel) resident on the device
-    with its AO, HDR and LDR outputs and the scratch of each call."""
+    with its AO, HDR and LDR outputs and the scratch of each call.
+
+    ``solo_scratch=False`` skips the scratch of the single-view calls (views
+    that are only rendered in batches, or that share one scratch buffer:
+    assign ``ssao_scratch`` and ``postp.scratch`` before calling them).
+    ``src`` takes the G-buffer from another device view (converted to
+    ``gdtype`` on the device) instead of uploading it again."""
 
     def __init__(self, view, ibl: DeviceIBL, gdtype=E.EPB_F32, ao_dtype=E.EPB_F32,
-                 hdr_dtype=E.EPB_F32, device="cuda", bloom_levels=6):
+                 hdr_dtype=E.EPB_F32, device="cuda", bloom_levels=6, solo_scratch=True,
+                 src: Optional["DeviceView"] = None):
         self.view = view
         self.ibl = ibl
         self.device = device
@@ -118,12 +126,17 @@ class DeviceView:
         self.gdtype, self.ao_dtype, self.hdr_dtype = gdtype, ao_dtype, hdr_dtype
         g = view.gbuf
         gt = _TORCH_DT[gdtype]
-        dev = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dt)
-        self.depth = dev(g["depth"])
-        self.normal = dev(g["normal"], gt)
-        self.albedo = dev(g["albedo"], gt)
-        self.rough = dev(g["roughness"], gt)
-        self.metal = dev(g["metalness"], gt)
+        dev = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(device).to(dt)
+        if src is None:
+            self.depth = dev(g["depth"])
+            self.normal = dev(g["normal"], gt)
+            self.albedo = dev(g["albedo"], gt)
+            self.rough = dev(g["roughness"], gt)
+            self.metal = dev(g["metalness"], gt)
+        else:
+            self.depth = src.depth
+            self.normal, self.albedo = src.normal.to(gt), src.albedo.to(gt)
+            self.rough, self.metal = src.rough.to(gt), src.metal.to(gt)
         self.kernel = dev(view.ssao_kernel)
         self.noise = dev(view.ssao_noise)
         self.cam = _cam_struct(view.cam)
@@ -148,13 +161,15 @@ class DeviceView:
                 s.shadow_bias = float(L.shadow_bias)
             self.lights.append(s)
         self.postp = DevicePost(W, H, bloom_levels, view.bloom_threshold, view.bloom_strength,
-                                view.exposure, view.gamma, device, pyr_dtype=hdr_dtype)
+                                view.exposure, view.gamma, device, pyr_dtype=hdr_dtype,
+                                scratch=solo_scratch)
         self.post = self.postp.post
         self.ldr = self.postp.ldr
         self.ao = torch.empty((self.Hh, self.Wh), dtype=_TORCH_DT[ao_dtype], device=device)
         self.hdr = torch.empty((3, H, W), dtype=_TORCH_DT[hdr_dtype], device=device)
         self.ssao_scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_SSAO, W, H, self.ssao_params)
-        self.ssao_scratch = torch.empty(self.ssao_scratch_bytes, dtype=torch.uint8, device=device)
+        self.ssao_scratch = (torch.empty(self.ssao_scratch_bytes, dtype=torch.uint8, device=device)
+                             if solo_scratch else None)
 
     # -- the three per-frame calls ------------------------------------------
     def ssao(self, stream=None, blur: bool = True):

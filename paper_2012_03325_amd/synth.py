@@ -26,8 +26,11 @@ Conventions shared with the shading code are *definitions of the data*:
 """
 from __future__ import annotations
 
+import ctypes
 import dataclasses
 import math
+import os
+import subprocess
 from typing import List, Optional
 
 import numpy as np
@@ -142,13 +145,14 @@ def _sphere_bbox(cam: Camera, c: np.ndarray, r: float):
     return (x0, x1, y0, y1)
 
 
-def raycast(scene: SphereScene, cam: Camera, depth_only: bool = False) -> dict:
+def raycast_numpy(scene: SphereScene, cam: Camera, depth_only: bool = False) -> dict:
     """Nearest-hit ray cast of the scene through every pixel of ``cam``.
 
     Returns float32 planes: ``depth`` (H, W) linear view depth or +inf; unless
     ``depth_only``, also ``normal`` and ``albedo`` (3, H, W) and ``roughness``,
     ``metalness`` (H, W).  Spheres are tested in index order and the plane last;
-    an exactly equal hit distance keeps the earlier object."""
+    an exactly equal hit distance keeps the earlier object.  Slow; the same cast
+    as :func:`raycast`, kept as its reference."""
     W, H = cam.width, cam.height
     depth = np.full((H, W), np.inf, np.float64)
     ident = np.full((H, W), -1, np.int32)
@@ -215,6 +219,61 @@ def raycast(scene: SphereScene, cam: Camera, depth_only: bool = False) -> dict:
     metal[ys, xs] = mtl
     out.update(normal=normal.astype(np.float32), albedo=albedo.astype(np.float32),
                roughness=rough.astype(np.float32), metalness=metal.astype(np.float32))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# the same ray cast in C (OpenMP over rows): fast enough for many large views
+# ----------------------------------------------------------------------------
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_RC_SRC = os.path.join(_HERE, "synth_raycast.c")
+_RC_LIB = os.path.join(_HERE, "libsynth.so")
+_rc = None
+
+
+def build_raycaster() -> str:
+    subprocess.run(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared", _RC_SRC,
+                    "-o", _RC_LIB, "-lm"], check=True)
+    return _RC_LIB
+
+
+def _raycaster():
+    global _rc
+    if _rc is None:
+        if not os.path.exists(_RC_LIB) or os.path.getmtime(_RC_LIB) < os.path.getmtime(_RC_SRC):
+            build_raycaster()
+        lib = ctypes.CDLL(_RC_LIB)
+        lib.syn_raycast.restype = None
+        _rc = lib
+    return _rc
+
+
+def raycast(scene: SphereScene, cam: Camera, depth_only: bool = False) -> dict:
+    """Nearest-hit ray cast of the scene through every pixel of ``cam`` (same
+    contract as :func:`raycast_numpy`, computed by the C caster)."""
+    W, H = cam.width, cam.height
+    n = len(scene.radii)
+    bbox = np.zeros((max(n, 1), 4), np.int32)
+    for k in range(n):
+        bb = _sphere_bbox(cam, scene.centers[k], scene.radii[k])
+        bbox[k] = (0, W, 0, H) if bb is None else bb
+    f64 = lambda a: np.ascontiguousarray(a, np.float64)
+    centers, radii = f64(scene.centers.reshape(-1, 3)), f64(scene.radii)
+    alb, rgh, mtl = f64(scene.albedo.reshape(-1, 3)), f64(scene.roughness), f64(scene.metalness)
+    R, o = f64(cam.R), f64(cam.position)
+    depth = np.empty((H, W), np.float32)
+    outs = [None] * 4 if depth_only else [np.empty((3, H, W), np.float32), np.empty((3, H, W), np.float32),
+                                          np.empty((H, W), np.float32), np.empty((H, W), np.float32)]
+    P = lambda a: None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+    d = ctypes.c_double
+    _raycaster().syn_raycast(
+        ctypes.c_int(n), P(centers), P(radii), P(alb), P(rgh), P(mtl), ctypes.c_int(1 if scene.plane else 0),
+        P(f64(scene.plane_albedo)), d(scene.plane_roughness), d(scene.plane_metalness), P(R), P(o),
+        d(cam.fx), d(cam.fy), d(cam.cx), d(cam.cy), ctypes.c_int(W), ctypes.c_int(H), P(bbox), P(depth),
+        *[P(a) for a in outs])
+    out = {"depth": depth}
+    if not depth_only:
+        out.update(normal=outs[0], albedo=outs[1], roughness=outs[2], metalness=outs[3])
     return out
 
 
@@ -344,6 +403,7 @@ class ViewInputs:
     ibl: dict = dataclasses.field(default_factory=lambda: dict(
         irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=1024,
         lut_size=256, lut_samples=1024))
+    scene: int = -1          # index of the shared scene (many-view workloads)
 
     @property
     def width(self) -> int:
@@ -430,3 +490,109 @@ def config_reduced(width: int, height: int, seed: int = 5, shadow_size: int = 25
                pref_levels=min(5, base.bit_length() - 1), lut_size=32, lut_samples=256)
     return make_view(f"reduced-{width}x{height}", width, height, n_spheres, True, seed, n_lights,
                      shadow_size, env_size, "sun", ssao_n, ibl)
+
+
+# ----------------------------------------------------------------------------
+# many views of many scenes (the batched and serving workloads)
+# ----------------------------------------------------------------------------
+BATCH_RESOLUTIONS = ((320, 240), (640, 480), (1280, 720), (1920, 1080))
+SERVING_RESOLUTIONS = ((256, 256), (640, 480), (1920, 1080), (3840, 2160))
+
+
+@dataclasses.dataclass
+class SceneInputs:
+    """A scene shared by many views: spheres on the plane, one white light at
+    (3, 5, 4) without a depth map, its own HDR sky-and-sun cube (seeded sun
+    direction and tints), and the SSAO kernel and noise of its views."""
+    seed: int
+    spheres: SphereScene
+    env: np.ndarray
+    light: Light
+    ssao_kernel: np.ndarray
+    ssao_noise: np.ndarray
+    ibl: dict
+
+
+@dataclasses.dataclass
+class ViewSpec:
+    scene: int
+    cam: Camera
+
+
+def make_scene(seed: int, env_size: int = 256, ssao_n: int = 16, sphere_range=(64, 1024),
+               ibl: Optional[dict] = None) -> SceneInputs:
+    """Sphere count ~ U{lo..hi}; sun azimuth ~ U[0, 360), elevation ~ U[20, 70]
+    degrees; sky tint ~ U[0.6, 1]^3, sun tint ~ U[0.85, 1]^3."""
+    rng = np.random.default_rng(seed)
+    n = int(rng.integers(sphere_range[0], sphere_range[1] + 1))
+    spheres = make_spheres(rng, n, True)
+    az = rng.uniform(0.0, 2.0 * math.pi)
+    el = math.radians(rng.uniform(20.0, 70.0))
+    sun = (math.cos(el) * math.cos(az), math.sin(el), math.cos(el) * math.sin(az))
+    env = env_sky_sun(env_size, sun_dir=sun, sky_tint=tuple(rng.uniform(0.6, 1.0, 3)),
+                      sun_tint=tuple(rng.uniform(0.85, 1.0, 3)))
+    light = Light(np.array([3.0, 5.0, 4.0]), np.array([1.0, 1.0, 1.0]), 1500.0)
+    krng = np.random.default_rng(seed + 10000)
+    kern = ssao_kernel(krng, ssao_n)
+    noise = ssao_noise(krng)
+    base = min(128, env_size)
+    p = dict(irr_size=32, irr_src_size=min(64, env_size), pref_size=base,
+             pref_levels=min(5, base.bit_length() - 1), pref_samples=1024, lut_size=256, lut_samples=1024)
+    if ibl is not None:
+        p.update(ibl)
+    return SceneInputs(seed, spheres, env, light, kern, noise, p)
+
+
+def orbit_camera(rng: np.random.Generator, width: int, height: int) -> Camera:
+    """Camera looking at the origin from azimuth ~ U[0, 360), elevation ~
+    U[15, 45] degrees and distance ~ U[7, 10], vertical field of view 45."""
+    az = rng.uniform(0.0, 2.0 * math.pi)
+    el = math.radians(rng.uniform(15.0, 45.0))
+    dist = rng.uniform(7.0, 10.0)
+    eye = (dist * math.cos(el) * math.cos(az), dist * math.sin(el), dist * math.cos(el) * math.sin(az))
+    return look_at(eye, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, width, height)
+
+
+def view_specs(n_scenes: int, n_views: int, seed: int, resolutions=BATCH_RESOLUTIONS) -> List[ViewSpec]:
+    """View k draws its scene ~ U{n_scenes}, its resolution ~ U(resolutions) and an
+    orbit camera, in that order."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n_views):
+        s = int(rng.integers(0, n_scenes))
+        w, h = resolutions[int(rng.integers(0, len(resolutions)))]
+        out.append(ViewSpec(s, orbit_camera(rng, w, h)))
+    return out
+
+
+def scene_view(scene: SceneInputs, cam: Camera, name: str, gbuf: Optional[dict] = None,
+               index: int = -1) -> ViewInputs:
+    """The inputs of one view of a shared scene (the cube map is shared, not copied)."""
+    if gbuf is None:
+        gbuf = raycast(scene.spheres, cam)
+    v = ViewInputs(name, cam, gbuf, [scene.light], scene.env, scene.ssao_kernel, scene.ssao_noise,
+                   scene=index)
+    v.exposure = 0.012
+    v.ibl = dict(scene.ibl)
+    return v
+
+
+def config_batch(n_scenes: int = 16, n_views: int = 256, scene_seed: int = 100, view_seed: int = 200,
+                 resolutions=BATCH_RESOLUTIONS, env_size: int = 256, ssao_n: int = 16,
+                 sphere_range=(64, 1024), ibl: Optional[dict] = None):
+    """Many views of uneven resolution over shared scenes: scenes from seeds
+    scene_seed + i, views from view_seed.  Returns (scenes, views)."""
+    scenes = [make_scene(scene_seed + i, env_size, ssao_n, sphere_range, ibl) for i in range(n_scenes)]
+    specs = view_specs(n_scenes, n_views, view_seed, resolutions)
+    gbufs = [raycast(scenes[s.scene].spheres, s.cam) for s in specs]
+    views = [scene_view(scenes[s.scene], s.cam, f"view{k}-scene{s.scene}-{s.cam.width}x{s.cam.height}", g,
+                        s.scene) for k, (s, g) in enumerate(zip(specs, gbufs))]
+    return scenes, views
+
+
+def config_batch_small(seed: int = 40):
+    """A reduced batch for parity tests: 3 scenes with 16 - 48 spheres and 16^2
+    cubes, 12 views of ragged sizes."""
+    return config_batch(3, 12, scene_seed=seed, view_seed=seed + 1,
+                        resolutions=((64, 48), (33, 17), (130, 70), (5, 3)), env_size=16,
+                        sphere_range=(16, 48), ibl=dict(pref_samples=128, lut_size=32, lut_samples=128))

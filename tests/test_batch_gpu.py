@@ -160,3 +160,31 @@ def test_batched_view_oracle_parity(k):
     dv = dvs[k]
     assert_interval(f"batched view {k} HDR", dv.hdr.cpu().numpy(), *ref["hdr"], min_frac=0.9999)
     assert_ldr(f"batched view {k} LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
+
+
+def test_autotuned_schedule_equals_default():
+    """The tuner's pick renders the same images as the default schedule, and
+    a second tuning of the same batch signature comes from the cache."""
+    from paper_2012_03325_amd import autotune
+    from paper_2012_03325_amd import frame as fr
+    scenes, views = synth.config_batch_small()
+    ibls = [fr.DeviceIBL(sc.env, **sc.ibl) for sc in scenes]
+    for ibl in ibls:
+        ibl.precompute()
+    dvs = [fr.DeviceView(v, ibls[v.scene], solo_scratch=False) for v in views]
+    b = fr.DeviceBatch(dvs)
+    b.render()
+    default = _outputs(dvs)
+    log(f"[autotune] {len(dvs)} views of {sorted(set((v.width, v.height) for v in views))}")
+    sched, trace = autotune.tune(b, reps=2, passes=1)
+    log(f"[autotune] picked {autotune._as_dict(sched)} after {len(trace)} trials")
+    assert len(trace) >= sum(len(v) for v in autotune.SPACE.values()) - len(autotune.SPACE) + 1
+    for dv in dvs:
+        dv.ldr.zero_()
+    b.render()
+    tuned = _outputs(dvs)
+    for k, (x, y) in enumerate(zip(default, tuned)):
+        for p, q in zip(x, y):
+            assert torch.equal(p, q), k
+    s2, t2 = autotune.tune(b)
+    assert t2[0].get("cached") and autotune._as_dict(s2) == autotune._as_dict(sched)
