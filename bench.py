@@ -237,6 +237,108 @@ def bench_batched(args, torch, E, frame, synth) -> dict:
     return res
 
 
+def bench_serving(args, torch, E, frame, synth, schedule=None) -> dict:
+    """The serving form: 32 resident scenes with FP16 G-buffers at 256^2,
+    640x480, 1920x1080 and 3840x2160 (one pose each) and precomputed IBL;
+    Poisson request streams at swept rates through the continuous-batching
+    server (p50/p99 latency from arrival to the completion event of the
+    request's batch), and a closed-loop saturation run comparing the batched
+    server (FP16 and FP32) with the plain single-view calls (FP32)."""
+    from paper_2012_03325_amd import serve as S
+    t0 = time.time()
+    scenes = [synth.make_scene(300 + i, env_size=256) for i in range(32)]
+    rng = np.random.default_rng(399)
+    views = {}
+    for i, sc in enumerate(scenes):
+        pose = synth.orbit_camera(rng, 8, 8)
+        for w, h in synth.SERVING_RESOLUTIONS:
+            cam = synth.look_at(pose.position, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, w, h)
+            views[(i, (w, h))] = synth.scene_view(sc, cam, f"scene{i}-{w}x{h}", index=i)
+    log(f"serving inputs: 32 scenes x 4 resolutions in {time.time() - t0:.1f} s")
+    rs = S.ResidentScenes(scenes, views, E.EPB_F16, fp32_too=True)
+    del views
+    torch.cuda.synchronize()
+    sched = schedule if schedule is not None else E.epb_schedule(2, 1, 1, 0)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    out = {"workload": "32 resident scenes (64-1024 spheres + plane, own 6x256^2 HDR cube, precomputed IBL), "
+                       "FP16 G-buffers of one pose at 256x256, 640x480, 1920x1080, 3840x2160; Poisson arrivals, "
+                       "scene ~ U{32}, resolution ~ U{4}; 1 light, SSAO 16 + blur, 6-level bloom",
+           "resident_gbuffer_GB": round(rs.gbuffer_bytes() / 1e9, 3), "hbm_budget_GB": args.serve_budget_gb,
+           "schedule": {k: int(getattr(sched, k)) for k in ("shade_tile", "ssao_tile", "ssao_batch",
+                                                             "blocks_per_cu")},
+           "latency": "arrival to the completion event of the request's batch (LDR in HBM)"}
+
+    def server(templates, max_views=64):
+        ex = S.GpuExecutor(templates, schedule=sched, n_streams=2, max_inflight=3, max_batch_views=max_views)
+        return S.Server(ex, budget, max_batch_views=max_views, max_inflight=3)
+
+    rates = []
+    for k, rate in enumerate((50, 100, 200, 500, 1000, 2000)):
+        dur = min(10.0, max(args.serve_seconds, args.serve_min_requests / rate))
+        reqs = S.poisson_arrivals(float(rate), 400 + k, 32, synth.SERVING_RESOLUTIONS, duration=dur)
+        srv = server(rs.templates)
+        st = srv.run(reqs, S.RealClock())
+        srv.pool.clear()
+        rates.append(dict(rate=rate, duration_s=round(dur, 2), requests=st["requests"],
+                          p50_ms=round(st["p50_ms"], 3), p99_ms=round(st["p99_ms"], 3),
+                          mean_ms=round(st["mean_ms"], 3), Mpix_s=round(st["Mpix_s"], 1),
+                          offered_Mpix_s=round(sum(r.px for r in reqs) / dur / 1e6, 1),
+                          mean_batch_views=round(st["mean_batch_views"], 2),
+                          peak_reserved_GB=round(st["peak_reserved_bytes"] / 1e9, 3)))
+        log(f"serving {rate} req/s: {rates[-1]}")
+    out["rates"] = rates
+
+    # closed loop: every request queued at t = 0
+    n_sat = args.serve_saturation
+    sat_reqs = lambda: [S.Request(r.rid, r.scene, r.width, r.height, 0.0)
+                        for r in S.poisson_arrivals(1000.0, 450, 32, synth.SERVING_RESOLUTIONS, count=n_sat)]
+    sat = {}
+    for name, tmpl in (("batched_fp16", rs.templates), ("batched_fp32", None)):
+        if tmpl is None:
+            tmpl = {}
+            for key, dv in rs.dviews32.items():
+                t = dv.batch_view(blur=True, keep_ao=False, keep_hdr=False)
+                t.ldr = None
+                tmpl[key] = t
+        srv = server(tmpl)
+        reqs = sat_reqs()
+        srv.run(reqs[:64], S.RealClock())  # warm-up (slot allocation)
+        srv.pool.clear()
+        srv = server(tmpl)
+        st = srv.run(reqs, S.RealClock())
+        srv.pool.clear()
+        sat[name] = dict(Mpix_s=round(st["Mpix_s"], 1), requests=st["requests"],
+                         p50_ms=round(st["p50_ms"], 2), p99_ms=round(st["p99_ms"], 2),
+                         mean_batch_views=round(st["mean_batch_views"], 2))
+        log(f"saturation {name}: {sat[name]}")
+    # plain: the single-view calls, request after request, FP32 G-buffers
+    outs = {}
+    for (w, h) in synth.SERVING_RESOLUTIONS:
+        outs[(w, h)] = (torch.empty(((h + 1) // 2, (w + 1) // 2), device="cuda"),
+                        torch.empty((3, h, w), device="cuda"),
+                        torch.empty((h, w, 4), dtype=torch.uint8, device="cuda"))
+    ss = torch.empty(max(dv.ssao_scratch_bytes for dv in rs.dviews32.values()), dtype=torch.uint8, device="cuda")
+    ps = torch.empty(max(dv.postp.scratch_bytes for dv in rs.dviews32.values()), dtype=torch.uint8, device="cuda")
+    for key, dv in rs.dviews32.items():
+        dv.ao, dv.hdr, dv.postp.ldr = outs[key[1]]
+        dv.ssao_scratch, dv.postp.scratch = ss, ps
+    reqs = sat_reqs()
+    for r in reqs[:32]:
+        rs.dviews32[(r.scene, r.res)].render()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for r in reqs:
+        rs.dviews32[(r.scene, r.res)].render()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t1
+    sat["plain_fp32"] = dict(Mpix_s=round(sum(r.px for r in reqs) / el / 1e6, 1), requests=len(reqs))
+    log(f"saturation plain_fp32: {sat['plain_fp32']}")
+    out["saturation"] = sat
+    del rs
+    torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(view, budget_s: float) -> dict:
     """The FP64 oracle on the host cores: whole frames (SSAO, blur, shading,
     bloom + tonemap, without the per-environment precompute) until the time
@@ -274,6 +376,11 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-view batched form")
     ap.add_argument("--batch-steps", type=int, default=10, help="timed replays of the batched frame")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving form")
+    ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of arrivals per rate (max 10)")
+    ap.add_argument("--serve-min-requests", type=int, default=200, help="requests per rate at least")
+    ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of request slots")
+    ap.add_argument("--serve-saturation", type=int, default=1000, help="requests of the closed-loop run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
@@ -410,8 +517,14 @@ def main():
             for name, m in res.items()
         },
     }
+    sched = None
     if not args.no_batch:
         out["batched"] = bench_batched(args, torch, E, frame, synth)
+        tuned = out["batched"]["fp16"]["schedule"]
+        sched = E.epb_schedule(tuned["shade_tile"], tuned["ssao_tile"], tuned["ssao_batch"],
+                               tuned["blocks_per_cu"])
+    if not args.no_serve:
+        out["serving"] = bench_serving(args, torch, E, frame, synth, sched)
     if not args.no_cpu:
         log("timing the FP64 oracle on the host cores ...")
         out["cpu_baseline"] = cpu_baseline(view, args.cpu_budget)

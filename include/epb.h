@@ -291,6 +291,9 @@ typedef struct {
     void *ao;                     /* [Hh][Wh] AO output, or NULL: kept in scratch */
     void *hdr;                    /* [3][H][W] HDR output, or NULL: in scratch  */
     uint8_t *ldr;                 /* [H][W][4] RGBA8 output (required)          */
+    void *scratch;                /* this view's own scratch of at least
+                                     epb_view_scratch_bytes(view) bytes, or NULL:
+                                     a region of the batch scratch             */
 } epb_view;
 
 /* Launch shapes of a batch.  They change the speed, never the results: every
@@ -306,9 +309,14 @@ typedef struct {
 /* Bytes of the batch table for n_views views (0 if n_views is out of range). */
 size_t epb_batch_table_bytes(int32_t n_views);
 
-/* Bytes of device scratch a batch of these views needs: per view the SSAO
- * and bloom scratch of the single-view calls, plus AO and HDR images for the
- * views that leave them NULL.  0 for invalid arguments. */
+/* Bytes of device scratch one view needs: the SSAO and bloom scratch of the
+ * single-view calls, plus AO and HDR images when the view leaves them NULL.
+ * 0 for invalid arguments. */
+size_t epb_view_scratch_bytes(const epb_view *view);
+
+/* Bytes of batch scratch a batch of these views needs: the sum of
+ * epb_view_scratch_bytes over the views that bring no scratch of their own
+ * (0 when all do, or for invalid arguments). */
 size_t epb_batch_scratch_bytes(const epb_view *views, int32_t n_views);
 
 /*
@@ -318,7 +326,8 @@ size_t epb_batch_scratch_bytes(const epb_view *views, int32_t n_views);
  *   views     host array; each view is checked as the single-view calls check
  *             their arguments (same status codes)
  *   schedule  launch shapes, or NULL for all zeros
- *   scratch   device buffer of >= epb_batch_scratch_bytes(views, n_views)
+ *   scratch   device buffer of >= epb_batch_scratch_bytes(views, n_views);
+ *             may be NULL when every view brings its own scratch
  *   table     host buffer of >= epb_batch_table_bytes(n_views)
  *
  * All views must share the G-buffer dtype, the AO dtype, the HDR dtype, the

@@ -242,7 +242,7 @@ int batch_scratch(const epb_view *views, int32_t n, size_t *bytes) {
         ViewScratch s;
         int st = view_scratch(views[i], &s);
         if (st) return st;
-        total += s.total;
+        if (!views[i].scratch) total += s.total;
     }
     *bytes = total;
     return EPB_OK;
@@ -349,6 +349,12 @@ size_t epb_batch_table_bytes(int32_t n_views) {
     return epb::batch_table_bytes(n_views);
 }
 
+size_t epb_view_scratch_bytes(const epb_view *view) {
+    ViewScratch s;
+    if (!view || view_scratch(*view, &s) != EPB_OK) return 0;
+    return s.total;
+}
+
 size_t epb_batch_scratch_bytes(const epb_view *views, int32_t n_views) {
     size_t bytes = 0;
     return batch_scratch(views, n_views, &bytes) == EPB_OK ? bytes : 0;
@@ -365,8 +371,8 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
     if (table_bytes < epb::batch_table_bytes(n_views)) return EPB_ERR_SIZE;
     size_t need = 0;
     if ((st = batch_scratch(views, n_views, &need))) return st;
-    if (!scratch || scratch_bytes < need) return EPB_ERR_SCRATCH;
-    if (!aligned16(scratch)) return EPB_ERR_ALIGN;
+    if (need > 0 && (!scratch || scratch_bytes < need)) return EPB_ERR_SCRATCH;
+    if (need > 0 && !aligned16(scratch)) return EPB_ERR_ALIGN;
     const epb_view &v0 = views[0];
     for (int i = 0; i < n_views; ++i) {
         const epb_view &v = views[i];
@@ -384,10 +390,12 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
         const epb_view &v = views[i];
         ViewScratch vs;
         view_scratch(v, &vs);
-        char *s_ssao = sc, *s_post = sc + vs.ssao;
+        if (v.scratch && !aligned16(v.scratch)) return EPB_ERR_ALIGN;
+        char *base = v.scratch ? (char *)v.scratch : sc;
+        if (!v.scratch) sc += vs.total;
+        char *s_ssao = base, *s_post = base + vs.ssao;
         void *ao = v.ao ? v.ao : (void *)(s_post + vs.post);
         void *hdr = v.hdr ? v.hdr : (void *)(s_post + vs.post + vs.ao);
-        sc += vs.total;
         epb::ViewDesc d;
         std::memset(&d, 0, sizeof(d));
         if ((st = build_ssao(&v.gbuf, &v.cam, v.ssao, ao, s_ssao, vs.ssao, &d.ssao))) return st;

@@ -38,7 +38,8 @@ EPB_OP_BLOOM_TONEMAP = 2
 
 ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
                 "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
-                "epb_batch_table_bytes", "epb_batch_scratch_bytes", "epb_batch_build",
+                "epb_batch_table_bytes", "epb_view_scratch_bytes", "epb_batch_scratch_bytes",
+                "epb_batch_build",
                 "epb_render_batch")
 
 
@@ -97,7 +98,8 @@ class epb_view(C.Structure):
     _fields_ = [("gbuf", epb_gbuffer), ("cam", epb_camera), ("lights", C.c_void_p),
                 ("n_lights", C.c_int32), ("ibl", C.c_void_p), ("env", C.c_void_p),
                 ("ssao", C.c_void_p), ("post", C.c_void_p), ("hdr_dtype", C.c_int),
-                ("ao", C.c_void_p), ("hdr", C.c_void_p), ("ldr", C.c_void_p)]
+                ("ao", C.c_void_p), ("hdr", C.c_void_p), ("ldr", C.c_void_p),
+                ("scratch", C.c_void_p)]
 
 
 class epb_schedule(C.Structure):
@@ -137,6 +139,8 @@ def _load() -> C.CDLL:
     lib.epb_last_hip_error.argtypes = []
     lib.epb_batch_table_bytes.argtypes = [C.c_int32]
     lib.epb_batch_table_bytes.restype = C.c_size_t
+    lib.epb_view_scratch_bytes.argtypes = [P]
+    lib.epb_view_scratch_bytes.restype = C.c_size_t
     lib.epb_batch_scratch_bytes.argtypes = [P, C.c_int32]
     lib.epb_batch_scratch_bytes.restype = C.c_size_t
     lib.epb_batch_build.argtypes = [P, C.c_int32, P, P, C.c_size_t, P, C.c_size_t]
@@ -226,6 +230,10 @@ def epb_batch_table_bytes(n_views: int) -> int:
 
 def _views(views) -> C.Array:
     return (epb_view * len(views))(*views)
+
+
+def epb_view_scratch_bytes(view: epb_view) -> int:
+    return lib.epb_view_scratch_bytes(C.addressof(view))
 
 
 def epb_batch_scratch_bytes(views: Sequence[epb_view]) -> int:

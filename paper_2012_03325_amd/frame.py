@@ -79,10 +79,11 @@ class DevicePost:
     """Bloom and tone-mapping outputs and scratch for a W x H frame."""
 
     def __init__(self, W: int, H: int, bloom_levels=6, threshold=1.0, strength=0.04,
-                 exposure=1.0, gamma=2.2, device="cuda", pyr_dtype=E.EPB_F32, scratch=True):
+                 exposure=1.0, gamma=2.2, device="cuda", pyr_dtype=E.EPB_F32, scratch=True,
+                 outputs=True):
         self.W, self.H = W, H
         self.post = E.epb_post_params(bloom_levels, threshold, strength, exposure, gamma, pyr_dtype)
-        self.ldr = torch.empty((H, W, 4), dtype=torch.uint8, device=device)
+        self.ldr = torch.empty((H, W, 4), dtype=torch.uint8, device=device) if outputs else None
         self.scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, W, H, self.post)
         self.scratch = (torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
                         if scratch else None)
@@ -112,11 +113,12 @@ class DeviceView:
     that are only rendered in batches, or that share one scratch buffer:
     assign ``ssao_scratch`` and ``postp.scratch`` before calling them).
     ``src`` takes the G-buffer from another device view (converted to
-    ``gdtype`` on the device) instead of uploading it again."""
+    ``gdtype`` on the device) instead of uploading it again.  ``outputs=False``
+    allocates no AO, HDR or LDR image (views that only serve as templates)."""
 
     def __init__(self, view, ibl: DeviceIBL, gdtype=E.EPB_F32, ao_dtype=E.EPB_F32,
                  hdr_dtype=E.EPB_F32, device="cuda", bloom_levels=6, solo_scratch=True,
-                 src: Optional["DeviceView"] = None):
+                 src: Optional["DeviceView"] = None, outputs: bool = True):
         self.view = view
         self.ibl = ibl
         self.device = device
@@ -162,11 +164,11 @@ class DeviceView:
             self.lights.append(s)
         self.postp = DevicePost(W, H, bloom_levels, view.bloom_threshold, view.bloom_strength,
                                 view.exposure, view.gamma, device, pyr_dtype=hdr_dtype,
-                                scratch=solo_scratch)
+                                scratch=solo_scratch, outputs=outputs)
         self.post = self.postp.post
         self.ldr = self.postp.ldr
-        self.ao = torch.empty((self.Hh, self.Wh), dtype=_TORCH_DT[ao_dtype], device=device)
-        self.hdr = torch.empty((3, H, W), dtype=_TORCH_DT[hdr_dtype], device=device)
+        self.ao = torch.empty((self.Hh, self.Wh), dtype=_TORCH_DT[ao_dtype], device=device) if outputs else None
+        self.hdr = torch.empty((3, H, W), dtype=_TORCH_DT[hdr_dtype], device=device) if outputs else None
         self.ssao_scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_SSAO, W, H, self.ssao_params)
         self.ssao_scratch = (torch.empty(self.ssao_scratch_bytes, dtype=torch.uint8, device=device)
                              if solo_scratch else None)
@@ -210,9 +212,9 @@ class DeviceView:
         v.ssao = C.addressof(self.ssao_params)
         v.post = C.addressof(self.post)
         v.hdr_dtype = self.hdr_dtype
-        v.ao = self.ao.data_ptr() if keep_ao else None
-        v.hdr = self.hdr.data_ptr() if keep_hdr else None
-        v.ldr = self.ldr.data_ptr()
+        v.ao = self.ao.data_ptr() if keep_ao and self.ao is not None else None
+        v.hdr = self.hdr.data_ptr() if keep_hdr and self.hdr is not None else None
+        v.ldr = self.ldr.data_ptr() if self.ldr is not None else None
         return v
 
 

@@ -302,6 +302,21 @@ def test_batch_build_validation():
     assert bad.build() == E.EPB_ERR_NULL
 
 
+def test_views_with_their_own_scratch():
+    b = _Batch([(64, 48), (33, 17)])
+    per = [E.lib.epb_view_scratch_bytes(C.addressof(b.arr[k])) for k in range(2)]
+    assert all(p > 0 for p in per)
+    assert E.lib.epb_batch_scratch_bytes(C.addressof(b.arr), 2) == sum(per)
+    b.arr[0].scratch = FAKE
+    assert E.lib.epb_batch_scratch_bytes(C.addressof(b.arr), 2) == per[1]
+    b.arr[1].scratch = FAKE + 4096
+    assert E.lib.epb_batch_scratch_bytes(C.addressof(b.arr), 2) == 0
+    assert b.build(sc=None, sc_bytes=0) == E.EPB_OK  # no batch scratch needed
+    b.arr[1].scratch = FAKE + 8
+    assert b.build(sc=None, sc_bytes=0) == E.EPB_ERR_ALIGN
+    assert E.lib.epb_view_scratch_bytes(None) == 0
+
+
 def test_render_batch_rejects_foreign_tables():
     junk = (C.c_uint8 * 4096)()
     assert E.lib.epb_render_batch(C.addressof(junk), FAKE, None) == E.EPB_ERR_PARAM
