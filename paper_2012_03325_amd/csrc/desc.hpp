@@ -80,8 +80,9 @@ struct PostDesc {
 // ---------------------------------------------------------------------------
 constexpr int kSsaoPrepW = 256;           // half-resolution texels per prep item
 constexpr int kBlurTx = 16, kBlurTy = 8;  // SSAO blur tile
-constexpr int kPostTx = 32, kPostTy = 8;  // composite and bloom-blur tiles
-constexpr int kDownTile = 32;             // bloom_down: 32x32 level-1 texels (64x64 pixels)
+constexpr int kPostTx = 32, kPostTy = 8;  // composite tile
+constexpr int kBloomTx = 32, kBloomTy = 16;  // bloom-blur tile
+constexpr int kDownTile = 16;             // bloom_down: 16x16 level-1 texels (32x32 pixels)
 
 // Selectable shapes (the schedule picks one per stage).
 struct TileShape {

@@ -2,12 +2,13 @@
 // gamma correction (Sec. 5.4).
 //
 // gfx950 mapping:
-//  * bloom_down: one workgroup per 64x64-pixel tile reads the HDR planes
-//    once, forms the bright map and its 2x2 means, and builds pyramid levels
-//    1..5 of that tile in LDS (a level-1 tile of 32x32 texels halves down to
-//    2x2 at level 5), writing every level once.
-//  * bloom_blur: all levels in one launch; each workgroup stages a 36x12
-//    texel footprint of its 32x8 tile in LDS and applies the separable
+//  * bloom_down: one workgroup per 32x32-pixel tile reads the HDR planes
+//    once (one level-1 texel per thread, its twelve loads in flight together),
+//    forms the bright map and its 2x2 means, and builds pyramid levels 1..5 of
+//    that tile in LDS (16x16 level-1 texels halve down to one at level 5),
+//    writing every level once.
+//  * bloom_blur: all levels in one launch; each workgroup stages the 36x20
+//    texel footprint of its 32x16 tile in LDS and applies the separable
 //    [1 4 6 4 1] / 16 binomial (clamp to edge) horizontally then vertically.
 //  * composite: the footprint of a 32x8 pixel tile on every blurred level
 //    (at most 252 texels) is staged in LDS; each thread adds the bilinearly
@@ -46,13 +47,13 @@ template <> __device__ __forceinline__ Half4 pack<Half4>(float4 v) {
 }
 
 // ---------------------------------------------------------------------------
-// bloom_down: one 32x32 level-1 tile -> levels 1..5 of that tile
+// bloom_down: one 16x16 level-1 tile (32x32 pixels) -> levels 1..5 of that tile
 // ---------------------------------------------------------------------------
 struct DownLds {
-    float4 s1[32][33];
-    float4 s2[16][17];
-    float4 s3[8][9];
-    float4 s4[4][5];
+    float4 s1[16][17];
+    float4 s2[8][9];
+    float4 s3[4][5];
+    float4 s4[2][3];
 };
 
 // Level L texel (lx, ly) of tile (bx, by) as the mean of its in-range
@@ -85,60 +86,72 @@ __device__ __forceinline__ void bloom_down_tile(const PostDesc &c, int tile, Dow
     int t = threadIdx.x;
     const TH *hdr = (const TH *)c.hdr;
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
-    // level 1: bright map averaged over the in-range 2x2 children
-    int lx = t % 32;
+    // level 1, one texel per thread: the bright map averaged over its in-range 2x2 children
+    int lx = t % kDownTile, ly = t / kDownTile;
+    int X = bx * kDownTile + lx, Y = by * kDownTile + ly;
+    float4 v = make_float4(0, 0, 0, 0);
+    if (X < c.lw[1] && Y < c.lh[1]) {
+        float R[4], G[4], B[4];
+        bool in[4];
 #pragma unroll
-    for (int ly = t / 32; ly < 32; ly += 8) {
-        int X = bx * 32 + lx, Y = by * 32 + ly;
-        float4 v = make_float4(0, 0, 0, 0);
-        if (X < c.lw[1] && Y < c.lh[1]) {
-            float n = 0.0f;
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-#pragma unroll
-                for (int a = 0; a < 2; ++a) {
-                    int px = 2 * X + a, py = 2 * Y + b;
-                    if (px < c.W && py < c.H) {
-                        unsigned p = __umul24((unsigned)py, (unsigned)c.W) + (unsigned)px;
-                        float R = ldf(hdr, p), G = ldf(hdr, plane + p), B = ldf(hdr, 2 * plane + p);
-                        float Yl = fmaf(0.2126f, R, fmaf(0.7152f, G, 0.0722f * B));
-                        float sc = Yl > 0.0f ? fmaxf(Yl - c.threshold, 0.0f) / Yl : 0.0f;
-                        v.x = fmaf(R, sc, v.x);
-                        v.y = fmaf(G, sc, v.y);
-                        v.z = fmaf(B, sc, v.z);
-                        n += 1.0f;
-                    }
-                }
-            v = scale4(v, 1.0f / n);
-            ((TP *)c.raw[1])[(size_t)Y * c.lw[1] + X] = pack<TP>(v);
+        for (int k = 0; k < 4; ++k) {  // all twelve loads in flight together
+            int px = 2 * X + (k & 1), py = 2 * Y + (k >> 1);
+            in[k] = px < c.W && py < c.H;
+            unsigned p = in[k] ? __umul24((unsigned)py, (unsigned)c.W) + (unsigned)px : 0u;
+            R[k] = ldf(hdr, p);
+            G[k] = ldf(hdr, plane + p);
+            B[k] = ldf(hdr, 2 * plane + p);
         }
-        sm.s1[ly][lx] = v;
+        float n = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if (!in[k]) continue;
+            float Yl = fmaf(0.2126f, R[k], fmaf(0.7152f, G[k], 0.0722f * B[k]));
+            float sc = Yl > 0.0f ? fmaxf(Yl - c.threshold, 0.0f) / Yl : 0.0f;
+            v.x = fmaf(R[k], sc, v.x);
+            v.y = fmaf(G[k], sc, v.y);
+            v.z = fmaf(B[k], sc, v.z);
+            n += 1.0f;
+        }
+        v = scale4(v, 1.0f / n);
+        ((TP *)c.raw[1])[(size_t)Y * c.lw[1] + X] = pack<TP>(v);
     }
+    sm.s1[ly][lx] = v;
     __syncthreads();
     // levels 2..5 inside the tile (the level count is uniform: barriers are safe)
     if (c.nl >= 2) {
-        down_level<2, 16, TP>(c, bx, by, sm.s1, sm.s2);
+        down_level<2, 8, TP>(c, bx, by, sm.s1, sm.s2);
         __syncthreads();
     }
     if (c.nl >= 3) {
-        down_level<3, 8, TP>(c, bx, by, sm.s2, sm.s3);
+        down_level<3, 4, TP>(c, bx, by, sm.s2, sm.s3);
         __syncthreads();
     }
     if (c.nl >= 4) {
-        down_level<4, 4, TP>(c, bx, by, sm.s3, sm.s4);
+        down_level<4, 2, TP>(c, bx, by, sm.s3, sm.s4);
         __syncthreads();
     }
-    if (c.nl >= 5) down_level<5, 2, TP>(c, bx, by, sm.s4, (float4(*)[5]) nullptr);
+    if (c.nl >= 5) down_level<5, 1, TP>(c, bx, by, sm.s4, (float4(*)[3]) nullptr);
     __syncthreads();  // the next item of a batched launch refills the LDS
 }
 
 // ---------------------------------------------------------------------------
-// bloom_blur: one 32x8 tile of one level
+// bloom_blur: one 32x16 tile of one level
 // ---------------------------------------------------------------------------
-struct BlurLds {
-    float4 in[12][36];
-    float4 h[12][32];
+struct Rgb {
+    float x, y, z;
 };
+constexpr int kBbW = kBloomTx + 4, kBbH = kBloomTy + 4;  // footprint with the 2-texel halo
+struct BlurLds {
+    Rgb in[kBbH][kBbW];
+    Rgb h[kBbH][kBloomTx];
+};
+
+__device__ __forceinline__ Rgb binomial5(Rgb a, Rgb b, Rgb m, Rgb d, Rgb e) {
+    return Rgb{(a.x + e.x + 4.0f * (b.x + d.x) + 6.0f * m.x) * 0.0625f,
+               (a.y + e.y + 4.0f * (b.y + d.y) + 6.0f * m.y) * 0.0625f,
+               (a.z + e.z + 4.0f * (b.z + d.z) + 6.0f * m.z) * 0.0625f};
+}
 
 template <typename TP>
 __device__ __forceinline__ void bloom_blur_item(const PostDesc &c, int item, BlurLds &sm) {
@@ -146,37 +159,33 @@ __device__ __forceinline__ void bloom_blur_item(const PostDesc &c, int item, Blu
     while (L < c.nl && item >= c.blk_start[L + 1]) ++L;
     int local = item - c.blk_start[L];
     int w = c.lw[L], h = c.lh[L];
-    int tx = (w + kPostTx - 1) / kPostTx;
-    int X0 = (local % tx) * kPostTx, Y0 = (local / tx) * kPostTy;
+    int tx = (w + kBloomTx - 1) / kBloomTx;
+    int ty = local / tx;
+    int X0 = (local - ty * tx) * kBloomTx, Y0 = ty * kBloomTy;
     const TP *src = (const TP *)c.raw[L];
     int t = threadIdx.x;
-    for (int q = t; q < 12 * 36; q += 256) {
-        int r = q / 36, cc = q % 36;
+    for (int q = t; q < kBbH * kBbW; q += 256) {  // every load of the footprint in flight together
+        int r = q / kBbW, cc = q - r * kBbW;
         int gy = min(max(Y0 + r - 2, 0), h - 1);
         int gx = min(max(X0 + cc - 2, 0), w - 1);
-        sm.in[r][cc] = unpack(src[(size_t)gy * w + gx]);
+        float4 v = unpack(ldo(src, (__umul24((unsigned)gy, (unsigned)w) + (unsigned)gx) * (unsigned)sizeof(TP)));
+        sm.in[r][cc] = Rgb{v.x, v.y, v.z};
     }
     __syncthreads();
-    for (int q = t; q < 12 * 32; q += 256) {
-        int r = q / 32, cc = q % 32;
-        float4 a = sm.in[r][cc], bb = sm.in[r][cc + 1], m = sm.in[r][cc + 2], d = sm.in[r][cc + 3],
-               e = sm.in[r][cc + 4];
-        sm.h[r][cc] = make_float4((a.x + e.x + 4.0f * (bb.x + d.x) + 6.0f * m.x) * 0.0625f,
-                                  (a.y + e.y + 4.0f * (bb.y + d.y) + 6.0f * m.y) * 0.0625f,
-                                  (a.z + e.z + 4.0f * (bb.z + d.z) + 6.0f * m.z) * 0.0625f, 0.0f);
+    for (int q = t; q < kBbH * kBloomTx; q += 256) {
+        int r = q / kBloomTx, cc = q % kBloomTx;
+        sm.h[r][cc] = binomial5(sm.in[r][cc], sm.in[r][cc + 1], sm.in[r][cc + 2], sm.in[r][cc + 3], sm.in[r][cc + 4]);
     }
     __syncthreads();
-    int ox = t % 32, oy = t / 32;
-    int X = X0 + ox, Y = Y0 + oy;
-    if (X < w && Y < h) {
-        float4 a = sm.h[oy][ox], bb = sm.h[oy + 1][ox], m = sm.h[oy + 2][ox], d = sm.h[oy + 3][ox],
-               e = sm.h[oy + 4][ox];
-        ((TP *)c.blur[L])[(size_t)Y * w + X] =
-            pack<TP>(make_float4((a.x + e.x + 4.0f * (bb.x + d.x) + 6.0f * m.x) * 0.0625f,
-                                 (a.y + e.y + 4.0f * (bb.y + d.y) + 6.0f * m.y) * 0.0625f,
-                                 (a.z + e.z + 4.0f * (bb.z + d.z) + 6.0f * m.z) * 0.0625f, 0.0f));
+    for (int q = t; q < kBloomTy * kBloomTx; q += 256) {
+        int oy = q / kBloomTx, ox = q % kBloomTx;
+        int X = X0 + ox, Y = Y0 + oy;
+        if (X < w && Y < h) {
+            Rgb v = binomial5(sm.h[oy][ox], sm.h[oy + 1][ox], sm.h[oy + 2][ox], sm.h[oy + 3][ox], sm.h[oy + 4][ox]);
+            ((TP *)c.blur[L])[(size_t)Y * w + X] = pack<TP>(make_float4(v.x, v.y, v.z, 0.0f));
+        }
     }
-    __syncthreads();
+    __syncthreads();  // the next item of a batched launch refills the LDS
 }
 
 // ---------------------------------------------------------------------------
@@ -192,9 +201,11 @@ __device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_g
     return (uint32_t)fminf(fmaxf(q, 0.0f), 255.0f);
 }
 
-// Texel footprint of a 32x8 pixel tile on level l (scale 2^-l): from
-// floor((X0 + .5) 2^-l - .5) to floor((X0 + 31.5) 2^-l - .5) + 1, i.e. at most
-// 32 / 2^l + 2 columns and 8 / 2^l + 2 rows (+1 for rounding).
+// Level l samples pixel x at (x + 1/2) 2^-l - 1/2 = v / 2^(l+1) with v = 2x + 1 - 2^l:
+// the texel is v >> (l+1) (an arithmetic shift floors) and the weight is the
+// remainder (v & (2^(l+1) - 1)) / 2^(l+1), exact in float -- the same numbers as
+// the float form, without floor or conversions.  A 32x8 pixel tile reads at
+// most 32 / 2^l + 2 columns and 8 / 2^l + 2 rows of level l (+1 for rounding).
 constexpr int kCompLds = (19 * 7) + (11 * 5) + (7 * 4) + (5 * 4) + (4 * 4);
 
 template <typename TH, typename TP>
@@ -202,37 +213,33 @@ __device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, floa
     int tiles_x = (c.W + kPostTx - 1) / kPostTx;
     int ty = tile / tiles_x;
     int X0 = (tile - ty * tiles_x) * kPostTx, Y0 = ty * kPostTy;
-    int x = X0 + (int)(threadIdx.x % kPostTx);
-    int y = Y0 + (int)(threadIdx.x / kPostTx);
+    int tc = (int)(threadIdx.x % kPostTx), tr = (int)(threadIdx.x / kPostTx);
+    int x = X0 + tc, y = Y0 + tr;
     bool live = x < c.W && y < c.H;
     unsigned p = live ? __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x : 0u;
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
     const TH *hdr = (const TH *)c.hdr;
     // the pixel's HDR first (in flight while the pyramid footprint is staged)
     float R0 = ldf(hdr, p), G0 = ldf(hdr, plane + p), B0 = ldf(hdr, 2 * plane + p);
-    // stage the clamped footprint of every blurred level; a footprint is at
-    // most 19 x 7 texels, one texel per thread (row = thread / 32, col = thread % 32)
-    int base[EPB_MAX_BLOOM_LEVELS], sx0[EPB_MAX_BLOOM_LEVELS], sy0[EPB_MAX_BLOOM_LEVELS],
+    // stage the clamped footprint of every blurred level, one texel per thread
+    int base[EPB_MAX_BLOOM_LEVELS], ax[EPB_MAX_BLOOM_LEVELS], ay[EPB_MAX_BLOOM_LEVELS],
         cols[EPB_MAX_BLOOM_LEVELS];
     int off = 0;
-    int tr = threadIdx.x / 32, tc = threadIdx.x % 32;
 #pragma unroll
     for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
         if (L > c.nl) break;
-        const float sc = 1.0f / (float)(1 << L);
+        const int sh = L + 1, o = 1 - (1 << L);
         int w = c.lw[L], h = c.lh[L];
-        int ax = (int)floorf(fmaf((float)X0 + 0.5f, sc, -0.5f));
-        int ay = (int)floorf(fmaf((float)Y0 + 0.5f, sc, -0.5f));
-        int bx = (int)floorf(fmaf((float)X0 + 31.5f, sc, -0.5f)) + 1;
-        int by = (int)floorf(fmaf((float)Y0 + 7.5f, sc, -0.5f)) + 1;
-        int nc = bx - ax + 1, nr = by - ay + 1;
+        ax[L] = (2 * X0 + o) >> sh;
+        ay[L] = (2 * Y0 + o) >> sh;
+        int nc = ((2 * (X0 + kPostTx - 1) + o) >> sh) + 2 - ax[L];
+        int nr = ((2 * (Y0 + kPostTy - 1) + o) >> sh) + 2 - ay[L];
         if (tc < nc && tr < nr) {
-            int gx = min(max(ax + tc, 0), w - 1), gy = min(max(ay + tr, 0), h - 1);
-            sb[off + tr * nc + tc] = unpack(((const TP *)c.blur[L])[(size_t)gy * w + gx]);
+            int gx = min(max(ax[L] + tc, 0), w - 1), gy = min(max(ay[L] + tr, 0), h - 1);
+            unsigned t = __umul24((unsigned)gy, (unsigned)w) + (unsigned)gx;
+            sb[off + __mul24(tr, nc) + tc] = unpack(ldo((const TP *)c.blur[L], t * (unsigned)sizeof(TP)));
         }
         base[L] = off;
-        sx0[L] = ax;
-        sy0[L] = ay;
         cols[L] = nc;
         off += nc * nr;
     }
@@ -242,12 +249,11 @@ __device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, floa
 #pragma unroll
         for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
             if (L > c.nl) break;
-            const float sc = 1.0f / (float)(1 << L);
-            float fx = fmaf((float)x + 0.5f, sc, -0.5f), fy = fmaf((float)y + 0.5f, sc, -0.5f);
-            float x0f = floorf(fx), y0f = floorf(fy);
-            float wx = fx - x0f, wy = fy - y0f;
-            int lx = (int)x0f - sx0[L], ly = (int)y0f - sy0[L];
-            const float4 *r0 = sb + base[L] + ly * cols[L] + lx;
+            const int sh = L + 1, o = 1 - (1 << L), m = (1 << sh) - 1;
+            const float inv = 1.0f / (float)(1 << sh);
+            int vx = 2 * x + o, vy = 2 * y + o;
+            float wx = (float)(vx & m) * inv, wy = (float)(vy & m) * inv;
+            const float4 *r0 = sb + base[L] + __mul24((vy >> sh) - ay[L], cols[L]) + ((vx >> sh) - ax[L]);
             const float4 *r1 = r0 + cols[L];
             float4 v = lerp4(lerp4(r0[0], r0[1], wx), lerp4(r1[0], r1[1], wx), wy);
             sx += v.x;
@@ -375,7 +381,7 @@ PostDesc post_desc(const PostPlan &q, const void *hdr, float threshold, float st
     int nb = 0;
     for (int l = 1; l <= c.nl; ++l) {
         c.blk_start[l] = nb;
-        nb += ceil_div(c.lw[l], kPostTx) * ceil_div(c.lh[l], kPostTy);
+        nb += ceil_div(c.lw[l], kBloomTx) * ceil_div(c.lh[l], kBloomTy);
     }
     c.blk_start[c.nl + 1] = nb;
     c.threshold = threshold;

@@ -125,18 +125,6 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
         float alpha = r * r, a2 = alpha * alpha;
         float kd = (r + 1.0f) * (r + 1.0f) * 0.125f;
         float gv = fmaf(NoV, 1.0f - kd, kd);
-        // ambient inputs first: their gathers overlap the direct-light math
-        float2 AB = lut_bilinear(c.lut, c.lut_size, c.f_lut, NoV, r);
-        float4 E = cube_bilinear(c.irr, c.irr_size, c.f_irr, n);
-        v3 Rf = n * (2.0f * nv_raw) - V;
-        float lod = fminf(fmaxf(r * c.f_levels1, 0.0f), c.f_levels1);
-        int l0 = (int)lod;
-        int l1 = min(l0 + 1, c.pref_levels - 1);
-        float fl = lod - (float)l0;
-        FaceST fs = cube_face(Rf);
-        int s0 = c.pref_base >> l0, s1 = c.pref_base >> l1;
-        float4 P0 = face_bilinear(c.pref, c.pref_off[l0], s0, (float)s0, fs);
-        float4 P1 = face_bilinear(c.pref, c.pref_off[l1], s1, (float)s1, fs);
         float ao = 1.0f;
         if (c.ao) {
             const TA *aop = (const TA *)c.ao;
@@ -176,6 +164,19 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
                 Lo[ch] = fmaf(f, L.rad[ch] * e, Lo[ch]);
             }
         }
+        // ambient inputs after the light loop: gathered before it, their taps would stay live
+        // through the loop (123 VGPRs, 4 waves/SIMD); here the kernel needs 65 (7 waves/SIMD)
+        float2 AB = lut_bilinear(c.lut, c.lut_size, c.f_lut, NoV, r);
+        float4 E = cube_bilinear(c.irr, c.irr_size, c.f_irr, n);
+        v3 Rf = n * (2.0f * nv_raw) - V;
+        float lod = fminf(fmaxf(r * c.f_levels1, 0.0f), c.f_levels1);
+        int l0 = (int)lod;
+        int l1 = min(l0 + 1, c.pref_levels - 1);
+        float fl = lod - (float)l0;
+        FaceST fs = cube_face(Rf);
+        int s0 = c.pref_base >> l0, s1 = c.pref_base >> l1;
+        float4 P0 = face_bilinear(c.pref, c.pref_off[l0], s0, (float)s0, fs);
+        float4 P1 = face_bilinear(c.pref, c.pref_off[l1], s1, (float)s1, fs);
         float4 P = lerp4(P0, P1, fl);
         float fc5 = pow5(1.0f - NoV);
         float Pc[3] = {P.x, P.y, P.z}, Ec[3] = {E.x, E.y, E.z};

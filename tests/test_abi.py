@@ -246,8 +246,8 @@ def _expected_items(w, h, levels=6):
     for _ in range(1, levels):
         lw, lh = (lw + 1) // 2, (lh + 1) // 2
         dims.append((lw, lh))
-        blur_items += _cdiv(lw, 32) * _cdiv(lh, 8)
-    down = _cdiv(dims[0][0], 32) * _cdiv(dims[0][1], 32) if dims else 0
+        blur_items += _cdiv(lw, 32) * _cdiv(lh, 16)
+    down = _cdiv(dims[0][0], 16) * _cdiv(dims[0][1], 16) if dims else 0
     return [hh * _cdiv(wh, 256), _cdiv(wh, 16) * _cdiv(hh, 8), _cdiv(wh, 16) * _cdiv(hh, 8),
             _cdiv(w, 32) * _cdiv(h, 8), down, blur_items, _cdiv(w, 32) * _cdiv(h, 8)]
 
