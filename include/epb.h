@@ -29,7 +29,7 @@
  *    +X, -X, +Y, -Y, +Z, -Z; texel (i, j) has s = 2 (i + .5) / S - 1,
  *    t = 2 (j + .5) / S - 1 and points along +X (1,-t,-s), -X (-1,-t,s),
  *    +Y (s,1,t), -Y (s,-1,-t), +Z (s,-t,1), -Z (-s,-t,-1).  Lookups pick the
- *    major axis (ties x, then y, then z) and filter bilinearly with
+ *    major axis (ties z, then y, then x) and filter bilinearly with
  *    clamp-to-edge inside the face; every filtered level has faces of at
  *    least 2x2 texels.
  *  - Half resolution is Wh = ceil(W / 2), Hh = ceil(H / 2); half-resolution

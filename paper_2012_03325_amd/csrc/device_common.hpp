@@ -83,34 +83,21 @@ __device__ __forceinline__ v3 mul_Rt(const float *R, v3 v) {
 // cube maps: [face][S][S] float4 texels, faces +X -X +Y -Y +Z -Z
 // ---------------------------------------------------------------------------
 struct FaceST {
-    int face;
+    float face;  // 0 .. 5 (+X, -X, +Y, -Y, +Z, -Z), as the cube instructions return it
     float s, t;  // in [-1, 1] on the face
 };
 
-// Major axis with ties broken x, then y, then z.
+// Face and in-face coordinates of direction d by the CDNA cube instructions:
+// the major axis with ties broken z, then y, then x; a zero component counts
+// as positive; cubesc / cubetc give the OpenGL s and t numerators and cubema
+// twice the signed major component, so s = sc / |major| = sc * (2 / |ma|).
+// Four instructions and no branches (lanes look along different axes).
 __device__ __forceinline__ FaceST cube_face(v3 d) {
-    float ax = fabsf(d.x), ay = fabsf(d.y), az = fabsf(d.z);
     FaceST r;
-    float ma, sc, tc;
-    if (ax >= ay && ax >= az) {
-        ma = ax;
-        r.face = d.x >= 0.0f ? 0 : 1;
-        sc = d.x >= 0.0f ? -d.z : d.z;
-        tc = -d.y;
-    } else if (ay >= az) {
-        ma = ay;
-        r.face = d.y >= 0.0f ? 2 : 3;
-        sc = d.x;
-        tc = d.y >= 0.0f ? d.z : -d.z;
-    } else {
-        ma = az;
-        r.face = d.z >= 0.0f ? 4 : 5;
-        sc = d.z >= 0.0f ? d.x : -d.x;
-        tc = -d.y;
-    }
-    float inv = rcp(ma);
-    r.s = sc * inv;
-    r.t = tc * inv;
+    r.face = __builtin_amdgcn_cubeid(d.x, d.y, d.z);
+    float inv = 2.0f * rcp(fabsf(__builtin_amdgcn_cubema(d.x, d.y, d.z)));  // == rcp(|major|)
+    r.s = __builtin_amdgcn_cubesc(d.x, d.y, d.z) * inv;
+    r.t = __builtin_amdgcn_cubetc(d.x, d.y, d.z) * inv;
     return r;
 }
 
@@ -132,8 +119,8 @@ __device__ __forceinline__ float4 face_bilinear(const float4 *__restrict__ lvl, 
     float y = fminf(fmaxf(fmaf(f.t, half, half - 0.5f), 0.0f), hi);
     float x0f = fminf(floorf(x), hi - 1.0f), y0f = fminf(floorf(y), hi - 1.0f);
     float wx = x - x0f, wy = y - y0f;
-    unsigned idx = off + __umul24(__umul24((unsigned)f.face, (unsigned)S) + (unsigned)y0f, (unsigned)S) +
-                   (unsigned)x0f;
+    // row of the texel in the level: face S + y0, exact in float (below 2^24)
+    unsigned idx = off + __umul24((unsigned)fmaf(f.face, fS, y0f), (unsigned)S) + (unsigned)x0f;
     unsigned o0 = idx * 16u, o1 = o0 + (unsigned)S * 16u;
     float4 a = ldo(lvl, o0), b = ldo(lvl, o0 + 16u);
     float4 c = ldo(lvl, o1), d = ldo(lvl, o1 + 16u);

@@ -75,7 +75,6 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile, const
     float Z0 = -P.z;
     v3 Xv = Mx * ax + Zv * bx, Yv = My * ay + Zv * by;
     float X0 = fmaf(ax, P.x, bx * Z0), Y0 = fmaf(ay, P.y, by * Z0);
-    float fWh = (float)c.Wh, fHh = (float)c.Hh;
     float occ = 0.0f;
     for (int k0 = 0; k0 < c.n; k0 += KB) {
         float ds[KB], zqs[KB];
@@ -88,10 +87,12 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile, const
             float nx = fmaf(Xv.x, sx, fmaf(Xv.y, sy, fmaf(Xv.z, sz, X0)));
             float ny = fmaf(Yv.x, sx, fmaf(Yv.y, sy, fmaf(Yv.z, sz, Y0)));
             float iz = rcp(zq);
-            float hx = nx * iz, hy = ny * iz;
-            ok[b] = (k0 + b < c.n) && zq > 0.0f && hx >= 0.0f && hx < fWh && hy >= 0.0f && hy < fHh;
-            // truncation is floor on the accepted (non-negative) range
-            unsigned idx = ok[b] ? __umul24((unsigned)(int)hy, (unsigned)c.Wh) + (unsigned)(int)hx : 0u;
+            // floor-convert: 0 <= hx < Wh exactly when 0 <= floor(hx) < Wh (one unsigned
+            // compare; NaN and out-of-range values convert outside the range or are
+            // rejected by zq > 0)
+            int ix = (int)floorf(nx * iz), iy = (int)floorf(ny * iz);
+            ok[b] = (k0 + b < c.n) && zq > 0.0f && (unsigned)ix < (unsigned)c.Wh && (unsigned)iy < (unsigned)c.Hh;
+            unsigned idx = ok[b] ? __umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix : 0u;
             ds[b] = ldf(c.hdepth, idx);
             zqs[b] = zq;
         }
