@@ -11,9 +11,10 @@
 //    texel footprint of its 32x16 tile in LDS and applies the separable
 //    [1 4 6 4 1] / 16 binomial (clamp to edge) horizontally then vertically.
 //  * composite: the footprint of a 32x8 pixel tile on every blurred level
-//    (at most 252 texels) is staged in LDS; each thread adds the bilinearly
-//    upsampled levels to its pixel, applies exposure, the ACES fit, gamma and
-//    8-bit rounding, and writes one 32-bit RGBA word.
+//    (at most 252 texels) is staged in LDS and interpolated separably (rows
+//    at the tile's columns, then per pixel between two rows); each thread adds
+//    the upsampled levels to its pixel, applies exposure, the ACES fit, gamma
+//    and 8-bit rounding, and writes one 32-bit RGBA word.
 //  * pyramid texels are float4, or four halves in the FP16 form.
 //  * every stage has a single-view kernel and a batched kernel that walks the
 //    work items of many views.
@@ -206,10 +207,20 @@ __device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_g
 // remainder (v & (2^(l+1) - 1)) / 2^(l+1), exact in float -- the same numbers as
 // the float form, without floor or conversions.  A 32x8 pixel tile reads at
 // most 32 / 2^l + 2 columns and 8 / 2^l + 2 rows of level l (+1 for rounding).
+// The bilinear upsampling is done separably: every footprint row is first
+// interpolated at the tile's 32 pixel columns (one item per thread and level,
+// as a footprint has at most 7 rows), then each pixel interpolates its two rows
+// -- the same two-step lerp per pixel, with the horizontal steps shared by the
+// pixels of a column.
 constexpr int kCompLds = (19 * 7) + (11 * 5) + (7 * 4) + (5 * 4) + (4 * 4);
+constexpr int kCompRows = 7 + 5 + 4 + 4 + 4;
+struct CompLds {
+    float4 tex[kCompLds];            // level footprints
+    float4 row[kCompRows][kPostTx];  // footprint rows interpolated at the tile's columns
+};
 
 template <typename TH, typename TP>
-__device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, float4 *sb) {
+__device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, CompLds &sm) {
     int tiles_x = (c.W + kPostTx - 1) / kPostTx;
     int ty = tile / tiles_x;
     int X0 = (tile - ty * tiles_x) * kPostTx, Y0 = ty * kPostTy;
@@ -222,9 +233,9 @@ __device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, floa
     // the pixel's HDR first (in flight while the pyramid footprint is staged)
     float R0 = ldf(hdr, p), G0 = ldf(hdr, plane + p), B0 = ldf(hdr, 2 * plane + p);
     // stage the clamped footprint of every blurred level, one texel per thread
-    int base[EPB_MAX_BLOOM_LEVELS], ax[EPB_MAX_BLOOM_LEVELS], ay[EPB_MAX_BLOOM_LEVELS],
-        cols[EPB_MAX_BLOOM_LEVELS];
-    int off = 0;
+    int base[EPB_MAX_BLOOM_LEVELS], rbase[EPB_MAX_BLOOM_LEVELS], ax[EPB_MAX_BLOOM_LEVELS],
+        ay[EPB_MAX_BLOOM_LEVELS], cols[EPB_MAX_BLOOM_LEVELS], rows[EPB_MAX_BLOOM_LEVELS];
+    int off = 0, roff = 0;
 #pragma unroll
     for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
         if (L > c.nl) break;
@@ -237,11 +248,28 @@ __device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, floa
         if (tc < nc && tr < nr) {
             int gx = min(max(ax[L] + tc, 0), w - 1), gy = min(max(ay[L] + tr, 0), h - 1);
             unsigned t = __umul24((unsigned)gy, (unsigned)w) + (unsigned)gx;
-            sb[off + __mul24(tr, nc) + tc] = unpack(ldo((const TP *)c.blur[L], t * (unsigned)sizeof(TP)));
+            sm.tex[off + __mul24(tr, nc) + tc] = unpack(ldo((const TP *)c.blur[L], t * (unsigned)sizeof(TP)));
         }
         base[L] = off;
+        rbase[L] = roff;
         cols[L] = nc;
+        rows[L] = nr;
         off += nc * nr;
+        roff += nr;
+    }
+    __syncthreads();
+    // horizontal step: footprint row tr of each level at this thread's column
+#pragma unroll
+    for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
+        if (L > c.nl) break;
+        if (tr < rows[L]) {
+            const int sh = L + 1, o = 1 - (1 << L), m = (1 << sh) - 1;
+            const float inv = 1.0f / (float)(1 << sh);
+            int vx = 2 * x + o;
+            float wx = (float)(vx & m) * inv;
+            const float4 *t0 = sm.tex + base[L] + __mul24(tr, cols[L]) + ((vx >> sh) - ax[L]);
+            sm.row[rbase[L] + tr][tc] = lerp4(t0[0], t0[1], wx);
+        }
     }
     __syncthreads();
     if (live) {
@@ -251,11 +279,10 @@ __device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, floa
             if (L > c.nl) break;
             const int sh = L + 1, o = 1 - (1 << L), m = (1 << sh) - 1;
             const float inv = 1.0f / (float)(1 << sh);
-            int vx = 2 * x + o, vy = 2 * y + o;
-            float wx = (float)(vx & m) * inv, wy = (float)(vy & m) * inv;
-            const float4 *r0 = sb + base[L] + __mul24((vy >> sh) - ay[L], cols[L]) + ((vx >> sh) - ax[L]);
-            const float4 *r1 = r0 + cols[L];
-            float4 v = lerp4(lerp4(r0[0], r0[1], wx), lerp4(r1[0], r1[1], wx), wy);
+            int vy = 2 * y + o;
+            float wy = (float)(vy & m) * inv;
+            int r0 = rbase[L] + ((vy >> sh) - ay[L]);
+            float4 v = lerp4(sm.row[r0][tc], sm.row[r0 + 1][tc], wy);
             sx += v.x;
             sy += v.y;
             sz += v.z;
@@ -287,8 +314,8 @@ __global__ void __launch_bounds__(256) k_bloom_blur(const PostDesc c) {
 
 template <typename TH, typename TP>
 __global__ void __launch_bounds__(256) k_composite(const PostDesc c, int tiles) {
-    __shared__ float4 sb[kCompLds];
-    composite_tile<TH, TP>(c, xcd_tile(blockIdx.x, tiles), sb);
+    __shared__ CompLds sm;
+    composite_tile<TH, TP>(c, xcd_tile(blockIdx.x, tiles), sm);
 }
 
 template <typename TH, typename TP>
@@ -321,7 +348,7 @@ __global__ void __launch_bounds__(256) k_bloom_blur_batch(const void *__restrict
 
 template <typename TH, typename TP>
 __global__ void __launch_bounds__(256) k_composite_batch(const void *__restrict__ table) {
-    __shared__ float4 sb[kCompLds];
+    __shared__ CompLds sm;
     const BatchHeader *h = (const BatchHeader *)table;
     const int *start = batch_start(table, kStComposite);
     const ViewDesc *views = batch_views(table);
@@ -329,7 +356,7 @@ __global__ void __launch_bounds__(256) k_composite_batch(const void *__restrict_
     for (int it = w.lb; it < w.count; it += w.stride) {
         int g = w.first + it;
         int v = find_view(start, h->n_views, g);
-        composite_tile<TH, TP>(views[v].post, g - start[v], sb);
+        composite_tile<TH, TP>(views[v].post, g - start[v], sm);
     }
 }
 
