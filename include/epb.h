@@ -94,15 +94,20 @@ typedef struct {
 } epb_camera;
 
 /* G-buffer (Sec. 4, Tab. 1): depth is always float32 (the paper's R32 target);
- * the attribute planes use `dtype`. */
+ * the attribute planes use `dtype`.  A surfel-splatted G-buffer (Sec. 4.4)
+ * holds accumulated attributes and their accumulated weight: shading first
+ * divides albedo, roughness and metalness by the weight on pixels whose weight
+ * is > 0 (the normal is renormalised anyway, so its division is implied); with
+ * weight == NULL the attributes are used as they are. */
 typedef struct {
     int32_t width, height;
-    epb_dtype dtype;      /* of normal, albedo, roughness, metalness        */
+    epb_dtype dtype;      /* of normal, albedo, roughness, metalness, weight */
     const float *depth;   /* [H][W] linear view depth, +inf = background    */
     const void *normal;   /* [3][H][W] world-space normal                   */
     const void *albedo;   /* [3][H][W] linear base colour in [0, 1]         */
     const void *roughness;/* [H][W] perceptual roughness in (0, 1]          */
     const void *metalness;/* [H][W] in [0, 1]                               */
+    const void *weight;   /* [H][W] accumulated surfel weight, or NULL      */
 } epb_gbuffer;
 
 /* A float32 cube map with `levels` mip levels of sizes size >> m (size <= 4096). */

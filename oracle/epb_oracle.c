@@ -480,6 +480,29 @@ void orc_ssao_blur(const double *raw_lo, const double *raw_hi, const double *dep
 }
 
 /* ------------------------------------------------------------------------ */
+/* surfel G-buffer (Sec. 4.4): overlapping surfels add their attributes and  */
+/* a weight; the compose pass first divides by that weight                   */
+/* ------------------------------------------------------------------------ */
+
+/* Normalises the accumulated normal, albedo, roughness and metalness of every
+ * pixel with weight > 0 by that weight, in place; pixels with weight <= 0 are
+ * left as they are (no surfel covered them). */
+void orc_normalize_gbuffer(const double *weight, int W, int H, double *normal, double *albedo,
+                           double *rough, double *metal) {
+    size_t n = (size_t)W * H;
+    for (size_t p = 0; p < n; ++p) {
+        double w = weight[p];
+        if (!(w > 0.0)) continue;
+        for (int c = 0; c < 3; ++c) {
+            normal[c * n + p] /= w;
+            albedo[c * n + p] /= w;
+        }
+        rough[p] /= w;
+        metal[p] /= w;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* a4: deferred shading (Sec. 3, 3.1, 4, 5.1, 5.4)                           */
 /* ------------------------------------------------------------------------ */
 

@@ -73,6 +73,12 @@ void orc_ssao_blur(const double *raw_lo, const double *raw_hi, const double *dep
                    int H, double tau, double *lo, double *hi);
 
 /* a4 shading */
+/* Surfel G-buffer (Sec. 4.4): divides the accumulated normal, albedo,
+ * roughness and metalness by the accumulated weight (pixels with weight > 0),
+ * in place; the shading step then proceeds as for any G-buffer. */
+void orc_normalize_gbuffer(const double *weight, int W, int H, double *normal, double *albedo,
+                           double *rough, double *metal);
+
 void orc_shade(const double *depth, const double *normal, const double *albedo,
                const double *rough, const double *metal, const orc_camera *cam,
                const double *ao_lo, const double *ao_hi, const orc_light *lights, int n_lights,

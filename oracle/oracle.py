@@ -84,6 +84,7 @@ def lib():
         L.orc_shade.argtypes = [_D, _D, _D, _D, _D, C.POINTER(OrcCamera), _D, _D,
                                 C.POINTER(OrcLight), C.c_int, _D, C.c_int, _D, _D, C.c_int, C.c_int,
                                 _D, C.c_int, _D, C.c_int, C.POINTER(OrcTie), _D, _D]
+        L.orc_normalize_gbuffer.argtypes = [_D, C.c_int, C.c_int, _D, _D, _D, _D]
         L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                         C.c_double, C.c_double, C.POINTER(C.c_uint8), _D, _D]
         _lib = L
@@ -238,12 +239,24 @@ def ssao_blur(raw_lo, raw_hi, depth, tau=0.1) -> Tuple[np.ndarray, np.ndarray]:
 # ---------------------------------------------------------------------------
 # a4: shading
 # ---------------------------------------------------------------------------
+def normalize_gbuffer(weight, normal, albedo, rough, metal) -> None:
+    """Surfel G-buffer normalisation (Sec. 4.4), in place on float64 arrays."""
+    w = _d(weight)
+    H, W = w.shape
+    for a in (normal, albedo, rough, metal):
+        assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    lib().orc_normalize_gbuffer(_p(w), W, H, _p(normal), _p(albedo), _p(rough), _p(metal))
+
+
 def shade(gbuf: dict, cam, ao_lo, ao_hi, lights: Sequence, ibl: dict, env,
           tie=DEFAULT_TIE) -> Tuple[np.ndarray, np.ndarray]:
     depth, normal, albedo = _d(gbuf["depth"]), _d(gbuf["normal"]), _d(gbuf["albedo"])
     rough, metal = _d(gbuf["roughness"]), _d(gbuf["metalness"])
     ao_lo, ao_hi = _d(ao_lo), _d(ao_hi)
     H, W = depth.shape
+    if gbuf.get("weight") is not None:  # surfel G-buffer: normalise first (copies: in place)
+        normal, albedo, rough, metal = (np.array(a, np.float64) for a in (normal, albedo, rough, metal))
+        normalize_gbuffer(gbuf["weight"], normal, albedo, rough, metal)
     keep = []
     arr = (OrcLight * max(1, len(lights)))()
     for k, L in enumerate(lights):

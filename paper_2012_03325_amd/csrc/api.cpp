@@ -53,7 +53,7 @@ int check_gbuffer(const epb_gbuffer *g, const epb_camera *cam) {
     if (g->width != cam->width || g->height != cam->height) return EPB_ERR_SIZE;
     if (!valid_dtype(g->dtype)) return EPB_ERR_DTYPE;
     if (!aligned16(g->depth) || !aligned16(g->normal) || !aligned16(g->albedo) || !aligned16(g->roughness) ||
-        !aligned16(g->metalness))
+        !aligned16(g->metalness) || (g->weight && !aligned16(g->weight)))
         return EPB_ERR_ALIGN;
     return EPB_OK;
 }
@@ -127,6 +127,7 @@ int build_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, 
     epb::ShadeArgs a{};
     a.depth = gbuf->depth;
     a.normal = gbuf->normal; a.albedo = gbuf->albedo; a.rough = gbuf->roughness; a.metal = gbuf->metalness;
+    a.weight = gbuf->weight;
     a.gdtype = gbuf->dtype;
     a.W = cam->width; a.H = cam->height;
     a.cam = host_cam(cam);

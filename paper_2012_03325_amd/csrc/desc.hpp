@@ -49,6 +49,7 @@ struct SsaoDesc {
 struct ShadeDesc {
     const float *depth;
     const void *normal, *albedo, *rough, *metal;
+    const void *weight;  // accumulated surfel weight, or null
     const void *ao;  // may be null
     void *hdr;
     const float4 *irr, *pref, *env;

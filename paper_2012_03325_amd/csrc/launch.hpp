@@ -53,6 +53,7 @@ hipError_t launch_ssao_batch(const BatchHeader &h, const void *table, hipStream_
 struct ShadeArgs {
     const float *depth;
     const void *normal, *albedo, *rough, *metal;
+    const void *weight;  // accumulated surfel weight, or null
     epb_dtype gdtype;
     int W, H;
     HostCam cam;

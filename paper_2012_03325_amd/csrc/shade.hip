@@ -1,4 +1,5 @@
-// Compose pass (paper Sec. 4.2): position from depth (Sec. 4), Cook-Torrance
+// Compose pass (paper Sec. 4.2): surfel G-buffers normalised by their
+// accumulated weight (Sec. 4.4), position from depth (Sec. 4), Cook-Torrance
 // direct lighting in the Unreal Engine 4 variant (Sec. 3) with 3x3
 // percentage-closer shadow tests (Sec. 5.1), split-sum image-based lighting
 // with multiple-scattering compensation (Sec. 3.1) scaled by ambient
@@ -112,6 +113,15 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
         float a[3] = {ldf(alb, p), ldf(alb, plane + p), ldf(alb, 2 * plane + p)};
         float r = ldf((const TG *)c.rough, p);
         float mt = ldf((const TG *)c.metal, p);
+        if (c.weight) {  // surfel G-buffer: accumulated attributes over their weight
+            float w = ldf((const TG *)c.weight, p);
+            if (w > 0.0f) {
+                float iw = rcp(w);
+                a[0] *= iw; a[1] *= iw; a[2] *= iw;
+                r *= iw;
+                mt *= iw;
+            }
+        }
         float nv_raw = dot(n, V);
         float NoV = fminf(fmaxf(nv_raw, 1e-4f), 1.0f);
         float F0[3], cd[3], omF0[3], cdpi[3];
@@ -227,6 +237,7 @@ ShadeDesc shade_desc(const ShadeArgs &a) {
     ShadeDesc k{};
     k.depth = a.depth;
     k.normal = a.normal; k.albedo = a.albedo; k.rough = a.rough; k.metal = a.metal;
+    k.weight = a.weight;
     k.ao = a.ao;
     k.hdr = a.hdr;
     k.irr = (const float4 *)a.irr;

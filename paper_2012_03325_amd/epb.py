@@ -60,7 +60,7 @@ class epb_camera(C.Structure):
 class epb_gbuffer(C.Structure):
     _fields_ = [("width", C.c_int32), ("height", C.c_int32), ("dtype", C.c_int),
                 ("depth", C.c_void_p), ("normal", C.c_void_p), ("albedo", C.c_void_p),
-                ("roughness", C.c_void_p), ("metalness", C.c_void_p)]
+                ("roughness", C.c_void_p), ("metalness", C.c_void_p), ("weight", C.c_void_p)]
 
 
 class epb_cube(C.Structure):

@@ -142,8 +142,12 @@ class DeviceView:
         self.kernel = dev(view.ssao_kernel)
         self.noise = dev(view.ssao_noise)
         self.cam = _cam_struct(view.cam)
+        self.weight = None
+        if g.get("weight") is not None:  # surfel-splatted G-buffer
+            self.weight = dev(g["weight"], gt) if src is None else src.weight.to(gt)
         self.gbuf = E.epb_gbuffer(W, H, gdtype, self.depth.data_ptr(), self.normal.data_ptr(),
-                                  self.albedo.data_ptr(), self.rough.data_ptr(), self.metal.data_ptr())
+                                  self.albedo.data_ptr(), self.rough.data_ptr(), self.metal.data_ptr(),
+                                  self.weight.data_ptr() if self.weight is not None else None)
         self.ssao_params = E.epb_ssao_params(self.kernel.shape[0], self.kernel.data_ptr(),
                                              self.noise.data_ptr(), view.ssao_radius, view.ssao_bias,
                                              view.blur_tau, 1, ao_dtype)

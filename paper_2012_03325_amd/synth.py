@@ -596,3 +596,42 @@ def config_batch_small(seed: int = 40):
     return config_batch(3, 12, scene_seed=seed, view_seed=seed + 1,
                         resolutions=((64, 48), (33, 17), (130, 70), (5, 3)), env_size=16,
                         sphere_range=(16, 48), ibl=dict(pref_samples=128, lut_size=32, lut_samples=128))
+
+
+# ----------------------------------------------------------------------------
+# surfel-splatted G-buffers (accumulated attributes and weights)
+# ----------------------------------------------------------------------------
+def surfel_accumulate(view: ViewInputs, seed: int, max_surfels: int = 4, jitter: float = 0.05) -> ViewInputs:
+    """The view's G-buffer as surfel splatting would leave it: on every surface
+    pixel k ~ U{1..max_surfels} overlapping surfels with splat weights u ~
+    U[0.25, 1] each add u times their own attributes (the pixel's albedo,
+    roughness and metalness scaled by U[1 - jitter, 1 + jitter] and clamped to
+    their ranges, the normal tilted by the same amount) to the accumulated
+    planes, and u to the weight plane.  Background pixels keep weight 0 and zero
+    attributes; depth is unchanged."""
+    import copy
+    rng = np.random.default_rng(seed)
+    g = view.gbuf
+    H, W = g["depth"].shape
+    fg = np.isfinite(g["depth"])
+    k = rng.integers(1, max_surfels + 1, (H, W))
+    wsum = np.zeros((H, W))
+    nsum = np.zeros((3, H, W))
+    asum = np.zeros((3, H, W))
+    rsum = np.zeros((H, W))
+    msum = np.zeros((H, W))
+    for s in range(max_surfels):
+        on = fg & (k > s)
+        u = rng.uniform(0.25, 1.0, (H, W)) * on
+        jit = lambda shape: rng.uniform(1.0 - jitter, 1.0 + jitter, shape)
+        nsum += u * (g["normal"] + rng.uniform(-jitter, jitter, (3, H, W)))
+        asum += u * np.clip(g["albedo"] * jit((3, H, W)), 0.0, 1.0)
+        rsum += u * np.clip(g["roughness"] * jit((H, W)), 0.05, 1.0)
+        msum += u * np.clip(g["metalness"] * jit((H, W)), 0.0, 1.0)
+        wsum += u
+    out = copy.copy(view)
+    out.name = view.name + "-surfels"
+    f32 = lambda a: np.where(fg, a, 0.0).astype(np.float32)
+    out.gbuf = dict(depth=g["depth"], normal=f32(nsum), albedo=f32(asum), roughness=f32(rsum),
+                    metalness=f32(msum), weight=f32(wsum))
+    return out

@@ -36,9 +36,11 @@ SIZES = [(256, 256, 31, 16), (201, 137, 32, 16), (97, 61, 33, 64), (3, 2, 34, 8)
 
 def _views():
     if "views" not in _cache:
-        _cache["views"] = [synth.config_reduced(w, h, seed=s, shadow_size=128, env_size=16, ssao_n=n,
-                                                n_spheres=24, n_lights=1 + s % 3)
-                           for w, h, s, n in SIZES]
+        views = [synth.config_reduced(w, h, seed=s, shadow_size=128, env_size=16, ssao_n=n,
+                                      n_spheres=24, n_lights=1 + s % 3)
+                 for w, h, s, n in SIZES]
+        views[4] = synth.surfel_accumulate(views[4], seed=41)  # one surfel-splatted G-buffer
+        _cache["views"] = views
     return [copy.deepcopy(v) for v in _cache["views"]]
 
 

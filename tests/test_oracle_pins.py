@@ -503,3 +503,47 @@ def test_intervals_are_ordered_on_a_full_scene():
     assert np.isfinite(lo).all() and np.isfinite(hi).all()
     # the ambiguous share stays small
     assert (hi > lo).mean() < 0.5
+
+
+# ---------------------------------------------------------------------------
+# surfel G-buffer normalisation (Sec. 4.4)
+# ---------------------------------------------------------------------------
+def test_normalize_gbuffer_divides_by_the_weight():
+    rng = np.random.default_rng(3)
+    H, W = 5, 7
+    w = rng.uniform(0.25, 4.0, (H, W))
+    w[0, :3] = 0.0   # no surfel: left as it is
+    w[1, 0] = -1.0
+    n, a = rng.uniform(-2, 2, (3, H, W)), rng.uniform(0, 3, (3, H, W))
+    r, m = rng.uniform(0, 3, (H, W)), rng.uniform(0, 3, (H, W))
+    n2, a2, r2, m2 = n.copy(), a.copy(), r.copy(), m.copy()
+    O.normalize_gbuffer(w, n2, a2, r2, m2)
+    pos = w > 0
+    for x, y in ((n, n2), (a, a2)):
+        assert np.array_equal(y[:, pos], x[:, pos] / w[pos])
+        assert np.array_equal(y[:, ~pos], x[:, ~pos])
+    for x, y in ((r, r2), (m, m2)):
+        assert np.array_equal(y[pos], x[pos] / w[pos]) and np.array_equal(y[~pos], x[~pos])
+
+
+def test_surfel_gbuffer_shades_like_its_normalised_attributes():
+    """Accumulated attributes w * a with weight w shade exactly as a (up to the
+    rounding of the division): the normalisation happens before shading, and a
+    scaled normal shades like the unit one."""
+    v = synth.config_reduced(40, 28, seed=12, shadow_size=64, env_size=16, ssao_n=8, n_spheres=12)
+    g = v.gbuf
+    rng = np.random.default_rng(5)
+    fg = np.isfinite(g["depth"])
+    w = np.where(fg, rng.uniform(0.25, 4.0, g["depth"].shape), 0.0)
+    acc = dict(depth=g["depth"], weight=w, normal=g["normal"] * w, albedo=g["albedo"] * w,
+               roughness=g["roughness"] * w, metalness=g["metalness"] * w)
+    ibl = O.precompute_ibl(v.env, **dict(v.ibl, pref_samples=32, lut_size=16, lut_samples=32))
+    ao = np.ones(((v.height + 1) // 2, (v.width + 1) // 2))
+    lo0, hi0 = O.shade(g, v.cam, ao, ao, v.lights, ibl, v.env)
+    lo1, hi1 = O.shade(acc, v.cam, ao, ao, v.lights, ibl, v.env)
+    assert np.allclose(lo1, lo0, rtol=1e-12, atol=1e-12 * np.abs(lo0).max())
+    assert np.allclose(hi1, hi0, rtol=1e-12, atol=1e-12 * np.abs(hi0).max())
+    # a weight of one changes nothing
+    one = dict(g, weight=np.where(fg, 1.0, 0.0))
+    lo2, _ = O.shade(one, v.cam, ao, ao, v.lights, ibl, v.env)
+    assert np.array_equal(lo2, lo0)

@@ -294,8 +294,9 @@ FP16_RTOL = 1e-3 + 2 * 2.0 ** -11
 
 
 def _round_gbuffer_f16(view):
-    for k in ("normal", "albedo", "roughness", "metalness"):
-        view.gbuf[k] = view.gbuf[k].astype(np.float16).astype(np.float32)
+    for k in ("normal", "albedo", "roughness", "metalness", "weight"):
+        if view.gbuf.get(k) is not None:
+            view.gbuf[k] = view.gbuf[k].astype(np.float16).astype(np.float32)
     return view
 
 
@@ -343,3 +344,26 @@ def test_fp16_form_error_against_fp32_inputs():
     assert ao_err.max() < 2e-3
     assert np.percentile(rel, 99) < 1e-2
     assert (dist <= 1).mean() >= 0.999
+
+
+# ---------------------------------------------------------------------------
+# surfel-splatted G-buffer: accumulated attributes in half, divided by the
+# accumulated weight before shading (Sec. 4.4)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("kind,store", [("ragged-201x137", "f32-out"), ("full-1080p", "f32-out"),
+                                        ("ragged-97x61-n64", "f16-out")])
+def test_surfel_gbuffer_parity(kind, store):
+    from paper_2012_03325_amd import epb as E
+    v = _round_gbuffer_f16(synth.surfel_accumulate(_view(kind), seed=77))
+    ref = O.render(v)
+    out = E.EPB_F16 if store == "f16-out" else E.EPB_F32
+    dv = _device_view(v, v.ibl, gdtype=E.EPB_F16, ao_dtype=out, hdr_dtype=out)
+    log(f"[surfel] {kind}: {v.width}x{v.height}, weights {v.gbuf['weight'].max():.2f} max, outputs {store}")
+    dv.render()
+    torch.cuda.synchronize()
+    hdr = dv.hdr.float().cpu().numpy()
+    lo, hi = (np.minimum(x, HALF_MAX) for x in ref["hdr"]) if out == E.EPB_F16 else ref["hdr"]
+    rtol = FP16_RTOL if out == E.EPB_F16 else 1e-3
+    fh = assert_interval(f"{kind} surfel HDR", hdr, lo, hi, rtol=rtol, min_frac=0.9999)
+    frac, exact = assert_ldr(f"{kind} surfel LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
+    log(f"[surfel] {kind}: HDR within {100 * fh:.4f}%, LDR +-1 {100 * frac:.4f}% (exact {100 * exact:.3f}%)")
