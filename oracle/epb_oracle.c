@@ -480,6 +480,75 @@ void orc_ssao_blur(const double *raw_lo, const double *raw_hi, const double *dep
 }
 
 /* ------------------------------------------------------------------------ */
+/* G-buffer and shadow-map pass: nearest-hit ray cast of a sphere field      */
+/* ------------------------------------------------------------------------ */
+
+void orc_raycast(const orc_scene *s, const orc_camera *cam, double rel, double *depth, int32_t *id,
+                 double *normal, double *albedo, double *rough, double *metal, uint8_t *ambiguous) {
+    const int W = cam->width, H = cam->height;
+    const double *M = cam->world_to_cam;
+    double o[3];  /* camera position -R^T t */
+    for (int c = 0; c < 3; ++c) o[c] = -(M[c] * M[3] + M[4 + c] * M[7] + M[8 + c] * M[11]);
+    size_t plane_px = (size_t)W * H;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int y = 0; y < H; ++y) {
+        for (int x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            double v[3] = {(x + 0.5 - cam->cx) / cam->fx, -(y + 0.5 - cam->cy) / cam->fy, -1.0};
+            double d[3];
+            for (int c = 0; c < 3; ++c) d[c] = M[c] * v[0] + M[4 + c] * v[1] + M[8 + c] * v[2];
+            double best = INFINITY;
+            int who = -1, amb = 0;
+            double aa = dot3(d, d);
+            for (int k = 0; k < s->n; ++k) {
+                const double *ck = s->center + 3 * k;
+                double oc[3] = {o[0] - ck[0], o[1] - ck[1], o[2] - ck[2]};
+                double b = dot3(d, oc);
+                double c0 = dot3(oc, oc) - s->radius[k] * s->radius[k];
+                double disc = b * b - aa * c0;
+                if (fabs(disc) <= rel * fmax(b * b, fabs(aa * c0))) amb = 1;  /* grazing */
+                if (disc < 0.0) continue;
+                double t = (-b - sqrt(disc)) / aa;
+                if (!(t > 0.0)) continue;
+                if (fabs(t - best) <= rel * fmin(t, best)) amb = 1;  /* near tie */
+                if (t < best) { best = t; who = k; }
+            }
+            if (s->plane && d[1] < 0.0) {
+                double t = -o[1] / d[1];
+                if (t > 0.0) {
+                    if (fabs(t - best) <= rel * fmin(t, best)) amb = 1;
+                    if (t < best) { best = t; who = s->n; }
+                }
+            }
+            depth[p] = best;
+            id[p] = who;
+            if (ambiguous) ambiguous[p] = (uint8_t)amb;
+            if (!normal) continue;
+            double nr[3] = {0, 0, 0}, al[3] = {0, 0, 0}, rg = 0, mt = 0;
+            if (who >= 0 && who < s->n) {
+                const double *ck = s->center + 3 * who;
+                for (int c = 0; c < 3; ++c) nr[c] = (o[c] + best * d[c] - ck[c]) / s->radius[who];
+                normalize3(nr);
+                for (int c = 0; c < 3; ++c) al[c] = s->albedo[3 * who + c];
+                rg = s->rough[who];
+                mt = s->metal[who];
+            } else if (who == s->n) {
+                nr[1] = 1.0;
+                for (int c = 0; c < 3; ++c) al[c] = s->plane_albedo[c];
+                rg = s->plane_rough;
+                mt = s->plane_metal;
+            }
+            for (int c = 0; c < 3; ++c) {
+                normal[c * plane_px + p] = nr[c];
+                albedo[c * plane_px + p] = al[c];
+            }
+            rough[p] = rg;
+            metal[p] = mt;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
 /* surfel G-buffer (Sec. 4.4): overlapping surfels add their attributes and  */
 /* a weight; the compose pass first divides by that weight                   */
 /* ------------------------------------------------------------------------ */

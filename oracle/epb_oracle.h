@@ -86,6 +86,33 @@ void orc_shade(const double *depth, const double *normal, const double *albedo,
                int pref_base, int pref_levels, const double *lut, int lut_size, const double *env,
                int env_size, const orc_tie *tie, double *hdr_lo, double *hdr_hi);
 
+/* ---- the G-buffer and shadow-map pass on sphere fields (stand-in for the
+ * rasterised geometry pass, Sec. 4, and the depth renders of Sec. 5.1) ---- */
+typedef struct {
+    int32_t n;
+    const double *center;  /* [n][3] */
+    const double *radius;  /* [n] */
+    const double *albedo;  /* [n][3] */
+    const double *rough;   /* [n] */
+    const double *metal;   /* [n] */
+    int32_t plane;         /* 1: the plane y = 0 (normal +y) behind every sphere */
+    double plane_albedo[3], plane_rough, plane_metal;
+} orc_scene;
+
+/* Nearest-hit ray cast of every pixel of cam.  Pixel (x, y) casts o + t d with
+ * o the camera position and d = R^T ((x + .5 - cx) / fx, -(y + .5 - cy) / fy, -1),
+ * so t is the linear view depth.  A sphere is hit at the nearer root of
+ * |o + t d - c| = r when that root is positive; the plane where d.y < 0 at
+ * t = -o.y / d.y > 0.  The nearest hit wins, spheres in index order first and
+ * the plane last, an equal t keeping the earlier object.
+ *   depth [H][W] (+inf: no hit), id [H][W] (-1 none, n = plane);
+ *   normal, albedo [3][H][W], rough, metal [H][W] (NULL: depth and id only);
+ *   ambiguous [H][W] (may be NULL): 1 where the decision is within the tie
+ *   margin -- two candidate hits within rel * t of each other, or a sphere
+ *   whose discriminant is within rel of its terms (a grazing ray). */
+void orc_raycast(const orc_scene *s, const orc_camera *cam, double rel, double *depth, int32_t *id,
+                 double *normal, double *albedo, double *rough, double *metal, uint8_t *ambiguous);
+
 /* a5 / a6 bloom, composite, tonemap.  pyramid (optional) receives the blurred
  * levels 1..levels-1 as planar [3][H_l][W_l] blocks one after another. */
 void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double threshold,

@@ -58,6 +58,13 @@ class OrcLight(C.Structure):
 _D = C.POINTER(C.c_double)
 
 
+class OrcScene(C.Structure):
+    _fields_ = [("n", C.c_int32), ("center", _D), ("radius", _D), ("albedo", _D), ("rough", _D),
+                ("metal", _D), ("plane", C.c_int32), ("plane_albedo", C.c_double * 3),
+                ("plane_rough", C.c_double), ("plane_metal", C.c_double)]
+
+
+
 def lib():
     global _lib
     if _lib is None:
@@ -85,6 +92,8 @@ def lib():
                                 C.POINTER(OrcLight), C.c_int, _D, C.c_int, _D, _D, C.c_int, C.c_int,
                                 _D, C.c_int, _D, C.c_int, C.POINTER(OrcTie), _D, _D]
         L.orc_normalize_gbuffer.argtypes = [_D, C.c_int, C.c_int, _D, _D, _D, _D]
+        L.orc_raycast.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcCamera), C.c_double, _D,
+                                  C.POINTER(C.c_int32), _D, _D, _D, _D, C.POINTER(C.c_uint8)]
         L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                         C.c_double, C.c_double, C.POINTER(C.c_uint8), _D, _D]
         _lib = L
@@ -239,6 +248,40 @@ def ssao_blur(raw_lo, raw_hi, depth, tau=0.1) -> Tuple[np.ndarray, np.ndarray]:
 # ---------------------------------------------------------------------------
 # a4: shading
 # ---------------------------------------------------------------------------
+RAY_TIE_REL = 1e-9
+
+
+def raycast(scene, cam, attributes: bool = True, rel: float = RAY_TIE_REL) -> dict:
+    """Nearest-hit ray cast of a sphere field (and the plane y = 0) through every
+    pixel of ``cam`` in float64 (the step the GPU ray caster performs).  ``scene``
+    has centers (n, 3), radii, albedo (n, 3), roughness, metalness, plane and the
+    plane material.  Returns depth, id, ambiguous and, with ``attributes``, the
+    normal, albedo, roughness and metalness planes."""
+    n = len(scene.radii)
+    cen, rad = _d(np.asarray(scene.centers).reshape(-1, 3)), _d(scene.radii)
+    alb, rgh, mtl = _d(np.asarray(scene.albedo).reshape(-1, 3)), _d(scene.roughness), _d(scene.metalness)
+    sc = OrcScene()
+    sc.n = n
+    sc.center, sc.radius, sc.albedo, sc.rough, sc.metal = _p(cen), _p(rad), _p(alb), _p(rgh), _p(mtl)
+    sc.plane = 1 if scene.plane else 0
+    for c in range(3):
+        sc.plane_albedo[c] = float(scene.plane_albedo[c])
+    sc.plane_rough, sc.plane_metal = float(scene.plane_roughness), float(scene.plane_metalness)
+    W, H = cam.width, cam.height
+    depth = np.empty((H, W))
+    ids = np.empty((H, W), np.int32)
+    amb = np.empty((H, W), np.uint8)
+    out = dict(depth=depth, id=ids, ambiguous=amb)
+    if attributes:
+        out.update(normal=np.empty((3, H, W)), albedo=np.empty((3, H, W)), roughness=np.empty((H, W)),
+                   metalness=np.empty((H, W)))
+    P = lambda k: _p(out[k]) if attributes else C.cast(None, _D)
+    lib().orc_raycast(C.byref(sc), C.byref(_cam(cam)), rel, _p(depth), ids.ctypes.data_as(C.POINTER(C.c_int32)),
+                      P("normal"), P("albedo"), P("roughness"), P("metalness"),
+                      amb.ctypes.data_as(C.POINTER(C.c_uint8)))
+    return out
+
+
 def normalize_gbuffer(weight, normal, albedo, rough, metal) -> None:
     """Surfel G-buffer normalisation (Sec. 4.4), in place on float64 arrays."""
     w = _d(weight)

@@ -547,3 +547,69 @@ def test_surfel_gbuffer_shades_like_its_normalised_attributes():
     one = dict(g, weight=np.where(fg, 1.0, 0.0))
     lo2, _ = O.shade(one, v.cam, ao, ao, v.lights, ibl, v.env)
     assert np.array_equal(lo2, lo0)
+
+
+# ---------------------------------------------------------------------------
+# G-buffer / shadow-map pass: nearest-hit ray cast of a sphere field
+# ---------------------------------------------------------------------------
+def _scene(centers, radii, plane=False):
+    n = len(radii)
+    return synth.SphereScene(np.asarray(centers, np.float64).reshape(n, 3), np.asarray(radii, np.float64),
+                             np.tile([0.2, 0.4, 0.6], (n, 1)) + 0.1 * np.arange(n)[:, None],
+                             np.full(n, 0.5) + 0.01 * np.arange(n), np.zeros(n), plane)
+
+
+def _rays(cam):
+    ys, xs = np.meshgrid(np.arange(cam.height, dtype=np.float64), np.arange(cam.width, dtype=np.float64), indexing="ij")
+    v = np.stack([(xs + 0.5 - cam.cx) / cam.fx, -(ys + 0.5 - cam.cy) / cam.fy, -np.ones_like(xs)], -1)
+    return cam.position, v @ cam.R
+
+
+def test_raycast_single_sphere_closed_forms():
+    cam = synth.look_at((0.0, 0.0, 5.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 40.0, 65, 65)
+    sc = _scene([[0.0, 0.0, 0.0]], [1.0])
+    r = O.raycast(sc, cam)
+    o, d = _rays(cam)
+    # the central ray goes through the centre: depth 5 - 1, normal towards the camera
+    assert r["depth"][32, 32] == pytest.approx(4.0, abs=1e-12)
+    assert np.allclose(r["normal"][:, 32, 32], [0, 0, 1], atol=1e-12)
+    # hit exactly where the ray passes the centre closer than the radius
+    dist = np.linalg.norm(np.cross(d, -o[None, None, :]), axis=-1) / np.linalg.norm(d, axis=-1)
+    ok = r["ambiguous"] == 0
+    assert np.array_equal((dist < 1.0)[ok], np.isfinite(r["depth"])[ok])
+    assert (~ok).sum() < 8
+    # every hit lies on the sphere, on the side facing the camera, with the outward unit normal
+    hit = np.isfinite(r["depth"])
+    p = o + np.where(hit, r["depth"], 0.0)[..., None] * d
+    assert np.allclose(np.linalg.norm(p[hit], axis=-1), 1.0, atol=1e-12)
+    assert (np.einsum("ij,ij->i", d[hit], p[hit]) < 0).all()
+    assert np.allclose(np.moveaxis(r["normal"], 0, -1)[hit], p[hit], atol=1e-12)
+    assert (r["id"][hit] == 0).all() and (r["id"][~hit] == -1).all()
+    assert np.allclose(r["albedo"][:, hit].T, sc.albedo[0]) and np.allclose(r["roughness"][hit], 0.5)
+
+
+def test_raycast_plane_depth_and_background():
+    cam = synth.look_at((0.0, 2.0, 6.0), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 60.0, 40, 30)
+    r = O.raycast(_scene(np.zeros((0, 3)), np.zeros(0), plane=True), cam)
+    o, d = _rays(cam)
+    down = d[..., 1] < 0
+    assert np.array_equal(np.isfinite(r["depth"]), down)
+    assert np.allclose(r["depth"][down], -o[1] / d[..., 1][down], rtol=1e-14)
+    assert (r["id"][down] == 0).all()  # n = 0: the plane's id
+    assert np.allclose(r["normal"][:, down].T, [0, 1, 0])
+
+
+def test_raycast_nearest_hit_and_ties_to_the_lower_index():
+    cam = synth.look_at((0.0, 1.0, 6.0), (0.0, 0.5, 0.0), (0.0, 1.0, 0.0), 50.0, 48, 40)
+    # sphere 1 in front of sphere 0; sphere 2 duplicates sphere 0 exactly (a tie everywhere)
+    sc = _scene([[0.0, 0.5, 0.0], [0.3, 0.5, 1.5], [0.0, 0.5, 0.0]], [0.8, 0.4, 0.8], plane=True)
+    r = O.raycast(sc, cam)
+    both = np.isfinite(r["depth"])
+    alone = [O.raycast(_scene([sc.centers[k]], [sc.radii[k]]), cam)["depth"] for k in range(2)]
+    plane = O.raycast(_scene(np.zeros((0, 3)), np.zeros(0), plane=True), cam)["depth"]
+    nearest = np.minimum(np.minimum(alone[0], alone[1]), plane)
+    assert np.allclose(r["depth"][both], nearest[both], rtol=1e-14)
+    assert not (r["id"] == 2).any()  # the duplicate never wins
+    assert (r["ambiguous"][r["id"] == 0] == 1).all()  # and every pixel it ties on is flagged
+    front = np.isfinite(alone[1]) & (alone[1] < alone[0])
+    assert (r["id"][front] == 1).all()
