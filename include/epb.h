@@ -173,8 +173,29 @@ typedef struct {
     epb_dtype pyr_dtype;  /* storage of the bloom pyramid in scratch            */
 } epb_post_params;
 
+/* A field of spheres with an optional ground plane y = 0: the geometry the
+ * ray caster turns into G-buffers and shadow maps (a stand-in for the paper's
+ * rasterised geometry pass, Sec. 4, and its depth renders from each light,
+ * Sec. 5.1).  Geometry is double precision; materials are float. */
+#define EPB_MAX_SPHERES 65536
+typedef struct {
+    int32_t n;              /* 0 .. EPB_MAX_SPHERES                              */
+    const double *center;   /* device [n][3] (finite)                            */
+    const double *radius;   /* device [n] (> 0)                                  */
+    const float *albedo;    /* device [n][3]                                     */
+    const float *rough;     /* device [n]                                        */
+    const float *metal;     /* device [n]                                        */
+    int32_t plane;          /* 1: the plane y = 0 with normal +y                 */
+    float plane_albedo[3], plane_rough, plane_metal;
+} epb_sphere_scene;
+
 /* Operation ids for epb_scratch_bytes. */
-typedef enum { EPB_OP_PRECOMPUTE_IBL = 0, EPB_OP_SSAO = 1, EPB_OP_BLOOM_TONEMAP = 2 } epb_op;
+typedef enum {
+    EPB_OP_PRECOMPUTE_IBL = 0,
+    EPB_OP_SSAO = 1,
+    EPB_OP_BLOOM_TONEMAP = 2,
+    EPB_OP_RAYCAST = 3 /* params: epb_sphere_scene */
+} epb_op;
 
 /*
  * epb_precompute_ibl -- image-based-lighting tables of one environment
@@ -352,10 +373,34 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
  */
 int epb_render_batch(const void *table, const void *table_dev, hipStream_t stream);
 
+/*
+ * epb_raycast -- G-buffer (or depth map) of a sphere field seen by `cam`: the
+ * pass before shading, on the device, so that a renderer can take new cameras
+ * and re-render shadow maps when lights or objects move.
+ *
+ *   out      destination planes of cam's size; out->depth is required; with
+ *            out->normal == NULL only depth is written (a shadow map), else
+ *            normal, albedo, roughness and metalness too, in out->dtype;
+ *            out->weight must be NULL
+ *   scratch  >= epb_scratch_bytes(EPB_OP_RAYCAST, W, H, scene)
+ *
+ * Pixel (x, y) casts o + t d, o the camera position, d = R^T ((x + .5 - cx) /
+ * fx, -(y + .5 - cy) / fy, -1), so that t is the linear view depth.  A sphere is
+ * hit at the nearer root of |o + t d - c| = r when it is positive; the plane
+ * where d.y < 0 at t = -o.y / d.y > 0.  The nearest hit wins (spheres in index
+ * order, then the plane; an equal t keeps the earlier object); no hit gives
+ * depth +inf and zero attributes.  The normal is the unit (p - c) / r (plane:
+ * +y); albedo, roughness and metalness are the hit object's.  Intersections
+ * are computed in double precision and stored rounded to the destination type.
+ */
+int epb_raycast(const epb_sphere_scene *scene, const epb_camera *cam, const epb_gbuffer *out,
+                void *scratch, size_t scratch_bytes, hipStream_t stream);
+
 /* Bytes of scratch the operation needs for a W x H image (for
  * EPB_OP_PRECOMPUTE_IBL pass the environment size as W and H and an
  * epb_ibl_params; for EPB_OP_SSAO an epb_ssao_params or NULL; for
- * EPB_OP_BLOOM_TONEMAP an epb_post_params).  Returns 0 for invalid arguments. */
+ * EPB_OP_BLOOM_TONEMAP an epb_post_params; for EPB_OP_RAYCAST an
+ * epb_sphere_scene).  Returns 0 for invalid arguments. */
 size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *params);
 
 /* Static description of a status code (never NULL). */

@@ -287,6 +287,12 @@ size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *
     }
     case EPB_OP_SSAO:
         return epb::ssao_plan(width, height).bytes;
+    case EPB_OP_RAYCAST: {
+        if (!params) return 0;
+        const epb_sphere_scene *sc = (const epb_sphere_scene *)params;
+        if (sc->n < 0 || sc->n > EPB_MAX_SPHERES) return 0;
+        return align256((size_t)16 * (sc->n > 0 ? sc->n : 1));
+    }
     case EPB_OP_BLOOM_TONEMAP: {
         if (!params) return 0;
         const epb_post_params *p = (const epb_post_params *)params;
@@ -359,6 +365,52 @@ size_t epb_view_scratch_bytes(const epb_view *view) {
 size_t epb_batch_scratch_bytes(const epb_view *views, int32_t n_views) {
     size_t bytes = 0;
     return batch_scratch(views, n_views, &bytes) == EPB_OK ? bytes : 0;
+}
+
+int epb_raycast(const epb_sphere_scene *scene, const epb_camera *cam, const epb_gbuffer *out, void *scratch,
+                size_t scratch_bytes, hipStream_t stream) {
+    if (!scene || !cam || !out || !out->depth) return EPB_ERR_NULL;
+    int st = check_camera(cam);
+    if (st) return st;
+    if (out->width != cam->width || out->height != cam->height) return EPB_ERR_SIZE;
+    if (scene->n < 0 || scene->n > EPB_MAX_SPHERES) return EPB_ERR_SIZE;
+    if (scene->n > 0 && (!scene->center || !scene->radius || !scene->albedo || !scene->rough || !scene->metal))
+        return EPB_ERR_NULL;
+    if (scene->n > 0 && (!aligned16(scene->center) || !aligned16(scene->radius) || !aligned16(scene->albedo) ||
+                         !aligned16(scene->rough) || !aligned16(scene->metal)))
+        return EPB_ERR_ALIGN;
+    for (float v : scene->plane_albedo)
+        if (!finite(v)) return EPB_ERR_PARAM;
+    if (!finite(scene->plane_rough) || !finite(scene->plane_metal)) return EPB_ERR_PARAM;
+    if (out->weight) return EPB_ERR_PARAM;
+    bool attrs = out->normal != nullptr;
+    if (attrs && (!out->albedo || !out->roughness || !out->metalness)) return EPB_ERR_NULL;
+    if (attrs && !valid_dtype(out->dtype)) return EPB_ERR_DTYPE;
+    if (!aligned16(out->depth) ||
+        (attrs && (!aligned16(out->normal) || !aligned16(out->albedo) || !aligned16(out->roughness) ||
+                   !aligned16(out->metalness))))
+        return EPB_ERR_ALIGN;
+    size_t need = align256((size_t)16 * (scene->n > 0 ? scene->n : 1));
+    if (!scratch || scratch_bytes < need) return EPB_ERR_SCRATCH;
+    if (!aligned16(scratch)) return EPB_ERR_ALIGN;
+    epb::RayScene s{};
+    s.n = scene->n;
+    s.center = scene->center; s.radius = scene->radius;
+    s.albedo = scene->albedo; s.rough = scene->rough; s.metal = scene->metal;
+    s.plane = scene->plane ? 1 : 0;
+    for (int k = 0; k < 3; ++k) s.plane_albedo[k] = scene->plane_albedo[k];
+    s.plane_rough = scene->plane_rough; s.plane_metal = scene->plane_metal;
+    epb::RayCam c{};
+    for (int k = 0; k < 12; ++k) c.M[k] = cam->world_to_cam[k];
+    c.fx = cam->fx; c.fy = cam->fy; c.cx = cam->cx; c.cy = cam->cy;
+    c.W = cam->width; c.H = cam->height;
+    epb::RayOut o{};
+    o.depth = (float *)out->depth;
+    if (attrs) {
+        o.normal = (void *)out->normal; o.albedo = (void *)out->albedo;
+        o.rough = (void *)out->roughness; o.metal = (void *)out->metalness;
+    }
+    return hip_status(epb::launch_raycast(s, c, o, attrs ? out->dtype : EPB_F32, scratch, stream));
 }
 
 int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *schedule, void *scratch,

@@ -76,6 +76,24 @@ struct PostDesc {
     uint32_t *ldr;
 };
 
+// Ray-cast pass: sphere field, double-precision camera, destination planes.
+struct RayScene {
+    int n;
+    const double *center, *radius;
+    const float *albedo, *rough, *metal;
+    int plane;
+    float plane_albedo[3], plane_rough, plane_metal;
+};
+struct RayCam {
+    double M[12];  // row-major [R | t]
+    double fx, fy, cx, cy;
+    int W, H;
+};
+struct RayOut {
+    float *depth;
+    void *normal, *albedo, *rough, *metal;  // null normal: depth only
+};
+
 // ---------------------------------------------------------------------------
 // tile shapes
 // ---------------------------------------------------------------------------

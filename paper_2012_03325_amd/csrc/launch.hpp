@@ -94,4 +94,8 @@ int post_items(const PostDesc &c, int stage);
 hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s);
 hipError_t launch_post_batch(const BatchHeader &h, const void *table, hipStream_t s);
 
+// ---- ray-cast G-buffers and depth maps (raycast.hip) ------------------------
+hipError_t launch_raycast(const RayScene &s, const RayCam &c, const RayOut &out, epb_dtype dtype, void *scratch,
+                          hipStream_t st);
+
 }  // namespace epb

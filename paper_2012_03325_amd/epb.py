@@ -35,12 +35,14 @@ EPB_MAX_BATCH_VIEWS = 4096
 EPB_OP_PRECOMPUTE_IBL = 0
 EPB_OP_SSAO = 1
 EPB_OP_BLOOM_TONEMAP = 2
+EPB_OP_RAYCAST = 3
+EPB_MAX_SPHERES = 65536
 
 ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
                 "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
                 "epb_batch_table_bytes", "epb_view_scratch_bytes", "epb_batch_scratch_bytes",
                 "epb_batch_build",
-                "epb_render_batch")
+                "epb_render_batch", "epb_raycast")
 
 
 class EpbError(RuntimeError):
@@ -94,6 +96,12 @@ class epb_post_params(C.Structure):
                 ("exposure", C.c_float), ("gamma", C.c_float), ("pyr_dtype", C.c_int)]
 
 
+class epb_sphere_scene(C.Structure):
+    _fields_ = [("n", C.c_int32), ("center", C.c_void_p), ("radius", C.c_void_p), ("albedo", C.c_void_p),
+                ("rough", C.c_void_p), ("metal", C.c_void_p), ("plane", C.c_int32),
+                ("plane_albedo", C.c_float * 3), ("plane_rough", C.c_float), ("plane_metal", C.c_float)]
+
+
 class epb_view(C.Structure):
     _fields_ = [("gbuf", epb_gbuffer), ("cam", epb_camera), ("lights", C.c_void_p),
                 ("n_lights", C.c_int32), ("ibl", C.c_void_p), ("env", C.c_void_p),
@@ -110,7 +118,8 @@ class epb_schedule(C.Structure):
 STRUCTS = dict(epb_camera=epb_camera, epb_gbuffer=epb_gbuffer, epb_cube=epb_cube,
                epb_ibl_params=epb_ibl_params, epb_ibl_maps=epb_ibl_maps,
                epb_ssao_params=epb_ssao_params, epb_light=epb_light,
-               epb_post_params=epb_post_params, epb_view=epb_view, epb_schedule=epb_schedule)
+               epb_post_params=epb_post_params, epb_view=epb_view, epb_schedule=epb_schedule,
+               epb_sphere_scene=epb_sphere_scene)
 
 
 def _load() -> C.CDLL:
@@ -145,8 +154,10 @@ def _load() -> C.CDLL:
     lib.epb_batch_scratch_bytes.restype = C.c_size_t
     lib.epb_batch_build.argtypes = [P, C.c_int32, P, P, C.c_size_t, P, C.c_size_t]
     lib.epb_render_batch.argtypes = [P, P, P]
+    lib.epb_raycast.argtypes = [C.POINTER(epb_sphere_scene), C.POINTER(epb_camera), C.POINTER(epb_gbuffer), P,
+                                C.c_size_t, P]
     for fn in ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
-               "epb_last_hip_error", "epb_batch_build", "epb_render_batch"):
+               "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast"):
         getattr(lib, fn).restype = C.c_int
     return lib
 
@@ -256,6 +267,12 @@ def epb_render_batch(table, table_dev, stream=None, check: bool = True) -> int:
     tab = C.addressof(table) if isinstance(table, C.Array) else _ptr(table)
     st = lib.epb_render_batch(tab, _ptr(table_dev), _stream(stream))
     return _check("epb_render_batch", st, check)
+
+
+def epb_raycast(scene: epb_sphere_scene, cam: epb_camera, out: epb_gbuffer, scratch, scratch_bytes: int,
+                stream=None, check: bool = True) -> int:
+    st = lib.epb_raycast(C.byref(scene), C.byref(cam), C.byref(out), _ptr(scratch), scratch_bytes, _stream(stream))
+    return _check("epb_raycast", st, check)
 
 
 # ---------------------------------------------------------------------------

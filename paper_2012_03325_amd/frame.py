@@ -257,3 +257,49 @@ class DeviceBatch:
 
     def render(self, stream=None):
         E.epb_render_batch(self.table_host.data_ptr(), self.table_dev, stream)
+
+
+class DeviceScene:
+    """A sphere field resident on the device (geometry in double, materials in
+    float) and the ray-cast pass that turns it into G-buffers and depth maps."""
+
+    def __init__(self, spheres, device="cuda"):
+        n = len(spheres.radii)
+        self.n = n
+        f64 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float64)).to(device)
+        f32 = lambda a: torch.from_numpy(np.ascontiguousarray(a, np.float32)).to(device)
+        self.center = f64(np.asarray(spheres.centers).reshape(n, 3))
+        self.radius = f64(spheres.radii)
+        self.albedo = f32(np.asarray(spheres.albedo).reshape(n, 3))
+        self.rough = f32(spheres.roughness)
+        self.metal = f32(spheres.metalness)
+        pa = (C.c_float * 3)(*[float(v) for v in spheres.plane_albedo])
+        ptr = lambda t: t.data_ptr() if n > 0 else None
+        self.struct = E.epb_sphere_scene(n, ptr(self.center), ptr(self.radius), ptr(self.albedo), ptr(self.rough),
+                                         ptr(self.metal), 1 if spheres.plane else 0, pa,
+                                         float(spheres.plane_roughness), float(spheres.plane_metalness))
+        self.scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_RAYCAST, 1, 1, self.struct)
+        self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
+        self.device = device
+
+    def render_gbuffer(self, cam, dtype=E.EPB_F32, stream=None) -> dict:
+        """G-buffer planes (torch tensors) of the scene seen by ``cam``."""
+        W, H = cam.width, cam.height
+        dt = _TORCH_DT[dtype]
+        g = dict(depth=torch.empty((H, W), device=self.device),
+                 normal=torch.empty((3, H, W), dtype=dt, device=self.device),
+                 albedo=torch.empty((3, H, W), dtype=dt, device=self.device),
+                 roughness=torch.empty((H, W), dtype=dt, device=self.device),
+                 metalness=torch.empty((H, W), dtype=dt, device=self.device))
+        out = E.epb_gbuffer(W, H, dtype, g["depth"].data_ptr(), g["normal"].data_ptr(), g["albedo"].data_ptr(),
+                            g["roughness"].data_ptr(), g["metalness"].data_ptr(), None)
+        E.epb_raycast(self.struct, _cam_struct(cam), out, self.scratch, self.scratch_bytes, stream)
+        return g
+
+    def render_depth(self, cam, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Depth map of the scene seen by ``cam`` (a light's shadow map)."""
+        W, H = cam.width, cam.height
+        d = out if out is not None else torch.empty((H, W), device=self.device)
+        g = E.epb_gbuffer(W, H, E.EPB_F32, d.data_ptr(), None, None, None, None, None)
+        E.epb_raycast(self.struct, _cam_struct(cam), g, self.scratch, self.scratch_bytes, stream)
+        return d

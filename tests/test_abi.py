@@ -325,3 +325,36 @@ def test_render_batch_rejects_foreign_tables():
     assert b.build() == E.EPB_OK
     assert E.lib.epb_render_batch(C.addressof(b.table), None, None) == E.EPB_ERR_NULL
     assert E.lib.epb_render_batch(C.addressof(b.table), FAKE + 8, None) == E.EPB_ERR_ALIGN
+
+
+def test_raycast_validation():
+    pa = (C.c_float * 3)(0.5, 0.5, 0.5)
+    sc = E.epb_sphere_scene(4, FAKE, FAKE, FAKE, FAKE, FAKE, 1, pa, 0.6, 0.0)
+    cam = _cam(64, 48)
+    need = E.epb_scratch_bytes(E.EPB_OP_RAYCAST, 64, 48, sc)
+    assert need >= 4 * 16
+
+    def call(s=sc, c=cam, g=None, scr=FAKE, n=need):
+        g = g or _gbuf(64, 48)
+        return E.lib.epb_raycast(C.byref(s), C.byref(c), C.byref(g), scr, n, None)
+
+    assert E.lib.epb_raycast(None, C.byref(cam), C.byref(_gbuf()), FAKE, need, None) == E.EPB_ERR_NULL
+    assert call(g=_gbuf(32, 48)) == E.EPB_ERR_SIZE
+    assert call(s=E.epb_sphere_scene(-1, FAKE, FAKE, FAKE, FAKE, FAKE, 0, pa, 0.6, 0.0)) == E.EPB_ERR_SIZE
+    assert call(s=E.epb_sphere_scene(E.EPB_MAX_SPHERES + 1, FAKE, FAKE, FAKE, FAKE, FAKE, 0, pa, 0.6, 0.0)) \
+        == E.EPB_ERR_SIZE
+    assert call(s=E.epb_sphere_scene(4, None, FAKE, FAKE, FAKE, FAKE, 0, pa, 0.6, 0.0)) == E.EPB_ERR_NULL
+    assert call(s=E.epb_sphere_scene(4, FAKE + 8, FAKE, FAKE, FAKE, FAKE, 0, pa, 0.6, 0.0)) == E.EPB_ERR_ALIGN
+    assert call(s=E.epb_sphere_scene(4, FAKE, FAKE, FAKE, FAKE, FAKE, 0, pa, float("nan"), 0.0)) == E.EPB_ERR_PARAM
+    w = _gbuf(64, 48)
+    w.weight = FAKE
+    assert call(g=w) == E.EPB_ERR_PARAM
+    half = _gbuf(64, 48)
+    half.albedo = None
+    assert call(g=half) == E.EPB_ERR_NULL
+    assert call(n=need - 1) == E.EPB_ERR_SCRATCH
+    assert call(scr=None) == E.EPB_ERR_SCRATCH
+    assert call(scr=FAKE + 4) == E.EPB_ERR_ALIGN
+    # no spheres: no sphere arrays needed
+    empty = E.epb_sphere_scene(0, None, None, None, None, None, 1, pa, 0.6, 0.0)
+    assert E.epb_scratch_bytes(E.EPB_OP_RAYCAST, 64, 48, empty) > 0
