@@ -99,7 +99,7 @@ struct RayOut {
 // ---------------------------------------------------------------------------
 constexpr int kSsaoPrepW = 256;           // half-resolution texels per prep item
 constexpr int kBlurTx = 16, kBlurTy = 8;  // SSAO blur tile
-constexpr int kPostTx = 32, kPostTy = 8;  // composite tile
+constexpr int kPostTx = 64, kPostTy = 8;  // composite: one wavefront, a column of 8 pixels per thread
 constexpr int kBloomTx = 32, kBloomTy = 16;  // bloom-blur tile
 constexpr int kDownTile = 16;             // bloom_down: 16x16 level-1 texels (32x32 pixels)
 

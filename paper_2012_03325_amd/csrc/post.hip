@@ -10,11 +10,11 @@
 //  * bloom_blur: all levels in one launch; each workgroup stages the 36x20
 //    texel footprint of its 32x16 tile in LDS and applies the separable
 //    [1 4 6 4 1] / 16 binomial (clamp to edge) horizontally then vertically.
-//  * composite: the footprint of a 32x8 pixel tile on every blurred level
-//    (at most 252 texels) is staged in LDS and interpolated separably (rows
-//    at the tile's columns, then per pixel between two rows); each thread adds
-//    the upsampled levels to its pixel, applies exposure, the ACES fit, gamma
-//    and 8-bit rounding, and writes one 32-bit RGBA word.
+//  * composite: a wavefront covers 64 columns x 8 rows, a thread one column
+//    of 8 pixels; every blurred level is interpolated at the column (rows
+//    first, then between two rows per pixel) in registers; each thread adds
+//    the upsampled levels to its pixels, applies exposure, the ACES fit,
+//    gamma and 8-bit rounding, and writes one 32-bit RGBA word per pixel.
 //  * pyramid texels are float4, or four halves in the FP16 form.
 //  * every stage has a single-view kernel and a batched kernel that walks the
 //    work items of many views.
@@ -202,99 +202,101 @@ __device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_g
     return (uint32_t)fminf(fmaxf(q, 0.0f), 255.0f);
 }
 
-// Level l samples pixel x at (x + 1/2) 2^-l - 1/2 = v / 2^(l+1) with v = 2x + 1 - 2^l:
-// the texel is v >> (l+1) (an arithmetic shift floors) and the weight is the
-// remainder (v & (2^(l+1) - 1)) / 2^(l+1), exact in float -- the same numbers as
-// the float form, without floor or conversions.  A 32x8 pixel tile reads at
-// most 32 / 2^l + 2 columns and 8 / 2^l + 2 rows of level l (+1 for rounding).
-// The bilinear upsampling is done separably: every footprint row is first
-// interpolated at the tile's 32 pixel columns (one item per thread and level,
-// as a footprint has at most 7 rows), then each pixel interpolates its two rows
-// -- the same two-step lerp per pixel, with the horizontal steps shared by the
-// pixels of a column.
-constexpr int kCompLds = (19 * 7) + (11 * 5) + (7 * 4) + (5 * 4) + (4 * 4);
-constexpr int kCompRows = 7 + 5 + 4 + 4 + 4;
-struct CompLds {
-    float4 tex[kCompLds];            // level footprints
-    float4 row[kCompRows][kPostTx];  // footprint rows interpolated at the tile's columns
+// Level L samples pixel x at (x + 1/2) 2^-L - 1/2 = v / 2^(L+1) with v = 2x + 1 - 2^L:
+// the texel is v >> (L+1) (an arithmetic shift floors) and the weight is the
+// remainder (v & (2^(L+1) - 1)) / 2^(L+1), exact in float -- the same numbers as
+// the float form, without floor or conversions.
+//
+// A thread owns one pixel column of an 8-row strip (the strip starts at a
+// multiple of 8).  For each blurred level it first interpolates, at its column,
+// the level rows under the strip (6, 4, 3, 2, 2 rows for levels 1..5: two texel
+// loads per row, neighbouring lanes share cache lines), then every pixel of
+// the column interpolates between two of those rows.  Because the strip starts
+// at a multiple of 8, which rows a pixel uses is fixed at compile time (levels
+// 1..3), or is the first pair for all eight pixels (levels 4 and 5, where the
+// strip lies inside one texel row pair); the weights of levels 1..3 are
+// compile-time constants as well.  Everything stays in registers: no LDS, no
+// barriers, and the strip's 24 HDR loads are in flight while the pyramid is
+// read.
+template <int L>
+struct LevelRows {
+    static constexpr int sh = L + 1, o = 1 - (1 << L), m = (1 << sh) - 1;
+    static constexpr int n = L == 1 ? 6 : L == 2 ? 4 : L == 3 ? 3 : 2;
+    static constexpr float inv = 1.0f / (float)(1 << sh);
+    // first row (relative to the strip's first footprint row) of pixel j
+    static constexpr int rel(int j) { return L <= 3 ? ((2 * j + o) >> sh) - (o >> sh) : 0; }
 };
 
+template <int L, typename TP>
+__device__ __forceinline__ void add_level(const PostDesc &c, int x, int Y0, float (&acc)[kPostTy][3]) {
+    using LR = LevelRows<L>;
+    const int w = c.lw[L], h = c.lh[L];
+    const TP *lvl = (const TP *)c.blur[L];
+    int vx = 2 * x + LR::o;
+    float wx = (float)(vx & LR::m) * LR::inv;
+    int cx = vx >> LR::sh;
+    unsigned c0 = (unsigned)min(max(cx, 0), w - 1), c1 = (unsigned)min(max(cx + 1, 0), w - 1);
+    int ay = (2 * Y0 + LR::o) >> LR::sh;
+    float rows[LR::n][3];
+#pragma unroll
+    for (int r = 0; r < LR::n; ++r) {
+        unsigned gy = (unsigned)min(max(ay + r, 0), h - 1);
+        unsigned base = __umul24(gy, (unsigned)w);
+        float4 a = unpack(ldo(lvl, (base + c0) * (unsigned)sizeof(TP)));
+        float4 b = unpack(ldo(lvl, (base + c1) * (unsigned)sizeof(TP)));
+        rows[r][0] = fmaf(wx, b.x - a.x, a.x);
+        rows[r][1] = fmaf(wx, b.y - a.y, a.y);
+        rows[r][2] = fmaf(wx, b.z - a.z, a.z);
+    }
+#pragma unroll
+    for (int j = 0; j < kPostTy; ++j) {
+        const int r0 = LR::rel(j);
+        float wy = L <= 3 ? (float)((2 * j + LR::o) & LR::m) * LR::inv
+                          : (float)((2 * (Y0 + j) + LR::o) & LR::m) * LR::inv;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch)
+            acc[j][ch] += fmaf(wy, rows[r0 + 1][ch] - rows[r0][ch], rows[r0][ch]);
+    }
+}
+
 template <typename TH, typename TP>
-__device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, CompLds &sm) {
+__device__ __forceinline__ void composite_tile(const PostDesc &c, int tile) {
     int tiles_x = (c.W + kPostTx - 1) / kPostTx;
     int ty = tile / tiles_x;
-    int X0 = (tile - ty * tiles_x) * kPostTx, Y0 = ty * kPostTy;
-    int tc = (int)(threadIdx.x % kPostTx), tr = (int)(threadIdx.x / kPostTx);
-    int x = X0 + tc, y = Y0 + tr;
-    bool live = x < c.W && y < c.H;
-    unsigned p = live ? __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x : 0u;
+    int x = (tile - ty * tiles_x) * kPostTx + (int)threadIdx.x, Y0 = ty * kPostTy;
+    if (x >= c.W) return;
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
     const TH *hdr = (const TH *)c.hdr;
-    // the pixel's HDR first (in flight while the pyramid footprint is staged)
-    float R0 = ldf(hdr, p), G0 = ldf(hdr, plane + p), B0 = ldf(hdr, 2 * plane + p);
-    // stage the clamped footprint of every blurred level, one texel per thread
-    int base[EPB_MAX_BLOOM_LEVELS], rbase[EPB_MAX_BLOOM_LEVELS], ax[EPB_MAX_BLOOM_LEVELS],
-        ay[EPB_MAX_BLOOM_LEVELS], cols[EPB_MAX_BLOOM_LEVELS], rows[EPB_MAX_BLOOM_LEVELS];
-    int off = 0, roff = 0;
+    // the strip's HDR first (in flight while the pyramid is read); rows below the image are
+    // clamped to the last row and not stored
+    float px[kPostTy][3];
 #pragma unroll
-    for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
-        if (L > c.nl) break;
-        const int sh = L + 1, o = 1 - (1 << L);
-        int w = c.lw[L], h = c.lh[L];
-        ax[L] = (2 * X0 + o) >> sh;
-        ay[L] = (2 * Y0 + o) >> sh;
-        int nc = ((2 * (X0 + kPostTx - 1) + o) >> sh) + 2 - ax[L];
-        int nr = ((2 * (Y0 + kPostTy - 1) + o) >> sh) + 2 - ay[L];
-        if (tc < nc && tr < nr) {
-            int gx = min(max(ax[L] + tc, 0), w - 1), gy = min(max(ay[L] + tr, 0), h - 1);
-            unsigned t = __umul24((unsigned)gy, (unsigned)w) + (unsigned)gx;
-            sm.tex[off + __mul24(tr, nc) + tc] = unpack(ldo((const TP *)c.blur[L], t * (unsigned)sizeof(TP)));
-        }
-        base[L] = off;
-        rbase[L] = roff;
-        cols[L] = nc;
-        rows[L] = nr;
-        off += nc * nr;
-        roff += nr;
+    for (int j = 0; j < kPostTy; ++j) {
+        unsigned p = __umul24((unsigned)min(Y0 + j, c.H - 1), (unsigned)c.W) + (unsigned)x;
+        px[j][0] = ldf(hdr, p);
+        px[j][1] = ldf(hdr, plane + p);
+        px[j][2] = ldf(hdr, 2 * plane + p);
     }
-    __syncthreads();
-    // horizontal step: footprint row tr of each level at this thread's column
+    float acc[kPostTy][3];
 #pragma unroll
-    for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
-        if (L > c.nl) break;
-        if (tr < rows[L]) {
-            const int sh = L + 1, o = 1 - (1 << L), m = (1 << sh) - 1;
-            const float inv = 1.0f / (float)(1 << sh);
-            int vx = 2 * x + o;
-            float wx = (float)(vx & m) * inv;
-            const float4 *t0 = sm.tex + base[L] + __mul24(tr, cols[L]) + ((vx >> sh) - ax[L]);
-            sm.row[rbase[L] + tr][tc] = lerp4(t0[0], t0[1], wx);
-        }
-    }
-    __syncthreads();
-    if (live) {
-        float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+    for (int j = 0; j < kPostTy; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
+    // levels 1 .. nl (nl is uniform)
+    if (c.nl >= 1) add_level<1, TP>(c, x, Y0, acc);
+    if (c.nl >= 2) add_level<2, TP>(c, x, Y0, acc);
+    if (c.nl >= 3) add_level<3, TP>(c, x, Y0, acc);
+    if (c.nl >= 4) add_level<4, TP>(c, x, Y0, acc);
+    if (c.nl >= 5) add_level<5, TP>(c, x, Y0, acc);
 #pragma unroll
-        for (int L = 1; L < EPB_MAX_BLOOM_LEVELS; ++L) {
-            if (L > c.nl) break;
-            const int sh = L + 1, o = 1 - (1 << L), m = (1 << sh) - 1;
-            const float inv = 1.0f / (float)(1 << sh);
-            int vy = 2 * y + o;
-            float wy = (float)(vy & m) * inv;
-            int r0 = rbase[L] + ((vy >> sh) - ay[L]);
-            float4 v = lerp4(sm.row[r0][tc], sm.row[r0 + 1][tc], wy);
-            sx += v.x;
-            sy += v.y;
-            sz += v.z;
-        }
-        float R = fmaf(c.strength, sx, R0);
-        float G = fmaf(c.strength, sy, G0);
-        float Bc = fmaf(c.strength, sz, B0);
+    for (int j = 0; j < kPostTy; ++j) {
+        if (Y0 + j >= c.H) break;
+        float R = fmaf(c.strength, acc[j][0], px[j][0]);
+        float G = fmaf(c.strength, acc[j][1], px[j][1]);
+        float Bc = fmaf(c.strength, acc[j][2], px[j][2]);
         uint32_t word = encode8(R, c.exposure, c.inv_gamma) | (encode8(G, c.exposure, c.inv_gamma) << 8) |
                         (encode8(Bc, c.exposure, c.inv_gamma) << 16) | (255u << 24);
+        unsigned p = __umul24((unsigned)(Y0 + j), (unsigned)c.W) + (unsigned)x;
         sto(c.ldr, p * 4u, word);
     }
-    __syncthreads();  // the next item of a batched launch refills the LDS
 }
 
 // ---------------------------------------------------------------------------
@@ -313,9 +315,8 @@ __global__ void __launch_bounds__(256) k_bloom_blur(const PostDesc c) {
 }
 
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(256) k_composite(const PostDesc c, int tiles) {
-    __shared__ CompLds sm;
-    composite_tile<TH, TP>(c, xcd_tile(blockIdx.x, tiles), sm);
+__global__ void __launch_bounds__(kPostTx) k_composite(const PostDesc c, int tiles) {
+    composite_tile<TH, TP>(c, xcd_tile(blockIdx.x, tiles));
 }
 
 template <typename TH, typename TP>
@@ -347,8 +348,7 @@ __global__ void __launch_bounds__(256) k_bloom_blur_batch(const void *__restrict
 }
 
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(256) k_composite_batch(const void *__restrict__ table) {
-    __shared__ CompLds sm;
+__global__ void __launch_bounds__(kPostTx) k_composite_batch(const void *__restrict__ table) {
     const BatchHeader *h = (const BatchHeader *)table;
     const int *start = batch_start(table, kStComposite);
     const ViewDesc *views = batch_views(table);
@@ -356,7 +356,7 @@ __global__ void __launch_bounds__(256) k_composite_batch(const void *__restrict_
     for (int it = w.lb; it < w.count; it += w.stride) {
         int g = w.first + it;
         int v = find_view(start, h->n_views, g);
-        composite_tile<TH, TP>(views[v].post, g - start[v], sm);
+        composite_tile<TH, TP>(views[v].post, g - start[v]);
     }
 }
 
@@ -434,7 +434,7 @@ static void launch_post(const PostDesc &c, hipStream_t s) {
         hipLaunchKernelGGL(k_bloom_blur<TP>, dim3(post_items(c, kStBloomBlur)), dim3(256), 0, s, c);
     }
     int tiles = post_items(c, kStComposite);
-    hipLaunchKernelGGL((k_composite<TH, TP>), dim3(tiles), dim3(256), 0, s, c, tiles);
+    hipLaunchKernelGGL((k_composite<TH, TP>), dim3(tiles), dim3(kPostTx), 0, s, c, tiles);
 }
 
 template <typename TH, typename TP>
@@ -446,7 +446,7 @@ static void launch_post_batch_t(const BatchHeader &h, const void *table, hipStre
         hipLaunchKernelGGL(k_bloom_blur_batch<TP>, dim3(batch_grid(h.total[kStBloomBlur], h.blocks_per_cu)),
                            dim3(256), 0, s, table);
     hipLaunchKernelGGL((k_composite_batch<TH, TP>), dim3(batch_grid(h.total[kStComposite], h.blocks_per_cu)),
-                       dim3(256), 0, s, table);
+                       dim3(kPostTx), 0, s, table);
 }
 
 hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s) {
