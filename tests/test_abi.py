@@ -249,7 +249,7 @@ def _expected_items(w, h, levels=6):
         blur_items += _cdiv(lw, 32) * _cdiv(lh, 16)
     down = _cdiv(dims[0][0], 16) * _cdiv(dims[0][1], 16) if dims else 0
     return [hh * _cdiv(wh, 256), _cdiv(wh, 16) * _cdiv(hh, 8), _cdiv(wh, 16) * _cdiv(hh, 8),
-            _cdiv(w, 32) * _cdiv(h, 8), down, blur_items, _cdiv(w, 32) * _cdiv(h, 8)]
+            _cdiv(w, 32) * _cdiv(h, 8), down, blur_items, _cdiv(w, 64) * _cdiv(h, 8)]
 
 
 def test_batch_sizes():
