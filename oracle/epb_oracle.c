@@ -762,6 +762,83 @@ void orc_shade(const double *depth, const double *normal, const double *albedo,
 }
 
 /* ------------------------------------------------------------------------ */
+/* Eye-dome lighting of depth-only renders such as point clouds (Sec. 4.3):  */
+/* the compositing step darkens a pixel by how far it lies behind the pixels  */
+/* around it in screen space, using nothing but the depth map.               */
+/* ------------------------------------------------------------------------ */
+
+/* The neighbourhood: n_dirs directions 2 pi k / n_dirs around the pixel, each
+ * taken radius pixels away and rounded to the nearest pixel (x right, y down),
+ * halves away from zero; a coordinate within 1e-9 of a half counts as the half
+ * (sin 30 degrees is not exactly 1/2 in floating point). */
+static int edl_round(double v) {
+    double m = floor(fabs(v) + 0.5 + 1e-9);
+    return (int)(v < 0 ? -m : m);
+}
+void orc_edl_offsets(int radius, int n_dirs, int *dx, int *dy) {
+    for (int k = 0; k < n_dirs; ++k) {
+        double a = 2.0 * PI * (double)k / (double)n_dirs;
+        dx[k] = edl_round(radius * cos(a));
+        dy[k] = edl_round(radius * sin(a));
+    }
+}
+
+/* Depth on the logarithmic scale the comparison uses; background (+inf) and
+ * anything farther than far_depth count as far_depth. */
+static double edl_log_depth(double d, double far_depth) { return log2(d < far_depth ? d : far_depth); }
+
+/* Per pixel p: response = (1 / n) sum over the in-image neighbours q of
+ * max(0, log2 d_p - log2 d_q) (neighbours outside the image add nothing);
+ * shade = 2^(-strength * response).  Foreground pixels return shade * AO *
+ * colour (AO upsampled as in shading; NULL means 1), background pixels shade
+ * times the environment along the view ray (NULL environment: black). */
+void orc_edl(const double *depth, const double *color, const orc_camera *cam, const double *ao_lo,
+             const double *ao_hi, int radius, int n_dirs, double strength, double far_depth,
+             const double *env, int env_size, double tie_rel, double *hdr_lo, double *hdr_hi) {
+    int W = cam->width, H = cam->height;
+    int Wh = (W + 1) / 2, Hh = (H + 1) / 2;
+    size_t plane = (size_t)W * H;
+    const double *M = cam->world_to_cam;
+    int dx[64], dy[64];
+    orc_edl_offsets(radius, n_dirs, dx, dy);
+#pragma omp parallel for schedule(dynamic)
+    for (int y = 0; y < H; ++y)
+        for (int x = 0; x < W; ++x) {
+            size_t p = (size_t)y * W + x;
+            double zp = edl_log_depth(depth[p], far_depth);
+            double response = 0.0;
+            for (int k = 0; k < n_dirs; ++k) {
+                int qx = x + dx[k], qy = y + dy[k];
+                if (qx < 0 || qx >= W || qy < 0 || qy >= H) continue;
+                response += maxd(0.0, zp - edl_log_depth(depth[(size_t)qy * W + qx], far_depth));
+            }
+            response /= n_dirs;
+            double shade = exp2(-strength * response);
+            double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+            if (isinf(depth[p])) {
+                if (env) {
+                    double dirv[3] = {(x + 0.5 - cam->cx) / cam->fx, -(y + 0.5 - cam->cy) / cam->fy, -1.0};
+                    double dw[3];
+                    rot_t(M, dirv, dw);
+                    cube_bilinear_iv(env, env_size, dw, tie_rel, lo, hi);
+                }
+                for (int c = 0; c < 3; ++c) { lo[c] *= shade; hi[c] *= shade; }
+            } else {
+                double aol = ao_lo ? ao_upsample(ao_lo, Wh, Hh, x, y) : 1.0;
+                double aoh = ao_hi ? ao_upsample(ao_hi, Wh, Hh, x, y) : 1.0;
+                for (int c = 0; c < 3; ++c) {
+                    lo[c] = shade * aol * color[c * plane + p];
+                    hi[c] = shade * aoh * color[c * plane + p];
+                }
+            }
+            for (int c = 0; c < 3; ++c) {
+                hdr_lo[c * plane + p] = lo[c];
+                hdr_hi[c * plane + p] = hi[c];
+            }
+        }
+}
+
+/* ------------------------------------------------------------------------ */
 /* a5 / a6: bloom pyramid, composite, ACES tonemap, gamma, 8 bit             */
 /* ------------------------------------------------------------------------ */
 

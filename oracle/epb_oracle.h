@@ -113,6 +113,16 @@ typedef struct {
 void orc_raycast(const orc_scene *s, const orc_camera *cam, double rel, double *depth, int32_t *id,
                  double *normal, double *albedo, double *rough, double *metal, uint8_t *ambiguous);
 
+/* Eye-dome lighting (Sec. 4.3) of a depth map with per-pixel colour: shade =
+ * 2^(-strength * mean over n_dirs neighbours at radius pixels of
+ * max(0, log2 d_p - log2 d_q)), depths capped at far_depth (background too);
+ * foreground = shade * AO * colour, background = shade * environment.
+ * ao_lo / ao_hi and env may be NULL.  n_dirs <= 64. */
+void orc_edl_offsets(int radius, int n_dirs, int *dx, int *dy);
+void orc_edl(const double *depth, const double *color, const orc_camera *cam, const double *ao_lo,
+             const double *ao_hi, int radius, int n_dirs, double strength, double far_depth,
+             const double *env, int env_size, double tie_rel, double *hdr_lo, double *hdr_hi);
+
 /* a5 / a6 bloom, composite, tonemap.  pyramid (optional) receives the blurred
  * levels 1..levels-1 as planar [3][H_l][W_l] blocks one after another. */
 void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double threshold,

@@ -94,6 +94,9 @@ def lib():
         L.orc_normalize_gbuffer.argtypes = [_D, C.c_int, C.c_int, _D, _D, _D, _D]
         L.orc_raycast.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcCamera), C.c_double, _D,
                                   C.POINTER(C.c_int32), _D, _D, _D, _D, C.POINTER(C.c_uint8)]
+        L.orc_edl_offsets.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.orc_edl.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, _D, C.c_int, C.c_int, C.c_double,
+                              C.c_double, _D, C.c_int, C.c_double, _D, _D]
         L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
                                         C.c_double, C.c_double, C.POINTER(C.c_uint8), _D, _D]
         _lib = L
@@ -329,6 +332,37 @@ def shade(gbuf: dict, cam, ao_lo, ao_hi, lights: Sequence, ibl: dict, env,
                     _p(ao_lo), _p(ao_hi), arr, len(lights), _p(irr), irr.shape[1], _p(pref),
                     _p(pref_hi), ibl["prefiltered"][0].shape[1], len(ibl["prefiltered"]), _p(lut), lut.shape[0],
                     _p(env), env.shape[1], C.byref(t), _p(lo), _p(hi))
+    return lo, hi
+
+
+# ---------------------------------------------------------------------------
+# eye-dome lighting (Sec. 4.3)
+# ---------------------------------------------------------------------------
+def edl_offsets(radius: int, n_dirs: int) -> List[Tuple[int, int]]:
+    dx = (C.c_int * n_dirs)()
+    dy = (C.c_int * n_dirs)()
+    lib().orc_edl_offsets(radius, n_dirs, dx, dy)
+    return list(zip(dx, dy))
+
+
+def edl(depth, color, cam, ao_lo=None, ao_hi=None, radius=1, n_dirs=8, strength=8.0,
+        far_depth=1000.0, env=None, tie=DEFAULT_TIE) -> Tuple[np.ndarray, np.ndarray]:
+    """Eye-dome lighting of a depth map with per-pixel colour; ``(lo, hi)`` differ
+    only through the AO interval and cube-face ties of the background."""
+    assert 1 <= n_dirs <= 64
+    depth, color = _d(depth), _d(color)
+    H, W = depth.shape
+    null = C.cast(None, _D)
+    aol = _d(ao_lo) if ao_lo is not None else None
+    aoh = _d(ao_hi) if ao_hi is not None else aol
+    envd = _d(env) if env is not None else None
+    lo = np.zeros((3, H, W))
+    hi = np.zeros((3, H, W))
+    c = _cam(cam)
+    lib().orc_edl(_p(depth), _p(color), C.byref(c), _p(aol) if aol is not None else null,
+                  _p(aoh) if aoh is not None else null, radius, n_dirs, strength, far_depth,
+                  _p(envd) if envd is not None else null, envd.shape[1] if envd is not None else 0,
+                  tie[1], _p(lo), _p(hi))
     return lo, hi
 
 

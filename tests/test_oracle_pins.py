@@ -613,3 +613,115 @@ def test_raycast_nearest_hit_and_ties_to_the_lower_index():
     assert (r["ambiguous"][r["id"] == 0] == 1).all()  # and every pixel it ties on is flagged
     front = np.isfinite(alone[1]) & (alone[1] < alone[0])
     assert (r["id"][front] == 1).all()
+
+
+# ---------------------------------------------------------------------------
+# eye-dome lighting (Sec. 4.3)
+# ---------------------------------------------------------------------------
+def test_edl_offsets_are_the_rounded_circle():
+    """8 directions at radius 1 are the 8-neighbourhood; 4 at radius 2 the axis
+    points at distance 2; the 12 at radius 3 by hand (3 cos 30 deg = 2.598 -> 3,
+    3 sin 30 deg = 1.5 -> 2, halves away from zero, also where floating point
+    puts sin 30 deg a hair below 1/2), symmetric under negation."""
+    assert O.edl_offsets(1, 8) == [(1, 0), (1, 1), (0, 1), (-1, 1), (-1, 0), (-1, -1), (0, -1), (1, -1)]
+    assert O.edl_offsets(2, 4) == [(2, 0), (0, 2), (-2, 0), (0, -2)]
+    o12 = O.edl_offsets(3, 12)
+    assert o12[:4] == [(3, 0), (3, 2), (2, 3), (0, 3)]
+    assert all(o12[k + 6] == (-o12[k][0], -o12[k][1]) for k in range(6))
+
+
+def _edl_cam(W, H):
+    return synth.Camera(np.concatenate([np.eye(3), np.zeros((3, 1))], 1), 100.0, 100.0, W / 2.0,
+                        H / 2.0, W, H)
+
+
+def test_edl_flat_depth_is_unshaded():
+    """Equal depths everywhere: every log-depth difference is 0, shade 1, so the
+    output is the colour times the AO exactly."""
+    H, W = 9, 13
+    rng = np.random.default_rng(3)
+    col = rng.uniform(0, 1, (3, H, W))
+    ao = rng.uniform(0.2, 1, ((H + 1) // 2, (W + 1) // 2))
+    lo, hi = O.edl(np.full((H, W), 4.5), col, _edl_cam(W, H), ao, ao, radius=2, n_dirs=8, strength=5)
+    # AO upsampling by hand at (x/2, y/2): even pixels take the texel, odd ones average
+    up = np.zeros((H, W))
+    for y in range(H):
+        for x in range(W):
+            x0, y0 = x // 2, y // 2
+            x1, y1 = min(x0 + 1, ao.shape[1] - 1), min(y0 + 1, ao.shape[0] - 1)
+            wx, wy = 0.5 * (x % 2), 0.5 * (y % 2)
+            up[y, x] = ((1 - wy) * ((1 - wx) * ao[y0, x0] + wx * ao[y0, x1])
+                        + wy * ((1 - wx) * ao[y1, x0] + wx * ao[y1, x1]))
+    assert np.array_equal(lo, hi)
+    assert np.allclose(lo, col * up, rtol=1e-15, atol=0)
+
+
+def test_edl_depth_step_by_hand():
+    """A vertical step: columns x < 5 at depth 2, x >= 5 at depth 8.  With the 4
+    axis neighbours at radius 1 only the far column next to the step sees a
+    nearer neighbour (its left one): response = log2(8 / 2) / 4 = 1/2, shade =
+    2^(-s / 2); all other pixels, the near side included, keep shade 1."""
+    H, W, s = 6, 10, 3.0
+    depth = np.where(np.arange(W)[None, :] < 5, 2.0, 8.0) * np.ones((H, W))
+    col = np.ones((3, H, W))
+    lo, _ = O.edl(depth, col, _edl_cam(W, H), radius=1, n_dirs=4, strength=s)
+    want = np.ones((H, W))
+    want[:, 5] = 2.0 ** (-s / 2)
+    assert np.allclose(lo[0], want, rtol=1e-15, atol=0)
+    # radius 2: the far columns 5 and 6 both reach a near pixel, 2 units left
+    lo2, _ = O.edl(depth, col, _edl_cam(W, H), radius=2, n_dirs=4, strength=s)
+    want2 = np.ones((H, W))
+    want2[:, 5:7] = 2.0 ** (-s / 2)
+    assert np.allclose(lo2[0], want2, rtol=1e-15, atol=0)
+
+
+def test_edl_is_scale_invariant_and_darkens_with_strength():
+    """The response compares log depths, so scaling every depth (and the far
+    cap) by c changes nothing; a larger strength can only darken."""
+    rng = np.random.default_rng(7)
+    H, W = 12, 15
+    depth = rng.uniform(1, 20, (H, W))
+    depth[rng.uniform(size=(H, W)) < 0.2] = np.inf
+    col = rng.uniform(0, 1, (3, H, W))
+    cam = _edl_cam(W, H)
+    a, _ = O.edl(depth, col, cam, radius=2, n_dirs=8, strength=4, far_depth=50.0)
+    b, _ = O.edl(depth * 3.0, col, cam, radius=2, n_dirs=8, strength=4, far_depth=150.0)
+    assert np.allclose(a, b, rtol=1e-12, atol=0)
+    c, _ = O.edl(depth, col, cam, radius=2, n_dirs=8, strength=9, far_depth=50.0)
+    assert np.all(c <= a + 1e-15)
+    z, _ = O.edl(depth, col, cam, radius=2, n_dirs=8, strength=0, far_depth=50.0)
+    fg = np.isfinite(depth)
+    assert np.array_equal(z[:, fg], col[:, fg])  # strength 0: no darkening at all
+
+
+def test_edl_brute_force_and_background_outline():
+    """Brute force on a small random field, written out here from the definition,
+    including background pixels (depth counted as the far cap) whose nearer
+    neighbours give the dark outline, and neighbours that leave the image."""
+    rng = np.random.default_rng(11)
+    H, W, r, n, s, far = 7, 9, 2, 6, 2.5, 40.0
+    depth = rng.uniform(2, 30, (H, W))
+    depth[rng.uniform(size=(H, W)) < 0.3] = np.inf
+    col = rng.uniform(0, 1, (3, H, W))
+    env = np.ones((6, 4, 4, 4)) * np.array([0.2, 0.4, 0.8, 0.0])  # constant sky
+    lo, hi = O.edl(depth, col, _edl_cam(W, H), radius=r, n_dirs=n, strength=s, far_depth=far, env=env)
+    rnd = lambda v: int(math.copysign(math.floor(abs(v) + 0.5 + 1e-9), v))
+    offs = [(rnd(r * math.cos(2 * math.pi * k / n)), rnd(r * math.sin(2 * math.pi * k / n))) for k in range(n)]
+    z = np.log2(np.minimum(depth, far))
+    for y in range(H):
+        for x in range(W):
+            acc = 0.0
+            for dx, dy in offs:
+                if 0 <= x + dx < W and 0 <= y + dy < H:
+                    acc += max(0.0, z[y, x] - z[y + dy, x + dx])
+            sh = 2.0 ** (-s * acc / n)
+            base = np.array([0.2, 0.4, 0.8]) if np.isinf(depth[y, x]) else col[:, y, x]
+            assert np.allclose(lo[:, y, x], sh * base, rtol=1e-13, atol=0)
+            assert np.allclose(hi[:, y, x], sh * base, rtol=1e-13, atol=0)
+    # a background pixel whose neighbours are all foreground at depth d is
+    # darkened to 2^(-s log2(far / d)) = (d / far)^s
+    d = np.full((5, 5), 5.0)
+    d[2, 2] = np.inf
+    o, _ = O.edl(d, np.ones((3, 5, 5)), _edl_cam(5, 5), radius=1, n_dirs=8, strength=s, far_depth=far,
+                 env=env)
+    assert abs(o[2, 2, 2] - 0.8 * (5.0 / far) ** s) < 1e-15
