@@ -162,6 +162,51 @@ def frame_algorithmic_bytes(view, half: bool = False) -> int:
     return ssao + ao + shade + hdr + bloom + 4 * px
 
 
+def edl_algorithmic_bytes(pc, half: bool = False) -> int:
+    """Bytes epb_edl must move: every depth once (the halo re-reads hit the
+    cache), the colour of every point pixel, the half-resolution AO once, the
+    HDR output and the environment cube once."""
+    H, W = pc.depth.shape
+    fg = int(np.isfinite(pc.depth).sum())
+    vb = 2 if half else 4
+    ao = ((W + 1) // 2) * ((H + 1) // 2) * vb
+    return 4 * W * H + 3 * vb * fg + ao + 3 * vb * W * H + pc.env.nbytes
+
+
+def bench_edl(args, torch, E, frame, synth) -> dict:
+    """Eye-dome lighting (the point-cloud compositing step) on a 1920x1080
+    render of 4M seeded points: back-to-back launches over rotated copies of
+    every buffer, HIP events on the launch stream."""
+    t0 = time.time()
+    pc = synth.point_cloud_view(1920, 1080, 4_000_000, seed=17)
+    log(f"point cloud generated in {time.time() - t0:.1f} s ({100 * np.isfinite(pc.depth).mean():.1f}% pixels)")
+    s = torch.cuda.current_stream()
+    res = {"workload": "edl-1920x1080: 4M points sampled by area on 512 seeded spheres and the ground square "
+                       "[-8,8]^2, one-pixel points with a depth test; radius 2, 8 directions, strength 8, "
+                       "half-resolution AO, 6x64^2 sky-gradient background",
+           "point_pixels_frac": round(float(np.isfinite(pc.depth).mean()), 4)}
+    for name, dt in (("fp32", E.EPB_F32), ("fp16", E.EPB_F16)):
+        devs = [frame.DeviceEDL(pc, color_dtype=dt, ao_dtype=dt, hdr_dtype=dt) for _ in range(8)]
+        for k in range(16):
+            devs[k % 8].run()
+        torch.cuda.synchronize()
+        K = max(50, args.steps)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for k in range(K):
+            devs[k % 8].run()
+        e1.record(s)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / K
+        nbytes = edl_algorithmic_bytes(pc, half=(dt == E.EPB_F16))
+        res[name] = {"ms": round(ms, 5), "Mpix_s": round(pc.depth.size / (ms / 1e3) / 1e6, 1),
+                     "algorithmic_bytes": nbytes, "GBps": round(nbytes / (ms / 1e3) / 1e9, 1),
+                     "frac_hbm_peak": round(nbytes / (ms / 1e3) / 1e9 / HBM_PEAK_GBPS, 4)}
+        log(f"edl {name}: {res[name]}")
+        del devs
+    return res
+
+
 def bench_batched(args, torch, E, frame, synth) -> dict:
     """The batched form on 16 scenes / 256 views of uneven resolution: the plain
     single-view calls over every view (eager, and captured in one graph)
@@ -405,6 +450,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-view batched form")
     ap.add_argument("--batch-steps", type=int, default=10, help="timed replays of the batched frame")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving form")
+    ap.add_argument("--no-edl", action="store_true", help="skip the eye-dome lighting measurement")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of arrivals per rate (max 10)")
     ap.add_argument("--serve-min-requests", type=int, default=200, help="requests per rate at least")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of request slots")
@@ -557,6 +603,8 @@ def main():
             for name, m in res.items()
         },
     }
+    if not args.no_edl:
+        out["edl"] = bench_edl(args, torch, E, frame, synth)
     sched = None
     if not args.no_batch:
         out["batched"] = bench_batched(args, torch, E, frame, synth)

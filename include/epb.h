@@ -16,6 +16,11 @@
  *   epb_bloom_tonemap   -- bright-map pyramid bloom, ACES, gamma, 8 bit
  *                          (Sec. 5.3, 5.4)
  *
+ * Beside them: a batched form of the per-frame calls, a device ray caster of
+ * sphere fields (the G-buffer and shadow-map pass before shading) and
+ * eye-dome lighting, the compositing step of depth-only point-cloud renders
+ * (Sec. 4.3).
+ *
  * Conventions (the paper leaves them open; every call uses the same ones):
  *  - Images are row-major, y down.  Multi-channel images are planar [c][H][W].
  *  - Pinhole cameras: pixel centres at (x + 0.5, y + 0.5); the view-space point
@@ -171,7 +176,13 @@ typedef struct {
     float exposure;       /* multiplies HDR before the ACES curve (1.0)         */
     float gamma;          /* display gamma (2.2)                                */
     epb_dtype pyr_dtype;  /* storage of the bloom pyramid in scratch            */
+    int32_t tonemap;      /* EPB_TONEMAP_ACES (0, the default) or
+                             EPB_TONEMAP_REINHARD (1)                          */
 } epb_post_params;
+
+/* Tone-mapping operators of the final compositing step (Sec. 5.4). */
+#define EPB_TONEMAP_ACES 0
+#define EPB_TONEMAP_REINHARD 1
 
 /* A field of spheres with an optional ground plane y = 0: the geometry the
  * ray caster turns into G-buffers and shadow maps (a stand-in for the paper's
@@ -276,8 +287,9 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao,
  * of size ceil(W / 2^l) x ceil(H / 2^l) is the mean of the in-range children of
  * level l - 1; levels 1 .. L-1 are blurred with the separable [1 4 6 4 1] / 16
  * kernel (clamp to edge) and added, times strength, bilinearly upsampled; the
- * result goes through exposure, the ACES fit x (2.51 x + .03) / (x (2.43 x + .59)
- * + .14), clamp to [0, 1], x^(1 / gamma) and rounding to 8 bits.
+ * result goes through exposure, the tone curve -- the ACES fit x (2.51 x + .03) /
+ * (x (2.43 x + .59) + .14), or the global Reinhard operator x / (1 + x) -- per
+ * channel, clamp to [0, 1], x^(1 / gamma) and rounding to 8 bits.
  */
 int epb_bloom_tonemap(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32_t height,
                       const epb_post_params *params, uint8_t *ldr_out, void *scratch,
@@ -395,6 +407,43 @@ int epb_render_batch(const void *table, const void *table_dev, hipStream_t strea
  */
 int epb_raycast(const epb_sphere_scene *scene, const epb_camera *cam, const epb_gbuffer *out,
                 void *scratch, size_t scratch_bytes, hipStream_t stream);
+
+/* Eye-dome lighting (Sec. 4.3) of depth-only renders such as point clouds. */
+#define EPB_MAX_EDL_RADIUS 16
+#define EPB_MAX_EDL_DIRS 32
+typedef struct {
+    int32_t radius;   /* neighbour distance in pixels, 1 .. EPB_MAX_EDL_RADIUS     */
+    int32_t n_dirs;   /* neighbours on the circle, 1 .. EPB_MAX_EDL_DIRS           */
+    float strength;   /* shade = 2^(-strength * response), finite and >= 0         */
+    float far_depth;  /* depth given to background and depths beyond it, > 0       */
+} epb_edl_params;
+
+/*
+ * epb_edl -- the compositing step for depth-only renders (Sec. 4.3): no normals,
+ * so no PBR; pixels are darkened where their depth jumps behind their
+ * neighbours.
+ *
+ *   depth        [H][W] linear view depth, +inf = background (H, W from cam)
+ *   color        [3][H][W] linear colour of the points, of color_dtype
+ *   cam          the camera of the render (background view directions)
+ *   ao, ao_dtype [Hh][Wh] ambient occlusion (e.g. from epb_ssao), or NULL for 1
+ *   env          environment cube shown behind the points (level 0), or NULL
+ *                for black
+ *   hdr_out      [3][H][W] of hdr_dtype
+ *
+ * Neighbour k of n_dirs is the pixel offset (round(radius cos a_k),
+ * round(radius sin a_k)), a_k = 2 pi k / n_dirs, x right and y down, rounded
+ * half away from zero (within 1e-9 of a half counts as the half).  With
+ * z = log2(min(d, far_depth)) (background: log2 far_depth), the response of
+ * pixel p is (1 / n_dirs) sum over the neighbours q inside the image of
+ * max(0, z_p - z_q), and shade = 2^(-strength * response).  Foreground pixels
+ * get shade * AO * colour (AO bilinearly upsampled as in epb_shade),
+ * background pixels shade * env along the view ray, so the background next to
+ * the points receives a dark outline.
+ */
+int epb_edl(const float *depth, const void *color, epb_dtype color_dtype, const epb_camera *cam,
+            const void *ao, epb_dtype ao_dtype, const epb_edl_params *params, const epb_cube *env,
+            void *hdr_out, epb_dtype hdr_dtype, hipStream_t stream);
 
 /* Bytes of scratch the operation needs for a W x H image (for
  * EPB_OP_PRECOMPUTE_IBL pass the environment size as W and H and an

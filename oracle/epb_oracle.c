@@ -848,6 +848,17 @@ double orc_aces(double x) {
 }
 
 /* Exposure, ACES, clamp to [0, 1], gamma 1/g, round half up to 8 bits. */
+/* Reinhard's global operator, per channel (the paper's second tone curve). */
+double orc_reinhard(double x) { return x / (1.0 + x); }
+
+int orc_encode_u8_op(double x, double exposure, double gamma, int tonemap) {
+    double e = exposure * x;
+    double y = clampd(tonemap == 1 ? orc_reinhard(e) : orc_aces(e), 0.0, 1.0);
+    double g = pow(y, 1.0 / gamma);
+    int q = (int)floor(255.0 * g + 0.5);
+    return q < 0 ? 0 : (q > 255 ? 255 : q);
+}
+
 int orc_encode_u8(double x, double exposure, double gamma) {
     double y = clampd(orc_aces(exposure * x), 0.0, 1.0);
     double g = pow(y, 1.0 / gamma);
@@ -872,7 +883,7 @@ static void binomial_pass(const double *src, double *dst, int w, int h, int hori
 }
 
 void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double threshold,
-                       double strength, double exposure, double gamma, uint8_t *ldr,
+                       double strength, double exposure, double gamma, int tonemap, uint8_t *ldr,
                        double *composite, double *pyramid) {
     size_t plane = (size_t)W * H;
     int nl = levels - 1; /* levels 1 .. levels-1 are built, blurred and added back */
@@ -951,7 +962,7 @@ void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double thres
             }
             for (int c = 0; c < 3; ++c) {
                 if (composite) composite[c * plane + p] = C[c];
-                ldr[4 * p + c] = (uint8_t)orc_encode_u8(C[c], exposure, gamma);
+                ldr[4 * p + c] = (uint8_t)orc_encode_u8_op(C[c], exposure, gamma, tonemap);
             }
             ldr[4 * p + 3] = 255;
         }

@@ -56,7 +56,10 @@ double orc_texel_solid_angle(int i, int j, int S);
 double orc_ggx_D(double NoH, double alpha);
 void orc_brdf_lut_point(double NoV, double rough, int samples, double AB[2]);
 double orc_aces(double x);
+double orc_reinhard(double x);
 int orc_encode_u8(double x, double exposure, double gamma);
+/* tonemap 0: ACES, 1: Reinhard */
+int orc_encode_u8_op(double x, double exposure, double gamma, int tonemap);
 
 /* a1 image-based-lighting precompute */
 void orc_env_downsample(const double *src, int S, double *dst);
@@ -126,7 +129,7 @@ void orc_edl(const double *depth, const double *color, const orc_camera *cam, co
 /* a5 / a6 bloom, composite, tonemap.  pyramid (optional) receives the blurred
  * levels 1..levels-1 as planar [3][H_l][W_l] blocks one after another. */
 void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double threshold,
-                       double strength, double exposure, double gamma, uint8_t *ldr,
+                       double strength, double exposure, double gamma, int tonemap, uint8_t *ldr,
                        double *composite, double *pyramid);
 
 #endif

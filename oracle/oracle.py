@@ -81,6 +81,10 @@ def lib():
         L.orc_aces.restype = C.c_double
         L.orc_encode_u8.argtypes = [C.c_double, C.c_double, C.c_double]
         L.orc_encode_u8.restype = C.c_int
+        L.orc_reinhard.argtypes = [C.c_double]
+        L.orc_reinhard.restype = C.c_double
+        L.orc_encode_u8_op.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
+        L.orc_encode_u8_op.restype = C.c_int
         L.orc_env_downsample.argtypes = [_D, C.c_int, _D]
         L.orc_irradiance.argtypes = [_D, C.c_int, _D, C.c_int]
         L.orc_prefilter.argtypes = [_D, C.c_int, _D, _D, C.c_int, C.c_int, C.c_int, C.c_double]
@@ -98,7 +102,7 @@ def lib():
         L.orc_edl.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, _D, C.c_int, C.c_int, C.c_double,
                               C.c_double, _D, C.c_int, C.c_double, _D, _D]
         L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
-                                        C.c_double, C.c_double, C.POINTER(C.c_uint8), _D, _D]
+                                        C.c_double, C.c_double, C.c_int, C.POINTER(C.c_uint8), _D, _D]
         _lib = L
     return _lib
 
@@ -153,8 +157,14 @@ def aces(x: float) -> float:
     return lib().orc_aces(x)
 
 
-def encode_u8(x: float, exposure: float = 1.0, gamma: float = 2.2) -> int:
+def encode_u8(x: float, exposure: float = 1.0, gamma: float = 2.2, tonemap: int = 0) -> int:
+    if tonemap:
+        return lib().orc_encode_u8_op(x, exposure, gamma, tonemap)
     return lib().orc_encode_u8(x, exposure, gamma)
+
+
+def reinhard(x: float) -> float:
+    return lib().orc_reinhard(x)
 
 
 # ---------------------------------------------------------------------------
@@ -370,7 +380,7 @@ def edl(depth, color, cam, ao_lo=None, ao_hi=None, radius=1, n_dirs=8, strength=
 # a5 / a6: bloom + tonemap (monotone, so an interval maps end to end)
 # ---------------------------------------------------------------------------
 def bloom_tonemap(hdr, levels=6, threshold=1.0, strength=0.04, exposure=1.0, gamma=2.2,
-                  want_composite=False, want_pyramid=False):
+                  want_composite=False, want_pyramid=False, tonemap=0):
     hdr = _d(hdr)
     _, H, W = hdr.shape
     ldr = np.zeros((H, W, 4), np.uint8)
@@ -381,7 +391,7 @@ def bloom_tonemap(hdr, levels=6, threshold=1.0, strength=0.04, exposure=1.0, gam
         w, h = (w + 1) // 2, (h + 1) // 2
         sizes.append((h, w))
     pyr = np.zeros(sum(3 * a * b for a, b in sizes)) if want_pyramid else None
-    lib().orc_bloom_tonemap(_p(hdr), W, H, levels, threshold, strength, exposure, gamma,
+    lib().orc_bloom_tonemap(_p(hdr), W, H, levels, threshold, strength, exposure, gamma, tonemap,
                             ldr.ctypes.data_as(C.POINTER(C.c_uint8)),
                             _p(comp) if comp is not None else C.cast(None, _D),
                             _p(pyr) if pyr is not None else C.cast(None, _D))
@@ -411,7 +421,7 @@ def render(view, tie=DEFAULT_TIE, ibl: Optional[dict] = None) -> dict:
     ao_lo, ao_hi = ssao_blur(raw_lo, raw_hi, g["depth"], view.blur_tau)
     hdr_lo, hdr_hi = shade(g, view.cam, ao_lo, ao_hi, view.lights, ibl, view.env, tie)
     post = dict(threshold=view.bloom_threshold, strength=view.bloom_strength,
-                exposure=view.exposure, gamma=view.gamma)
+                exposure=view.exposure, gamma=view.gamma, tonemap=getattr(view, "tonemap", 0))
     lo = bloom_tonemap(hdr_lo, **post)["ldr"]
     hi = bloom_tonemap(hdr_hi, **post)["ldr"]
     return dict(ibl=ibl, ao_raw=(raw_lo, raw_hi), ao=(ao_lo, ao_hi), hdr=(hdr_lo, hdr_hi),

@@ -189,6 +189,7 @@ int check_post_params(const epb_post_params *params) {
     if (!finite(params->threshold) || !finite(params->strength) || !(params->exposure > 0) ||
         !finite(params->exposure) || !(params->gamma > 0) || !finite(params->gamma))
         return EPB_ERR_PARAM;
+    if (params->tonemap != EPB_TONEMAP_ACES && params->tonemap != EPB_TONEMAP_REINHARD) return EPB_ERR_PARAM;
     if (!valid_dtype(params->pyr_dtype)) return EPB_ERR_DTYPE;
     return EPB_OK;
 }
@@ -204,8 +205,8 @@ int build_post(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32_t heig
     epb::PostPlan plan = epb::post_plan(width, height, params->bloom_levels, params->pyr_dtype);
     if (!scratch || scratch_bytes < plan.bytes) return EPB_ERR_SCRATCH;
     if (!aligned16(scratch)) return EPB_ERR_ALIGN;
-    *out = epb::post_desc(plan, hdr, params->threshold, params->strength, params->exposure, params->gamma, ldr_out,
-                          scratch);
+    *out = epb::post_desc(plan, hdr, params->threshold, params->strength, params->exposure, params->gamma,
+                          params->tonemap, ldr_out, scratch);
     return EPB_OK;
 }
 
@@ -275,6 +276,53 @@ const char *epb_status_str(int status) {
 }
 
 int epb_last_hip_error(void) { return g_last_hip_error; }
+
+// Neighbour offsets of eye-dome lighting: the direction 2 pi k / n rounded to the
+// nearest pixel at the radius, halves away from zero (1e-9 slack at halves).
+static int edl_round(double v) {
+    double m = std::floor(std::fabs(v) + 0.5 + 1e-9);
+    return (int)(v < 0 ? -m : m);
+}
+
+int epb_edl(const float *depth, const void *color, epb_dtype color_dtype, const epb_camera *cam,
+            const void *ao, epb_dtype ao_dtype, const epb_edl_params *params, const epb_cube *env,
+            void *hdr_out, epb_dtype hdr_dtype, hipStream_t stream) {
+    if (!depth || !color || !cam || !params || !hdr_out) return EPB_ERR_NULL;
+    int st = check_camera(cam);
+    if (st) return st;
+    if (!valid_dtype(color_dtype) || !valid_dtype(ao_dtype) || !valid_dtype(hdr_dtype)) return EPB_ERR_DTYPE;
+    if (params->radius < 1 || params->radius > EPB_MAX_EDL_RADIUS || params->n_dirs < 1 ||
+        params->n_dirs > EPB_MAX_EDL_DIRS)
+        return EPB_ERR_PARAM;
+    if (!finite(params->strength) || params->strength < 0 || !finite(params->far_depth) || !(params->far_depth > 0))
+        return EPB_ERR_PARAM;
+    if (env && (st = check_cube(env, 1, 2))) return st;
+    if (!aligned16(depth) || !aligned16(color) || (ao && !aligned16(ao)) || !aligned16(hdr_out))
+        return EPB_ERR_ALIGN;
+    epb::HostCam hc = host_cam(cam);
+    epb::EdlDesc c{};
+    c.depth = depth; c.color = color; c.ao = ao; c.hdr = hdr_out;
+    c.env = env ? (const float4 *)env->data : nullptr;
+    for (int i = 0; i < 9; ++i) c.R[i] = hc.R[i];
+    c.cx = hc.cx; c.cy = hc.cy; c.inv_fx = hc.inv_fx; c.inv_fy = hc.inv_fy;
+    c.W = cam->width; c.H = cam->height; c.Wh = (c.W + 1) / 2; c.Hh = (c.H + 1) / 2;
+    c.env_size = env ? env->size : 0;
+    c.f_env = (float)c.env_size;
+    c.radius = params->radius;
+    c.n_dirs = params->n_dirs;
+    c.neg_strength_over_n = (float)(-(double)params->strength / params->n_dirs);
+    c.far_depth = params->far_depth;
+    const double two_pi = 6.283185307179586476925286766559;
+    int pitch = 32 + 2 * params->radius;  // LDS tile pitch of the kernel (32-pixel rows + halo)
+    for (int k = 0; k < params->n_dirs; ++k) {
+        double a = two_pi * k / params->n_dirs;
+        int dx = edl_round(params->radius * std::cos(a)), dy = edl_round(params->radius * std::sin(a));
+        if (dx < -params->radius || dx > params->radius || dy < -params->radius || dy > params->radius)
+            return EPB_ERR_PARAM;  // cannot happen: |round(r cos a)| <= r
+        c.loff[k] = dy * pitch + dx;
+    }
+    return hip_status(epb::launch_edl(c, color_dtype, ao_dtype, hdr_dtype, stream));
+}
 
 size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *params) {
     if (width < 1 || height < 1 || width > EPB_MAX_IMAGE_SIZE || height > EPB_MAX_IMAGE_SIZE) return 0;

@@ -72,8 +72,27 @@ struct PostDesc {
     void *blur[EPB_MAX_BLOOM_LEVELS];  // blurred level texels
     int blk_start[EPB_MAX_BLOOM_LEVELS + 1];  // first blur work item of each level
     float threshold, strength, exposure, inv_gamma;
+    int tonemap;  // EPB_TONEMAP_ACES or EPB_TONEMAP_REINHARD
     const void *hdr;
     uint32_t *ldr;
+};
+
+// Eye-dome lighting of a depth map with per-pixel colour.
+struct EdlDesc {
+    const float *depth;
+    const void *color;  // [3][H][W]
+    const void *ao;     // half resolution, may be null
+    void *hdr;
+    const float4 *env;  // level 0 shown behind the cloud, may be null
+    float R[9];
+    float cx, cy, inv_fx, inv_fy;
+    int W, H, Wh, Hh;
+    int env_size;
+    float f_env;
+    int radius, n_dirs;
+    float neg_strength_over_n;  // -strength / n_dirs
+    float far_depth;
+    int loff[EPB_MAX_EDL_DIRS];  // LDS index delta of each neighbour (tile pitch 32 + 2 radius)
 };
 
 // Ray-cast pass: sphere field, double-precision camera, destination planes.

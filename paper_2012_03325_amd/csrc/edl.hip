@@ -1,0 +1,112 @@
+// Eye-dome lighting (paper Sec. 4.3): the compositing step for depth-only
+// renders such as point clouds, where no normals exist for PBR.  A pixel is
+// darkened by how far it lies behind its screen-space neighbours on a log
+// depth scale: shade = 2^(-strength * mean_k max(0, log2 d_p - log2 d_q)) over
+// n_dirs neighbours at a fixed pixel radius (neighbours outside the image add
+// nothing); background and depths beyond far_depth count as far_depth, so the
+// background right next to the cloud gets a dark outline.  Foreground pixels
+// return shade * AO * colour, background pixels shade * environment.
+//
+// gfx950 mapping: one thread per pixel in 32x8 tiles (a wavefront = 32x2
+// pixels, two 128-byte row segments of every plane); the tile's log depths
+// plus a halo of the radius are computed once per texel into LDS (log2 taken
+// once per texel, not once per neighbour read), texels outside the image hold
+// +inf so that they add max(0, z - inf) = 0 without a branch.  The neighbour
+// offsets are LDS index deltas precomputed on the host for the tile pitch and
+// read from the kernel arguments with scalar loads.  The kernel streams
+// depth + colour + AO in and HDR out once: HBM-bound.
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace epb {
+
+constexpr int kEdlTx = 32, kEdlTy = 8;
+constexpr int kEdlPitchMax = kEdlTx + 2 * EPB_MAX_EDL_RADIUS;
+constexpr int kEdlRowsMax = kEdlTy + 2 * EPB_MAX_EDL_RADIUS;
+
+template <typename TG, typename TA, typename TH>
+__global__ void __launch_bounds__(kEdlTx *kEdlTy) k_edl(const EdlDesc c, int tiles) {
+    __shared__ float z[kEdlPitchMax * kEdlRowsMax];
+    int tile = xcd_tile(blockIdx.x, tiles);
+    int tiles_x = (c.W + kEdlTx - 1) / kEdlTx;
+    int ty = tile / tiles_x;
+    int X0 = (tile - ty * tiles_x) * kEdlTx, Y0 = ty * kEdlTy;
+    int t = (int)threadIdx.x;
+    int r = c.radius, pitch = kEdlTx + 2 * r, area = pitch * (kEdlTy + 2 * r);
+    // log depths of the tile and its halo (one log2 per texel)
+    for (int q = t; q < area; q += kEdlTx * kEdlTy) {
+        int ry = q / pitch, rx = q - ry * pitch;
+        int gx = X0 - r + rx, gy = Y0 - r + ry;
+        float v = __builtin_inff();
+        if (gx >= 0 && gx < c.W && gy >= 0 && gy < c.H)
+            v = log2f(fminf(ldf(c.depth, __umul24((unsigned)gy, (unsigned)c.W) + (unsigned)gx), c.far_depth));
+        z[q] = v;
+    }
+    __syncthreads();
+    int lx = t % kEdlTx, ly = t / kEdlTx;
+    int x = X0 + lx, y = Y0 + ly;
+    if (x >= c.W || y >= c.H) return;
+    int centre = (ly + r) * pitch + lx + r;
+    float zp = z[centre];
+    float acc = 0.0f;
+    for (int k = 0; k < c.n_dirs; ++k) acc += fmaxf(zp - z[centre + c.loff[k]], 0.0f);
+    float shade = exp2f(c.neg_strength_over_n * acc);
+    unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
+    unsigned plane = (unsigned)c.W * (unsigned)c.H;
+    float out[3] = {0.0f, 0.0f, 0.0f};
+    float d = ldf(c.depth, p);
+    if (__builtin_isinf(d)) {
+        if (c.env) {
+            float dvx = ((float)x + 0.5f - c.cx) * c.inv_fx;
+            float dvy = -((float)y + 0.5f - c.cy) * c.inv_fy;
+            v3 dw = mul_Rt(c.R, mk3(dvx, dvy, -1.0f));
+            float4 e = cube_bilinear(c.env, c.env_size, c.f_env, dw);
+            out[0] = shade * e.x; out[1] = shade * e.y; out[2] = shade * e.z;
+        }
+    } else {
+        float ao = 1.0f;
+        if (c.ao) {  // bilinear upsampling at (x / 2, y / 2), clamped, as in shading
+            const TA *aop = (const TA *)c.ao;
+            unsigned x0 = x >> 1, y0 = y >> 1;
+            unsigned dx = (x & 1) && (int)x0 + 1 < c.Wh ? 1u : 0u;
+            unsigned dy = (y & 1) && (int)y0 + 1 < c.Hh ? (unsigned)c.Wh : 0u;
+            unsigned q = __umul24(y0, (unsigned)c.Wh) + x0;
+            float a00 = ldf(aop, q), a10 = ldf(aop, q + dx), a01 = ldf(aop, q + dy), a11 = ldf(aop, q + dy + dx);
+            float wx = (x & 1) ? 0.5f : 0.0f, wy = (y & 1) ? 0.5f : 0.0f;
+            float top = fmaf(wx, a10 - a00, a00), bot = fmaf(wx, a11 - a01, a01);
+            ao = fmaf(wy, bot - top, top);
+        }
+        const TG *col = (const TG *)c.color;
+        float s = shade * ao;
+        out[0] = s * ldf(col, p);
+        out[1] = s * ldf(col, plane + p);
+        out[2] = s * ldf(col, 2 * plane + p);
+    }
+    TH *hdr = (TH *)c.hdr;
+    stf(hdr, p, out[0]);
+    stf(hdr, plane + p, out[1]);
+    stf(hdr, 2 * plane + p, out[2]);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <typename TG, typename TA>
+static void go_h(const EdlDesc &c, epb_dtype hd, int tiles, hipStream_t s) {
+    if (hd == EPB_F32) hipLaunchKernelGGL((k_edl<TG, TA, float>), dim3(tiles), dim3(kEdlTx * kEdlTy), 0, s, c, tiles);
+    else hipLaunchKernelGGL((k_edl<TG, TA, __half>), dim3(tiles), dim3(kEdlTx * kEdlTy), 0, s, c, tiles);
+}
+template <typename TG>
+static void go_a(const EdlDesc &c, epb_dtype ad, epb_dtype hd, int tiles, hipStream_t s) {
+    if (ad == EPB_F32) go_h<TG, float>(c, hd, tiles, s);
+    else go_h<TG, __half>(c, hd, tiles, s);
+}
+
+hipError_t launch_edl(const EdlDesc &c, epb_dtype cdtype, epb_dtype ao_dtype, epb_dtype hdr_dtype, hipStream_t s) {
+    int tiles = ceil_div(c.W, kEdlTx) * ceil_div(c.H, kEdlTy);
+    if (cdtype == EPB_F32) go_a<float>(c, ao_dtype, hdr_dtype, tiles, s);
+    else go_a<__half>(c, ao_dtype, hdr_dtype, tiles, s);
+    return hipGetLastError();
+}
+
+}  // namespace epb

@@ -89,10 +89,13 @@ struct PostPlan {
 };
 PostPlan post_plan(int W, int H, int levels, epb_dtype pyr_dtype);
 PostDesc post_desc(const PostPlan &q, const void *hdr, float threshold, float strength, float exposure,
-                   float gamma, uint8_t *ldr, void *scratch);
+                   float gamma, int tonemap, uint8_t *ldr, void *scratch);
 int post_items(const PostDesc &c, int stage);
 hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s);
 hipError_t launch_post_batch(const BatchHeader &h, const void *table, hipStream_t s);
+
+// ---- eye-dome lighting (edl.hip) ---------------------------------------------
+hipError_t launch_edl(const EdlDesc &c, epb_dtype cdtype, epb_dtype ao_dtype, epb_dtype hdr_dtype, hipStream_t s);
 
 // ---- ray-cast G-buffers and depth maps (raycast.hip) ------------------------
 hipError_t launch_raycast(const RayScene &s, const RayCam &c, const RayOut &out, epb_dtype dtype, void *scratch,

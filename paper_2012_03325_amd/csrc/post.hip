@@ -195,8 +195,11 @@ __device__ __forceinline__ void bloom_blur_item(const PostDesc &c, int item, Blu
 __device__ __forceinline__ float aces(float x) {
     return x * fmaf(2.51f, x, 0.03f) * rcp(fmaf(x, fmaf(2.43f, x, 0.59f), 0.14f));
 }
-__device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_gamma) {
-    float y = clamp01(aces(exposure * x));
+// Reinhard's global operator on each channel (the paper's alternative curve).
+__device__ __forceinline__ float reinhard(float x) { return x * rcp(1.0f + x); }
+__device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_gamma, int tonemap) {
+    float e = exposure * x;
+    float y = clamp01(tonemap == EPB_TONEMAP_REINHARD ? reinhard(e) : aces(e));
     float g = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(y) * inv_gamma);
     float q = floorf(fmaf(255.0f, g, 0.5f));
     return (uint32_t)fminf(fmaxf(q, 0.0f), 255.0f);
@@ -292,8 +295,9 @@ __device__ __forceinline__ void composite_tile(const PostDesc &c, int tile) {
         float R = fmaf(c.strength, acc[j][0], px[j][0]);
         float G = fmaf(c.strength, acc[j][1], px[j][1]);
         float Bc = fmaf(c.strength, acc[j][2], px[j][2]);
-        uint32_t word = encode8(R, c.exposure, c.inv_gamma) | (encode8(G, c.exposure, c.inv_gamma) << 8) |
-                        (encode8(Bc, c.exposure, c.inv_gamma) << 16) | (255u << 24);
+        uint32_t word = encode8(R, c.exposure, c.inv_gamma, c.tonemap) |
+                        (encode8(G, c.exposure, c.inv_gamma, c.tonemap) << 8) |
+                        (encode8(Bc, c.exposure, c.inv_gamma, c.tonemap) << 16) | (255u << 24);
         unsigned p = __umul24((unsigned)(Y0 + j), (unsigned)c.W) + (unsigned)x;
         sto(c.ldr, p * 4u, word);
     }
@@ -391,7 +395,7 @@ PostPlan post_plan(int W, int H, int levels, epb_dtype pyr_dtype) {
 }
 
 PostDesc post_desc(const PostPlan &q, const void *hdr, float threshold, float strength, float exposure,
-                   float gamma, uint8_t *ldr, void *scratch) {
+                   float gamma, int tonemap, uint8_t *ldr, void *scratch) {
     PostDesc c{};
     c.W = q.W;
     c.H = q.H;
@@ -415,6 +419,7 @@ PostDesc post_desc(const PostPlan &q, const void *hdr, float threshold, float st
     c.strength = strength;
     c.exposure = exposure;
     c.inv_gamma = 1.0f / gamma;
+    c.tonemap = tonemap;
     c.hdr = hdr;
     c.ldr = (uint32_t *)ldr;
     return c;

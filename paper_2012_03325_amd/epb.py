@@ -37,12 +37,16 @@ EPB_OP_SSAO = 1
 EPB_OP_BLOOM_TONEMAP = 2
 EPB_OP_RAYCAST = 3
 EPB_MAX_SPHERES = 65536
+EPB_TONEMAP_ACES = 0
+EPB_TONEMAP_REINHARD = 1
+EPB_MAX_EDL_RADIUS = 16
+EPB_MAX_EDL_DIRS = 32
 
 ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
                 "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
                 "epb_batch_table_bytes", "epb_view_scratch_bytes", "epb_batch_scratch_bytes",
                 "epb_batch_build",
-                "epb_render_batch", "epb_raycast")
+                "epb_render_batch", "epb_raycast", "epb_edl")
 
 
 class EpbError(RuntimeError):
@@ -93,7 +97,8 @@ class epb_light(C.Structure):
 
 class epb_post_params(C.Structure):
     _fields_ = [("bloom_levels", C.c_int32), ("threshold", C.c_float), ("strength", C.c_float),
-                ("exposure", C.c_float), ("gamma", C.c_float), ("pyr_dtype", C.c_int)]
+                ("exposure", C.c_float), ("gamma", C.c_float), ("pyr_dtype", C.c_int),
+                ("tonemap", C.c_int32)]
 
 
 class epb_sphere_scene(C.Structure):
@@ -110,6 +115,11 @@ class epb_view(C.Structure):
                 ("scratch", C.c_void_p)]
 
 
+class epb_edl_params(C.Structure):
+    _fields_ = [("radius", C.c_int32), ("n_dirs", C.c_int32), ("strength", C.c_float),
+                ("far_depth", C.c_float)]
+
+
 class epb_schedule(C.Structure):
     _fields_ = [("shade_tile", C.c_int32), ("ssao_tile", C.c_int32), ("ssao_batch", C.c_int32),
                 ("blocks_per_cu", C.c_int32)]
@@ -119,7 +129,7 @@ STRUCTS = dict(epb_camera=epb_camera, epb_gbuffer=epb_gbuffer, epb_cube=epb_cube
                epb_ibl_params=epb_ibl_params, epb_ibl_maps=epb_ibl_maps,
                epb_ssao_params=epb_ssao_params, epb_light=epb_light,
                epb_post_params=epb_post_params, epb_view=epb_view, epb_schedule=epb_schedule,
-               epb_sphere_scene=epb_sphere_scene)
+               epb_sphere_scene=epb_sphere_scene, epb_edl_params=epb_edl_params)
 
 
 def _load() -> C.CDLL:
@@ -156,8 +166,10 @@ def _load() -> C.CDLL:
     lib.epb_render_batch.argtypes = [P, P, P]
     lib.epb_raycast.argtypes = [C.POINTER(epb_sphere_scene), C.POINTER(epb_camera), C.POINTER(epb_gbuffer), P,
                                 C.c_size_t, P]
+    lib.epb_edl.argtypes = [P, P, C.c_int, C.POINTER(epb_camera), P, C.c_int, C.POINTER(epb_edl_params),
+                            C.POINTER(epb_cube), P, C.c_int, P]
     for fn in ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
-               "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast"):
+               "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast", "epb_edl"):
         getattr(lib, fn).restype = C.c_int
     return lib
 
@@ -273,6 +285,13 @@ def epb_raycast(scene: epb_sphere_scene, cam: epb_camera, out: epb_gbuffer, scra
                 stream=None, check: bool = True) -> int:
     st = lib.epb_raycast(C.byref(scene), C.byref(cam), C.byref(out), _ptr(scratch), scratch_bytes, _stream(stream))
     return _check("epb_raycast", st, check)
+
+
+def epb_edl(depth, color, color_dtype: int, cam: epb_camera, ao, ao_dtype: int, params: epb_edl_params,
+            env: Optional[epb_cube], hdr_out, hdr_dtype: int, stream=None, check: bool = True) -> int:
+    st = lib.epb_edl(_ptr(depth), _ptr(color), color_dtype, C.byref(cam), _ptr(ao), ao_dtype, C.byref(params),
+                     C.byref(env) if env is not None else None, _ptr(hdr_out), hdr_dtype, _stream(stream))
+    return _check("epb_edl", st, check)
 
 
 # ---------------------------------------------------------------------------

@@ -80,9 +80,9 @@ class DevicePost:
 
     def __init__(self, W: int, H: int, bloom_levels=6, threshold=1.0, strength=0.04,
                  exposure=1.0, gamma=2.2, device="cuda", pyr_dtype=E.EPB_F32, scratch=True,
-                 outputs=True):
+                 outputs=True, tonemap=E.EPB_TONEMAP_ACES):
         self.W, self.H = W, H
-        self.post = E.epb_post_params(bloom_levels, threshold, strength, exposure, gamma, pyr_dtype)
+        self.post = E.epb_post_params(bloom_levels, threshold, strength, exposure, gamma, pyr_dtype, tonemap)
         self.ldr = torch.empty((H, W, 4), dtype=torch.uint8, device=device) if outputs else None
         self.scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, W, H, self.post)
         self.scratch = (torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
@@ -168,7 +168,7 @@ class DeviceView:
             self.lights.append(s)
         self.postp = DevicePost(W, H, bloom_levels, view.bloom_threshold, view.bloom_strength,
                                 view.exposure, view.gamma, device, pyr_dtype=hdr_dtype,
-                                scratch=solo_scratch, outputs=outputs)
+                                scratch=solo_scratch, outputs=outputs, tonemap=view.tonemap)
         self.post = self.postp.post
         self.ldr = self.postp.ldr
         self.ao = torch.empty((self.Hh, self.Wh), dtype=_TORCH_DT[ao_dtype], device=device) if outputs else None
@@ -303,3 +303,27 @@ class DeviceScene:
         g = E.epb_gbuffer(W, H, E.EPB_F32, d.data_ptr(), None, None, None, None, None)
         E.epb_raycast(self.struct, _cam_struct(cam), g, self.scratch, self.scratch_bytes, stream)
         return d
+
+
+class DeviceEDL:
+    """A point-cloud render (depth + colour) on the device and the eye-dome
+    lighting call that composes it."""
+
+    def __init__(self, pc, color_dtype=E.EPB_F32, ao_dtype=E.EPB_F32, hdr_dtype=E.EPB_F32, device="cuda",
+                 use_ao: bool = True, use_env: bool = True):
+        H, W = pc.depth.shape
+        self.W, self.H = W, H
+        dev = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to(device).to(dt)
+        self.color_dtype, self.ao_dtype, self.hdr_dtype = color_dtype, ao_dtype, hdr_dtype
+        self.depth = dev(pc.depth)
+        self.color = dev(pc.color, _TORCH_DT[color_dtype])
+        self.ao = dev(pc.ao, _TORCH_DT[ao_dtype]) if use_ao else None
+        self.env = dev(pc.env) if use_env else None
+        self.env_c = E.epb_cube(pc.env.shape[1], 1, self.env.data_ptr()) if use_env else None
+        self.cam = _cam_struct(pc.cam)
+        self.params = E.epb_edl_params(pc.edl_radius, pc.edl_dirs, pc.edl_strength, pc.edl_far)
+        self.hdr = torch.empty((3, H, W), dtype=_TORCH_DT[hdr_dtype], device=device)
+
+    def run(self, stream=None, hdr: Optional[torch.Tensor] = None):
+        E.epb_edl(self.depth, self.color, self.color_dtype, self.cam, self.ao, self.ao_dtype, self.params,
+                  self.env_c, hdr if hdr is not None else self.hdr, self.hdr_dtype, stream)

@@ -400,6 +400,7 @@ class ViewInputs:
     bloom_strength: float = 0.04
     exposure: float = 1.0
     gamma: float = 2.2
+    tonemap: int = 0         # 0 ACES, 1 Reinhard (Sec. 5.4)
     ibl: dict = dataclasses.field(default_factory=lambda: dict(
         irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=1024,
         lut_size=256, lut_samples=1024))
@@ -635,3 +636,69 @@ def surfel_accumulate(view: ViewInputs, seed: int, max_surfels: int = 4, jitter:
     out.gbuf = dict(depth=g["depth"], normal=f32(nsum), albedo=f32(asum), roughness=f32(rsum),
                     metalness=f32(msum), weight=f32(wsum))
     return out
+
+
+# ----------------------------------------------------------------------------
+# point clouds (the depth-only renders eye-dome lighting composes)
+# ----------------------------------------------------------------------------
+@dataclasses.dataclass
+class PointCloudView:
+    name: str
+    cam: Camera
+    depth: np.ndarray   # (H, W) float32 linear view depth of the nearest point, +inf = none
+    color: np.ndarray   # (3, H, W) float32 colour of that point (0 where none)
+    env: np.ndarray     # background cube (6, S, S, 4)
+    ao: np.ndarray      # (Hh, Wh) float32 ambient occlusion in [0.3, 1] (smooth noise)
+    edl_radius: int = 2
+    edl_dirs: int = 8
+    edl_strength: float = 8.0
+    edl_far: float = 1000.0
+
+
+def point_cloud_view(width: int, height: int, n_points: int, seed: int, n_spheres: int = 512,
+                     env_size: int = 64, ground: float = 8.0) -> PointCloudView:
+    """A seeded point cloud sampled from a sphere field and its ground patch,
+    rendered as one-pixel points with a depth test (the nearest point of a pixel
+    wins, an equal depth the lower index): points uniform by area over the sphere
+    surfaces and the square [-ground, ground]^2 of the plane y = 0, coloured by their
+    object's albedo, seen by the 1080p workload's camera.  Sparse clouds leave
+    holes (background) and let far surfaces show through, which is what the
+    eye-dome shading has to make legible."""
+    rng = np.random.default_rng(seed)
+    scene = make_spheres(rng, n_spheres, True)
+    cam = look_at((0.0, 3.5, 8.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, width, height)
+    areas = np.concatenate([4.0 * math.pi * scene.radii ** 2, [(2.0 * ground) ** 2]])
+    obj = rng.choice(len(areas), size=n_points, p=areas / areas.sum())
+    on_plane = obj == n_spheres
+    u = rng.normal(size=(n_points, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    sph = np.minimum(obj, n_spheres - 1)
+    pts = scene.centers[sph] + scene.radii[sph, None] * u
+    pts[on_plane] = np.stack([rng.uniform(-ground, ground, on_plane.sum()), np.zeros(on_plane.sum()),
+                              rng.uniform(-ground, ground, on_plane.sum())], 1)
+    col = np.where(on_plane[:, None], np.asarray(scene.plane_albedo)[None, :], scene.albedo[sph])
+    pv = pts @ cam.R.T + cam.t
+    d = -pv[:, 2]
+    ok = d > 1e-6
+    px = np.floor(cam.cx + cam.fx * pv[:, 0] / np.where(ok, d, 1.0)).astype(np.int64)
+    py = np.floor(cam.cy - cam.fy * pv[:, 1] / np.where(ok, d, 1.0)).astype(np.int64)
+    ok &= (px >= 0) & (px < width) & (py >= 0) & (py < height)
+    idx = np.nonzero(ok)[0]
+    pix = py[idx] * width + px[idx]
+    d32 = d[idx].astype(np.float32)
+    # depth test: positive float32 bit patterns order like the values, so the
+    # smallest (depth bits, point index) key of a pixel is its nearest point
+    key = (d32.view(np.uint32).astype(np.uint64) << np.uint64(32)) | idx.astype(np.uint64)
+    zbuf = np.full(width * height, np.iinfo(np.uint64).max, np.uint64)
+    np.minimum.at(zbuf, pix, key)
+    hit = zbuf != np.iinfo(np.uint64).max
+    win = (zbuf[hit] & np.uint64(0xFFFFFFFF)).astype(np.int64)
+    depth = np.full(width * height, np.inf, np.float32)
+    color = np.zeros((3, width * height), np.float32)
+    depth[hit] = d[win].astype(np.float32)
+    color[:, hit] = col[win].T.astype(np.float32)
+    Wh, Hh = (width + 1) // 2, (height + 1) // 2
+    yy, xx = np.mgrid[0:Hh, 0:Wh]
+    ao = (0.65 + 0.35 * np.sin(0.21 * xx + 0.5 * rng.uniform()) * np.cos(0.17 * yy)).astype(np.float32)
+    return PointCloudView(f"points-{width}x{height}-{n_points}", cam, depth.reshape(height, width),
+                          color.reshape(3, height, width), env_sky_gradient(env_size), ao)

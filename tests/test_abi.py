@@ -168,6 +168,8 @@ def test_bloom_tonemap_validation():
     assert call(pp=E.epb_post_params(0, 1.0, 0.04, 1.0, 2.2)) == E.EPB_ERR_PARAM
     assert call(pp=E.epb_post_params(6, 1.0, 0.04, 0.0, 2.2)) == E.EPB_ERR_PARAM
     assert call(pp=E.epb_post_params(6, 1.0, 0.04, 1.0, float("nan"))) == E.EPB_ERR_PARAM
+    assert call(pp=E.epb_post_params(6, 1.0, 0.04, 1.0, 2.2, E.EPB_F32, 2)) == E.EPB_ERR_PARAM
+    assert call(pp=E.epb_post_params(6, 1.0, 0.04, 1.0, 2.2, E.EPB_F32, -1)) == E.EPB_ERR_PARAM
     assert call(out=FAKE + 1) == E.EPB_ERR_ALIGN
     assert call(n=need - 1) == E.EPB_ERR_SCRATCH
 
@@ -358,3 +360,34 @@ def test_raycast_validation():
     # no spheres: no sphere arrays needed
     empty = E.epb_sphere_scene(0, None, None, None, None, None, 1, pa, 0.6, 0.0)
     assert E.epb_scratch_bytes(E.EPB_OP_RAYCAST, 64, 48, empty) > 0
+
+
+def test_edl_validation():
+    cam = _cam(64, 48)
+    ok = E.epb_edl_params(2, 8, 6.0, 1000.0)
+    env = E.epb_cube(8, 1, FAKE)
+
+    def call(depth=FAKE, color=FAKE, cd=E.EPB_F32, c=cam, ao=None, ad=E.EPB_F32, p=ok, e=env, hdr=FAKE,
+             hd=E.EPB_F32):
+        return E.lib.epb_edl(depth, color, cd, C.byref(c) if c is not None else None, ao, ad,
+                             C.byref(p) if p is not None else None, C.byref(e) if e is not None else None,
+                             hdr, hd, None)
+
+    assert call(depth=None) == E.EPB_ERR_NULL
+    assert call(color=None) == E.EPB_ERR_NULL
+    assert call(c=None) == E.EPB_ERR_NULL
+    assert call(p=None) == E.EPB_ERR_NULL
+    assert call(hdr=None) == E.EPB_ERR_NULL
+    assert call(c=_cam(0, 48)) == E.EPB_ERR_SIZE
+    assert call(cd=7) == E.EPB_ERR_DTYPE
+    assert call(hd=2) == E.EPB_ERR_DTYPE
+    for bad in (E.epb_edl_params(0, 8, 6.0, 1000.0), E.epb_edl_params(E.EPB_MAX_EDL_RADIUS + 1, 8, 6.0, 1000.0),
+                E.epb_edl_params(2, 0, 6.0, 1000.0), E.epb_edl_params(2, E.EPB_MAX_EDL_DIRS + 1, 6.0, 1000.0),
+                E.epb_edl_params(2, 8, -1.0, 1000.0), E.epb_edl_params(2, 8, float("inf"), 1000.0),
+                E.epb_edl_params(2, 8, 6.0, 0.0), E.epb_edl_params(2, 8, 6.0, float("nan"))):
+        assert call(p=bad) == E.EPB_ERR_PARAM
+    assert call(e=E.epb_cube(8, 1, None)) == E.EPB_ERR_NULL
+    assert call(e=E.epb_cube(1, 1, FAKE)) == E.EPB_ERR_SIZE
+    assert call(depth=FAKE + 4) == E.EPB_ERR_ALIGN
+    assert call(ao=FAKE + 8) == E.EPB_ERR_ALIGN
+    assert call(hdr=FAKE + 2) == E.EPB_ERR_ALIGN

@@ -437,6 +437,28 @@ def test_aces_and_u8_table():
     assert np.all(np.diff([O.aces(x) for x in grid]) > 0)
 
 
+def test_reinhard_curve_by_hand():
+    """Reinhard's global operator x / (1 + x): 1 maps to 1/2, whose 8-bit code
+    after gamma 2.2 is floor(255 * 0.5^(1/2.2) + .5) = floor(186.57) = 186 (worked
+    by hand); 3 maps to 3/4 -> floor(255 * 0.877 + .5) = 224; 0 -> 0; the curve
+    never reaches 1, so only x >= 254.5^2.2-level radiance rounds to 255;
+    exposure scales the input; and it is monotone."""
+    assert O.reinhard(1.0) == 0.5 and O.reinhard(3.0) == 0.75 and O.reinhard(0.0) == 0.0
+    assert O.encode_u8(1.0, 1.0, 2.2, tonemap=1) == 186
+    assert O.encode_u8(3.0, 1.0, 2.2, tonemap=1) == 224
+    assert O.encode_u8(0.0, 1.0, 2.2, tonemap=1) == 0
+    assert O.encode_u8(0.5, 2.0, 2.2, tonemap=1) == 186
+    assert O.encode_u8(1e9, 1.0, 2.2, tonemap=1) == 255
+    xs = np.geomspace(1e-4, 1e4, 400)
+    codes = [O.encode_u8(float(x), 1.0, 2.2, tonemap=1) for x in xs]
+    assert all(a <= b for a, b in zip(codes, codes[1:]))
+    # the frame path applies the same curve: a constant field below the bloom
+    # threshold composes to itself and encodes pixel by pixel
+    hdr = np.full((3, 5, 7), 0.8)
+    out = O.bloom_tonemap(hdr, tonemap=1)["ldr"]
+    assert (out[..., :3] == O.encode_u8(0.8, 1.0, 2.2, tonemap=1)).all()
+
+
 def test_bloom_adds_nothing_below_threshold():
     rng = np.random.default_rng(5)
     hdr = rng.uniform(0, 0.99, (3, 37, 53))

@@ -235,6 +235,26 @@ def test_bloom_tonemap_parity(shape, levels):
     log(f"[bloom] {W}x{H}: exact {100 * exact:.3f}%")
 
 
+@pytest.mark.parametrize("shape", [(333, 199), (1920, 1080)])
+def test_bloom_tonemap_reinhard_parity(shape):
+    """The Reinhard curve (Sec. 5.4's second tone mapper) through the same
+    composite: 8-bit codes within +-1 of the oracle on every pixel."""
+    W, H = shape
+    rng = np.random.default_rng(W * 11 + H)
+    hdr = _f32(10.0 ** rng.uniform(-2, 1.5, (3, H, W)))
+    ref = O.bloom_tonemap(hdr, levels=6, exposure=0.5, tonemap=1)
+    fr = _frame()
+    dp = fr.DevicePost(W, H, bloom_levels=6, exposure=0.5, tonemap=1)
+    log(f"[reinhard] {W}x{H}")
+    dp.run(torch.from_numpy(hdr).cuda())
+    torch.cuda.synchronize()
+    ldr = dp.ldr.cpu().numpy()
+    frac, exact = assert_ldr(f"reinhard {W}x{H}", ldr, ref["ldr"], ref["ldr"], min_frac=1.0)
+    aces = O.bloom_tonemap(hdr, levels=6, exposure=0.5)["ldr"]
+    assert (np.abs(aces[..., :3].astype(int) - ldr[..., :3].astype(int)) > 1).any()  # the curve is in use
+    log(f"[reinhard] {W}x{H}: exact {100 * exact:.3f}%")
+
+
 # ---------------------------------------------------------------------------
 # the whole pass
 # ---------------------------------------------------------------------------
