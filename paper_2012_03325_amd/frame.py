@@ -281,6 +281,16 @@ class DeviceScene:
         self.scratch_bytes = E.epb_scratch_bytes(E.EPB_OP_RAYCAST, 1, 1, self.struct)
         self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
         self.device = device
+        self.version = 0  # bumped whenever the geometry changes (shadow maps go stale)
+
+    def move(self, centers=None, radii=None):
+        """Replace sphere centres and/or radii in place (same count); every depth
+        map rendered before is stale afterwards."""
+        if centers is not None:
+            self.center.copy_(torch.from_numpy(np.ascontiguousarray(centers, np.float64).reshape(self.n, 3)))
+        if radii is not None:
+            self.radius.copy_(torch.from_numpy(np.ascontiguousarray(radii, np.float64).reshape(self.n)))
+        self.version += 1
 
     def render_gbuffer(self, cam, dtype=E.EPB_F32, stream=None) -> dict:
         """G-buffer planes (torch tensors) of the scene seen by ``cam``."""
@@ -327,3 +337,44 @@ class DeviceEDL:
     def run(self, stream=None, hdr: Optional[torch.Tensor] = None):
         E.epb_edl(self.depth, self.color, self.color_dtype, self.cam, self.ao, self.ao_dtype, self.params,
                   self.env_c, hdr if hdr is not None else self.hdr, self.hdr_dtype, stream)
+
+
+class ShadowCache:
+    """Depth maps of the lights of one scene, kept between frames and rendered
+    again only when the scene's geometry or the light's camera changed (the
+    paper's shadow maps are updated only when objects or lights move, Sec. 5.1).
+
+    ``scene`` provides ``version`` (bumped on every geometry change) and
+    ``render_depth(cam, out=None, stream=None)``; ``maps(cams)`` returns one
+    depth map per light camera, reusing the stored map of a light whose camera
+    and scene version are those it was rendered with.  ``renders`` counts the
+    depth renders issued."""
+
+    def __init__(self, scene):
+        self.scene = scene
+        self._entries = {}  # light index -> (camera key, scene version, map)
+        self.renders = 0
+
+    @staticmethod
+    def _key(cam) -> tuple:
+        return (tuple(np.asarray(cam.world_to_cam, np.float64).reshape(-1).tolist()), float(cam.fx), float(cam.fy),
+                float(cam.cx), float(cam.cy), int(cam.width), int(cam.height))
+
+    def maps(self, cams, stream=None) -> list:
+        out = []
+        for i, cam in enumerate(cams):
+            key = self._key(cam)
+            ent = self._entries.get(i)
+            if ent is not None and ent[0] == key and ent[1] == self.scene.version:
+                out.append(ent[2])
+                continue
+            reuse = ent[2] if ent is not None and tuple(ent[2].shape) == (cam.height, cam.width) else None
+            m = self.scene.render_depth(cam, out=reuse, stream=stream)
+            self.renders += 1
+            self._entries[i] = (key, self.scene.version, m)
+            out.append(m)
+        return out
+
+    def invalidate(self):
+        """Forget every stored map (the next call renders all of them)."""
+        self._entries.clear()

@@ -64,7 +64,29 @@ def _make_view(kind):
                                     n_spheres=8)
     if kind == "full-1080p":
         return synth.config_1080p()
+    if kind == "auto-params-160x120":
+        return _auto_params_view()
     raise KeyError(kind)
+
+
+def _auto_params_view():
+    """A scene lit and framed by the automatic parameters (Sec. 6): fitted
+    camera, key/fill/rim lights with depth maps, SSAO radius 5 % of the scale."""
+    from paper_2012_03325_amd import autoparams as A
+    rng = np.random.default_rng(21)
+    sc = synth.make_spheres(rng, 30, True)
+    b = A.sphere_bounds(sc)
+    cam = A.fit_camera(b, (0.2, 0.6, 1.0), 160, 120)
+    lights = A.three_point_lights(b, cam, radiance=3.0)
+    for L in lights:
+        L.shadow_cam = synth.look_at(L.pos, b.center, (0.0, 1.0, 0.0), 90.0, 128, 128)
+        L.shadow_map = synth.raycast(sc, L.shadow_cam, depth_only=True)["depth"]
+    krng = np.random.default_rng(21 + 10000)
+    v = synth.ViewInputs("auto-params-160x120", cam, synth.raycast(sc, cam), lights, synth.env_sky_gradient(16),
+                         synth.ssao_kernel(krng, 16), synth.ssao_noise(krng), ssao_radius=A.ssao_radius(b))
+    v.ibl = dict(irr_size=8, irr_src_size=16, pref_size=16, pref_levels=4, pref_samples=256, lut_size=32,
+                 lut_samples=256)
+    return v
 
 
 def _oracle_ibl_small(view):
@@ -259,7 +281,7 @@ def test_bloom_tonemap_reinhard_parity(shape):
 # the whole pass
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "tiny-3x2", "strip-16384x2",
-                                  "full-1080p"])
+                                  "auto-params-160x120", "full-1080p"])
 def test_end_to_end(kind):
     v = _view(kind)
     ref = O.render(v)

@@ -139,3 +139,36 @@ def test_raycast_then_render_matches_the_oracle_pipeline():
     log("[raycast] cast + render 160x96")
     assert_interval("cast+render HDR", dv.hdr.cpu().numpy(), *ref["hdr"], min_frac=0.999)
     assert_ldr("cast+render LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
+
+
+def test_shadow_cache_on_device():
+    """Cached depth maps equal fresh renders; a moved sphere re-renders every
+    map, a moved light only its own, an unchanged frame none."""
+    from paper_2012_03325_amd import frame
+    rng = np.random.default_rng(5)
+    spheres = synth.make_spheres(rng, 64, True)
+    scene = frame.DeviceScene(spheres)
+    cams = [synth.look_at((6.0 * np.cos(a), 6.0, 6.0 * np.sin(a)), (0, 0, 0), (0, 1, 0), 90.0, 96, 96)
+            for a in (0.8, 2.4, 3.9, 5.5)]
+    cache = frame.ShadowCache(scene)
+    log("[shadow-cache] first frame")
+    m0 = [m.clone() for m in cache.maps(cams)]
+    torch.cuda.synchronize()
+    for m, c in zip(m0, cams):
+        assert torch.equal(m, scene.render_depth(c))
+    cache.maps(cams)
+    assert cache.renders == 4
+    cams[1] = synth.look_at((2.0, 7.0, -5.0), (0, 0, 0), (0, 1, 0), 90.0, 96, 96)
+    m1 = cache.maps(cams)
+    assert cache.renders == 5
+    torch.cuda.synchronize()
+    assert torch.equal(m1[1], scene.render_depth(cams[1]))
+    centers = spheres.centers.copy()
+    centers[:, 1] += 0.25  # lift every sphere
+    scene.move(centers=centers)
+    m2 = [m.clone() for m in cache.maps(cams)]
+    assert cache.renders == 9
+    torch.cuda.synchronize()
+    for m, c, old in zip(m2, cams, m0):
+        assert torch.equal(m, scene.render_depth(c))
+    assert not torch.equal(m2[0], m0[0])
