@@ -288,8 +288,33 @@ void orc_irradiance(const double *src, int S_src, double *out, int S_out) {
  * directions from a Hammersley sequence, looked up bilinearly in level 0.  A
  * sample whose cube-face choice is within the tie margin contributes the
  * smaller face value to lo and the larger to hi. */
+/* Prefiltered chain.  With fis == 0 every GGX sample reads the environment
+ * itself (level 0).  With fis != 0 (filtered importance sampling, Krivanek and
+ * Colbert 2008) a sample reads a pre-blurred copy instead: the environment
+ * chain (level m = solid-angle-weighted 2x2 means of level m - 1, down to 2x2
+ * faces) at the level whose texels subtend the solid angle the sample stands
+ * for, lod = 1/2 log2(omega_s / omega_p) + 1 with omega_s = 1 / (N pdf),
+ * omega_p = 4 pi / (6 S^2) the base texel's mean solid angle and pdf the density
+ * of the reflected direction, D(n.h) (n.h) / (4 v.h) = D / 4 for v = n; clamped
+ * to the chain and read trilinearly. */
 void orc_prefilter(const double *env, int S, double *out_lo, double *out_hi, int base, int levels,
-                   int samples, double tie_rel) {
+                   int samples, double tie_rel, int fis) {
+    int M = 0; /* last level of the environment chain (faces of at least 2x2) */
+    while ((S >> (M + 1)) >= 2) ++M;
+    double *chain = NULL;
+    if (fis) {
+        size_t tot = 0;
+        for (int m = 0; m <= M; ++m) tot += (size_t)6 * (S >> m) * (S >> m) * 4;
+        chain = malloc(sizeof(double) * tot);
+        memcpy(chain, env, sizeof(double) * 6 * (size_t)S * S * 4);
+        size_t o = 0;
+        for (int m = 1; m <= M; ++m) {
+            size_t prev = (size_t)6 * (S >> (m - 1)) * (S >> (m - 1)) * 4;
+            orc_env_downsample(chain + o, S >> (m - 1), chain + o + prev);
+            o += prev;
+        }
+    }
+    double omega_p = 4.0 * PI / (6.0 * S * S);
     size_t off = 0;
     for (int m = 0; m < levels; ++m) {
         int sm = base >> m;
@@ -311,7 +336,14 @@ void orc_prefilter(const double *env, int S, double *out_lo, double *out_hi, int
                 for (int c = 0; c < 3; ++c) l[c] = 2.0 * vh * h[c] - n[c];
                 double nl = dot3(n, l);
                 if (nl > 0.0) {
-                    cube_bilinear_iv(env, S, l, tie_rel, Llo, Lhi);
+                    if (fis && alpha > 0.0) {
+                        double pdf = orc_ggx_D(vh, alpha) * vh / (4.0 * vh);
+                        double omega_s = 1.0 / (samples * pdf);
+                        double lod = clampd(0.5 * log2(omega_s / omega_p) + 1.0, 0.0, (double)M);
+                        chain_trilinear_iv(chain, S, M + 1, l, lod, tie_rel, Llo, Lhi);
+                    } else {
+                        cube_bilinear_iv(env, S, l, tie_rel, Llo, Lhi);
+                    }
                     for (int c = 0; c < 3; ++c) { alo[c] += Llo[c] * nl; ahi[c] += Lhi[c] * nl; }
                     w += nl;
                 }
@@ -322,6 +354,7 @@ void orc_prefilter(const double *env, int S, double *out_lo, double *out_hi, int
         }
         off += (size_t)6 * sm * sm * 4;
     }
+    free(chain);
 }
 
 /* Split-sum environment BRDF (Karis 2013): with N = +z and V in the xz plane at

@@ -64,8 +64,10 @@ int orc_encode_u8_op(double x, double exposure, double gamma, int tonemap);
 /* a1 image-based-lighting precompute */
 void orc_env_downsample(const double *src, int S, double *dst);
 void orc_irradiance(const double *src, int S_src, double *out, int S_out);
+/* fis != 0: filtered importance sampling (each sample reads the environment's
+ * solid-angle-weighted mip chain at the level its pdf asks for). */
 void orc_prefilter(const double *env, int S, double *out_lo, double *out_hi, int base, int levels,
-                   int samples, double tie_rel);
+                   int samples, double tie_rel, int fis);
 void orc_brdf_lut(double *out, int size, int samples);
 
 /* a2 / a3 screen-space ambient occlusion */

@@ -87,7 +87,7 @@ def lib():
         L.orc_encode_u8_op.restype = C.c_int
         L.orc_env_downsample.argtypes = [_D, C.c_int, _D]
         L.orc_irradiance.argtypes = [_D, C.c_int, _D, C.c_int]
-        L.orc_prefilter.argtypes = [_D, C.c_int, _D, _D, C.c_int, C.c_int, C.c_int, C.c_double]
+        L.orc_prefilter.argtypes = [_D, C.c_int, _D, _D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int]
         L.orc_brdf_lut.argtypes = [_D, C.c_int, C.c_int]
         L.orc_ssao_raw.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, C.c_int, _D, C.c_double,
                                    C.c_double, C.POINTER(OrcTie), _D, _D]
@@ -194,14 +194,15 @@ def irradiance(src, out_size: int) -> np.ndarray:
 
 
 def prefilter(env, base: int, levels: int, samples: int, tie=DEFAULT_TIE,
-              with_hi: bool = False):
+              with_hi: bool = False, fis: bool = False):
     """Prefiltered chain as a list of (6, s, s, 4) levels; with ``with_hi`` also
-    the upper ends of the face-tie intervals."""
+    the upper ends of the face-tie intervals; ``fis`` reads each sample from the
+    environment's mip chain at the level its pdf asks for."""
     env = _d(env)
     total = sum(6 * (base >> m) ** 2 * 4 for m in range(levels))
     lo = np.zeros(total)
     hi = np.zeros(total)
-    lib().orc_prefilter(_p(env), env.shape[1], _p(lo), _p(hi), base, levels, samples, tie[1])
+    lib().orc_prefilter(_p(env), env.shape[1], _p(lo), _p(hi), base, levels, samples, tie[1], 1 if fis else 0)
 
     def split(out):
         res, off = [], 0
@@ -222,13 +223,13 @@ def brdf_lut(size: int, samples: int) -> np.ndarray:
 
 
 def precompute_ibl(env, irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5,
-                   pref_samples=1024, lut_size=256, lut_samples=1024, **_unused) -> dict:
+                   pref_samples=1024, lut_size=256, lut_samples=1024, pref_fis=0, **_unused) -> dict:
     """The whole per-environment precompute (Sec. 3.1)."""
     env = _d(env)
     S = env.shape[1]
     src = irradiance_source(env, min(S, irr_src_size))
     base = min(S, pref_size)
-    plo, phi = prefilter(env, base, pref_levels, pref_samples, with_hi=True)
+    plo, phi = prefilter(env, base, pref_levels, pref_samples, with_hi=True, fis=bool(pref_fis))
     return dict(irradiance=irradiance(src, irr_size), prefiltered=plo, prefiltered_hi=phi,
                 lut=brdf_lut(lut_size, lut_samples))
 
