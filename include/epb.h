@@ -132,6 +132,10 @@ typedef struct {
     int32_t pref_samples; /* GGX samples per prefiltered texel (1024)              */
     int32_t lut_size;     /* BRDF table size (256)                                 */
     int32_t lut_samples;  /* GGX samples per table entry (1024)                    */
+    int32_t pref_fis;     /* 1: filtered importance sampling of the prefilter (each
+                             sample reads the environment's mip chain at the level
+                             its pdf asks for; needs a power-of-two size); 0: every
+                             sample reads level 0 (the default)                    */
 } epb_ibl_params;
 
 /* Outputs of epb_precompute_ibl, inputs of epb_shade. */
@@ -224,7 +228,12 @@ typedef enum {
  * of the solid-angle-weighted average of env at size irr_src.  Prefiltered level
  * m: the N.L-weighted mean of env level 0 over pref_samples GGX reflection
  * samples (Hammersley) with N = V = R the texel direction and roughness
- * m / (pref_levels - 1).  BRDF table: the Karis scale and bias integrals
+ * m / (pref_levels - 1).  With pref_fis, a sample reads instead the mip chain
+ * of env (level k = solid-angle-weighted 2x2 means of level k - 1, down to 2x2
+ * faces) trilinearly at lod = 1/2 log2(omega_s / omega_p) + 1, clamped to the
+ * chain, where omega_s = 1 / (N pdf) is the sample's solid angle (pdf = D / 4
+ * for V = N) and omega_p = 4 pi / (6 S^2) (Krivanek and Colbert's filtered
+ * importance sampling).  BRDF table: the Karis scale and bias integrals
  * (k = alpha / 2) at N.V = (i + .5) / lut_size, roughness = (j + .5) / lut_size.
  * Sums are Kahan-compensated in float32.
  */

@@ -199,6 +199,7 @@ def prefilter(env, base: int, levels: int, samples: int, tie=DEFAULT_TIE,
     the upper ends of the face-tie intervals; ``fis`` reads each sample from the
     environment's mip chain at the level its pdf asks for."""
     env = _d(env)
+    assert not fis or (env.shape[1] & (env.shape[1] - 1)) == 0, "filtered importance sampling needs a power-of-two size"
     total = sum(6 * (base >> m) ** 2 * 4 for m in range(levels))
     lo = np.zeros(total)
     hi = np.zeros(total)

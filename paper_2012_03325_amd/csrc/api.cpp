@@ -73,6 +73,8 @@ int check_ibl_params(int S, const epb_ibl_params *p) {
         return EPB_ERR_SIZE;
     if (p->pref_samples < 1 || p->pref_samples > (1 << 20) || p->lut_samples < 1 || p->lut_samples > (1 << 20))
         return EPB_ERR_PARAM;
+    if (p->pref_fis != 0 && p->pref_fis != 1) return EPB_ERR_PARAM;
+    if (p->pref_fis && !is_pow2(S)) return EPB_ERR_SIZE;  // the mip chain halves exactly
     int src = S < p->irr_src_size ? S : p->irr_src_size;
     if (S % src != 0 || !is_pow2(S / src)) return EPB_ERR_SIZE;
     int base = S < p->pref_size ? S : p->pref_size;

@@ -14,6 +14,8 @@
 //  * roughness-0 prefilter level: every GGX half vector equals the normal, so
 //    the N.L-weighted mean is the environment along the texel direction; one
 //    bilinear lookup per texel.
+#include <cmath>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -174,6 +176,97 @@ __global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ en
     }
 }
 
+// Environment mip chain for filtered importance sampling.  Level 0 is a copy
+// of the environment so that every level sits at a closed-form offset of one
+// buffer: level k (faces S >> k, S a power of two) starts at texel
+// 8 (S^2 - (S >> k)^2) = 6 (S^2 + (S/2)^2 + ... + (S >> (k-1))^2).
+__device__ __forceinline__ unsigned chain_offset_pow2(int S, int k) {
+    unsigned s = (unsigned)S, sk = (unsigned)(S >> k);
+    return 8u * (s * s - sk * sk);
+}
+
+__global__ void __launch_bounds__(256) k_env_copy(const float4 *__restrict__ env, int n, float4 *__restrict__ dst) {
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < n) dst[o] = env[o];
+}
+
+// Level k from level k - 1 (face size Sp = 2 Sd): solid-angle-weighted mean of
+// the 2x2 children, as the irradiance source is built.
+__global__ void __launch_bounds__(256) k_env_down(const float4 *__restrict__ src, int Sp,
+                                                  float4 *__restrict__ dst) {
+    int Sd = Sp >> 1;
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= 6 * Sd * Sd) return;
+    int f = o / (Sd * Sd), j = (o / Sd) % Sd, i = o % Sd;
+    const float4 *face = src + (size_t)f * Sp * Sp;
+    float r = 0.0f, g = 0.0f, b = 0.0f, w = 0.0f;
+    for (int bj = 0; bj < 2; ++bj)
+        for (int bi = 0; bi < 2; ++bi) {
+            int ci = 2 * i + bi, cj = 2 * j + bj;
+            float dw = texel_solid_angle(ci, cj, Sp);
+            float4 L = face[(size_t)cj * Sp + ci];
+            r = fmaf(L.x, dw, r);
+            g = fmaf(L.y, dw, g);
+            b = fmaf(L.z, dw, b);
+            w += dw;
+        }
+    float iw = 1.0f / w;
+    dst[o] = make_float4(r * iw, g * iw, b * iw, 0.0f);
+}
+
+// Filtered importance sampling: as k_prefilter, but sample l reads the chain
+// trilinearly at lod = lod0 - log2(den) clamped to [0, last], where den =
+// (1 - u2) + alpha^2 u2 is the GGX sampling denominator: for V = N the pdf of l
+// is D / 4 = den^2 / (4 pi alpha^2), so 1/2 log2(omega_s / omega_p) + 1 =
+// 1/2 log2(6 S^2 alpha^2 / N) + 1 - log2(den) (lod0 is that constant part,
+// computed on the host in double precision).
+__global__ void __launch_bounds__(256) k_prefilter_fis(const float4 *__restrict__ chain, int S, int last,
+                                                       int sm, float alpha, int samples, float lod0,
+                                                       float4 *__restrict__ out) {
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    int o = blockIdx.x * 4 + wave;
+    if (o >= 6 * sm * sm) return;  // whole wavefront leaves together
+    int f = o / (sm * sm), j = (o / sm) % sm, i = o % sm;
+    v3 n = normalize(cube_texel_dir(f, i, j, sm));
+    v3 T, B;
+    tangent_frame(n, T, B);
+    float a2 = alpha * alpha;
+    float inv_n = 1.0f / (float)samples;
+    float flast = (float)last;
+    Kahan r{0, 0}, g{0, 0}, b{0, 0}, w{0, 0};
+    for (int k = lane; k < samples; k += 64) {
+        float u2 = radical_inverse2((uint32_t)k);
+        v3 h = ggx_half((float)k * inv_n, u2, a2, n, T, B);
+        float vh = dot(n, h);
+        v3 l = h * (2.0f * vh) - n;
+        float nl = dot(n, l);
+        if (nl > 0.0f) {
+            float den = fmaf(a2, u2, 1.0f - u2);
+            float lod = fminf(fmaxf(lod0 - __log2f(den), 0.0f), flast);
+            int l0 = (int)lod;
+            int l1 = min(l0 + 1, last);
+            float fl = lod - (float)l0;
+            FaceST fs = cube_face(l);
+            int s0 = S >> l0, s1 = S >> l1;
+            float4 L0 = face_bilinear(chain, chain_offset_pow2(S, l0), s0, (float)s0, fs);
+            float4 L1 = face_bilinear(chain, chain_offset_pow2(S, l1), s1, (float)s1, fs);
+            float4 L = lerp4(L0, L1, fl);
+            kahan_add(r, L.x * nl);
+            kahan_add(g, L.y * nl);
+            kahan_add(b, L.z * nl);
+            kahan_add(w, nl);
+        }
+    }
+    float R = wave_sum_compensated(kahan_value(r));
+    float G = wave_sum_compensated(kahan_value(g));
+    float Bv = wave_sum_compensated(kahan_value(b));
+    float W = wave_sum_compensated(kahan_value(w));
+    if (lane == 0) {
+        float iw = 1.0f / W;
+        out[o] = make_float4(R * iw, G * iw, Bv * iw, 0.0f);
+    }
+}
+
 // One wavefront per BRDF table entry: N = +z, V = (sqrt(1 - NoV^2), 0, NoV).
 // G_vis = G VoH / (NoH NoV) with G = G1(NoL) G1(NoV), G1(x) = x / (x(1-k)+k),
 // written without the division by NoV: NoL VoH / (NoH (NoL(1-k)+k)(NoV(1-k)+k)).
@@ -217,6 +310,9 @@ IblPlan ibl_plan(int S, const epb_ibl_params &p) {
     q.pref_samples = p.pref_samples;
     q.lut = p.lut_size;
     q.lut_samples = p.lut_samples;
+    q.fis = p.pref_fis;
+    q.chain_last = 0;
+    while ((S >> (q.chain_last + 1)) >= 2) ++q.chain_last;
     int nsrc = 6 * q.src * q.src;
     int nout = 6 * q.irr * q.irr;
     int out_blocks = (nout + 255) / 256;
@@ -235,6 +331,9 @@ IblPlan ibl_plan(int S, const epb_ibl_params &p) {
     q.off_src = take((size_t)nsrc * 16);
     q.off_tab = take((size_t)nsrc * 16);
     q.off_part = take((size_t)chunks * nout * 8 * 4);
+    // environment mip chain for filtered importance sampling: levels 0 .. last
+    // contiguous, level k at texel offset 8 (S^2 - (S >> k)^2)
+    q.off_chain = take(q.fis ? (size_t)8 * S * S * 16 : 0);
     q.bytes = off;
     return q;
 }
@@ -254,6 +353,17 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
                        nsrc, chunk_len, q.irr, part);
     hipLaunchKernelGGL(k_irradiance_final, dim3((nout + 255) / 256), dim3(256), 0, s, part, q.chunks, q.irr,
                        (float4 *)irr);
+    float4 *chain = (float4 *)(sc + q.off_chain);
+    if (q.fis) {
+        int n0 = 6 * q.S * q.S;
+        hipLaunchKernelGGL(k_env_copy, dim3((n0 + 255) / 256), dim3(256), 0, s, env4, n0, chain);
+        for (int k = 1; k <= q.chain_last; ++k) {
+            int Sd = q.S >> k;
+            hipLaunchKernelGGL(k_env_down, dim3((6 * Sd * Sd + 255) / 256), dim3(256), 0, s,
+                               (const float4 *)(chain + 8u * ((unsigned)q.S * q.S - (unsigned)(2 * Sd) * (2 * Sd))),
+                               2 * Sd, chain + 8u * ((unsigned)q.S * q.S - (unsigned)Sd * Sd));
+        }
+    }
     size_t off = 0;
     for (int m = 0; m < q.pref_levels; ++m) {
         int sm = q.pref_base >> m;
@@ -261,9 +371,14 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
         float alpha = rough * rough;
         int n = 6 * sm * sm;
         float4 *dst = (float4 *)pref + off;
-        if (alpha == 0.0f)
+        if (alpha == 0.0f) {
             hipLaunchKernelGGL(k_prefilter_mirror, dim3((n + 255) / 256), dim3(256), 0, s, env4, q.S, sm, dst);
-        else
+        } else if (q.fis) {
+            double a2 = (double)alpha * alpha;
+            float lod0 = (float)(0.5 * std::log2(6.0 * q.S * q.S * a2 / q.pref_samples) + 1.0);
+            hipLaunchKernelGGL(k_prefilter_fis, dim3((n + 3) / 4), dim3(256), 0, s, chain, q.S, q.chain_last, sm,
+                               alpha, q.pref_samples, lod0, dst);
+        } else
             hipLaunchKernelGGL(k_prefilter, dim3((n + 3) / 4), dim3(256), 0, s, env4, q.S, sm, alpha,
                                q.pref_samples, dst);
         off += (size_t)n;

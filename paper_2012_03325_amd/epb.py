@@ -76,7 +76,7 @@ class epb_cube(C.Structure):
 class epb_ibl_params(C.Structure):
     _fields_ = [("irr_size", C.c_int32), ("irr_src_size", C.c_int32), ("pref_size", C.c_int32),
                 ("pref_levels", C.c_int32), ("pref_samples", C.c_int32), ("lut_size", C.c_int32),
-                ("lut_samples", C.c_int32)]
+                ("lut_samples", C.c_int32), ("pref_fis", C.c_int32)]
 
 
 class epb_ibl_maps(C.Structure):

@@ -28,13 +28,13 @@ class DeviceIBL:
 
     def __init__(self, env: np.ndarray, irr_size=32, irr_src_size=64, pref_size=128,
                  pref_levels=5, pref_samples=1024, lut_size=256, lut_samples=1024,
-                 device="cuda", **_unused):
+                 device="cuda", pref_fis=0, **_unused):
         self.device = device
         self.env = torch.from_numpy(np.ascontiguousarray(env, np.float32)).to(device)
         S = env.shape[1]
         self.S = S
         p = E.epb_ibl_params(irr_size, irr_src_size, pref_size, pref_levels, pref_samples,
-                             lut_size, lut_samples)
+                             lut_size, lut_samples, pref_fis)
         self.params = p
         self.base = min(S, pref_size)
         self.levels = pref_levels

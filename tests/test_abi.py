@@ -391,3 +391,13 @@ def test_edl_validation():
     assert call(depth=FAKE + 4) == E.EPB_ERR_ALIGN
     assert call(ao=FAKE + 8) == E.EPB_ERR_ALIGN
     assert call(hdr=FAKE + 2) == E.EPB_ERR_ALIGN
+
+
+def test_precompute_ibl_fis_validation():
+    ok = E.epb_ibl_params(32, 64, 128, 5, 64, 64, 64, 1)
+    assert E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 512, 512, ok) > \
+        E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 512, 512, E.epb_ibl_params(32, 64, 128, 5, 64, 64, 64, 0))
+    # the mip chain halves exactly: a power-of-two size is required
+    assert E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 96, 96, E.epb_ibl_params(8, 48, 32, 3, 64, 16, 16, 1)) == 0
+    assert E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 96, 96, E.epb_ibl_params(8, 48, 32, 3, 64, 16, 16, 0)) > 0
+    assert E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 64, 64, E.epb_ibl_params(8, 16, 32, 3, 64, 16, 16, 2)) == 0

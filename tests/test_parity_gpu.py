@@ -124,6 +124,16 @@ IBL_CASES = {
     "sun-512-full": (lambda: synth.env_sky_sun(512),
                      dict(irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=1024,
                           lut_size=256, lut_samples=1024)),
+    # filtered importance sampling of the prefilter (mip-chain lookups at each sample's pdf level)
+    "sun-64-fis-64": (lambda: synth.env_sky_sun(64),
+                      dict(irr_size=8, irr_src_size=16, pref_size=64, pref_levels=5, pref_samples=64,
+                           lut_size=32, lut_samples=64, pref_fis=1)),
+    "gradient-16-fis-7": (lambda: synth.env_sky_gradient(16),
+                          dict(irr_size=4, irr_src_size=16, pref_size=16, pref_levels=4, pref_samples=7,
+                               lut_size=8, lut_samples=16, pref_fis=1)),
+    "sun-512-fis-256": (lambda: synth.env_sky_sun(512),
+                        dict(irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=256,
+                             lut_size=64, lut_samples=64, pref_fis=1)),
 }
 
 
