@@ -320,6 +320,41 @@ def test_repeatable_bitwise():
         assert torch.equal(x, y)
 
 
+@pytest.mark.parametrize("kind", ["ragged-201x137", "full-1080p"])
+def test_captured_frame_replays_match_eager(kind):
+    """A whole single-view frame (SSAO, shading, bloom/tonemap) captured in a
+    HIP graph: every replay, with eager work and synchronisations in between,
+    equals the eager frame bit for bit (the timed benchmark replays such graphs)."""
+    v = _view(kind)
+    dv = _device_view(v, v.ibl)
+    other = _device_view(_view("tiny-3x2"), _view("tiny-3x2").ibl)
+    log(f"[graph] {kind}: eager frame, capture, replays")
+    dv.render()
+    torch.cuda.synchronize()
+    ref = (dv.ao.clone(), dv.hdr.clone(), dv.ldr.clone())
+    s = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    side.wait_stream(s)
+    with torch.cuda.stream(side):
+        dv.render()
+    s.wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        dv.render()
+    for rep in range(4):
+        dv.ao.fill_(-1.0)
+        dv.hdr.fill_(-1.0)
+        dv.ldr.zero_()
+        other.render()  # eager work of another view between replays
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for x, y in zip(ref, (dv.ao, dv.hdr, dv.ldr)):
+            assert torch.equal(x, y), rep
+    log(f"[graph] {kind}: 4 replays bitwise equal")
+
+
 def test_validation_leaves_outputs_untouched():
     from paper_2012_03325_amd import epb as E
     v = _view("tiny-3x2")
