@@ -50,6 +50,8 @@ class Request:
     batch: int = -1
     slot: object = None
     rejected: bool = False
+    cam: object = None            # a camera of its own (synth.Camera of the request's size): the
+                                  # G-buffer is ray-cast for it on the device before shading
 
     @property
     def res(self) -> Res:
@@ -343,10 +345,16 @@ class GpuExecutor:
     scratch unset); a slot gives a request its LDR image and its view scratch
     (which also holds AO and HDR).  The batch table is written into a pinned
     host buffer, copied to the device on the batch's stream and rendered with
-    epb_render_batch; a HIP event marks completion."""
+    epb_render_batch; a HIP event marks completion.
+
+    With ``geometry`` (scene index -> frame.DeviceScene, the resident sphere
+    field of each scene) every slot also holds G-buffer planes and ray-cast
+    scratch, and a request that carries its own camera gets its G-buffer
+    ray-cast on the batch's stream (epb_raycast) before the batch renders it;
+    the scene's lights, IBL tables and parameters come from the template."""
 
     def __init__(self, templates: Dict[Tuple[int, Res], "object"], schedule=None, n_streams: int = 2,
-                 max_inflight: int = 2, max_batch_views: int = 64):
+                 max_inflight: int = 2, max_batch_views: int = 64, geometry: Optional[Dict[int, object]] = None):
         import torch
 
         from . import epb as E
@@ -364,6 +372,10 @@ class GpuExecutor:
         self._fp: Dict[Res, int] = {}
         self.ref = None
         self.t_ref = 0.0
+        self.geometry = geometry
+        self.ray_scratch = 0
+        if geometry:
+            self.ray_scratch = max(E.epb_scratch_bytes(E.EPB_OP_RAYCAST, 1, 1, g.struct) for g in geometry.values())
 
     def start(self, clock):
         torch = self.torch
@@ -379,10 +391,17 @@ class GpuExecutor:
                 return v
         raise KeyError(res)
 
+    def _gbuf_bytes(self, res: Res) -> int:
+        if not self.geometry:
+            return 0
+        vb = 2 if self._template(res).gbuf.dtype == self.E.EPB_F16 else 4
+        return res[0] * res[1] * (4 + 8 * vb) + self.ray_scratch
+
     def footprint(self, res: Res) -> int:
         if res not in self._fp:
             v = self._template(res)
-            self._fp[res] = (self.E.epb_view_scratch_bytes(v) + 4 * res[0] * res[1] + 255) & ~255
+            self._fp[res] = (self.E.epb_view_scratch_bytes(v) + 4 * res[0] * res[1] + self._gbuf_bytes(res)
+                             + 255) & ~255
         return self._fp[res]
 
     def alloc(self, res: Res):
@@ -390,7 +409,16 @@ class GpuExecutor:
         v = self._template(res)
         ldr = torch.empty((res[1], res[0], 4), dtype=torch.uint8, device="cuda")
         scratch = torch.empty(self.E.epb_view_scratch_bytes(v), dtype=torch.uint8, device="cuda")
-        return dict(ldr=ldr, scratch=scratch)
+        slot = dict(ldr=ldr, scratch=scratch)
+        if self.geometry:
+            w, h = res
+            dt = torch.float16 if v.gbuf.dtype == self.E.EPB_F16 else torch.float32
+            slot.update(depth=torch.empty((h, w), device="cuda"), normal=torch.empty((3, h, w), dtype=dt, device="cuda"),
+                        albedo=torch.empty((3, h, w), dtype=dt, device="cuda"),
+                        rough=torch.empty((h, w), dtype=dt, device="cuda"),
+                        metal=torch.empty((h, w), dtype=dt, device="cuda"),
+                        ray_scratch=torch.empty(max(self.ray_scratch, 16), dtype=torch.uint8, device="cuda"))
+        return slot
 
     def free(self, slot):
         slot.clear()
@@ -399,12 +427,23 @@ class GpuExecutor:
         torch, E = self.torch, self.E
         n = len(reqs)
         assert n <= self.max_views
+        from .frame import _cam_struct
         arr = (E.epb_view * n)()
+        casts = []
         for i, r in enumerate(reqs):
             v = E.epb_view.from_buffer_copy(self.templates[(r.scene, r.res)])
             v.ao, v.hdr = None, None
             v.ldr = r.slot["ldr"].data_ptr()
             v.scratch = r.slot["scratch"].data_ptr()
+            if r.cam is not None:
+                if not self.geometry or r.scene not in self.geometry:
+                    raise ValueError("a request with its own camera needs the scene's geometry")
+                sl = r.slot
+                g = E.epb_gbuffer(r.width, r.height, v.gbuf.dtype, sl["depth"].data_ptr(), sl["normal"].data_ptr(),
+                                  sl["albedo"].data_ptr(), sl["rough"].data_ptr(), sl["metal"].data_ptr(), None)
+                cam = _cam_struct(r.cam)
+                v.gbuf, v.cam = g, cam
+                casts.append((self.geometry[r.scene], cam, g, sl["ray_scratch"]))
             arr[i] = v
         host, dev = self.free_tables.pop()
         st = E.lib.epb_batch_build(C.addressof(arr), n, C.addressof(self.schedule), None, 0,
@@ -415,6 +454,8 @@ class GpuExecutor:
         s = self.streams[self.k % len(self.streams)]
         self.k += 1
         with torch.cuda.stream(s):
+            for scene, cam, g, rs in casts:  # G-buffers of requests with their own camera
+                E.epb_raycast(scene.struct, cam, g, rs, rs.numel(), s)
             dev.copy_(host, non_blocking=True)
             E.epb_render_batch(host.data_ptr(), dev, s)
             ev = torch.cuda.Event(enable_timing=True)

@@ -71,3 +71,48 @@ def test_each_result_same_alone_and_in_the_mix(dtype, budget_slots):
     r0 = S.Request(10_000, 1, 130, 70, 0.0)
     one.run([r0], S.RealClock())
     assert torch.equal(results[10_000], alone[(1, (130, 70))])
+
+
+@pytest.mark.parametrize("dtype", ["f16", "f32"])
+def test_requests_with_their_own_cameras(dtype):
+    """Requests that carry a camera of their own: the server ray-casts their
+    G-buffer on the device inside the request's slot, then shades it in the
+    batch; each image equals that camera's G-buffer (same device ray cast)
+    rendered alone with the single-view calls, bitwise."""
+    from paper_2012_03325_amd import epb as E
+    from paper_2012_03325_amd import frame
+    from paper_2012_03325_amd import serve as S
+    gdt = E.EPB_F16 if dtype == "f16" else E.EPB_F32
+    rs = _resident(gdt)
+    scenes = [synth.make_scene(500 + i, env_size=16, sphere_range=(16, 48),
+                               ibl=dict(pref_samples=128, lut_size=32, lut_samples=128)) for i in range(3)]
+    geometry = {i: frame.DeviceScene(sc.spheres) for i, sc in enumerate(scenes)}
+    ex = S.GpuExecutor(rs.templates, schedule=E.epb_schedule(0, 0, 0, 0), n_streams=2, max_inflight=3,
+                       max_batch_views=16, geometry=geometry)
+    budget = 24 * ex.footprint((256, 144))
+    results = {}
+
+    def on_done(r):
+        results[r.rid] = r.slot["ldr"].cpu()
+
+    srv = S.Server(ex, budget, max_batch_views=16, max_inflight=3, on_done=on_done)
+    reqs = S.poisson_arrivals(3000.0, 530, 3, RES, count=60)
+    rng = np.random.default_rng(531)
+    for r in reqs[::2]:  # every other request brings its own camera
+        r.cam = synth.orbit_camera(rng, r.width, r.height)
+    log(f"[serve-cam] {dtype}: {len(reqs)} requests, {len(reqs[::2])} with their own camera")
+    st = srv.run(reqs, S.RealClock())
+    log(f"[serve-cam] {st}")
+    assert st["requests"] == len(reqs) and st["rejected"] == 0
+    for r in reqs:
+        if r.cam is None:
+            dv = rs.dviews[(r.scene, r.res)]
+        else:
+            g = geometry[r.scene].render_gbuffer(r.cam, dtype=gdt)
+            torch.cuda.synchronize()
+            gb = {k: t.float().cpu().numpy() for k, t in g.items()}
+            v = synth.scene_view(scenes[r.scene], r.cam, f"cam-{r.rid}", gbuf=gb, index=r.scene)
+            dv = frame.DeviceView(v, rs.ibls[r.scene], gdtype=gdt, ao_dtype=gdt, hdr_dtype=gdt)
+        dv.render()
+        torch.cuda.synchronize()
+        assert torch.equal(results[r.rid], dv.ldr.cpu()), (r.rid, r.scene, r.res, r.cam is not None)
