@@ -56,15 +56,30 @@ def shade_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def counted_shade_traffic():
+def counted_shade_record():
+    """The committed counter record of the FP32 shading kernel, or None when the
+    kernel's sources changed since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     if rec.get("source_sha256") != shade_sources_sha256():
-        return None  # the kernel changed since the counters were taken
-    return rec.get("bytes_per_launch")
+        return None
+    return rec
+
+
+def counted_shade_traffic():
+    rec = counted_shade_record()
+    return rec.get("bytes_per_launch") if rec else None
+
+
+def counted_shade_utilisation():
+    """VALU and texture-address (TA) busy fractions of the shading kernel from
+    the committed counter runs (rocprofv3 VALUBusy and TA_BUSY_avr over
+    GRBM_GUI_ACTIVE), or None."""
+    rec = counted_shade_record()
+    return rec.get("utilisation") if rec else None
 
 
 def shadow_texels_touched(view) -> int:
@@ -619,6 +634,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": counted_shade_traffic(),
+            "utilisation": counted_shade_utilisation(),
             "algorithmic_bytes_per_launch": acc["total"],
             "algorithmic_bytes_per_px": round(acc["per_px"], 2),
             "avg_launch_ms": round(1e3 * shade_avg_s, 5),
