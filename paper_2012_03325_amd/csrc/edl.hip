@@ -13,8 +13,10 @@
 // once per texel, not once per neighbour read), texels outside the image hold
 // +inf so that they add max(0, z - inf) = 0 without a branch.  The neighbour
 // offsets are LDS index deltas precomputed on the host for the tile pitch and
-// read from the kernel arguments with scalar loads.  The kernel streams
-// depth + colour + AO in and HDR out once: HBM-bound.
+// read from the kernel arguments with scalar loads.  A block is short-lived,
+// so its memory round trips set its time: the pixel's own depth, colour and AO
+// are fetched before the barrier, in flight together with the halo fill.  The
+// kernel streams depth + colour + AO in and HDR out once: HBM-bound.
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -24,8 +26,23 @@ constexpr int kEdlTx = 32, kEdlTy = 8;
 constexpr int kEdlPitchMax = kEdlTx + 2 * EPB_MAX_EDL_RADIUS;
 constexpr int kEdlRowsMax = kEdlTy + 2 * EPB_MAX_EDL_RADIUS;
 
+// Log depth of halo-tile texel q (row-major, pitch = 32 + 2r) or +inf outside
+// the image; the load address is clamped so that every lane may issue it.
+struct HaloTexel {
+    unsigned idx;
+    bool in;
+};
+__device__ __forceinline__ HaloTexel halo_texel(const EdlDesc &c, int X0, int Y0, int pitch, int q) {
+    int ry = q / pitch, rx = q - ry * pitch;
+    int gx = X0 - c.radius + rx, gy = Y0 - c.radius + ry;
+    bool in = gx >= 0 && gx < c.W && gy >= 0 && gy < c.H;
+    return HaloTexel{in ? __umul24((unsigned)gy, (unsigned)c.W) + (unsigned)gx : 0u, in};
+}
+
 template <typename TG, typename TA, typename TH>
 __global__ void __launch_bounds__(kEdlTx *kEdlTy) k_edl(const EdlDesc c, int tiles) {
+    constexpr int kThreads = kEdlTx * kEdlTy;
+    constexpr int kEarly = 3;  // halo texels per thread fetched up front (all of them for radius <= 4)
     __shared__ float z[kEdlPitchMax * kEdlRowsMax];
     int tile = xcd_tile(blockIdx.x, tiles);
     int tiles_x = (c.W + kEdlTx - 1) / kEdlTx;
@@ -33,29 +50,60 @@ __global__ void __launch_bounds__(kEdlTx *kEdlTy) k_edl(const EdlDesc c, int til
     int X0 = (tile - ty * tiles_x) * kEdlTx, Y0 = ty * kEdlTy;
     int t = (int)threadIdx.x;
     int r = c.radius, pitch = kEdlTx + 2 * r, area = pitch * (kEdlTy + 2 * r);
-    // log depths of the tile and its halo (one log2 per texel)
-    for (int q = t; q < area; q += kEdlTx * kEdlTy) {
-        int ry = q / pitch, rx = q - ry * pitch;
-        int gx = X0 - r + rx, gy = Y0 - r + ry;
-        float v = __builtin_inff();
-        if (gx >= 0 && gx < c.W && gy >= 0 && gy < c.H)
-            v = log2f(fminf(ldf(c.depth, __umul24((unsigned)gy, (unsigned)c.W) + (unsigned)gx), c.far_depth));
-        z[q] = v;
-    }
-    __syncthreads();
     int lx = t % kEdlTx, ly = t / kEdlTx;
     int x = X0 + lx, y = Y0 + ly;
-    if (x >= c.W || y >= c.H) return;
+    bool valid = x < c.W && y < c.H;
+    unsigned p = valid ? __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x : 0u;
+    unsigned plane = (unsigned)c.W * (unsigned)c.H;
+    // Issue order: the pixel's depth, then the first halo texels, then (once
+    // the depth says the pixel holds a point) its colour and AO taps -- all
+    // before the barrier, so that the pixel's own fetches overlap the halo's.
+    float d = ldf(c.depth, p);
+    float hv[kEarly];
+    bool hin[kEarly];
+#pragma unroll
+    for (int e = 0; e < kEarly; ++e) {
+        int q = t + e * kThreads;
+        HaloTexel h = halo_texel(c, X0, Y0, pitch, q < area ? q : 0);
+        hin[e] = h.in && q < area;
+        hv[e] = ldf(c.depth, h.idx);
+    }
+    bool fg = valid && !__builtin_isinf(d);
+    float col[3] = {0.0f, 0.0f, 0.0f};
+    float a00 = 1.0f, a10 = 1.0f, a01 = 1.0f, a11 = 1.0f;
+    if (fg) {
+        const TG *cp = (const TG *)c.color;
+        col[0] = ldf(cp, p);
+        col[1] = ldf(cp, plane + p);
+        col[2] = ldf(cp, 2 * plane + p);
+        if (c.ao) {  // taps of the bilinear upsampling at (x / 2, y / 2), clamped, as in shading
+            const TA *aop = (const TA *)c.ao;
+            unsigned x0 = x >> 1, y0 = y >> 1;
+            unsigned dx = (x & 1) && (int)x0 + 1 < c.Wh ? 1u : 0u;
+            unsigned dy = (y & 1) && (int)y0 + 1 < c.Hh ? (unsigned)c.Wh : 0u;
+            unsigned q = __umul24(y0, (unsigned)c.Wh) + x0;
+            a00 = ldf(aop, q); a10 = ldf(aop, q + dx); a01 = ldf(aop, q + dy); a11 = ldf(aop, q + dy + dx);
+        }
+    }
+    // log depths of the tile and its halo (one log2 per texel; +inf outside the image)
+#pragma unroll
+    for (int e = 0; e < kEarly; ++e) {
+        int q = t + e * kThreads;
+        if (q < area) z[q] = hin[e] ? log2f(fminf(hv[e], c.far_depth)) : __builtin_inff();
+    }
+    for (int q = t + kEarly * kThreads; q < area; q += kThreads) {  // radius > 4 only
+        HaloTexel h = halo_texel(c, X0, Y0, pitch, q);
+        z[q] = h.in ? log2f(fminf(ldf(c.depth, h.idx), c.far_depth)) : __builtin_inff();
+    }
+    __syncthreads();
+    if (!valid) return;
     int centre = (ly + r) * pitch + lx + r;
     float zp = z[centre];
     float acc = 0.0f;
     for (int k = 0; k < c.n_dirs; ++k) acc += fmaxf(zp - z[centre + c.loff[k]], 0.0f);
     float shade = exp2f(c.neg_strength_over_n * acc);
-    unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
-    unsigned plane = (unsigned)c.W * (unsigned)c.H;
     float out[3] = {0.0f, 0.0f, 0.0f};
-    float d = ldf(c.depth, p);
-    if (__builtin_isinf(d)) {
+    if (!fg) {
         if (c.env) {
             float dvx = ((float)x + 0.5f - c.cx) * c.inv_fx;
             float dvy = -((float)y + 0.5f - c.cy) * c.inv_fy;
@@ -65,22 +113,15 @@ __global__ void __launch_bounds__(kEdlTx *kEdlTy) k_edl(const EdlDesc c, int til
         }
     } else {
         float ao = 1.0f;
-        if (c.ao) {  // bilinear upsampling at (x / 2, y / 2), clamped, as in shading
-            const TA *aop = (const TA *)c.ao;
-            unsigned x0 = x >> 1, y0 = y >> 1;
-            unsigned dx = (x & 1) && (int)x0 + 1 < c.Wh ? 1u : 0u;
-            unsigned dy = (y & 1) && (int)y0 + 1 < c.Hh ? (unsigned)c.Wh : 0u;
-            unsigned q = __umul24(y0, (unsigned)c.Wh) + x0;
-            float a00 = ldf(aop, q), a10 = ldf(aop, q + dx), a01 = ldf(aop, q + dy), a11 = ldf(aop, q + dy + dx);
+        if (c.ao) {
             float wx = (x & 1) ? 0.5f : 0.0f, wy = (y & 1) ? 0.5f : 0.0f;
             float top = fmaf(wx, a10 - a00, a00), bot = fmaf(wx, a11 - a01, a01);
             ao = fmaf(wy, bot - top, top);
         }
-        const TG *col = (const TG *)c.color;
         float s = shade * ao;
-        out[0] = s * ldf(col, p);
-        out[1] = s * ldf(col, plane + p);
-        out[2] = s * ldf(col, 2 * plane + p);
+        out[0] = s * col[0];
+        out[1] = s * col[1];
+        out[2] = s * col[2];
     }
     TH *hdr = (TH *)c.hdr;
     stf(hdr, p, out[0]);
