@@ -7,8 +7,8 @@
 // background right next to the cloud gets a dark outline.  Foreground pixels
 // return shade * AO * colour, background pixels shade * environment.
 //
-// gfx950 mapping: one thread per pixel in 32x8 tiles (a wavefront = 32x2
-// pixels, two 128-byte row segments of every plane); the tile's log depths
+// gfx950 mapping: 32x16 pixel tiles, 256 threads, two pixels per thread (8
+// rows apart; a wavefront's rows are 128-byte segments of every plane); the tile's log depths
 // plus a halo of the radius are computed once per texel into LDS (log2 taken
 // once per texel, not once per neighbour read), texels outside the image hold
 // +inf so that they add max(0, z - inf) = 0 without a branch.  The neighbour
@@ -22,7 +22,12 @@
 
 namespace epb {
 
-constexpr int kEdlTx = 32, kEdlTy = 8;
+// A block of 256 threads covers a 32 x (8 PPT) pixel tile, each thread PPT
+// pixels of one column, 8 rows apart (rows of a wavefront stay 128-byte
+// segments).  More pixels per thread put more independent fetches in flight
+// per wavefront at the same occupancy.
+constexpr int kEdlTx = 32, kEdlRows = 8, kEdlPpt = 2, kEdlTy = kEdlRows * kEdlPpt;
+constexpr int kEdlThreads = kEdlTx * kEdlRows;
 constexpr int kEdlPitchMax = kEdlTx + 2 * EPB_MAX_EDL_RADIUS;
 constexpr int kEdlRowsMax = kEdlTy + 2 * EPB_MAX_EDL_RADIUS;
 
@@ -40,9 +45,8 @@ __device__ __forceinline__ HaloTexel halo_texel(const EdlDesc &c, int X0, int Y0
 }
 
 template <typename TG, typename TA, typename TH>
-__global__ void __launch_bounds__(kEdlTx *kEdlTy) k_edl(const EdlDesc c, int tiles) {
-    constexpr int kThreads = kEdlTx * kEdlTy;
-    constexpr int kEarly = 3;  // halo texels per thread fetched up front (all of them for radius <= 4)
+__global__ void __launch_bounds__(kEdlThreads) k_edl(const EdlDesc c, int tiles) {
+    constexpr int kEarly = 4;  // halo texels per thread fetched up front (all of them for radius <= 4)
     __shared__ float z[kEdlPitchMax * kEdlRowsMax];
     int tile = xcd_tile(blockIdx.x, tiles);
     int tiles_x = (c.W + kEdlTx - 1) / kEdlTx;
@@ -51,82 +55,100 @@ __global__ void __launch_bounds__(kEdlTx *kEdlTy) k_edl(const EdlDesc c, int til
     int t = (int)threadIdx.x;
     int r = c.radius, pitch = kEdlTx + 2 * r, area = pitch * (kEdlTy + 2 * r);
     int lx = t % kEdlTx, ly = t / kEdlTx;
-    int x = X0 + lx, y = Y0 + ly;
-    bool valid = x < c.W && y < c.H;
-    unsigned p = valid ? __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x : 0u;
+    int x = X0 + lx;
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
-    // Issue order: the pixel's depth, then the first halo texels, then (once
-    // the depth says the pixel holds a point) its colour and AO taps -- all
-    // before the barrier, so that the pixel's own fetches overlap the halo's.
-    float d = ldf(c.depth, p);
+    // Issue order: the pixels' depths, then the first halo texels, then (once
+    // a depth says its pixel holds a point) that pixel's colour and AO taps --
+    // all before the barrier, so that the pixels' own fetches overlap the halo's.
+    bool valid[kEdlPpt], fg[kEdlPpt];
+    unsigned p[kEdlPpt];
+    float d[kEdlPpt];
+#pragma unroll
+    for (int k = 0; k < kEdlPpt; ++k) {
+        int y = Y0 + ly + k * kEdlRows;
+        valid[k] = x < c.W && y < c.H;
+        p[k] = valid[k] ? __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x : 0u;
+        d[k] = ldf(c.depth, p[k]);
+    }
     float hv[kEarly];
     bool hin[kEarly];
 #pragma unroll
     for (int e = 0; e < kEarly; ++e) {
-        int q = t + e * kThreads;
+        int q = t + e * kEdlThreads;
         HaloTexel h = halo_texel(c, X0, Y0, pitch, q < area ? q : 0);
         hin[e] = h.in && q < area;
         hv[e] = ldf(c.depth, h.idx);
     }
-    bool fg = valid && !__builtin_isinf(d);
-    float col[3] = {0.0f, 0.0f, 0.0f};
-    float a00 = 1.0f, a10 = 1.0f, a01 = 1.0f, a11 = 1.0f;
-    if (fg) {
-        const TG *cp = (const TG *)c.color;
-        col[0] = ldf(cp, p);
-        col[1] = ldf(cp, plane + p);
-        col[2] = ldf(cp, 2 * plane + p);
-        if (c.ao) {  // taps of the bilinear upsampling at (x / 2, y / 2), clamped, as in shading
-            const TA *aop = (const TA *)c.ao;
-            unsigned x0 = x >> 1, y0 = y >> 1;
-            unsigned dx = (x & 1) && (int)x0 + 1 < c.Wh ? 1u : 0u;
-            unsigned dy = (y & 1) && (int)y0 + 1 < c.Hh ? (unsigned)c.Wh : 0u;
-            unsigned q = __umul24(y0, (unsigned)c.Wh) + x0;
-            a00 = ldf(aop, q); a10 = ldf(aop, q + dx); a01 = ldf(aop, q + dy); a11 = ldf(aop, q + dy + dx);
+    float col[kEdlPpt][3];
+    float a00[kEdlPpt], a10[kEdlPpt], a01[kEdlPpt], a11[kEdlPpt];
+#pragma unroll
+    for (int k = 0; k < kEdlPpt; ++k) {
+        fg[k] = valid[k] && !__builtin_isinf(d[k]);
+        col[k][0] = col[k][1] = col[k][2] = 0.0f;
+        a00[k] = a10[k] = a01[k] = a11[k] = 1.0f;
+        if (fg[k]) {
+            const TG *cp = (const TG *)c.color;
+            col[k][0] = ldf(cp, p[k]);
+            col[k][1] = ldf(cp, plane + p[k]);
+            col[k][2] = ldf(cp, 2 * plane + p[k]);
+            if (c.ao) {  // taps of the bilinear upsampling at (x / 2, y / 2), clamped, as in shading
+                int y = Y0 + ly + k * kEdlRows;
+                const TA *aop = (const TA *)c.ao;
+                unsigned x0 = x >> 1, y0 = y >> 1;
+                unsigned dx = (x & 1) && (int)x0 + 1 < c.Wh ? 1u : 0u;
+                unsigned dy = (y & 1) && (int)y0 + 1 < c.Hh ? (unsigned)c.Wh : 0u;
+                unsigned q = __umul24(y0, (unsigned)c.Wh) + x0;
+                a00[k] = ldf(aop, q); a10[k] = ldf(aop, q + dx);
+                a01[k] = ldf(aop, q + dy); a11[k] = ldf(aop, q + dy + dx);
+            }
         }
     }
     // log depths of the tile and its halo (one log2 per texel; +inf outside the image)
 #pragma unroll
     for (int e = 0; e < kEarly; ++e) {
-        int q = t + e * kThreads;
+        int q = t + e * kEdlThreads;
         if (q < area) z[q] = hin[e] ? log2f(fminf(hv[e], c.far_depth)) : __builtin_inff();
     }
-    for (int q = t + kEarly * kThreads; q < area; q += kThreads) {  // radius > 4 only
+    for (int q = t + kEarly * kEdlThreads; q < area; q += kEdlThreads) {  // radius > 4 only
         HaloTexel h = halo_texel(c, X0, Y0, pitch, q);
         z[q] = h.in ? log2f(fminf(ldf(c.depth, h.idx), c.far_depth)) : __builtin_inff();
     }
     __syncthreads();
-    if (!valid) return;
-    int centre = (ly + r) * pitch + lx + r;
-    float zp = z[centre];
-    float acc = 0.0f;
-    for (int k = 0; k < c.n_dirs; ++k) acc += fmaxf(zp - z[centre + c.loff[k]], 0.0f);
-    float shade = exp2f(c.neg_strength_over_n * acc);
-    float out[3] = {0.0f, 0.0f, 0.0f};
-    if (!fg) {
-        if (c.env) {
-            float dvx = ((float)x + 0.5f - c.cx) * c.inv_fx;
-            float dvy = -((float)y + 0.5f - c.cy) * c.inv_fy;
-            v3 dw = mul_Rt(c.R, mk3(dvx, dvy, -1.0f));
-            float4 e = cube_bilinear(c.env, c.env_size, c.f_env, dw);
-            out[0] = shade * e.x; out[1] = shade * e.y; out[2] = shade * e.z;
-        }
-    } else {
-        float ao = 1.0f;
-        if (c.ao) {
-            float wx = (x & 1) ? 0.5f : 0.0f, wy = (y & 1) ? 0.5f : 0.0f;
-            float top = fmaf(wx, a10 - a00, a00), bot = fmaf(wx, a11 - a01, a01);
-            ao = fmaf(wy, bot - top, top);
-        }
-        float s = shade * ao;
-        out[0] = s * col[0];
-        out[1] = s * col[1];
-        out[2] = s * col[2];
-    }
     TH *hdr = (TH *)c.hdr;
-    stf(hdr, p, out[0]);
-    stf(hdr, plane + p, out[1]);
-    stf(hdr, 2 * plane + p, out[2]);
+#pragma unroll
+    for (int k = 0; k < kEdlPpt; ++k) {
+        if (!valid[k]) continue;
+        int y = Y0 + ly + k * kEdlRows;
+        int centre = (ly + k * kEdlRows + r) * pitch + lx + r;
+        float zp = z[centre];
+        float acc = 0.0f;
+        for (int n = 0; n < c.n_dirs; ++n) acc += fmaxf(zp - z[centre + c.loff[n]], 0.0f);
+        float shade = exp2f(c.neg_strength_over_n * acc);
+        float out[3] = {0.0f, 0.0f, 0.0f};
+        if (!fg[k]) {
+            if (c.env) {
+                float dvx = ((float)x + 0.5f - c.cx) * c.inv_fx;
+                float dvy = -((float)y + 0.5f - c.cy) * c.inv_fy;
+                v3 dw = mul_Rt(c.R, mk3(dvx, dvy, -1.0f));
+                float4 e = cube_bilinear(c.env, c.env_size, c.f_env, dw);
+                out[0] = shade * e.x; out[1] = shade * e.y; out[2] = shade * e.z;
+            }
+        } else {
+            float ao = 1.0f;
+            if (c.ao) {
+                float wx = (x & 1) ? 0.5f : 0.0f, wy = (y & 1) ? 0.5f : 0.0f;
+                float top = fmaf(wx, a10[k] - a00[k], a00[k]), bot = fmaf(wx, a11[k] - a01[k], a01[k]);
+                ao = fmaf(wy, bot - top, top);
+            }
+            float sv = shade * ao;
+            out[0] = sv * col[k][0];
+            out[1] = sv * col[k][1];
+            out[2] = sv * col[k][2];
+        }
+        stf(hdr, p[k], out[0]);
+        stf(hdr, plane + p[k], out[1]);
+        stf(hdr, 2 * plane + p[k], out[2]);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -134,8 +156,8 @@ __global__ void __launch_bounds__(kEdlTx *kEdlTy) k_edl(const EdlDesc c, int til
 // ---------------------------------------------------------------------------
 template <typename TG, typename TA>
 static void go_h(const EdlDesc &c, epb_dtype hd, int tiles, hipStream_t s) {
-    if (hd == EPB_F32) hipLaunchKernelGGL((k_edl<TG, TA, float>), dim3(tiles), dim3(kEdlTx * kEdlTy), 0, s, c, tiles);
-    else hipLaunchKernelGGL((k_edl<TG, TA, __half>), dim3(tiles), dim3(kEdlTx * kEdlTy), 0, s, c, tiles);
+    if (hd == EPB_F32) hipLaunchKernelGGL((k_edl<TG, TA, float>), dim3(tiles), dim3(kEdlThreads), 0, s, c, tiles);
+    else hipLaunchKernelGGL((k_edl<TG, TA, __half>), dim3(tiles), dim3(kEdlThreads), 0, s, c, tiles);
 }
 template <typename TG>
 static void go_a(const EdlDesc &c, epb_dtype ad, epb_dtype hd, int tiles, hipStream_t s) {

@@ -40,6 +40,7 @@ def _views():
                                       n_spheres=24, n_lights=1 + s % 3)
                  for w, h, s, n in SIZES]
         views[4] = synth.surfel_accumulate(views[4], seed=41)  # one surfel-splatted G-buffer
+        views[1].tonemap = 1  # one view tone-mapped with Reinhard instead of ACES
         _cache["views"] = views
     return [copy.deepcopy(v) for v in _cache["views"]]
 
