@@ -13,7 +13,10 @@ the timed loop rotates over several full copies of the G-buffer and of every
 output and scratch buffer (the scene-static shadow maps and IBL tables are
 shared, as a renderer keeps them resident).  Each copy's frame (its seven
 kernel launches) is captured once in a HIP graph; the timed steps replay the
-graphs in turn.  Eager frames are timed too (``eager_ms_per_step``).
+graphs with several frames in flight on as many streams (``frames_in_flight``;
+a copy always returns to the same stream).  Frames replayed one at a time give
+the per-frame latency (``serial_ms_per_frame``, p50/p99); eager frames are
+timed too (``eager_ms_per_step``).
 
 Prints one JSON line.  ``--gpus N`` with N > 1 is not supported (one GPU).
 """
@@ -461,7 +464,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--copies", type=int, default=4, help="rotated input/output copies (MALL)")
+    ap.add_argument("--copies", type=int, default=6, help="rotated input/output copies (MALL); a multiple of "
+                    "--frames-in-flight")
+    ap.add_argument("--frames-in-flight", type=int, default=3, help="frames replayed concurrently on as many streams")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-view batched form")
@@ -473,6 +478,9 @@ def main():
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of request slots")
     ap.add_argument("--serve-saturation", type=int, default=1000, help="requests of the closed-loop run")
     args = ap.parse_args()
+    if args.frames_in_flight < 1 or args.copies % args.frames_in_flight:
+        print("--copies must be a positive multiple of --frames-in-flight", file=sys.stderr)
+        sys.exit(2)
     if args.gpus != 1:
         print(f"bench.py measures one GPU: --gpus {args.gpus} is not supported "
               "(views shard across GPUs without communication; see the design notes)",
@@ -548,15 +556,36 @@ def main():
         for k in range(args.warmup):
             graphs[k % args.copies].replay()
         torch.cuda.synchronize()
+        # one frame at a time: the latency of a frame alone on the GPU
         marks = [torch.cuda.Event(enable_timing=True) for _ in range(K + 1)]
-        wall0 = time.perf_counter()
         marks[0].record(stream)
         for k in range(K):
             graphs[k % args.copies].replay()
             marks[k + 1].record(stream)
         torch.cuda.synchronize()
-        wall = time.perf_counter() - wall0
         step_ms = np.array([marks[k].elapsed_time(marks[k + 1]) for k in range(K)])
+        serial_ms = marks[0].elapsed_time(marks[K]) / K
+        # the timed steps: frames in flight, frame k on stream k mod F and copy k mod
+        # copies (copies is a multiple of F, so a copy always returns to the same
+        # stream and its next frame is ordered after its last)
+        F = args.frames_in_flight
+        streams = [torch.cuda.Stream() for _ in range(F)]
+        for rep in range(2):  # the first pass warms the streams up
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            wall0 = time.perf_counter()
+            e0.record(stream)
+            for st in streams:
+                st.wait_stream(stream)
+            for k in range(K if rep else args.warmup):
+                with torch.cuda.stream(streams[k % F]):
+                    graphs[k % args.copies].replay()
+            for st in streams:
+                stream.wait_stream(st)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - wall0
+        pipelined_ms = e0.elapsed_time(e1) / K
         del graphs
         # the shading kernel alone: back-to-back launches over the rotated copies
         # between two events on the launch stream (the per-frame events above also
@@ -571,7 +600,7 @@ def main():
         launch_ms = e0.elapsed_time(e1) / KS
         del views
         torch.cuda.empty_cache()
-        return dict(ms_per_step=marks[0].elapsed_time(marks[K]) / K, wall_ms=1e3 * wall / K,
+        return dict(ms_per_step=pipelined_ms, wall_ms=1e3 * wall / K, serial_ms_per_frame=serial_ms,
                     p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99)),
                     eager_ms_per_step=eager_ms,
                     shade_in_frame_ms=float(shade_ms.mean()), shade_ms=launch_ms, shade_launches=KS)
@@ -588,7 +617,8 @@ def main():
         m["shade_bytes_per_px"] = acc["per_px"]
         m["Mpix_s"] = px / (m["ms_per_step"] / 1e3) / 1e6
         res[name] = m
-        log(f"{name}: ms/step {m['ms_per_step']:.4f} (wall {m['wall_ms']:.4f}, eager {m['eager_ms_per_step']:.4f}); "
+        log(f"{name}: ms/step {m['ms_per_step']:.4f} (wall {m['wall_ms']:.4f}; one frame at a time "
+            f"{m['serial_ms_per_frame']:.4f}, eager {m['eager_ms_per_step']:.4f}); "
             f"shade {m['shade_ms']:.4f} ms, "
             f"{m['shade_GBps']:.0f} GB/s")
     plain = res["fp32"]
@@ -620,8 +650,11 @@ def main():
                         "bloom, ACES + gamma 2.2 to RGBA8; fp32 throughout",
             "width": view.width, "height": view.height, "form": "plain",
             "rotated_copies": args.copies,
-            "timed": "graph replays of the captured frame (ssao, shade, bloom/tonemap: seven launches), one graph per rotated copy",
+            "frames_in_flight": args.frames_in_flight,
+            "timed": "graph replays of the captured frame (ssao, shade, bloom/tonemap: seven launches), one graph per "
+                     "rotated copy, frames in flight on as many streams; p50/p99 are frames replayed one at a time",
         },
+        "serial_ms_per_frame": round(plain["serial_ms_per_frame"], 5),
         "p50_ms": round(plain["p50"], 5),
         "p99_ms": round(plain["p99"], 5),
         "ibl_precompute_ms": round(ibl_ms, 4),
@@ -644,6 +677,7 @@ def main():
         "forms": {
             name: {"Mpix_s": round(m["Mpix_s"], 2), "ms_per_step": round(m["ms_per_step"], 5),
                    "p50_ms": round(m["p50"], 5), "p99_ms": round(m["p99"], 5),
+                   "serial_ms_per_frame": round(m["serial_ms_per_frame"], 5),
                    "eager_ms_per_step": round(m["eager_ms_per_step"], 5),
                    "eager_Mpix_s": round(px / (m["eager_ms_per_step"] / 1e3) / 1e6, 2),
                    "shade_ms": round(m["shade_ms"], 5), "shade_in_frame_ms": round(m["shade_in_frame_ms"], 5),

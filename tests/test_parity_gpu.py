@@ -355,6 +355,54 @@ def test_captured_frame_replays_match_eager(kind):
     log(f"[graph] {kind}: 4 replays bitwise equal")
 
 
+@pytest.mark.parametrize("kind", ["ragged-201x137", "full-1080p"])
+def test_frames_in_flight_match_serial(kind):
+    """Three copies of a view, each frame captured in a HIP graph, replayed
+    concurrently on three streams (as the benchmark times them) for several
+    rounds: every copy's AO, HDR and LDR equal the eager single-stream frame."""
+    v = _view(kind)
+    fr = _frame()
+    ibl = fr.DeviceIBL(v.env, **v.ibl)
+    ibl.precompute()
+    dvs = [fr.DeviceView(v, ibl) for _ in range(3)]
+    log(f"[in-flight] {kind}: eager reference, capture, concurrent replays")
+    dvs[0].render()
+    torch.cuda.synchronize()
+    ref = (dvs[0].ao.clone(), dvs[0].hdr.clone(), dvs[0].ldr.clone())
+    s = torch.cuda.current_stream()
+    side = torch.cuda.Stream()
+    graphs = []
+    for dv in dvs:
+        side.wait_stream(s)
+        with torch.cuda.stream(side):
+            dv.render()
+        s.wait_stream(side)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            dv.render()
+        graphs.append(g)
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    for rnd in range(3):
+        for dv in dvs:
+            dv.ao.fill_(-1.0)
+            dv.hdr.fill_(-1.0)
+            dv.ldr.zero_()
+        torch.cuda.synchronize()
+        for st in streams:
+            st.wait_stream(s)
+        for k in range(6):  # two frames per copy, copy k % 3 on stream k % 3
+            with torch.cuda.stream(streams[k % 3]):
+                graphs[k % 3].replay()
+        for st in streams:
+            s.wait_stream(st)
+        torch.cuda.synchronize()
+        for i, dv in enumerate(dvs):
+            for x, y in zip(ref, (dv.ao, dv.hdr, dv.ldr)):
+                assert torch.equal(x, y), (rnd, i)
+    log(f"[in-flight] {kind}: 3 rounds x 6 concurrent frames bitwise equal")
+
+
 def test_validation_leaves_outputs_untouched():
     from paper_2012_03325_amd import epb as E
     v = _view("tiny-3x2")
