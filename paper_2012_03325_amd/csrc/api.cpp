@@ -170,7 +170,7 @@ int build_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, 
                 for (int k = 0; k < 3; ++k) o += (double)A[4 * r + k] * cp[k];
                 h.o[r] = (float)o;
             }
-            h.fx = L.shadow_cam.fx; h.fy = L.shadow_cam.fy; h.cx = L.shadow_cam.cx; h.cy = L.shadow_cam.cy;
+            h.fx = L.shadow_cam.fx; h.nfy = -L.shadow_cam.fy; h.cx = L.shadow_cam.cx; h.cy = L.shadow_cam.cy;
             h.w = L.shadow_cam.width; h.h = L.shadow_cam.height;
             h.fw = (float)h.w; h.fh = (float)h.h;
             h.bias = L.shadow_bias;

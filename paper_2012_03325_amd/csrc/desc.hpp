@@ -26,7 +26,7 @@ struct DevLight {
     float pos[3], rad[3];  // rad = colour * intensity
     const float *map;      // may be null
     float M[9], o[3];      // light view from camera view: P_l = M P_v + o
-    float fx, fy, cx, cy;
+    float fx, nfy, cx, cy;  // nfy = -fy (the map's v axis points down)
     int w, h;
     float fw, fh;          // w, h as floats
     float bias;

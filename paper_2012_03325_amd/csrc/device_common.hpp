@@ -62,6 +62,15 @@ __device__ __forceinline__ v3 cross(v3 a, v3 b) {
     return mk3(fmaf(a.y, b.z, -a.z * b.y), fmaf(a.z, b.x, -a.x * b.z), fmaf(a.x, b.y, -a.y * b.x));
 }
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+// floor and convert to int in one VALU instruction.  (int)floorf(x) is two
+// (v_floor, v_cvt), because the fused v_cvt_flr_i32_f32 is only selected under
+// finite-math, which these kernels cannot assume (+inf marks background).
+// Results agree for every input: both saturate out of range, NaN gives 0.
+__device__ __forceinline__ int floor_to_int(float x) {
+    int r;
+    asm("v_cvt_flr_i32_f32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ v3 normalize(v3 a) { return a * rsq(dot(a, a)); }
 __device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }

@@ -59,7 +59,7 @@ __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, fl
     float dl = -Pl.z;
     float idl = rcp(dl);
     float u = fmaf(L.fx * Pl.x, idl, L.cx);
-    float v = fmaf(-L.fy * Pl.y, idl, L.cy);
+    float v = fmaf(L.nfy * Pl.y, idl, L.cy);
     bool inside = dl > 0.0f && u >= 0.0f && u < L.fw && v >= 0.0f && v < L.fh;
     int i0 = inside ? (int)u : 1, j0 = inside ? (int)v : 1;  // truncation == floor when inside
     int bi = min(max(i0, 1), L.w - 2), bj = min(max(j0, 1), L.h - 2);

@@ -88,9 +88,9 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile, const
             float ny = fmaf(Yv.x, sx, fmaf(Yv.y, sy, fmaf(Yv.z, sz, Y0)));
             float iz = rcp(zq);
             // floor-convert: 0 <= hx < Wh exactly when 0 <= floor(hx) < Wh (one unsigned
-            // compare; NaN and out-of-range values convert outside the range or are
-            // rejected by zq > 0)
-            int ix = (int)floorf(nx * iz), iy = (int)floorf(ny * iz);
+            // compare; out-of-range values saturate outside the range, and a NaN
+            // (converted to 0) only arises with zq <= 0 or a NaN input, rejected by zq > 0)
+            int ix = floor_to_int(nx * iz), iy = floor_to_int(ny * iz);
             ok[b] = (k0 + b < c.n) && zq > 0.0f && (unsigned)ix < (unsigned)c.Wh && (unsigned)iy < (unsigned)c.Hh;
             unsigned idx = ok[b] ? __umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix : 0u;
             ds[b] = ldf(c.hdepth, idx);
