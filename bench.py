@@ -432,31 +432,53 @@ def bench_serving(args, torch, E, frame, synth, schedule=None) -> dict:
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(view, budget_s: float) -> dict:
     """The FP64 oracle on the host cores: whole frames (SSAO, blur, shading,
     bloom + tonemap, without the per-environment precompute) until the time
-    budget is used; Mpix/s over the frames completed."""
+    budget is used; Mpix/s over the frames completed.  Then the same on one
+    thread for a third of the budget."""
     from oracle import oracle as orc
     ibl = orc.precompute_ibl(view.env, **dict(view.ibl, pref_samples=64, lut_size=32,
                                               lut_samples=64))
     g = view.gbuf
-    frames, t0 = 0, time.perf_counter()
-    while True:
-        raw = orc.ssao_raw(g["depth"], g["normal"], view.cam, view.ssao_kernel, view.ssao_noise,
-                           view.ssao_radius, view.ssao_bias)
-        ao = orc.ssao_blur(*raw, g["depth"], view.blur_tau)
-        lo, hi = orc.shade(g, view.cam, *ao, view.lights, ibl, view.env)
-        orc.bloom_tonemap(lo, exposure=view.exposure)
-        frames += 1
-        el = time.perf_counter() - t0
-        if el >= budget_s:
-            break
-    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     px = view.width * view.height
+
+    def run(budget):
+        frames, t0 = 0, time.perf_counter()
+        while True:
+            raw = orc.ssao_raw(g["depth"], g["normal"], view.cam, view.ssao_kernel, view.ssao_noise,
+                               view.ssao_radius, view.ssao_bias)
+            ao = orc.ssao_blur(*raw, g["depth"], view.blur_tau)
+            lo, hi = orc.shade(g, view.cam, *ao, view.lights, ibl, view.env)
+            orc.bloom_tonemap(lo, exposure=view.exposure)
+            frames += 1
+            el = time.perf_counter() - t0
+            if el >= budget:
+                return frames, el
+
+    threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
+    orc.set_threads(threads)
+    frames, el = run(budget_s)
+    orc.set_threads(1)
+    frames1, el1 = run(budget_s / 3.0)
+    orc.set_threads(threads)
     return {"value": round(frames * px / el / 1e6, 3), "unit": "Mpix/s", "cores": threads,
-            "kind": "oracle",
+            "kind": "oracle", "cpu_model": _cpu_model(),
+            "single_thread_Mpix_s": round(frames1 * px / el1 / 1e6, 3),
             "sample": f"{frames} whole {view.width}x{view.height} frames of the FP64 oracle "
-                      f"(SSAO+blur+shade+bloom/tonemap, IBL tables precomputed outside) in {el:.1f} s"}
+                      f"(SSAO+blur+shade+bloom/tonemap, IBL tables precomputed outside) in {el:.1f} s on "
+                      f"{threads} threads; {frames1} frames in {el1:.1f} s on one thread"}
 
 
 def main():

@@ -24,6 +24,9 @@
 #include <math.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #define PI 3.14159265358979323846
 
@@ -1002,4 +1005,13 @@ void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double thres
     for (int l = 0; l <= nl; ++l) free(lvl[l]);
     for (int l = 1; l <= nl; ++l) free(blur[l]);
     free(lvl); free(blur); free(lw); free(lh);
+}
+
+/* Threads of the parallel loops (timing the oracle on 1 and on all cores). */
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
 }

@@ -134,4 +134,7 @@ void orc_bloom_tonemap(const double *hdr, int W, int H, int levels, double thres
                        double strength, double exposure, double gamma, int tonemap, uint8_t *ldr,
                        double *composite, double *pyramid);
 
+/* Threads used by the OpenMP loops of the oracle. */
+void orc_set_threads(int n);
+
 #endif

@@ -98,6 +98,7 @@ def lib():
         L.orc_normalize_gbuffer.argtypes = [_D, C.c_int, C.c_int, _D, _D, _D, _D]
         L.orc_raycast.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcCamera), C.c_double, _D,
                                   C.POINTER(C.c_int32), _D, _D, _D, _D, C.POINTER(C.c_uint8)]
+        L.orc_set_threads.argtypes = [C.c_int]
         L.orc_edl_offsets.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.orc_edl.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, _D, C.c_int, C.c_int, C.c_double,
                               C.c_double, _D, C.c_int, C.c_double, _D, _D]
@@ -350,6 +351,11 @@ def shade(gbuf: dict, cam, ao_lo, ao_hi, lights: Sequence, ibl: dict, env,
 # ---------------------------------------------------------------------------
 # eye-dome lighting (Sec. 4.3)
 # ---------------------------------------------------------------------------
+def set_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops."""
+    lib().orc_set_threads(int(n))
+
+
 def edl_offsets(radius: int, n_dirs: int) -> List[Tuple[int, int]]:
     dx = (C.c_int * n_dirs)()
     dy = (C.c_int * n_dirs)()
