@@ -18,7 +18,7 @@ import collections
 import json
 import os
 import threading
-from typing import Dict, List, Optional, Tuple
+from typing import Callable, Dict, List, Optional, Tuple
 
 import torch
 
@@ -44,11 +44,12 @@ def _as_sched(d: Dict[str, int]) -> E.epb_schedule:
     return E.epb_schedule(d["shade_tile"], d["ssao_tile"], d["ssao_batch"], d["blocks_per_cu"])
 
 
-def signature(batch) -> str:
+def signature(batch, device: Optional[str] = None) -> str:
     dv0 = batch.dviews[0]
     sizes = collections.Counter((dv.W, dv.H, int(dv.ssao_params.n_samples), len(dv.lights))
                                 for dv in batch.dviews)
-    key = dict(device=torch.cuda.get_device_name(), g=dv0.gdtype, a=dv0.ao_dtype, h=dv0.hdr_dtype,
+    key = dict(device=device if device is not None else torch.cuda.get_device_name(), g=dv0.gdtype,
+               a=dv0.ao_dtype, h=dv0.hdr_dtype,
                blur=int(dv0.ssao_params.blur),
                views=sorted([list(k) + [c] for k, c in sizes.items()]))
     return json.dumps(key, sort_keys=True)
@@ -69,10 +70,15 @@ def time_render(batch, reps: int = 3, stream=None) -> float:
 
 
 def tune(batch, reps: int = 3, passes: int = 2, cache_path: Optional[str] = None,
-         use_cache: bool = True) -> Tuple[E.epb_schedule, List[dict]]:
+         use_cache: bool = True, timer: Optional[Callable] = None,
+         device: Optional[str] = None) -> Tuple[E.epb_schedule, List[dict]]:
     """Pick the fastest schedule for ``batch`` (a frame.DeviceBatch) and leave
-    the batch built with it.  Returns the schedule and the timings tried."""
-    sig = signature(batch)
+    the batch built with it.  Returns the schedule and the timings tried.
+    ``timer(batch, reps)`` measures one schedule (default: HIP events around
+    renders); ``device`` names the device in the cache key (default: the
+    current GPU's name)."""
+    timer = timer or time_render
+    sig = signature(batch, device)
     if use_cache:
         with _lock:
             if not _cache and cache_path and os.path.exists(cache_path):
@@ -90,7 +96,7 @@ def tune(batch, reps: int = 3, passes: int = 2, cache_path: Optional[str] = None
         key = tuple(d[k] for k in ORDER)
         if key not in tried:
             batch.build(_as_sched(d))
-            tried[key] = time_render(batch, reps)
+            tried[key] = timer(batch, reps)
             trace.append(dict(schedule=dict(d), ms=tried[key]))
         return tried[key]
 
