@@ -159,16 +159,48 @@ typedef struct {
     epb_dtype out_dtype;  /* storage of the AO image                          */
 } epb_ssao_params;
 
+/* Storage layouts of a shadow map (epb_light.shadow_layout). */
+#define EPB_MAP_ROWS 0  /* [h][w] row-major                                        */
+#define EPB_MAP_TILES 1 /* the tiled form written by epb_shadow_tiles (below)      */
+
 /* Point light (Sec. 5.1) with an optional depth map rendered from the light. */
 typedef struct {
     float pos[3];
     float color[3];
     float intensity;          /* radiance at distance r is color * intensity / r^2 */
-    const float *shadow_map;  /* device [h][w] linear depth (+inf empty), or NULL;
-                                 at least 3x3 texels                              */
+    const float *shadow_map;  /* device linear depth (+inf empty) of w x h texels
+                                 (w, h from shadow_cam, at least 3x3) in
+                                 shadow_layout, or NULL                           */
     epb_camera shadow_cam;    /* camera the map was rendered with                 */
     float shadow_bias;        /* depth bias of the shadow test (e.g. 0.02)        */
+    int32_t shadow_layout;    /* EPB_MAP_ROWS or EPB_MAP_TILES (same results; the
+                                 tiled form fetches faster)                       */
 } epb_light;
+
+/*
+ * Tiled form of a shadow map.  The 3x3 percentage-closer test (Sec. 5.1)
+ * reads a 3x3 texel patch around each shaded point's projection; neighbouring
+ * pixels project onto a rotated strip of the map, so in row-major order one
+ * wavefront's patch rows fall on many different cache lines.  The tiled form
+ * cuts the map into tiles of 6x6 texels and stores each as an 8x8 block of
+ * floats that repeats the next two columns and rows (clamped to the map's last
+ * column and row): every 3x3 patch then lies inside one block, its three rows
+ * 8 floats apart, and a strip of the map covers far fewer lines.
+ *
+ *   nx = ceil((w - 2) / 6) tiles across, ny = ceil((h - 2) / 6) down, tiles in
+ *   row-major order; float (p nx + q) 64 + 8 j + i (0 <= i, j < 8) holds
+ *   map[min(6 p + j, h - 1)][min(6 q + i, w - 1)].
+ *
+ * epb_shadow_tiles_bytes(w, h) = 256 nx ny (0 unless 3 <= w, h <=
+ * EPB_MAX_IMAGE_SIZE).  epb_shadow_tiles copies the row-major [h][w] `map`
+ * into `tiles` (>= epb_shadow_tiles_bytes bytes, not overlapping `map`) on
+ * `stream`; a renderer calls it whenever it re-renders a map.  Statuses:
+ * EPB_ERR_NULL, EPB_ERR_SIZE (sizes out of range or `tiles` too small),
+ * EPB_ERR_ALIGN, EPB_ERR_PARAM (the two buffers overlap).
+ */
+size_t epb_shadow_tiles_bytes(int32_t width, int32_t height);
+int epb_shadow_tiles(const float *map, int32_t width, int32_t height, float *tiles, size_t tiles_bytes,
+                     hipStream_t stream);
 
 /* Bloom and tone mapping (Sec. 5.3, 5.4). */
 typedef struct {

@@ -174,6 +174,9 @@ int build_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, 
             h.w = L.shadow_cam.width; h.h = L.shadow_cam.height;
             h.fw = (float)h.w; h.fh = (float)h.h;
             h.bias = L.shadow_bias;
+            if (L.shadow_layout != EPB_MAP_ROWS && L.shadow_layout != EPB_MAP_TILES) return EPB_ERR_PARAM;
+            h.tiles = L.shadow_layout == EPB_MAP_TILES;
+            h.tile_pitch = h.tiles ? epb::shadow_tiles_plan(h.w, h.h).pitch : 0u;
         }
     }
     a.irr = ibl->irradiance.data; a.irr_size = ibl->irradiance.size;
@@ -324,6 +327,23 @@ int epb_edl(const float *depth, const void *color, epb_dtype color_dtype, const 
         c.loff[k] = dy * pitch + dx;
     }
     return hip_status(epb::launch_edl(c, color_dtype, ao_dtype, hdr_dtype, stream));
+}
+
+size_t epb_shadow_tiles_bytes(int32_t width, int32_t height) {
+    if (width < 3 || height < 3 || width > EPB_MAX_IMAGE_SIZE || height > EPB_MAX_IMAGE_SIZE) return 0;
+    return epb::shadow_tiles_plan(width, height).bytes;
+}
+
+int epb_shadow_tiles(const float *map, int32_t width, int32_t height, float *tiles, size_t tiles_bytes,
+                     hipStream_t stream) {
+    if (!map || !tiles) return EPB_ERR_NULL;
+    size_t need = epb_shadow_tiles_bytes(width, height);
+    if (!need || tiles_bytes < need) return EPB_ERR_SIZE;
+    if (!aligned16(map) || !aligned16(tiles)) return EPB_ERR_ALIGN;
+    uintptr_t m0 = (uintptr_t)map, m1 = m0 + (size_t)width * (size_t)height * 4u;
+    uintptr_t t0 = (uintptr_t)tiles, t1 = t0 + need;
+    if (m0 < t1 && t0 < m1) return EPB_ERR_PARAM;
+    return hip_status(epb::launch_shadow_tiles(map, width, height, tiles, stream));
 }
 
 size_t epb_scratch_bytes(int32_t op, int32_t width, int32_t height, const void *params) {

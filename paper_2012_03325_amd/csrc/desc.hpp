@@ -30,6 +30,8 @@ struct DevLight {
     int w, h;
     float fw, fh;          // w, h as floats
     float bias;
+    int tiles;             // map in the tiled form (6x6 texels per 8x8 block)
+    unsigned tile_pitch;   // byte step per row of tiles minus 6 block rows: 256 nx - 192
 };
 
 struct SsaoDesc {

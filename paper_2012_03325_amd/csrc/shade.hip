@@ -64,11 +64,24 @@ __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, fl
     int i0 = inside ? (int)u : 1, j0 = inside ? (int)v : 1;  // truncation == floor when inside
     int bi = min(max(i0, 1), L.w - 2), bj = min(max(j0, 1), L.h - 2);
     // three 12-byte row loads (dword aligned) cover the 3x3 block
-    unsigned q0 = (__umul24((unsigned)(bj - 1), (unsigned)L.w) + (unsigned)(bi - 1)) * 4u;
-    unsigned row = (unsigned)L.w * 4u;
-    Row3 a = ldo(reinterpret_cast<const Row3 *>(L.map), q0);
-    Row3 b = ldo(reinterpret_cast<const Row3 *>(L.map), q0 + row);
-    Row3 e = ldo(reinterpret_cast<const Row3 *>(L.map), q0 + 2u * row);
+    const Row3 *map = reinterpret_cast<const Row3 *>(L.map);
+    Row3 a, b, e;
+    if (L.tiles) {
+        // tiled form: the block (x .. x+2, y .. y+2) lies inside tile (y / 6, x / 6),
+        // whose 8x8 floats repeat the next two columns and rows; its rows are 32 bytes apart
+        unsigned x = (unsigned)(bi - 1), y = (unsigned)(bj - 1);
+        unsigned tq = __umulhi(x, 0x2AAAAAABu), tp = __umulhi(y, 0x2AAAAAABu);  // x / 6, y / 6 (exact below 2^31)
+        unsigned q0 = __umul24(tp, L.tile_pitch) + __umul24(tq, 232u) + y * 32u + x * 4u;
+        a = ldo(map, q0);
+        b = ldo(map, q0 + 32u);
+        e = ldo(map, q0 + 64u);
+    } else {
+        unsigned q0 = (__umul24((unsigned)(bj - 1), (unsigned)L.w) + (unsigned)(bi - 1)) * 4u;
+        unsigned row = (unsigned)L.w * 4u;
+        a = ldo(map, q0);
+        b = ldo(map, q0 + row);
+        e = ldo(map, q0 + 2u * row);
+    }
     float t[9] = {a.v[0], a.v[1], a.v[2], b.v[0], b.v[1], b.v[2], e.v[0], e.v[1], e.v[2]};
     float ref = dl - L.bias;
     int lit = 0;
@@ -306,6 +319,34 @@ hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
     ShadeDesc k = shade_desc(a);
     if (a.gdtype == EPB_F32) go_a<float>(nullptr, nullptr, &k, a.ao_dtype, a.hdr_dtype, s);
     else go_a<__half>(nullptr, nullptr, &k, a.ao_dtype, a.hdr_dtype, s);
+    return hipGetLastError();
+}
+
+// Tiled form of a shadow map: one thread per stored float, one row of tiles per
+// blockIdx.y; consecutive threads write consecutive floats and read runs of 8
+// texels of a map row.
+__global__ void __launch_bounds__(256) k_shadow_tiles(const float *__restrict__ map, int w, int h, int nx,
+                                                      float *__restrict__ tiles) {
+    unsigned t = blockIdx.x * 256u + threadIdx.x;  // float index inside this row of tiles
+    if (t >= (unsigned)nx * 64u) return;
+    unsigned p = blockIdx.y, q = t >> 6, j = (t >> 3) & 7u, i = t & 7u;
+    unsigned sx = min(6u * q + i, (unsigned)w - 1u), sy = min(6u * p + j, (unsigned)h - 1u);
+    tiles[(size_t)p * nx * 64u + t] = map[(size_t)sy * (unsigned)w + sx];
+}
+
+ShadowTilesPlan shadow_tiles_plan(int w, int h) {
+    ShadowTilesPlan t{};
+    t.nx = ceil_div(w - 2, 6);
+    t.ny = ceil_div(h - 2, 6);
+    t.bytes = (size_t)t.nx * (size_t)t.ny * 256u;
+    t.pitch = 256u * (unsigned)t.nx - 192u;
+    return t;
+}
+
+hipError_t launch_shadow_tiles(const float *map, int w, int h, float *tiles, hipStream_t s) {
+    ShadowTilesPlan t = shadow_tiles_plan(w, h);
+    dim3 grid(ceil_div(t.nx * 64, 256), t.ny);
+    k_shadow_tiles<<<grid, 256, 0, s>>>(map, w, h, t.nx, tiles);
     return hipGetLastError();
 }
 

@@ -41,12 +41,14 @@ EPB_TONEMAP_ACES = 0
 EPB_TONEMAP_REINHARD = 1
 EPB_MAX_EDL_RADIUS = 16
 EPB_MAX_EDL_DIRS = 32
+EPB_MAP_ROWS = 0
+EPB_MAP_TILES = 1
 
 ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
                 "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
                 "epb_batch_table_bytes", "epb_view_scratch_bytes", "epb_batch_scratch_bytes",
                 "epb_batch_build",
-                "epb_render_batch", "epb_raycast", "epb_edl")
+                "epb_render_batch", "epb_raycast", "epb_edl", "epb_shadow_tiles_bytes", "epb_shadow_tiles")
 
 
 class EpbError(RuntimeError):
@@ -92,7 +94,8 @@ class epb_ssao_params(C.Structure):
 
 class epb_light(C.Structure):
     _fields_ = [("pos", C.c_float * 3), ("color", C.c_float * 3), ("intensity", C.c_float),
-                ("shadow_map", C.c_void_p), ("shadow_cam", epb_camera), ("shadow_bias", C.c_float)]
+                ("shadow_map", C.c_void_p), ("shadow_cam", epb_camera), ("shadow_bias", C.c_float),
+                ("shadow_layout", C.c_int32)]
 
 
 class epb_post_params(C.Structure):
@@ -168,8 +171,12 @@ def _load() -> C.CDLL:
                                 C.c_size_t, P]
     lib.epb_edl.argtypes = [P, P, C.c_int, C.POINTER(epb_camera), P, C.c_int, C.POINTER(epb_edl_params),
                             C.POINTER(epb_cube), P, C.c_int, P]
+    lib.epb_shadow_tiles_bytes.argtypes = [C.c_int32, C.c_int32]
+    lib.epb_shadow_tiles_bytes.restype = C.c_size_t
+    lib.epb_shadow_tiles.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, P]
     for fn in ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
-               "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast", "epb_edl"):
+               "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast", "epb_edl",
+               "epb_shadow_tiles"):
         getattr(lib, fn).restype = C.c_int
     return lib
 
@@ -292,6 +299,16 @@ def epb_edl(depth, color, color_dtype: int, cam: epb_camera, ao, ao_dtype: int, 
     st = lib.epb_edl(_ptr(depth), _ptr(color), color_dtype, C.byref(cam), _ptr(ao), ao_dtype, C.byref(params),
                      C.byref(env) if env is not None else None, _ptr(hdr_out), hdr_dtype, _stream(stream))
     return _check("epb_edl", st, check)
+
+
+def epb_shadow_tiles_bytes(width: int, height: int) -> int:
+    return lib.epb_shadow_tiles_bytes(width, height)
+
+
+def epb_shadow_tiles(shadow_map, width: int, height: int, tiles, tiles_bytes: int, stream=None,
+                     check: bool = True) -> int:
+    st = lib.epb_shadow_tiles(_ptr(shadow_map), width, height, _ptr(tiles), tiles_bytes, _stream(stream))
+    return _check("epb_shadow_tiles", st, check)
 
 
 # ---------------------------------------------------------------------------

@@ -23,6 +23,16 @@ def _cam_struct(cam) -> E.epb_camera:
                          cam.cx, cam.cy, cam.width, cam.height)
 
 
+def tile_shadow_map(m: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Tiled form (EPB_MAP_TILES) of the row-major [h][w] float32 depth map ``m``."""
+    h, w = m.shape
+    n = E.epb_shadow_tiles_bytes(w, h)
+    if out is None or out.numel() * 4 < n:
+        out = torch.empty(n // 4, dtype=torch.float32, device=m.device)
+    E.epb_shadow_tiles(m, w, h, out, out.numel() * 4, stream)
+    return out
+
+
 class DeviceIBL:
     """Environment cube and its image-based-lighting tables on the device."""
 
@@ -114,11 +124,13 @@ class DeviceView:
     assign ``ssao_scratch`` and ``postp.scratch`` before calling them).
     ``src`` takes the G-buffer from another device view (converted to
     ``gdtype`` on the device) instead of uploading it again.  ``outputs=False``
-    allocates no AO, HDR or LDR image (views that only serve as templates)."""
+    allocates no AO, HDR or LDR image (views that only serve as templates).
+    ``shadow_layout`` is the storage of the lights' depth maps on the device:
+    EPB_MAP_TILES (the default, faster to fetch) or EPB_MAP_ROWS."""
 
     def __init__(self, view, ibl: DeviceIBL, gdtype=E.EPB_F32, ao_dtype=E.EPB_F32,
                  hdr_dtype=E.EPB_F32, device="cuda", bloom_levels=6, solo_scratch=True,
-                 src: Optional["DeviceView"] = None, outputs: bool = True):
+                 src: Optional["DeviceView"] = None, outputs: bool = True, shadow_layout=E.EPB_MAP_TILES):
         self.view = view
         self.ibl = ibl
         self.device = device
@@ -161,10 +173,13 @@ class DeviceView:
             s.intensity = float(L.intensity)
             if L.shadow_map is not None:
                 m = dev(L.shadow_map)
+                if shadow_layout == E.EPB_MAP_TILES:
+                    m = tile_shadow_map(m)
                 self.shadow_maps.append(m)
                 s.shadow_map = m.data_ptr()
                 s.shadow_cam = _cam_struct(L.shadow_cam)
                 s.shadow_bias = float(L.shadow_bias)
+                s.shadow_layout = shadow_layout
             self.lights.append(s)
         self.postp = DevicePost(W, H, bloom_levels, view.bloom_threshold, view.bloom_strength,
                                 view.exposure, view.gamma, device, pyr_dtype=hdr_dtype,
@@ -347,12 +362,14 @@ class ShadowCache:
     ``scene`` provides ``version`` (bumped on every geometry change) and
     ``render_depth(cam, out=None, stream=None)``; ``maps(cams)`` returns one
     depth map per light camera, reusing the stored map of a light whose camera
-    and scene version are those it was rendered with.  ``renders`` counts the
-    depth renders issued."""
+    and scene version are those it was rendered with.  With ``tiles=True`` the
+    maps are returned in the tiled form (EPB_MAP_TILES), converted once per
+    render.  ``renders`` counts the depth renders issued."""
 
-    def __init__(self, scene):
+    def __init__(self, scene, tiles: bool = False):
         self.scene = scene
-        self._entries = {}  # light index -> (camera key, scene version, map)
+        self.tiles = tiles
+        self._entries = {}  # light index -> (camera key, scene version, map, tiled map or None)
         self.renders = 0
 
     @staticmethod
@@ -366,13 +383,14 @@ class ShadowCache:
             key = self._key(cam)
             ent = self._entries.get(i)
             if ent is not None and ent[0] == key and ent[1] == self.scene.version:
-                out.append(ent[2])
+                out.append(ent[3] if self.tiles else ent[2])
                 continue
             reuse = ent[2] if ent is not None and tuple(ent[2].shape) == (cam.height, cam.width) else None
             m = self.scene.render_depth(cam, out=reuse, stream=stream)
             self.renders += 1
-            self._entries[i] = (key, self.scene.version, m)
-            out.append(m)
+            t = tile_shadow_map(m, out=ent[3] if ent is not None else None, stream=stream) if self.tiles else None
+            self._entries[i] = (key, self.scene.version, m, t)
+            out.append(t if self.tiles else m)
         return out
 
     def invalidate(self):

@@ -152,6 +152,39 @@ def test_shade_validation():
     unaligned_map[0].shadow_map = FAKE + 4
     assert E.lib.epb_shade(C.byref(g), C.byref(cam), FAKE, E.EPB_F32, unaligned_map, 1,
                            C.byref(maps), C.byref(cube), FAKE, E.EPB_F32, None) == E.EPB_ERR_ALIGN
+    bad_layout = (E.epb_light * 1)()
+    bad_layout[0].intensity = 1.0
+    bad_layout[0].shadow_map = FAKE
+    bad_layout[0].shadow_cam = _cam()
+    bad_layout[0].shadow_layout = 2
+    assert E.lib.epb_shade(C.byref(g), C.byref(cam), FAKE, E.EPB_F32, bad_layout, 1,
+                           C.byref(maps), C.byref(cube), FAKE, E.EPB_F32, None) == E.EPB_ERR_PARAM
+
+
+def test_shadow_tiles_sizes_and_validation():
+    """Tiles of 6x6 texels stored as 8x8 floats: ceil((w - 2) / 6) x
+    ceil((h - 2) / 6) tiles of 256 bytes."""
+    nb = E.epb_shadow_tiles_bytes
+    assert nb(2048, 2048) == 341 * 341 * 256
+    assert nb(3, 3) == nb(8, 8) == 256
+    assert nb(9, 8) == 2 * 256 and nb(9, 9) == 4 * 256
+    assert nb(1920, 1080) == 320 * 180 * 256
+    assert nb(16384, 16384) == 2731 * 2731 * 256 < 2 ** 32
+    assert nb(2, 9) == nb(9, 2) == nb(16385, 9) == nb(-1, 9) == 0
+    need = nb(64, 48)
+
+    def call(m=FAKE, w=64, h=48, t=FAKE + (1 << 20), n=need):
+        return E.lib.epb_shadow_tiles(m, w, h, t, n, None)
+
+    assert call(m=None) == E.EPB_ERR_NULL
+    assert call(t=None) == E.EPB_ERR_NULL
+    assert call(w=2) == E.EPB_ERR_SIZE
+    assert call(h=16385) == E.EPB_ERR_SIZE
+    assert call(n=need - 1) == E.EPB_ERR_SIZE
+    assert call(m=FAKE + 4) == E.EPB_ERR_ALIGN
+    assert call(t=FAKE + 8 + (1 << 20)) == E.EPB_ERR_ALIGN
+    assert call(t=FAKE + 64 * 48 * 4 - 16) == E.EPB_ERR_PARAM  # tiles start inside the map
+    assert call(t=FAKE - need + 16) == E.EPB_ERR_PARAM  # tiles end inside the map
 
 
 def test_bloom_tonemap_validation():
