@@ -38,6 +38,17 @@ __device__ __forceinline__ void stf(__half *base, unsigned i, float v) {
     sto(base, i * 2u, __float2half_rn(fminf(v, 65504.0f)));  // saturate (HDR peaks can exceed 65504)
 }
 
+// Raw buffer resource over the first `bytes` bytes at `base`.  A load through it
+// at a byte offset at or past `bytes` returns 0 without touching memory (the
+// buffer unit's range check), so a gather can be issued from an unchecked
+// offset and its result discarded when the offset was not valid.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void *base, unsigned bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_ldf(__amdgpu_buffer_rsrc_t r, unsigned byte_off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
+}
+
 __device__ __forceinline__ float ldc(const float *p) { return *p; }
 __device__ __forceinline__ float ldc(const __half *p) { return __half2float(*p); }
 

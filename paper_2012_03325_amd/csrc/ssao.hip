@@ -5,12 +5,18 @@
 //  * prep compacts the half-resolution depth (the depth at (2i, 2j)) into a
 //    dense Wh x Hh plane: 2 MB at 1080p, resident in one XCD's 4 MB L2, so
 //    the sample gathers hit L2 instead of striding the full-resolution plane.
-//  * raw: one thread per half-resolution texel; the sample kernel is staged in
-//    LDS and read as wave-uniform broadcasts.  A sample's depth and projected
-//    texel coordinates are affine in the kernel vector (three plane equations
-//    per pixel), so a sample costs 9 FMA, one reciprocal, two multiplies, a
-//    range test and one gathered depth; gathers are issued a batch at a time
-//    from clamped addresses before any is consumed.
+//    It stores h = (d + bias) / radius: the occlusion test d_s <= z_q - bias
+//    becomes h_s <= z_q / radius and the range term radius / |d - d_s| becomes
+//    1 / |h - h_s|, two instructions fewer per sample.
+//  * raw: one thread per half-resolution texel; the sample kernel is read with
+//    scalar loads (wave-uniform).  A sample's depth and projected texel
+//    coordinates, in units of the radius, are affine in the kernel vector
+//    (three plane equations per pixel), so a sample costs 9 FMA, one
+//    reciprocal, two multiplies, two floor-converts, a range test, one
+//    gathered depth and 5 instructions of smoothstep and sum; gathers are
+//    issued a batch at a time before any is consumed, through a buffer
+//    resource whose range check makes an out-of-image offset read 0 (the
+//    sample is discarded by its range test).
 //  * blur: 4x4 bilateral mean; the 19x11 depth/AO footprint of a 16x8 tile is
 //    staged through LDS.
 //  * every stage has a single-view kernel (one block per tile, XCD-aware
@@ -23,21 +29,57 @@ namespace epb {
 // ---------------------------------------------------------------------------
 // per-item work
 // ---------------------------------------------------------------------------
+// Stored form of a half-resolution depth: (d + bias) / radius (+inf stays +inf).
+__device__ __forceinline__ float ssao_h(const SsaoDesc &c, float d) { return (d + c.bias) * c.inv_radius; }
+
 __device__ __forceinline__ void ssao_prep_item(const SsaoDesc &c, int item) {
     int chunks = (c.Wh + kSsaoPrepW - 1) / kSsaoPrepW;
     int j = item / chunks;
     int i = (item - j * chunks) * kSsaoPrepW + (int)threadIdx.x;
     if (i >= c.Wh) return;
     stf(c.hdepth, __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i,
-        ldf(c.depth, __umul24((unsigned)(2 * j), (unsigned)c.W) + (unsigned)(2 * i)));
+        ssao_h(c, ldf(c.depth, __umul24((unsigned)(2 * j), (unsigned)c.W) + (unsigned)(2 * i))));
 }
 
-__device__ __forceinline__ void stage_kernel(const SsaoDesc &c, float *sk) {
-    for (int q = threadIdx.x; q < c.n * 3; q += blockDim.x) sk[q] = c.kernel[q];
+// KB samples of one pixel: all gathers issued before any is used.  `kern` points
+// at the batch's first kernel vector; with `ragged`, only the first `m` samples
+// exist (the others repeat the last one and are discarded).
+template <int KB, bool ragged>
+__device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const float *kern, int m, v3 Xv, v3 Yv, v3 Zv,
+                                            float X0, float Y0, float Z0, float hp, __amdgpu_buffer_rsrc_t hdepth,
+                                            float occ) {
+    float hs[KB], zqs[KB];
+    bool ok[KB];
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+        int k = ragged ? min(b, m - 1) : b;  // wave-uniform: scalar loads
+        float sx = kern[3 * k], sy = kern[3 * k + 1], sz = kern[3 * k + 2];
+        float zq = fmaf(Zv.x, sx, fmaf(Zv.y, sy, fmaf(Zv.z, sz, Z0)));
+        float nx = fmaf(Xv.x, sx, fmaf(Xv.y, sy, fmaf(Xv.z, sz, X0)));
+        float ny = fmaf(Yv.x, sx, fmaf(Yv.y, sy, fmaf(Yv.z, sz, Y0)));
+        float iz = rcp(zq);
+        // floor-convert: 0 <= hx < Wh exactly when 0 <= floor(hx) < Wh (one unsigned
+        // compare; out-of-range values saturate outside the range, and a NaN
+        // (converted to 0) only arises with zq <= 0 or a NaN input, rejected by zq > 0)
+        int ix = floor_to_int(nx * iz), iy = floor_to_int(ny * iz);
+        ok[b] = (!ragged || b < m) && zq > 0.0f && (unsigned)ix < (unsigned)c.Wh && (unsigned)iy < (unsigned)c.Hh;
+        // unchecked offset: when !ok it may point anywhere (a load past the plane
+        // reads 0, one inside it an unrelated texel) and the sample is discarded
+        hs[b] = buf_ldf(hdepth, (__umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix) * 4u);
+        zqs[b] = zq;
+    }
+#pragma unroll
+    for (int b = 0; b < KB; ++b) {
+        // smoothstep(radius / |d - d_s|) = u^2 (3 - 2u), u = clamp(1 / |h - h_s|)
+        float u = clamp01(rcp(fabsf(hp - hs[b])));
+        float u2 = u * u, w = fmaf(-2.0f, u, 3.0f);
+        occ = fmaf(u2, (ok[b] && hs[b] <= zqs[b]) ? w : 0.0f, occ);  // d_s <= z_q - bias
+    }
+    return occ;
 }
 
 template <int TX, int TY, int KB, typename TG, typename TA>
-__device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile, const float *sk) {
+__device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     int tiles_x = (c.Wh + TX - 1) / TX;
     int ty = tile / tiles_x;
     int i = (tile - ty * tiles_x) * TX + (int)(threadIdx.x % TX);
@@ -63,46 +105,29 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile, const
     v3 r = mk3(rn[0], rn[1], 0.0f);
     v3 t = normalize(r - nv * dot(nv, r));
     v3 bb = cross(nv, t);
-    // Sample s of the kernel lands at Q = P + radius (t sx + b sy + n sz).  Its
-    // depth zq = -Q.z and the numerators of its half-resolution texel
-    // coordinates hx = u / 2 + 1/4 = (fx/2 Q.x + (cx/2 + 1/4) zq) / zq (hy alike,
-    // y flipped) are affine in s: three plane equations per pixel.
+    // Sample s of the kernel lands at Q = P + radius (t sx + b sy + n sz).  In
+    // units of the radius its depth zq = -Q.z / radius and the numerators of its
+    // half-resolution texel coordinates hx = u / 2 + 1/4 = (fx/2 Q.x + (cx/2 +
+    // 1/4) (-Q.z)) / (-Q.z) (hy alike, y flipped) are affine in s: three plane
+    // equations per pixel.
     float ax = 0.5f * c.cam.fx, bx = 0.5f * c.cam.cx + 0.25f;
     float ay = -0.5f * c.cam.fy, by = 0.5f * c.cam.cy + 0.25f;
-    v3 Mx = mk3(t.x, bb.x, nv.x) * c.radius, My = mk3(t.y, bb.y, nv.y) * c.radius,
-       Mz = mk3(t.z, bb.z, nv.z) * c.radius;
-    v3 Zv = mk3(-Mz.x, -Mz.y, -Mz.z);
-    float Z0 = -P.z;
+    v3 Pr = P * c.inv_radius;
+    v3 Mx = mk3(t.x, bb.x, nv.x), My = mk3(t.y, bb.y, nv.y);
+    v3 Zv = mk3(-t.z, -bb.z, -nv.z);
+    float Z0 = -Pr.z;
     v3 Xv = Mx * ax + Zv * bx, Yv = My * ay + Zv * by;
-    float X0 = fmaf(ax, P.x, bx * Z0), Y0 = fmaf(ay, P.y, by * Z0);
+    float X0 = fmaf(ax, Pr.x, bx * Z0), Y0 = fmaf(ay, Pr.y, by * Z0);
+    float hp = ssao_h(c, d);  // the pixel's own stored depth, as prep computed it
+    __amdgpu_buffer_rsrc_t hdepth = raw_buffer(c.hdepth, (unsigned)c.Wh * (unsigned)c.Hh * 4u);
     float occ = 0.0f;
-    for (int k0 = 0; k0 < c.n; k0 += KB) {
-        float ds[KB], zqs[KB];
-        bool ok[KB];
-#pragma unroll
-        for (int b = 0; b < KB; ++b) {
-            int k = min(k0 + b, c.n - 1);
-            float sx = sk[3 * k], sy = sk[3 * k + 1], sz = sk[3 * k + 2];
-            float zq = fmaf(Zv.x, sx, fmaf(Zv.y, sy, fmaf(Zv.z, sz, Z0)));
-            float nx = fmaf(Xv.x, sx, fmaf(Xv.y, sy, fmaf(Xv.z, sz, X0)));
-            float ny = fmaf(Yv.x, sx, fmaf(Yv.y, sy, fmaf(Yv.z, sz, Y0)));
-            float iz = rcp(zq);
-            // floor-convert: 0 <= hx < Wh exactly when 0 <= floor(hx) < Wh (one unsigned
-            // compare; out-of-range values saturate outside the range, and a NaN
-            // (converted to 0) only arises with zq <= 0 or a NaN input, rejected by zq > 0)
-            int ix = floor_to_int(nx * iz), iy = floor_to_int(ny * iz);
-            ok[b] = (k0 + b < c.n) && zq > 0.0f && (unsigned)ix < (unsigned)c.Wh && (unsigned)iy < (unsigned)c.Hh;
-            unsigned idx = ok[b] ? __umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix : 0u;
-            ds[b] = ldf(c.hdepth, idx);
-            zqs[b] = zq;
-        }
-#pragma unroll
-        for (int b = 0; b < KB; ++b) {
-            float u = clamp01(c.radius * rcp(fabsf(d - ds[b])));
-            float sm = u * u * (3.0f - 2.0f * u);
-            occ += (ok[b] && ds[b] <= zqs[b] - c.bias) ? sm : 0.0f;
-        }
-    }
+    // whole batches of KB samples (their 3 KB kernel floats in one run of scalar
+    // loads), then the ragged last batch with its sample index clamped
+    int nfull = c.n - c.n % KB;
+    for (int k0 = 0; k0 < nfull; k0 += KB)
+        occ = ssao_batch<KB, false>(c, c.kernel + 3 * k0, KB, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
+    if (nfull < c.n)
+        occ = ssao_batch<KB, true>(c, c.kernel + 3 * nfull, c.n - nfull, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
     stf(out, o, 1.0f - occ * c.inv_n);
 }
 
@@ -127,10 +152,11 @@ __device__ __forceinline__ void ssao_blur_tile(const SsaoDesc &c, int tile, floa
     int ti = threadIdx.x % kBlurTx, tj = threadIdx.x / kBlurTx;
     int i = i0 + ti, j = j0 + tj;
     if (i < c.Wh && j < c.Hh) {
-        float dp = sd[tj + 2][ti + 2];
+        float dp = sd[tj + 2][ti + 2];  // stored form h = (d + bias) / radius
         float v = 1.0f;
         if (!__builtin_isinf(dp)) {
-            float inv = 1.0f / (c.tau * dp);
+            // |d_q - d_p| / (tau d_p) = |h_q - h_p| radius / (tau d_p)
+            float inv = c.radius / (c.tau * fmaf(dp, c.radius, -c.bias));
             float s = 0.0f, sw = 0.0f;
 #pragma unroll
             for (int dy = 0; dy < 4; ++dy)
@@ -157,10 +183,7 @@ __global__ void __launch_bounds__(kSsaoPrepW) k_ssao_prep(const SsaoDesc c, int 
 
 template <int TX, int TY, int KB, typename TG, typename TA>
 __global__ void __launch_bounds__(TX *TY) k_ssao_raw(const SsaoDesc c, int tiles) {
-    __shared__ float sk[EPB_MAX_SSAO_SAMPLES * 3];
-    stage_kernel(c, sk);
-    __syncthreads();
-    ssao_raw_tile<TX, TY, KB, TG, TA>(c, xcd_tile(blockIdx.x, tiles), sk);
+    ssao_raw_tile<TX, TY, KB, TG, TA>(c, xcd_tile(blockIdx.x, tiles));
 }
 
 template <typename TA>
@@ -187,23 +210,14 @@ __global__ void __launch_bounds__(kSsaoPrepW) k_ssao_prep_batch(const void *__re
 
 template <int TX, int TY, int KB, typename TG, typename TA>
 __global__ void __launch_bounds__(TX *TY) k_ssao_raw_batch(const void *__restrict__ table) {
-    __shared__ float sk[EPB_MAX_SSAO_SAMPLES * 3];
     const BatchHeader *h = (const BatchHeader *)table;
     const int *start = batch_start(table, kStRaw);
     const ViewDesc *views = batch_views(table);
     XcdRange w = xcd_range(h->total[kStRaw]);
-    int staged = -1;
     for (int it = w.lb; it < w.count; it += w.stride) {
         int g = w.first + it;
         int v = find_view(start, h->n_views, g);
-        const SsaoDesc &c = views[v].ssao;
-        if (v != staged) {  // uniform: the block restages the kernel of a new view
-            __syncthreads();
-            stage_kernel(c, sk);
-            __syncthreads();
-            staged = v;
-        }
-        ssao_raw_tile<TX, TY, KB, TG, TA>(c, g - start[v], sk);
+        ssao_raw_tile<TX, TY, KB, TG, TA>(views[v].ssao, g - start[v]);
     }
 }
 
@@ -260,6 +274,7 @@ SsaoDesc ssao_desc(const SsaoPlan &q, const float *depth, const void *normal, co
     c.cam.inv_fx = cam.inv_fx; c.cam.inv_fy = cam.inv_fy;
     c.cam.w = cam.w; c.cam.h = cam.h;
     c.radius = radius;
+    c.inv_radius = (float)(1.0 / (double)radius);
     c.bias = bias;
     c.tau = tau;
     c.n = n_samples;
