@@ -158,19 +158,21 @@ int build_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, 
             if ((st = check_camera(&L.shadow_cam))) return st;
             if (L.shadow_cam.width < 3 || L.shadow_cam.height < 3) return EPB_ERR_SIZE;
             if (!finite(L.shadow_bias)) return EPB_ERR_PARAM;
-            // light view from camera view: P_l = R_l (R^T (P_v - t) ) + t_l = M P_v + o
+            // light view from camera view: P_l = R_l (R^T (P_v - t) ) + t_l = M P_v + o, the
+            // rows of x and y scaled by fx and -fy so that they give (u - cx) d_l and (v - cy) d_l
             const float *A = L.shadow_cam.world_to_cam, *B = cam->world_to_cam;
+            const double row_scale[3] = {(double)L.shadow_cam.fx, -(double)L.shadow_cam.fy, 1.0};
             for (int r = 0; r < 3; ++r) {
                 for (int c = 0; c < 3; ++c) {
                     double s = 0;
                     for (int k = 0; k < 3; ++k) s += (double)A[4 * r + k] * B[4 * c + k];
-                    h.M[3 * r + c] = (float)s;
+                    h.M[3 * r + c] = (float)(row_scale[r] * s);
                 }
                 double o = A[4 * r + 3];
                 for (int k = 0; k < 3; ++k) o += (double)A[4 * r + k] * cp[k];
-                h.o[r] = (float)o;
+                h.o[r] = (float)(row_scale[r] * o);
             }
-            h.fx = L.shadow_cam.fx; h.nfy = -L.shadow_cam.fy; h.cx = L.shadow_cam.cx; h.cy = L.shadow_cam.cy;
+            h.cx = L.shadow_cam.cx; h.cy = L.shadow_cam.cy;
             h.w = L.shadow_cam.width; h.h = L.shadow_cam.height;
             h.fw = (float)h.w; h.fh = (float)h.h;
             h.bias = L.shadow_bias;

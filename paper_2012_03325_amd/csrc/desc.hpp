@@ -25,8 +25,11 @@ struct DevCam {
 struct DevLight {
     float pos[3], rad[3];  // rad = colour * intensity
     const float *map;      // may be null
-    float M[9], o[3];      // light view from camera view: P_l = M P_v + o
-    float fx, nfy, cx, cy;  // nfy = -fy (the map's v axis points down)
+    // light view from camera view, P_l = R P_v + t, with the rows of x and y scaled
+    // by fx and -fy (the map's v axis points down): M P_v + o = ((u - cx) d_l,
+    // (v - cy) d_l, -d_l) for the map coordinates (u, v) and light depth d_l
+    float M[9], o[3];
+    float cx, cy;
     int w, h;
     float fw, fh;          // w, h as floats
     float bias;

@@ -12,9 +12,9 @@
 // argument segment and are read with scalar loads.
 //
 // Float32 care where the reference is float64:
-//  * GGX: 1 - (N.H)^2 is taken as |N x H|^2, exact to rounding near the
-//    highlight peak where the subtraction would cancel (roughness 0.05 gives
-//    alpha^2 = 6e-6).
+//  * GGX: 1 - (N.H)^2 is taken as |H - (N.H) N|^2 (= |N x H|^2 for unit
+//    vectors), exact to rounding near the highlight peak where the
+//    subtraction would cancel (roughness 0.05 gives alpha^2 = 6e-6).
 //  * Smith-Schlick visibility G / (4 N.L N.V) is evaluated as
 //    1 / (4 (N.L(1-k)+k)(N.V(1-k)+k)): no division by a clamped N.V.
 //  * The view vector is -normalize(R^T P_view), free of the cancellation of
@@ -52,14 +52,14 @@ __device__ __forceinline__ float2 lut_bilinear(const float2 *__restrict__ lut, i
 // to the patch are dropped, the missing taps counting as lit.  Points outside
 // the light's frustum are lit.
 __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, float d) {
-    // P_l = M P_v + o with P_v = d (dvx, dvy, -1)
+    // M P_v + o = ((u - cx) d_l, (v - cy) d_l, -d_l) with P_v = d (dvx, dvy, -1)
     v3 Md = mk3(fmaf(L.M[0], dvx, fmaf(L.M[1], dvy, -L.M[2])), fmaf(L.M[3], dvx, fmaf(L.M[4], dvy, -L.M[5])),
                 fmaf(L.M[6], dvx, fmaf(L.M[7], dvy, -L.M[8])));
     v3 Pl = mk3(fmaf(Md.x, d, L.o[0]), fmaf(Md.y, d, L.o[1]), fmaf(Md.z, d, L.o[2]));
     float dl = -Pl.z;
     float idl = rcp(dl);
-    float u = fmaf(L.fx * Pl.x, idl, L.cx);
-    float v = fmaf(L.nfy * Pl.y, idl, L.cy);
+    float u = fmaf(Pl.x, idl, L.cx);
+    float v = fmaf(Pl.y, idl, L.cy);
     bool inside = dl > 0.0f && u >= 0.0f && u < L.fw && v >= 0.0f && v < L.fh;
     int i0 = inside ? (int)u : 1, j0 = inside ? (int)v : 1;  // truncation == floor when inside
     int bi = min(max(i0, 1), L.w - 2), bj = min(max(j0, 1), L.h - 2);
@@ -163,7 +163,7 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
         // direct light
         float Lo[3] = {0.0f, 0.0f, 0.0f};
         for (int li = 0; li < c.n_lights; ++li) {
-            const DevLight &L = c.lights[li];
+            const DevLight L = c.lights[li];  // a copy: its fields load into scalar registers together
             v3 lv = mk3(L.pos[0], L.pos[1], L.pos[2]) - Pw;
             float dist2 = dot(lv, lv);
             float il = rsq(dist2);
@@ -174,8 +174,8 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
             v3 h = normalize(V + l);
             float NoH = dot(n, h);
             float VoH = fmaxf(dot(V, h), 0.0f);
-            v3 nxh = cross(n, h);
-            float q = fmaf(NoH * NoH, a2, dot(nxh, nxh));
+            v3 hp = mk3(fmaf(-NoH, n.x, h.x), fmaf(-NoH, n.y, h.y), fmaf(-NoH, n.z, h.z));  // h minus its n part
+            float q = fmaf(NoH * NoH, a2, dot(hp, hp));
             // D * G / (4 NoL NoV) = alpha^2 / (pi q^2) * 1 / (4 (NoL(1-k)+k)(NoV(1-k)+k))
             float spec = (0.25f / kPi) * a2 * rcp(q * q * fmaf(NoL, 1.0f - kd, kd) * gv);
             float fc = pow5(1.0f - VoH);
