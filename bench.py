@@ -486,9 +486,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
-    ap.add_argument("--copies", type=int, default=6, help="rotated input/output copies (MALL); a multiple of "
+    ap.add_argument("--copies", type=int, default=8, help="rotated input/output copies (MALL); a multiple of "
                     "--frames-in-flight")
-    ap.add_argument("--frames-in-flight", type=int, default=3, help="frames replayed concurrently on as many streams")
+    ap.add_argument("--frames-in-flight", type=int, default=4, help="frames replayed concurrently on as many streams")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-view batched form")

@@ -49,6 +49,13 @@ __device__ __forceinline__ float buf_ldf(__amdgpu_buffer_rsrc_t r, unsigned byte
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, byte_off, 0, 0));
 }
 
+// Read-only data that every lane of a wavefront reads at the same address (a
+// sample kernel, a table): through the constant address space the compiler
+// issues scalar loads, also where the pointer itself was read from memory (the
+// batch table), which it otherwise treats as a generic per-lane address.
+typedef __attribute__((address_space(4))) const float ConstFloat;
+__device__ __forceinline__ const ConstFloat *as_constant(const float *p) { return (const ConstFloat *)p; }
+
 __device__ __forceinline__ float ldc(const float *p) { return *p; }
 __device__ __forceinline__ float ldc(const __half *p) { return __half2float(*p); }
 

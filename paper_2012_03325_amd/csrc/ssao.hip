@@ -45,7 +45,7 @@ __device__ __forceinline__ void ssao_prep_item(const SsaoDesc &c, int item) {
 // at the batch's first kernel vector; with `ragged`, only the first `m` samples
 // exist (the others repeat the last one and are discarded).
 template <int KB, bool ragged>
-__device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const float *kern, int m, v3 Xv, v3 Yv, v3 Zv,
+__device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const ConstFloat *kern, int m, v3 Xv, v3 Yv, v3 Zv,
                                             float X0, float Y0, float Z0, float hp, __amdgpu_buffer_rsrc_t hdepth,
                                             float occ) {
     float hs[KB], zqs[KB];
@@ -124,10 +124,11 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     // whole batches of KB samples (their 3 KB kernel floats in one run of scalar
     // loads), then the ragged last batch with its sample index clamped
     int nfull = c.n - c.n % KB;
+    const ConstFloat *kern = as_constant(c.kernel);
     for (int k0 = 0; k0 < nfull; k0 += KB)
-        occ = ssao_batch<KB, false>(c, c.kernel + 3 * k0, KB, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
+        occ = ssao_batch<KB, false>(c, kern + 3 * k0, KB, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
     if (nfull < c.n)
-        occ = ssao_batch<KB, true>(c, c.kernel + 3 * nfull, c.n - nfull, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
+        occ = ssao_batch<KB, true>(c, kern + 3 * nfull, c.n - nfull, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
     stf(out, o, 1.0f - occ * c.inv_n);
 }
 
