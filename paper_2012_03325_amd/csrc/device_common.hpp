@@ -23,13 +23,47 @@ constexpr int kNumXcd = 8;  // MI355X: 256 CUs in 8 accelerator complex dies
 // constant part folded into the immediate) instead of 64-bit address
 // arithmetic per lane.  Callers keep every offset below 2^32 (sizes are
 // validated on the host).
+// The access is made through the global address space: every buffer handed to
+// the library is device memory, and a pointer read from a batch table would
+// otherwise be a generic (flat) address, loaded per lane with 64-bit
+// arithmetic.  Values move as 16- or 32-bit words (class types cannot be
+// copied through a pointer of another address space).
 template <typename T>
 __device__ __forceinline__ T ldo(const T *base, unsigned byte_off) {
-    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(base) + byte_off);
+    typedef __attribute__((address_space(1))) const char GC;
+    typedef __attribute__((address_space(1))) const unsigned GU;
+    typedef __attribute__((address_space(1))) const unsigned short GS;
+    GC *a = (GC *)base + byte_off;
+    T r;
+    if constexpr (sizeof(T) % 4 == 0) {
+        unsigned w[sizeof(T) / 4];
+#pragma unroll
+        for (unsigned k = 0; k < sizeof(T) / 4; ++k) w[k] = ((GU *)a)[k];
+        __builtin_memcpy(&r, w, sizeof(T));
+    } else {
+        static_assert(sizeof(T) == 2, "16-bit or whole 32-bit words");
+        unsigned short h = *(GS *)a;
+        __builtin_memcpy(&r, &h, 2);
+    }
+    return r;
 }
 template <typename T>
 __device__ __forceinline__ void sto(T *base, unsigned byte_off, T v) {
-    *reinterpret_cast<T *>(reinterpret_cast<char *>(base) + byte_off) = v;
+    typedef __attribute__((address_space(1))) char GC;
+    typedef __attribute__((address_space(1))) unsigned GU;
+    typedef __attribute__((address_space(1))) unsigned short GS;
+    GC *a = (GC *)base + byte_off;
+    if constexpr (sizeof(T) % 4 == 0) {
+        unsigned w[sizeof(T) / 4];
+        __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+        for (unsigned k = 0; k < sizeof(T) / 4; ++k) ((GU *)a)[k] = w[k];
+    } else {
+        static_assert(sizeof(T) == 2, "16-bit or whole 32-bit words");
+        unsigned short h;
+        __builtin_memcpy(&h, &v, 2);
+        *(GS *)a = h;
+    }
 }
 __device__ __forceinline__ float ldf(const float *base, unsigned i) { return ldo(base, i * 4u); }
 __device__ __forceinline__ float ldf(const __half *base, unsigned i) { return __half2float(ldo(base, i * 2u)); }

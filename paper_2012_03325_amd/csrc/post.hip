@@ -75,7 +75,7 @@ __device__ __forceinline__ void down_level(const PostDesc &c, int bx, int by, SR
                     n += 1.0f;
                 }
         v = scale4(v, 1.0f / n);
-        ((TP *)c.raw[L])[(size_t)Y * c.lw[L] + X] = pack<TP>(v);
+        sto((TP *)c.raw[L], (unsigned)(Y * c.lw[L] + X) * (unsigned)sizeof(TP), pack<TP>(v));
     }
     if (dst) dst[ly][lx] = v;
 }
@@ -115,7 +115,7 @@ __device__ __forceinline__ void bloom_down_tile(const PostDesc &c, int tile, Dow
             n += 1.0f;
         }
         v = scale4(v, 1.0f / n);
-        ((TP *)c.raw[1])[(size_t)Y * c.lw[1] + X] = pack<TP>(v);
+        sto((TP *)c.raw[1], (unsigned)(Y * c.lw[1] + X) * (unsigned)sizeof(TP), pack<TP>(v));
     }
     sm.s1[ly][lx] = v;
     __syncthreads();
@@ -183,7 +183,7 @@ __device__ __forceinline__ void bloom_blur_item(const PostDesc &c, int item, Blu
         int X = X0 + ox, Y = Y0 + oy;
         if (X < w && Y < h) {
             Rgb v = binomial5(sm.h[oy][ox], sm.h[oy + 1][ox], sm.h[oy + 2][ox], sm.h[oy + 3][ox], sm.h[oy + 4][ox]);
-            ((TP *)c.blur[L])[(size_t)Y * w + X] = pack<TP>(make_float4(v.x, v.y, v.z, 0.0f));
+            sto((TP *)c.blur[L], (unsigned)(Y * w + X) * (unsigned)sizeof(TP), pack<TP>(make_float4(v.x, v.y, v.z, 0.0f)));
         }
     }
     __syncthreads();  // the next item of a batched launch refills the LDS

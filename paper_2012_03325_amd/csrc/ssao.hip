@@ -101,8 +101,8 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     v3 nw = mk3(ldf(normal, p), ldf(normal, plane + p), ldf(normal, 2 * plane + p));
     v3 nv = normalize(mul_R(c.cam.R, nw));
     // rotation noise, Gram-Schmidt against the normal
-    const float *rn = c.noise + 2 * ((j & 3) * 4 + (i & 3));
-    v3 r = mk3(rn[0], rn[1], 0.0f);
+    unsigned rn = 2u * (unsigned)((j & 3) * 4 + (i & 3));
+    v3 r = mk3(ldf(c.noise, rn), ldf(c.noise, rn + 1u), 0.0f);
     v3 t = normalize(r - nv * dot(nv, r));
     v3 bb = cross(nv, t);
     // Sample s of the kernel lands at Q = P + radius (t sx + b sy + n sz).  In
