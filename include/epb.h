@@ -17,8 +17,7 @@
  *                          (Sec. 5.3, 5.4)
  *
  * Beside them: a batched form of the per-frame calls, a device ray caster of
- * sphere fields (the G-buffer and shadow-map pass before shading), a tiled
- * storage form of shadow maps that the shadow test fetches faster, and
+ * sphere fields (the G-buffer and shadow-map pass before shading) and
  * eye-dome lighting, the compositing step of depth-only point-cloud renders
  * (Sec. 4.3).
  *
