@@ -57,6 +57,8 @@ def _make_view(kind):
     if kind == "ragged-97x61-n64":
         return synth.config_reduced(97, 61, seed=8, shadow_size=128, env_size=16, ssao_n=64,
                                     n_spheres=24)
+    if kind == "ragged-123x77-n13":  # 13 samples: a partial last batch of gathers
+        return synth.config_reduced(123, 77, seed=11, shadow_size=64, env_size=16, ssao_n=13, n_spheres=24)
     if kind == "tiny-3x2":
         return synth.config_reduced(3, 2, seed=9, shadow_size=16, env_size=8, ssao_n=8, n_spheres=4)
     if kind == "strip-16384x2":
@@ -160,8 +162,8 @@ def test_precompute_ibl_parity(case):
 # ---------------------------------------------------------------------------
 # a2 / a3: SSAO
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "tiny-3x2",
-                                  "full-1080p"])
+@pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "ragged-123x77-n13",
+                                  "tiny-3x2", "full-1080p"])
 def test_ssao_parity(kind):
     v = _view(kind)
     g = v.gbuf
