@@ -143,8 +143,9 @@ struct Rgb {
     float x, y, z;
 };
 constexpr int kBbW = kBloomTx + 4, kBbH = kBloomTy + 4;  // footprint with the 2-texel halo
+constexpr int kBbLdsRows = ((kBbH * kBbW + 255) / 256 * 256 + kBbW - 1) / kBbW;  // padding for whole rounds
 struct BlurLds {
-    Rgb in[kBbH][kBbW];
+    Rgb in[kBbLdsRows][kBbW];
     Rgb h[kBbH][kBloomTx];
 };
 
@@ -165,12 +166,21 @@ __device__ __forceinline__ void bloom_blur_item(const PostDesc &c, int item, Blu
     int X0 = (local - ty * tx) * kBloomTx, Y0 = ty * kBloomTy;
     const TP *src = (const TP *)c.raw[L];
     int t = threadIdx.x;
-    for (int q = t; q < kBbH * kBbW; q += 256) {  // every load of the footprint in flight together
+    // every load of the footprint in flight together: all issued before the first LDS store
+    constexpr int kN = kBbH * kBbW, kIt = (kN + 255) / 256;
+    TP v[kIt];
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {
+        int q = min(t + 256 * i, kN - 1);  // clamped: every lane issues every load
         int r = q / kBbW, cc = q - r * kBbW;
         int gy = min(max(Y0 + r - 2, 0), h - 1);
         int gx = min(max(X0 + cc - 2, 0), w - 1);
-        float4 v = unpack(ldo(src, (__umul24((unsigned)gy, (unsigned)w) + (unsigned)gx) * (unsigned)sizeof(TP)));
-        sm.in[r][cc] = Rgb{v.x, v.y, v.z};
+        v[i] = ldo(src, (__umul24((unsigned)gy, (unsigned)w) + (unsigned)gx) * (unsigned)sizeof(TP));
+    }
+#pragma unroll
+    for (int i = 0; i < kIt; ++i) {  // unconditional: entries past the footprint land in the padding rows
+        float4 f = unpack(v[i]);
+        (&sm.in[0][0])[t + 256 * i] = Rgb{f.x, f.y, f.z};
     }
     __syncthreads();
     for (int q = t; q < kBbH * kBloomTx; q += 256) {

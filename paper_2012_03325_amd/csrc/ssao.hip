@@ -132,6 +132,11 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     stf(out, o, 1.0f - occ * c.inv_n);
 }
 
+// LDS rows of the blur footprint (11 rows of 19) plus padding, so that every
+// thread's staging stores are unconditional (the last ones land in the padding)
+constexpr int kBlurLdsRows = ((kBlurTy + 3) * (kBlurTx + 3) + kBlurTx * kBlurTy - 1) / (kBlurTx * kBlurTy) *
+                                 (kBlurTx * kBlurTy) / (kBlurTx + 3) + 1;
+
 template <typename TA>
 __device__ __forceinline__ void ssao_blur_tile(const SsaoDesc &c, int tile, float (*sd)[kBlurTx + 3],
                                                float (*sa)[kBlurTx + 3]) {
@@ -140,14 +145,25 @@ __device__ __forceinline__ void ssao_blur_tile(const SsaoDesc &c, int tile, floa
     int ty = tile / tiles_x;
     int i0 = (tile - ty * tiles_x) * kBlurTx, j0 = ty * kBlurTy;
     const float *raw = (const float *)c.raw;
-    for (int q = threadIdx.x; q < LW * LH; q += blockDim.x) {
+    // every load of the footprint in flight together: all issued before the first LDS store
+    constexpr int kN = LW * LH, kThreads = kBlurTx * kBlurTy, kIt = (kN + kThreads - 1) / kThreads;
+    float dq[kIt], aq[kIt];
+    bool in[kIt];
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {
+        int q = min((int)threadIdx.x + kThreads * k, kN - 1);
         int li = q % LW, lj = q / LW;
         int gi = i0 + li - 2, gj = j0 + lj - 2;
-        bool in = gi >= 0 && gi < c.Wh && gj >= 0 && gj < c.Hh;
-        unsigned g = in ? __umul24((unsigned)gj, (unsigned)c.Wh) + (unsigned)gi : 0u;
-        float dq = ldf(c.hdepth, g), aq = ldf(raw, g);
-        sd[lj][li] = in ? dq : __builtin_inff();  // out of range: weight 0
-        sa[lj][li] = in ? aq : 0.0f;
+        in[k] = gi >= 0 && gi < c.Wh && gj >= 0 && gj < c.Hh;
+        unsigned g = in[k] ? __umul24((unsigned)gj, (unsigned)c.Wh) + (unsigned)gi : 0u;
+        dq[k] = ldf(c.hdepth, g);
+        aq[k] = ldf(raw, g);
+    }
+#pragma unroll
+    for (int k = 0; k < kIt; ++k) {  // unconditional: entries past the footprint land in the padding rows
+        int q = (int)threadIdx.x + kThreads * k;
+        (&sd[0][0])[q] = in[k] ? dq[k] : __builtin_inff();  // out of range: weight 0
+        (&sa[0][0])[q] = in[k] ? aq[k] : 0.0f;
     }
     __syncthreads();
     int ti = threadIdx.x % kBlurTx, tj = threadIdx.x / kBlurTx;
@@ -189,8 +205,8 @@ __global__ void __launch_bounds__(TX *TY) k_ssao_raw(const SsaoDesc c, int tiles
 
 template <typename TA>
 __global__ void __launch_bounds__(kBlurTx *kBlurTy) k_ssao_blur(const SsaoDesc c, int tiles) {
-    __shared__ float sd[kBlurTy + 3][kBlurTx + 3];
-    __shared__ float sa[kBlurTy + 3][kBlurTx + 3];
+    __shared__ float sd[kBlurLdsRows][kBlurTx + 3];
+    __shared__ float sa[kBlurLdsRows][kBlurTx + 3];
     ssao_blur_tile<TA>(c, xcd_tile(blockIdx.x, tiles), sd, sa);
 }
 
@@ -224,8 +240,8 @@ __global__ void __launch_bounds__(TX *TY) k_ssao_raw_batch(const void *__restric
 
 template <typename TA>
 __global__ void __launch_bounds__(kBlurTx *kBlurTy) k_ssao_blur_batch(const void *__restrict__ table) {
-    __shared__ float sd[kBlurTy + 3][kBlurTx + 3];
-    __shared__ float sa[kBlurTy + 3][kBlurTx + 3];
+    __shared__ float sd[kBlurLdsRows][kBlurTx + 3];
+    __shared__ float sa[kBlurLdsRows][kBlurTx + 3];
     const BatchHeader *h = (const BatchHeader *)table;
     const int *start = batch_start(table, kStBlur);
     const ViewDesc *views = batch_views(table);
