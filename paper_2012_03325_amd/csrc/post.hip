@@ -250,13 +250,20 @@ __device__ __forceinline__ void add_level(const PostDesc &c, int x, int Y0, floa
     int cx = vx >> LR::sh;
     unsigned c0 = (unsigned)min(max(cx, 0), w - 1), c1 = (unsigned)min(max(cx + 1, 0), w - 1);
     int ay = (2 * Y0 + LR::o) >> LR::sh;
-    float rows[LR::n][3];
+    // all the level's texel loads issued before any is used (one memory round trip per level)
+    TP ta[LR::n], tb[LR::n];
 #pragma unroll
     for (int r = 0; r < LR::n; ++r) {
         unsigned gy = (unsigned)min(max(ay + r, 0), h - 1);
         unsigned base = __umul24(gy, (unsigned)w);
-        float4 a = unpack(ldo(lvl, (base + c0) * (unsigned)sizeof(TP)));
-        float4 b = unpack(ldo(lvl, (base + c1) * (unsigned)sizeof(TP)));
+        ta[r] = ldo(lvl, (base + c0) * (unsigned)sizeof(TP));
+        tb[r] = ldo(lvl, (base + c1) * (unsigned)sizeof(TP));
+    }
+    __builtin_amdgcn_sched_barrier(0);  // keep the scheduler from interleaving the loads with their uses
+    float rows[LR::n][3];
+#pragma unroll
+    for (int r = 0; r < LR::n; ++r) {
+        float4 a = unpack(ta[r]), b = unpack(tb[r]);
         rows[r][0] = fmaf(wx, b.x - a.x, a.x);
         rows[r][1] = fmaf(wx, b.y - a.y, a.y);
         rows[r][2] = fmaf(wx, b.z - a.z, a.z);
