@@ -225,13 +225,22 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
+// Minimum waves per SIMD: 8 for the single-view kernel on an FP16 G-buffer (fewer
+// bytes per pixel, more issue-bound; 61 VGPRs), 7 otherwise (the FP32 kernel's
+// natural 65 VGPRs; the batched kernel, with the view lookup on top, would settle
+// at 6, and at 8 it would spill).
+template <typename TG>
+constexpr int shade_min_waves() { return sizeof(TG) == 2 ? 8 : 7; }
+
 template <int TX, int TY, typename TG, typename TA, typename TH>
-__global__ void __launch_bounds__(TX *TY) k_shade(const ShadeDesc c, int tiles) {
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(shade_min_waves<TG>())))
+k_shade(const ShadeDesc c, int tiles) {
     shade_tile<TX, TY, TG, TA, TH>(c, xcd_tile(blockIdx.x, tiles));
 }
 
 template <int TX, int TY, typename TG, typename TA, typename TH>
-__global__ void __launch_bounds__(TX *TY) k_shade_batch(const void *__restrict__ table) {
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(7)))
+k_shade_batch(const void *__restrict__ table) {
     const BatchHeader *h = (const BatchHeader *)table;
     const int *start = batch_start(table, kStShade);
     const ViewDesc *views = batch_views(table);
