@@ -438,26 +438,39 @@ void orc_ssao_raw(const double *depth, const double *normal, const orc_camera *c
             double r[3] = {rn[0], rn[1], 0.0};
             double rn_d = dot3(nv, r);
             double t[3] = {r[0] - nv[0] * rn_d, r[1] - nv[1] * rn_d, r[2] - nv[2] * rn_d};
+            double r_perp = sqrt(dot3(t, t)); /* conditioning of the Gram-Schmidt step */
             normalize3(t);
             double b[3];
             cross3(nv, t, b);
             double occ_min_sum = 0.0, occ_max_sum = 0.0;
+            double ax = P[0] / d, ay = P[1] / d; /* view-ray slopes of the pixel */
             for (int k = 0; k < n_samples; ++k) {
                 const double *s = kernel + 3 * (size_t)k;
-                double Q[3];
-                for (int c = 0; c < 3; ++c)
-                    Q[c] = P[c] + radius * (t[c] * s[0] + b[c] * s[1] + nv[c] * s[2]);
+                double w[3], Q[3];
+                for (int c = 0; c < 3; ++c) {
+                    w[c] = t[c] * s[0] + b[c] * s[1] + nv[c] * s[2];
+                    Q[c] = P[c] + radius * w[c];
+                }
                 double zq = -Q[2];
                 double omin = INFINITY, omax = -INFINITY;
-                double ztie = tie->rel * maxd(1.0, fabs(zq));
+                /* magnitude scales of the decisions (epb_oracle.h): the sample
+                 * offset's tangent part is amplified by the Gram-Schmidt step */
+                double cond = (fabs(s[0]) + fabs(s[1])) / r_perp;
+                double wn = sqrt(dot3(w, w));
+                double ztie = tie->ssao_depth * (d + radius * (1.0 + cond) + fabs(bias));
                 if (zq <= ztie) { omin = mind(omin, 0.0); omax = maxd(omax, 0.0); }
                 if (zq > 0.0) {
                     double u = cam->cx + cam->fx * Q[0] / zq;
                     double v = cam->cy - cam->fy * Q[1] / zq;
                     double hx = (u - 0.5) * 0.5 + 0.5, hy = (v - 0.5) * 0.5 + 0.5;
+                    double Dx = 0.5 * cam->fx * radius / zq, Dy = 0.5 * cam->fy * radius / zq;
+                    double bx = tie->ssao_coord *
+                                (1.0 + Dx * (fabs(w[0]) + fabs(ax * w[2]) + wn + cond) + fabs(hx) / 8.0);
+                    double by = tie->ssao_coord *
+                                (1.0 + Dy * (fabs(w[1]) + fabs(ay * w[2]) + wn + cond) + fabs(hy) / 8.0);
                     int cx[2], cy[2];
-                    int ncx = floor_candidates(hx, tie->pix, cx);
-                    int ncy = floor_candidates(hy, tie->pix, cy);
+                    int ncx = floor_candidates(hx, bx, cx);
+                    int ncy = floor_candidates(hy, by, cy);
                     for (int a = 0; a < ncx; ++a)
                         for (int bb = 0; bb < ncy; ++bb) {
                             int ix = cx[a], iy = cy[bb];
@@ -468,8 +481,8 @@ void orc_ssao_raw(const double *depth, const double *normal, const orc_camera *c
                             double ds = depth[(size_t)(2 * iy) * W + 2 * ix];
                             if (isinf(ds)) { omin = mind(omin, 0.0); omax = maxd(omax, 0.0); continue; }
                             double val = smoothstep01(radius / fabs(d - ds));
-                            double m = (zq - bias) - ds;
-                            double ctie = tie->rel * maxd(1.0, fabs(zq));
+                            double m = (zq - bias) - ds; /* occluded iff m >= 0 */
+                            double ctie = tie->ssao_depth * (fabs(ds - d) + radius * (1.0 + cond) + fabs(bias));
                             if (m >= ctie) { omin = mind(omin, val); omax = maxd(omax, val); }
                             else if (m <= -ctie) { omin = mind(omin, 0.0); omax = maxd(omax, 0.0); }
                             else {
@@ -612,24 +625,34 @@ void orc_normalize_gbuffer(const double *weight, int W, int H, double *normal, d
 /* ------------------------------------------------------------------------ */
 
 /* Lit fraction of a 3x3 percentage-closer patch around the projection of the
- * world point Pw into a light's depth map, as an interval over ties. */
-static void pcf_shadow(const orc_light *L, const double Pw[3], const orc_tie *tie, double *slo,
-                       double *shi) {
+ * world point Pw into a light's depth map, as an interval over ties; cam_pos
+ * is the position of the camera whose depth the point was reconstructed from
+ * (it sets the magnitude scale of the float decisions). */
+static void pcf_shadow(const orc_light *L, const double Pw[3], const double cam_pos[3],
+                       const orc_tie *tie, double *slo, double *shi) {
     const orc_camera *c = &L->shadow_cam;
     double Pl[3];
     rot(c->world_to_cam, Pw, Pl);
     Pl[0] += c->world_to_cam[3]; Pl[1] += c->world_to_cam[7]; Pl[2] += c->world_to_cam[11];
     double dl = -Pl[2];
+    /* magnitude scales: distances point - camera and camera - light camera */
+    double lt[3] = {c->world_to_cam[3], c->world_to_cam[7], c->world_to_cam[11]}, lpos[3];
+    rot_t(c->world_to_cam, lt, lpos);
+    double pc[3] = {Pw[0] - cam_pos[0], Pw[1] - cam_pos[1], Pw[2] - cam_pos[2]};
+    double cl[3] = {cam_pos[0] + lpos[0], cam_pos[1] + lpos[1], cam_pos[2] + lpos[2]};
+    double dist = sqrt(dot3(pc, pc)) + sqrt(dot3(cl, cl));
+    double dtie = tie->pcf_depth * (dist + fabs(dl) + fabs(L->shadow_bias));
     double lo = INFINITY, hi = -INFINITY;
-    double dtie = tie->rel * maxd(1.0, fabs(dl));
     if (dl <= dtie) { lo = 1.0; hi = 1.0; } /* behind the light camera: lit */
     if (dl > 0.0) {
         int w = c->width, h = c->height;
         double u = c->cx + c->fx * Pl[0] / dl;
         double v = c->cy - c->fy * Pl[1] / dl;
+        double bu = tie->pcf_coord * (c->fx * dist / dl + fabs(u - c->cx) + fabs(c->cx));
+        double bv = tie->pcf_coord * (c->fy * dist / dl + fabs(v - c->cy) + fabs(c->cy));
         int cu[2], cv[2];
-        int nu = floor_candidates(u, tie->pix, cu);
-        int nv = floor_candidates(v, tie->pix, cv);
+        int nu = floor_candidates(u, bu, cu);
+        int nv = floor_candidates(v, bv, cv);
         for (int a = 0; a < nu; ++a)
             for (int b = 0; b < nv; ++b) {
                 int i0 = cu[a], j0 = cv[b];
@@ -639,15 +662,14 @@ static void pcf_shadow(const orc_light *L, const double Pw[3], const orc_tie *ti
                 }
                 int sure = 0, maybe = 0;
                 double ref = dl - L->shadow_bias;
-                double ctie = tie->rel * maxd(1.0, fabs(dl));
                 for (int dj = -1; dj <= 1; ++dj)
                     for (int di = -1; di <= 1; ++di) {
                         int ti = i0 + di, tj = j0 + dj;
                         if (ti < 0 || ti >= w || tj < 0 || tj >= h) { ++sure; continue; }
                         double sd = L->shadow_map[(size_t)tj * w + ti];
                         double m = sd - ref; /* lit iff ref <= sd */
-                        if (isinf(sd) || m >= ctie) ++sure;
-                        else if (m > -ctie) ++maybe;
+                        if (isinf(sd) || m >= dtie) ++sure;
+                        else if (m > -dtie) ++maybe;
                     }
                 lo = mind(lo, sure / 9.0);
                 hi = maxd(hi, (sure + maybe) / 9.0);
@@ -712,7 +734,7 @@ void orc_shade(const double *depth, const double *normal, const double *albedo,
                 /* background: the environment along the view ray */
                 double dw[3];
                 rot_t(M, dirv, dw);
-                cube_bilinear_iv(env, env_size, dw, tie->rel, lo, hi);
+                cube_bilinear_iv(env, env_size, dw, tie->face, lo, hi);
             } else {
                 /* position from depth (Sec. 4): world point and unit view vector */
                 double Pv[3] = {dirv[0] * d, dirv[1] * d, -d};
@@ -749,7 +771,7 @@ void orc_shade(const double *depth, const double *normal, const double *albedo,
                     double G = smith_g1(NoL, kd) * smith_g1(NoV, kd);
                     double fc = pow5(1.0 - VoH);
                     double slo = 1.0, shi = 1.0;
-                    if (L->shadow_map) pcf_shadow(L, Pw, tie, &slo, &shi);
+                    if (L->shadow_map) pcf_shadow(L, Pw, cam_pos, tie, &slo, &shi);
                     for (int c = 0; c < 3; ++c) {
                         double F = F0[c] + (1.0 - F0[c]) * fc;
                         double f = cd[c] / PI + D * G * F / (4.0 * NoL * NoV);
@@ -763,14 +785,14 @@ void orc_shade(const double *depth, const double *normal, const double *albedo,
                 double AB[2];
                 lut_bilinear(lut, lut_size, NoV, r, AB);
                 double Elo[3], Ehi[3], Plo[3], Phi[3];
-                cube_bilinear_iv(irradiance, irr_size, n, tie->rel, Elo, Ehi);
+                cube_bilinear_iv(irradiance, irr_size, n, tie->face, Elo, Ehi);
                 double R[3] = {2.0 * nv_raw * n[0] - V[0], 2.0 * nv_raw * n[1] - V[1],
                                2.0 * nv_raw * n[2] - V[2]};
                 double Pa[3], Pb[3];
                 chain_trilinear_iv(pref_lo, pref_base, pref_levels, R, r * (pref_levels - 1),
-                                   tie->rel, Plo, Pa);
+                                   tie->face, Plo, Pa);
                 chain_trilinear_iv(pref_hi, pref_base, pref_levels, R, r * (pref_levels - 1),
-                                   tie->rel, Pb, Phi);
+                                   tie->face, Pb, Phi);
                 for (int c = 0; c < 3; ++c) { Plo[c] = mind(Plo[c], Pb[c]); Phi[c] = maxd(Phi[c], Pa[c]); }
                 double aol = ao_upsample(ao_lo, Wh, Hh, x, y);
                 double aoh = ao_upsample(ao_hi, Wh, Hh, x, y);

@@ -36,9 +36,35 @@ typedef struct {
     int32_t width, height;
 } orc_camera;
 
+/* Half-widths of the ambiguous bands of the float decisions.  A float32
+ * implementation forms each decision's operand from terms whose magnitudes
+ * add up to a scale S; its rounding error is then a small multiple of
+ * 2^-24 S.  Each field below is that multiple (as a fraction of S), and the
+ * oracle treats an operand within field * S of the threshold as a tie:
+ *   ssao_coord  floors and in-image tests of an SSAO sample's half-resolution
+ *               coordinate h = u/2 + 1/4 (v alike), formed as the pixel's own
+ *               coordinate plus the sample's offset:
+ *               S = 1 + D (|w_x| + |a_x w_z| + |w| + g) + |h| / 8, with
+ *               D = f_x r / (2 z_q), w the view-space offset of the kernel
+ *               vector s, a_x the pixel's view-ray slope (P_x / d) and
+ *               g = (|s_x| + |s_y|) / |r_perp|, the amplification of the
+ *               tangent's error by the Gram-Schmidt step (r_perp: the noise
+ *               vector minus its normal part, before normalisation);
+ *   ssao_depth  the SSAO depth test d_s <= z_q - bias, formed as the difference
+ *               of the sampled and the pixel's own depth against the sample's
+ *               offset: S = |d_s - d| + r (1 + g) + |bias|; the in-front test
+ *               z_q > 0: S = d + r (1 + g) + |bias|;
+ *   pcf_coord   the floors and in-map tests of the light-map coordinate u (v
+ *               alike) of a point reconstructed from camera depth:
+ *               S = f_l (|P - c| + |c - l|) / d_l + |u - c_l| + |c_l|, with P
+ *               the point, c the camera position, l the light camera's
+ *               position, f_l, c_l the light camera's focal length and
+ *               principal point;
+ *   pcf_depth   the PCF depth test d_l - bias <= map and the in-front test
+ *               d_l > 0: S = |P - c| + |c - l| + |d_l| + |bias|;
+ *   face        cube-face choices: S = the largest component magnitude. */
 typedef struct {
-    double pix; /* half-width of the ambiguous band around an integer, in texels */
-    double rel; /* relative half-width of the ambiguous band of a comparison     */
+    double ssao_coord, ssao_depth, pcf_coord, pcf_depth, face;
 } orc_tie;
 
 typedef struct {

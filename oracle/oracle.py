@@ -13,7 +13,7 @@ from __future__ import annotations
 import ctypes as C
 import os
 import subprocess
-from typing import List, Optional, Sequence, Tuple
+from typing import List, NamedTuple, Optional, Sequence, Tuple
 
 import numpy as np
 
@@ -21,10 +21,26 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "epb_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-# Decisions whose operands lie this close to the threshold count as ties.
-# ``pix``: texel units of a floor / in-range test; ``rel``: relative to the
-# compared magnitude (depth tests, cube-face choice, signs).
-DEFAULT_TIE = (5e-3, 1e-5)
+class Tie(NamedTuple):
+    """Half-widths of the ambiguous bands of the float decisions, each as a
+    fraction of its decision's magnitude scale S (defined in epb_oracle.h): an
+    operand within ``field * S`` of its threshold counts as a tie."""
+    ssao_coord: float
+    ssao_depth: float
+    pcf_coord: float
+    pcf_depth: float
+    face: float
+
+
+ULP32 = 2.0 ** -24  # unit roundoff of float32
+# A float32 implementation's operand error is a few units of 2^-24 S (one per
+# rounding on the operand's chain, S the decision's magnitude scale of
+# epb_oracle.h).  Bands: 16 units for the SSAO coordinate (its S carries the
+# final rounding of the sum twice), 8 for the SSAO depth test, 4 for the
+# light-map coordinate and depth, and 1e-5 of the largest component for
+# cube-face choices (directions of GPU sine and cosine evaluations).
+DEFAULT_TIE = Tie(16 * ULP32, 8 * ULP32, 4 * ULP32, 4 * ULP32, 1e-5)
+EXACT = Tie(0.0, 0.0, 0.0, 0.0, 0.0)  # every decision taken once, in float64
 
 
 def build() -> str:
@@ -46,7 +62,7 @@ class OrcCamera(C.Structure):
 
 
 class OrcTie(C.Structure):
-    _fields_ = [("pix", C.c_double), ("rel", C.c_double)]
+    _fields_ = [(k, C.c_double) for k in Tie._fields]
 
 
 class OrcLight(C.Structure):
@@ -126,9 +142,7 @@ def _cam(cam) -> OrcCamera:
 
 
 def _tie(tie) -> OrcTie:
-    t = OrcTie()
-    t.pix, t.rel = tie
-    return t
+    return OrcTie(*Tie(*tie))
 
 
 # ---------------------------------------------------------------------------
@@ -204,7 +218,8 @@ def prefilter(env, base: int, levels: int, samples: int, tie=DEFAULT_TIE,
     total = sum(6 * (base >> m) ** 2 * 4 for m in range(levels))
     lo = np.zeros(total)
     hi = np.zeros(total)
-    lib().orc_prefilter(_p(env), env.shape[1], _p(lo), _p(hi), base, levels, samples, tie[1], 1 if fis else 0)
+    lib().orc_prefilter(_p(env), env.shape[1], _p(lo), _p(hi), base, levels, samples, Tie(*tie).face,
+                       1 if fis else 0)
 
     def split(out):
         res, off = [], 0
@@ -380,7 +395,7 @@ def edl(depth, color, cam, ao_lo=None, ao_hi=None, radius=1, n_dirs=8, strength=
     lib().orc_edl(_p(depth), _p(color), C.byref(c), _p(aol) if aol is not None else null,
                   _p(aoh) if aoh is not None else null, radius, n_dirs, strength, far_depth,
                   _p(envd) if envd is not None else null, envd.shape[1] if envd is not None else 0,
-                  tie[1], _p(lo), _p(hi))
+                  Tie(*tie).face, _p(lo), _p(hi))
     return lo, hi
 
 

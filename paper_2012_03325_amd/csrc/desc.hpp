@@ -40,7 +40,6 @@ struct DevLight {
 struct SsaoDesc {
     DevCam cam;
     float radius, bias, tau, inv_n;
-    float inv_radius;  // 1 / radius: the stored half-resolution depth is (d + bias) / radius
     int n, blur;
     int W, H, Wh, Hh;
     const float *depth;

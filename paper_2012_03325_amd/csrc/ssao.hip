@@ -5,18 +5,25 @@
 //  * prep compacts the half-resolution depth (the depth at (2i, 2j)) into a
 //    dense Wh x Hh plane: 2 MB at 1080p, resident in one XCD's 4 MB L2, so
 //    the sample gathers hit L2 instead of striding the full-resolution plane.
-//    It stores h = (d + bias) / radius: the occlusion test d_s <= z_q - bias
-//    becomes h_s <= z_q / radius and the range term radius / |d - d_s| becomes
-//    1 / |h - h_s|, two instructions fewer per sample.
 //  * raw: one thread per half-resolution texel; the sample kernel is read with
-//    scalar loads (wave-uniform).  A sample's depth and projected texel
-//    coordinates, in units of the radius, are affine in the kernel vector
-//    (three plane equations per pixel), so a sample costs 9 FMA, one
-//    reciprocal, two multiplies, two floor-converts, a range test, one
-//    gathered depth and 5 instructions of smoothstep and sum; gathers are
-//    issued a batch at a time before any is consumed, through a buffer
-//    resource whose range check makes an out-of-image offset read 0 (the
-//    sample is discarded by its range test).
+//    scalar loads (wave-uniform).  Every float decision is formed from small
+//    quantities, so that its rounding error does not grow with the depth or
+//    the image size:
+//      - the sample's texel coordinate is the pixel's own coordinate plus the
+//        sample's offset, offset = (f/2) r (w_x + a_x w_z) / z_q (w the
+//        view-space kernel vector, a_x the pixel's view-ray slope), added in
+//        one fused multiply-add, so its error is a few roundings of the offset
+//        plus one of the sum;
+//      - the depth test d_s <= z_q - bias becomes (d_s - d) <= -(r w_z + bias),
+//        where d_s - d is exact whenever the two depths lie within a factor of
+//        two of each other (Sterbenz) and r w_z + bias is of the order of the
+//        radius; the range term radius / |d - d_s| uses the same difference.
+//    A sample costs 12 FMA for the offset numerators and r w_z + bias, one
+//    subtraction for z_q, one reciprocal, two fused offsets, two
+//    floor-converts, a range test, one gathered depth and 8 instructions of
+//    smoothstep and sum; gathers are issued a batch at a time before any is
+//    consumed, through a buffer resource whose range check makes an
+//    out-of-image offset read 0 (the sample is discarded by its range test).
 //  * blur: 4x4 bilateral mean; the 19x11 depth/AO footprint of a 16x8 tile is
 //    staged through LDS.
 //  * every stage has a single-view kernel (one block per tile, XCD-aware
@@ -29,51 +36,57 @@ namespace epb {
 // ---------------------------------------------------------------------------
 // per-item work
 // ---------------------------------------------------------------------------
-// Stored form of a half-resolution depth: (d + bias) / radius (+inf stays +inf).
-__device__ __forceinline__ float ssao_h(const SsaoDesc &c, float d) { return (d + c.bias) * c.inv_radius; }
-
 __device__ __forceinline__ void ssao_prep_item(const SsaoDesc &c, int item) {
     int chunks = (c.Wh + kSsaoPrepW - 1) / kSsaoPrepW;
     int j = item / chunks;
     int i = (item - j * chunks) * kSsaoPrepW + (int)threadIdx.x;
     if (i >= c.Wh) return;
     stf(c.hdepth, __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i,
-        ssao_h(c, ldf(c.depth, __umul24((unsigned)(2 * j), (unsigned)c.W) + (unsigned)(2 * i))));
+        ldf(c.depth, __umul24((unsigned)(2 * j), (unsigned)c.W) + (unsigned)(2 * i)));
 }
+
+// Per-pixel constants of the sample loop: the kernel vector s enters through
+// three dot products, e = r w_z + bias (Ev, bias), and the numerators of the
+// texel-coordinate offsets in x and y (Xv, Yv).
+struct SsaoPix {
+    v3 Ev, Xv, Yv;
+    float d, dpb, hx0, hy0;  // own depth, d + bias, own half-resolution coordinates + 1/2
+};
 
 // KB samples of one pixel: all gathers issued before any is used.  `kern` points
 // at the batch's first kernel vector; with `ragged`, only the first `m` samples
 // exist (the others repeat the last one and are discarded).
 template <int KB, bool ragged>
-__device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const ConstFloat *kern, int m, v3 Xv, v3 Yv, v3 Zv,
-                                            float X0, float Y0, float Z0, float hp, __amdgpu_buffer_rsrc_t hdepth,
-                                            float occ) {
-    float hs[KB], zqs[KB];
+__device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const ConstFloat *kern, int m, const SsaoPix &q,
+                                            __amdgpu_buffer_rsrc_t hdepth, float occ) {
+    float ds[KB], es[KB];
     bool ok[KB];
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
         int k = ragged ? min(b, m - 1) : b;  // wave-uniform: scalar loads
         float sx = kern[3 * k], sy = kern[3 * k + 1], sz = kern[3 * k + 2];
-        float zq = fmaf(Zv.x, sx, fmaf(Zv.y, sy, fmaf(Zv.z, sz, Z0)));
-        float nx = fmaf(Xv.x, sx, fmaf(Xv.y, sy, fmaf(Xv.z, sz, X0)));
-        float ny = fmaf(Yv.x, sx, fmaf(Yv.y, sy, fmaf(Yv.z, sz, Y0)));
+        float e = fmaf(q.Ev.x, sx, fmaf(q.Ev.y, sy, fmaf(q.Ev.z, sz, c.bias)));  // r w_z + bias
+        float zq = q.dpb - e;                                                   // d - r w_z
+        float nx = fmaf(q.Xv.x, sx, fmaf(q.Xv.y, sy, q.Xv.z * sz));
+        float ny = fmaf(q.Yv.x, sx, fmaf(q.Yv.y, sy, q.Yv.z * sz));
         float iz = rcp(zq);
-        // floor-convert: 0 <= hx < Wh exactly when 0 <= floor(hx) < Wh (one unsigned
+        // floor-convert: 0 <= h < Wh exactly when 0 <= floor(h) < Wh (one unsigned
         // compare; out-of-range values saturate outside the range, and a NaN
         // (converted to 0) only arises with zq <= 0 or a NaN input, rejected by zq > 0)
-        int ix = floor_to_int(nx * iz), iy = floor_to_int(ny * iz);
+        int ix = floor_to_int(fmaf(nx, iz, q.hx0)), iy = floor_to_int(fmaf(ny, iz, q.hy0));
         ok[b] = (!ragged || b < m) && zq > 0.0f && (unsigned)ix < (unsigned)c.Wh && (unsigned)iy < (unsigned)c.Hh;
         // unchecked offset: when !ok it may point anywhere (a load past the plane
         // reads 0, one inside it an unrelated texel) and the sample is discarded
-        hs[b] = buf_ldf(hdepth, (__umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix) * 4u);
-        zqs[b] = zq;
+        ds[b] = buf_ldf(hdepth, (__umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix) * 4u);
+        es[b] = e;
     }
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
-        // smoothstep(radius / |d - d_s|) = u^2 (3 - 2u), u = clamp(1 / |h - h_s|)
-        float u = clamp01(rcp(fabsf(hp - hs[b])));
+        float dd = ds[b] - q.d;  // exact when the depths are within a factor of two
+        // smoothstep(radius / |d - d_s|) = u^2 (3 - 2u), u = clamp(radius / |d - d_s|)
+        float u = clamp01(c.radius * rcp(fabsf(dd)));
         float u2 = u * u, w = fmaf(-2.0f, u, 3.0f);
-        occ = fmaf(u2, (ok[b] && hs[b] <= zqs[b]) ? w : 0.0f, occ);  // d_s <= z_q - bias
+        occ = fmaf(u2, (ok[b] && dd <= -es[b]) ? w : 0.0f, occ);  // d_s <= z_q - bias
     }
     return occ;
 }
@@ -96,8 +109,8 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     }
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
     const TG *normal = (const TG *)c.normal;
-    // view-space position and normal
-    v3 P = mk3(((float)x + 0.5f - c.cam.cx) * c.cam.inv_fx * d, -((float)y + 0.5f - c.cam.cy) * c.cam.inv_fy * d, -d);
+    // view-ray slopes of the pixel (its point is d (ax, ay, -1)) and view-space normal
+    float ax = ((float)x + 0.5f - c.cam.cx) * c.cam.inv_fx, ay = -((float)y + 0.5f - c.cam.cy) * c.cam.inv_fy;
     v3 nw = mk3(ldf(normal, p), ldf(normal, plane + p), ldf(normal, 2 * plane + p));
     v3 nv = normalize(mul_R(c.cam.R, nw));
     // rotation noise, Gram-Schmidt against the normal
@@ -105,20 +118,18 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     v3 r = mk3(ldf(c.noise, rn), ldf(c.noise, rn + 1u), 0.0f);
     v3 t = normalize(r - nv * dot(nv, r));
     v3 bb = cross(nv, t);
-    // Sample s of the kernel lands at Q = P + radius (t sx + b sy + n sz).  In
-    // units of the radius its depth zq = -Q.z / radius and the numerators of its
-    // half-resolution texel coordinates hx = u / 2 + 1/4 = (fx/2 Q.x + (cx/2 +
-    // 1/4) (-Q.z)) / (-Q.z) (hy alike, y flipped) are affine in s: three plane
-    // equations per pixel.
-    float ax = 0.5f * c.cam.fx, bx = 0.5f * c.cam.cx + 0.25f;
-    float ay = -0.5f * c.cam.fy, by = 0.5f * c.cam.cy + 0.25f;
-    v3 Pr = P * c.inv_radius;
-    v3 Mx = mk3(t.x, bb.x, nv.x), My = mk3(t.y, bb.y, nv.y);
-    v3 Zv = mk3(-t.z, -bb.z, -nv.z);
-    float Z0 = -Pr.z;
-    v3 Xv = Mx * ax + Zv * bx, Yv = My * ay + Zv * by;
-    float X0 = fmaf(ax, Pr.x, bx * Z0), Y0 = fmaf(ay, Pr.y, by * Z0);
-    float hp = ssao_h(c, d);  // the pixel's own stored depth, as prep computed it
+    // The sample lands at Q = P + radius w, w = t sx + b sy + n sz, depth
+    // z_q = d - radius w_z; its half-resolution coordinate is the pixel's own,
+    // i + 1/2, plus (fx radius / 2) (w_x + ax w_z) / z_q (y alike, flipped).
+    SsaoPix q;
+    q.Ev = mk3(t.z, bb.z, nv.z) * c.radius;
+    float sx = 0.5f * c.cam.fx * c.radius, sy = -0.5f * c.cam.fy * c.radius;
+    q.Xv = mk3(fmaf(ax, t.z, t.x), fmaf(ax, bb.z, bb.x), fmaf(ax, nv.z, nv.x)) * sx;
+    q.Yv = mk3(fmaf(ay, t.z, t.y), fmaf(ay, bb.z, bb.y), fmaf(ay, nv.z, nv.y)) * sy;
+    q.d = d;
+    q.dpb = d + c.bias;
+    q.hx0 = (float)i + 0.5f;
+    q.hy0 = (float)j + 0.5f;
     __amdgpu_buffer_rsrc_t hdepth = raw_buffer(c.hdepth, (unsigned)c.Wh * (unsigned)c.Hh * 4u);
     float occ = 0.0f;
     // whole batches of KB samples (their 3 KB kernel floats in one run of scalar
@@ -126,9 +137,9 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     int nfull = c.n - c.n % KB;
     const ConstFloat *kern = as_constant(c.kernel);
     for (int k0 = 0; k0 < nfull; k0 += KB)
-        occ = ssao_batch<KB, false>(c, kern + 3 * k0, KB, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
+        occ = ssao_batch<KB, false>(c, kern + 3 * k0, KB, q, hdepth, occ);
     if (nfull < c.n)
-        occ = ssao_batch<KB, true>(c, kern + 3 * nfull, c.n - nfull, Xv, Yv, Zv, X0, Y0, Z0, hp, hdepth, occ);
+        occ = ssao_batch<KB, true>(c, kern + 3 * nfull, c.n - nfull, q, hdepth, occ);
     stf(out, o, 1.0f - occ * c.inv_n);
 }
 
@@ -169,11 +180,10 @@ __device__ __forceinline__ void ssao_blur_tile(const SsaoDesc &c, int tile, floa
     int ti = threadIdx.x % kBlurTx, tj = threadIdx.x / kBlurTx;
     int i = i0 + ti, j = j0 + tj;
     if (i < c.Wh && j < c.Hh) {
-        float dp = sd[tj + 2][ti + 2];  // stored form h = (d + bias) / radius
+        float dp = sd[tj + 2][ti + 2];
         float v = 1.0f;
         if (!__builtin_isinf(dp)) {
-            // |d_q - d_p| / (tau d_p) = |h_q - h_p| radius / (tau d_p)
-            float inv = c.radius / (c.tau * fmaf(dp, c.radius, -c.bias));
+            float inv = 1.0f / (c.tau * dp);  // weight 1 - |d_q - d_p| / (tau d_p)
             float s = 0.0f, sw = 0.0f;
 #pragma unroll
             for (int dy = 0; dy < 4; ++dy)
@@ -291,7 +301,6 @@ SsaoDesc ssao_desc(const SsaoPlan &q, const float *depth, const void *normal, co
     c.cam.inv_fx = cam.inv_fx; c.cam.inv_fy = cam.inv_fy;
     c.cam.w = cam.w; c.cam.h = cam.h;
     c.radius = radius;
-    c.inv_radius = (float)(1.0 / (double)radius);
     c.bias = bias;
     c.tau = tau;
     c.n = n_samples;

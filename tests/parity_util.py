@@ -7,8 +7,10 @@ Tolerances, derived from the arithmetic:
 * AO: absolute 1e-4.  AO = 1 - (sum of N smoothstep terms) / N, each term a
   handful of float32 operations on O(1) values (<= 1e-6 each).
 * 8-bit output: +-1 code (the stated bar), on at least 99.9 % of pixels.
-Where the oracle reports an interval [lo, hi] (float decisions within the tie
-margin), the GPU value must lie in [lo - tol(lo), hi + tol(hi)].
+Where the oracle reports an interval [lo, hi] (float decisions within their
+float32 rounding band), every GPU value must lie in [lo - tol(lo), hi + tol(hi)];
+each check logs its worst excursion and the share of intervals wider than the
+tolerance.
 """
 from __future__ import annotations
 
@@ -36,9 +38,31 @@ def within_interval(g, lo, hi, rtol=HDR_RTOL, atol=None):
     return (g >= lo - (rtol * np.abs(lo) + atol)) & (g <= hi + (rtol * np.abs(hi) + atol))
 
 
+def interval_report(g, lo, hi, rtol=HDR_RTOL, atol=None):
+    """(worst, wide): the largest distance of ``g`` outside [lo, hi] in units of
+    the tolerance (< 1 passes; 0 inside the interval) and the share of values
+    whose interval is itself wider than the tolerance."""
+    g = np.asarray(g, np.float64)
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    if atol is None:
+        atol = HDR_ATOL_REL_MAX * max(1e-30, float(np.abs(hi).max()))
+    tol_lo = rtol * np.abs(lo) + atol
+    tol_hi = rtol * np.abs(hi) + atol
+    out = np.maximum(np.maximum(lo - g, 0.0) / tol_lo, np.maximum(g - hi, 0.0) / tol_hi)
+    wide = (hi - lo) > tol_lo
+    return float(out.max()) if out.size else 0.0, float(wide.mean()) if wide.size else 0.0
+
+
 def assert_interval(name, g, lo, hi, rtol=HDR_RTOL, atol=None, min_frac=1.0):
+    """Every value of ``g`` within the tolerance band of [lo, hi] (``min_frac``
+    of them when given); logs the worst excursion (in tolerances) and the
+    share of over-wide oracle intervals.  Returns the fraction within."""
     ok = within_interval(g, lo, hi, rtol, atol)
     frac = ok.mean()
+    worst, wide = interval_report(g, lo, hi, rtol, atol)
+    log(f"  {name}: worst {worst:.3f} of the tolerance outside the interval; "
+        f"intervals wider than the tolerance {100 * wide:.4f}%")
     if frac < min_frac:
         bad = np.argwhere(~ok)[:5]
         g64 = np.asarray(g, np.float64)

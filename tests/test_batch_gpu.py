@@ -162,7 +162,7 @@ def test_batched_view_oracle_parity(k):
     log(f"[batch-oracle] view {k} {v.width}x{v.height}")
     ref = O.render(v)
     dv = dvs[k]
-    assert_interval(f"batched view {k} HDR", dv.hdr.cpu().numpy(), *ref["hdr"], min_frac=0.9999)
+    assert_interval(f"batched view {k} HDR", dv.hdr.cpu().numpy(), *ref["hdr"])
     assert_ldr(f"batched view {k} LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
 
 

@@ -420,14 +420,15 @@ def test_pcf_lit_fraction_by_hand():
     cases.append((m, 8 / 9))
     for sm, frac in cases:
         light = synth.Light(np.zeros(3), np.ones(3), 4.0, scam, sm, 0.02)
-        lo, hi = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env, tie=(5e-3, 0.0))
+        lo, hi = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env, tie=O.EXACT)
         assert np.allclose(lo, ref * frac, rtol=1e-12, atol=0), frac
         assert np.allclose(hi, ref * frac, rtol=1e-12, atol=0), frac
-    # a depth within the tie margin of the threshold yields the interval [8/9, 1]
+    # a depth within the float32 band of the threshold (1.98 in float32 lies
+    # 1.9e-8 above 2 - 0.02) yields the interval [8/9, 1]
     sm = np.full((8, 8), np.inf, np.float32)
     sm[4, 4] = 1.98
     light = synth.Light(np.zeros(3), np.ones(3), 4.0, scam, sm, 0.02)
-    lo, hi = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env, tie=(5e-3, 1e-5))
+    lo, hi = O.shade(g, cam, ao, ao, [light], _zero_ibl(), env)
     assert np.allclose(lo, ref * 8 / 9) and np.allclose(hi, ref)
 
 
@@ -601,8 +602,51 @@ def test_intervals_are_ordered_on_a_full_scene():
         assert (np.asarray(lo, np.float64) <= np.asarray(hi, np.float64)).all(), key
     lo, hi = r["hdr"]
     assert np.isfinite(lo).all() and np.isfinite(hi).all()
-    # the ambiguous share stays small
-    assert (hi > lo).mean() < 0.5
+
+
+def _wide_shares(view, tie=O.DEFAULT_TIE):
+    """Shares of half-resolution texels whose raw AO interval is wider than the
+    AO tolerance (1e-4) and of pixels whose HDR interval is wider than the HDR
+    tolerance (1e-3 relative): where the oracle's bands admit outcomes that the
+    parity bar cannot tell apart.  Reduced IBL tables (their values do not enter
+    any SSAO or shadow decision)."""
+    g = view.gbuf
+    ibl = O.precompute_ibl(view.env, irr_size=8, irr_src_size=16, pref_size=32, pref_levels=5,
+                           pref_samples=64, lut_size=32, lut_samples=64)
+    rl, rh = O.ssao_raw(g["depth"], g["normal"], view.cam, view.ssao_kernel, view.ssao_noise,
+                        view.ssao_radius, view.ssao_bias, tie)
+    bl, bh = O.ssao_blur(rl, rh, g["depth"], view.blur_tau)
+    hl, hh = O.shade(g, view.cam, bl, bh, view.lights, ibl, view.env, tie)
+    tol = 1e-3 * np.abs(hl) + 1e-6 * np.abs(hh).max()
+    return float(((rh - rl) > 1e-4).mean()), float(((hh - hl) > tol).any(0).mean())
+
+
+def test_ambiguous_share_plain_256():
+    """256x256 view (one unshadowed light): under 0.1 % of AO texels and of
+    HDR pixels carry an interval wider than the parity tolerance."""
+    raw, hdr = _wide_shares(synth.config_small())
+    print(f"plain-256: raw AO wide {100 * raw:.4f}%, HDR wide {100 * hdr:.4f}%")
+    assert raw < 1e-3 and hdr < 1e-3
+
+
+@pytest.mark.slow
+def test_ambiguous_share_1080p():
+    """The 1080p benchmark view.  SSAO decisions (formed from the sample's
+    offset and the depth difference) leave under 0.1 % of AO texels and no
+    more than 0.1 % of HDR pixels with an interval wider than the tolerance.
+    The four 2048^2 shadow maps add the light-map decisions: a point
+    reconstructed from camera depth carries ~3e-4 texel and ~3e-6 of depth of
+    float32 error in any evaluation order, and one flipped tap moves 1/9 of a
+    light, so those pixels (~0.23 %) are wide by construction; bounded here."""
+    v = synth.config_1080p()
+    t = O.DEFAULT_TIE
+    raw, hdr = _wide_shares(v)
+    _, hdr_no_pcf = _wide_shares(v, t._replace(pcf_coord=0.0, pcf_depth=0.0))
+    print(f"1080p: raw AO wide {100 * raw:.4f}%, HDR wide {100 * hdr:.4f}% "
+          f"({100 * hdr_no_pcf:.4f}% without the light-map decisions)")
+    assert raw < 1e-3
+    assert hdr_no_pcf < 1e-3
+    assert hdr < 3e-3
 
 
 # ---------------------------------------------------------------------------

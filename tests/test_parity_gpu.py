@@ -303,7 +303,7 @@ def test_end_to_end(kind):
     torch.cuda.synchronize()
     hdr = dv.hdr.cpu().numpy()
     lo, hi = ref["hdr"]
-    fh = assert_interval(f"{kind} HDR", hdr, lo, hi, min_frac=0.9999)
+    fh = assert_interval(f"{kind} HDR", hdr, lo, hi)
     frac, exact = assert_ldr(f"{kind} LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
     log(f"[e2e] {kind}: HDR within {100 * fh:.4f}%, LDR +-1 {100 * frac:.4f}% (exact {100 * exact:.3f}%)")
 
@@ -450,7 +450,7 @@ def test_fp16_form_arithmetic_parity(kind):
     torch.cuda.synchronize()
     hdr = dv.hdr.float().cpu().numpy()
     lo, hi = (np.minimum(x, HALF_MAX) for x in ref["hdr"])  # storage saturates at 65504
-    fh = assert_interval(f"{kind} FP16 HDR", hdr, lo, hi, rtol=FP16_RTOL, min_frac=0.9999)
+    fh = assert_interval(f"{kind} FP16 HDR", hdr, lo, hi, rtol=FP16_RTOL)
     frac, exact = assert_ldr(f"{kind} FP16 LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
     log(f"[fp16] {kind}: HDR within {100 * fh:.4f}%, LDR +-1 {100 * frac:.4f}% (exact {100 * exact:.3f}%)")
 
@@ -478,7 +478,10 @@ def test_fp16_form_error_against_fp32_inputs():
     log(f"[fp16-e2e] AO max err {ao_err.max():.2e}; HDR rel err p50 {np.percentile(rel, 50):.2e} "
         f"p99 {np.percentile(rel, 99):.2e} p99.9 {np.percentile(rel, 99.9):.2e} max {rel.max():.2e}; "
         f"LDR LSB histogram {hist[:4].tolist()} (of {dist.size})")
-    assert ao_err.max() < 2e-3
+    # half normals move each sample by up to ~r 2^-10; a sample whose depth test
+    # flips moves raw AO by up to 1/N = 1/64, which the blur spreads (an isolated
+    # texel keeps it whole): bound at two flipped samples' worth
+    assert ao_err.max() < 2.0 / 64
     assert np.percentile(rel, 99) < 1e-2
     assert (dist <= 1).mean() >= 0.999
 
@@ -501,6 +504,6 @@ def test_surfel_gbuffer_parity(kind, store):
     hdr = dv.hdr.float().cpu().numpy()
     lo, hi = (np.minimum(x, HALF_MAX) for x in ref["hdr"]) if out == E.EPB_F16 else ref["hdr"]
     rtol = FP16_RTOL if out == E.EPB_F16 else 1e-3
-    fh = assert_interval(f"{kind} surfel HDR", hdr, lo, hi, rtol=rtol, min_frac=0.9999)
+    fh = assert_interval(f"{kind} surfel HDR", hdr, lo, hi, rtol=rtol)
     frac, exact = assert_ldr(f"{kind} surfel LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
     log(f"[surfel] {kind}: HDR within {100 * fh:.4f}%, LDR +-1 {100 * frac:.4f}% (exact {100 * exact:.3f}%)")

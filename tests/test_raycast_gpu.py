@@ -111,33 +111,34 @@ def test_raycast_half_gbuffer_and_depth_maps():
 
 
 def test_raycast_then_render_matches_the_oracle_pipeline():
-    """G-buffer and shadow maps cast on the GPU, then the whole pass, against
-    the oracle's cast followed by the oracle's pass (the two casts differ only
-    on tie-margin pixels, which SSAO and bloom spread to their neighbours)."""
+    """G-buffer and shadow maps cast on the GPU, then the whole pass on the GPU:
+    the casts equal the oracle's away from its tie pixels (within one float32
+    ulp), and the pass on the GPU-cast inputs matches the oracle's pass on those
+    same inputs on every pixel."""
     import copy
     from paper_2012_03325_amd import frame as fr
     v = synth.config_reduced(160, 96, seed=21, shadow_size=256, env_size=16, ssao_n=16, n_spheres=40)
     rng = np.random.default_rng(21)
     scene = synth.make_spheres(rng, 40, True)  # the same draw config_reduced used
-    ref_view = copy.deepcopy(v)
     rg = O.raycast(scene, v.cam)
-    ref_view.gbuf = {k: rg[k].astype(np.float32) for k in ("depth", "normal", "albedo", "roughness", "metalness")}
-    for L in ref_view.lights:
-        L.shadow_map = O.raycast(scene, L.shadow_cam, attributes=False)["depth"].astype(np.float32)
-    ref = O.render(ref_view)
     ds = fr.DeviceScene(scene)
     g = ds.render_gbuffer(v.cam)
     gpu_view = copy.deepcopy(v)
     gpu_view.gbuf = {k: t.cpu().numpy() for k, t in g.items()}
     for L in gpu_view.lights:
         L.shadow_map = ds.render_depth(L.shadow_cam).cpu().numpy()
+    ok = rg["ambiguous"] == 0
+    fin = ok & np.isfinite(rg["depth"])
+    assert np.array_equal(np.isfinite(gpu_view.gbuf["depth"])[ok], np.isfinite(rg["depth"])[ok])
+    assert _ulps(gpu_view.gbuf["depth"][fin], rg["depth"].astype(np.float32)[fin]).max() <= 1
+    ref = O.render(gpu_view)
     ibl = fr.DeviceIBL(v.env, **v.ibl)
     ibl.precompute()
     dv = fr.DeviceView(gpu_view, ibl)
     dv.render()
     torch.cuda.synchronize()
     log("[raycast] cast + render 160x96")
-    assert_interval("cast+render HDR", dv.hdr.cpu().numpy(), *ref["hdr"], min_frac=0.999)
+    assert_interval("cast+render HDR", dv.hdr.cpu().numpy(), *ref["hdr"])
     assert_ldr("cast+render LDR", dv.ldr.cpu().numpy(), *ref["ldr"])
 
 
