@@ -292,6 +292,25 @@ int epb_ssao(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_para
              void *ao_out, void *scratch, size_t scratch_bytes, hipStream_t stream);
 
 /*
+ * epb_ssao_static -- epb_ssao for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same computation and results, bit for bit, with the scratch
+ * taken from an array the library holds on every GPU it runs on
+ * (EPB_SSAO_STATIC_SCRATCH_BYTES, kept until the process ends).  Nothing is
+ * allocated; the caller passes inputs and outputs as for epb_ssao, on the
+ * current device.  Images whose SSAO scratch (epb_scratch_bytes(EPB_OP_SSAO,
+ * ...), two planes of ceil(W/2) x ceil(H/2) floats) exceeds the array return
+ * EPB_ERR_SIZE (3840 x 2160 fits); a failed device-address lookup returns
+ * EPB_ERR_HIP.  Every call on one GPU shares that GPU's array: calls that
+ * overlap on one GPU (concurrent streams) race, so callers serialise them.
+ * Nothing in the array needs to start at zero (every value is written before
+ * it is read within the call).
+ */
+#define EPB_SSAO_STATIC_SCRATCH_BYTES (16u << 20)
+int epb_ssao_static(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_params *params,
+                    void *ao_out, hipStream_t stream);
+
+/*
  * epb_shade -- the compose pass (Sec. 4.2) with PBR (Sec. 3) and IBL (Sec. 3.1).
  *
  *   gbuf, cam   G-buffer and camera (same W, H)

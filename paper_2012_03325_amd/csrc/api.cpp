@@ -405,6 +405,21 @@ int epb_ssao(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_para
     return hip_status(epb::launch_ssao(d, gbuf->dtype, params->out_dtype, stream));
 }
 
+int epb_ssao_static(const epb_gbuffer *gbuf, const epb_camera *cam, const epb_ssao_params *params,
+                    void *ao_out, hipStream_t stream) {
+    if (!gbuf || !cam || !params || !ao_out) return EPB_ERR_NULL;
+    int st = check_camera(cam);
+    if (st) return st;
+    if (epb::ssao_plan(cam->width, cam->height).bytes > (size_t)EPB_SSAO_STATIC_SCRATCH_BYTES) return EPB_ERR_SIZE;
+    void *scratch = nullptr;
+    st = hip_status(epb::ssao_static_scratch(&scratch));
+    if (st) return st;
+    epb::SsaoDesc d;
+    st = build_ssao(gbuf, cam, params, ao_out, scratch, EPB_SSAO_STATIC_SCRATCH_BYTES, &d);
+    if (st) return st;
+    return hip_status(epb::launch_ssao(d, gbuf->dtype, params->out_dtype, stream));
+}
+
 int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, epb_dtype ao_dtype,
               const epb_light *lights, int32_t n_lights, const epb_ibl_maps *ibl, const epb_cube *env,
               void *hdr_out, epb_dtype hdr_dtype, hipStream_t stream) {

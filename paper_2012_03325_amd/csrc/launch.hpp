@@ -50,6 +50,9 @@ SsaoDesc ssao_desc(const SsaoPlan &q, const float *depth, const void *normal, co
 int ssao_items(const SsaoDesc &c, int stage, int ssao_tile);
 hipError_t launch_ssao(const SsaoDesc &c, epb_dtype gdtype, epb_dtype ao_dtype, hipStream_t s);
 hipError_t launch_ssao_batch(const BatchHeader &h, const void *table, hipStream_t s);
+// Device address of the library's own SSAO scratch array on the current device
+// (EPB_SSAO_STATIC_SCRATCH_BYTES bytes), looked up once per device.
+hipError_t ssao_static_scratch(void **addr);
 
 // ---- shading (shade.hip) ----------------------------------------------------
 struct ShadeArgs {

@@ -28,6 +28,8 @@
 //    staged through LDS.
 //  * every stage has a single-view kernel (one block per tile, XCD-aware
 //    order) and a batched kernel that walks the tiles of many views.
+#include <mutex>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -345,6 +347,35 @@ hipError_t launch_ssao(const SsaoDesc &c, epb_dtype gdtype, epb_dtype ao_dtype, 
             hipLaunchKernelGGL(k_ssao_blur<__half>, dim3(tiles), dim3(kBlurTx * kBlurTy), 0, s, c, tiles);
     }
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// scratch held by the library (epb_ssao_static): one array per GPU, for callers
+// that cannot allocate.  In host code the array's name is only a stand-in; its
+// device address is looked up once per device and used everywhere instead.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) unsigned char static_scratch[EPB_SSAO_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void *g_static_addr[kMaxDevices];  // device address of static_scratch, per device
+}  // namespace
+
+hipError_t ssao_static_scratch(void **addr) {
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mu);
+    if (!g_static_addr[dev]) {  // first call on this device, which is current
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(static_scratch));
+        if (e != hipSuccess) return e;
+        g_static_addr[dev] = p;
+    }
+    *addr = g_static_addr[dev];
+    return hipSuccess;
 }
 
 // Grid of a batched stage: one block per item, or a persistent grid of

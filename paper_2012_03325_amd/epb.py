@@ -43,8 +43,9 @@ EPB_MAX_EDL_RADIUS = 16
 EPB_MAX_EDL_DIRS = 32
 EPB_MAP_ROWS = 0
 EPB_MAP_TILES = 1
+EPB_SSAO_STATIC_SCRATCH_BYTES = 16 << 20
 
-ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
+ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_ssao_static", "epb_shade", "epb_bloom_tonemap",
                 "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
                 "epb_batch_table_bytes", "epb_view_scratch_bytes", "epb_batch_scratch_bytes",
                 "epb_batch_build",
@@ -149,6 +150,8 @@ def _load() -> C.CDLL:
                                        C.POINTER(epb_ibl_maps), P, C.c_size_t, P]
     lib.epb_ssao.argtypes = [C.POINTER(epb_gbuffer), C.POINTER(epb_camera),
                              C.POINTER(epb_ssao_params), P, P, C.c_size_t, P]
+    lib.epb_ssao_static.argtypes = [C.POINTER(epb_gbuffer), C.POINTER(epb_camera),
+                                    C.POINTER(epb_ssao_params), P, P]
     lib.epb_shade.argtypes = [C.POINTER(epb_gbuffer), C.POINTER(epb_camera), P, C.c_int,
                               C.POINTER(epb_light), C.c_int32, C.POINTER(epb_ibl_maps),
                               C.POINTER(epb_cube), P, C.c_int, P]
@@ -174,7 +177,7 @@ def _load() -> C.CDLL:
     lib.epb_shadow_tiles_bytes.argtypes = [C.c_int32, C.c_int32]
     lib.epb_shadow_tiles_bytes.restype = C.c_size_t
     lib.epb_shadow_tiles.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, P]
-    for fn in ("epb_precompute_ibl", "epb_ssao", "epb_shade", "epb_bloom_tonemap",
+    for fn in ("epb_precompute_ibl", "epb_ssao", "epb_ssao_static", "epb_shade", "epb_bloom_tonemap",
                "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast", "epb_edl",
                "epb_shadow_tiles"):
         getattr(lib, fn).restype = C.c_int
@@ -235,6 +238,12 @@ def epb_ssao(gbuf: epb_gbuffer, cam: epb_camera, params: epb_ssao_params, ao_out
     st = lib.epb_ssao(C.byref(gbuf), C.byref(cam), C.byref(params), _ptr(ao_out), _ptr(scratch),
                       scratch_bytes, _stream(stream))
     return _check("epb_ssao", st, check)
+
+
+def epb_ssao_static(gbuf: epb_gbuffer, cam: epb_camera, params: epb_ssao_params, ao_out, stream=None,
+                    check: bool = True) -> int:
+    st = lib.epb_ssao_static(C.byref(gbuf), C.byref(cam), C.byref(params), _ptr(ao_out), _stream(stream))
+    return _check("epb_ssao_static", st, check)
 
 
 def epb_shade(gbuf: epb_gbuffer, cam: epb_camera, ao, ao_dtype: int, lights: Sequence[epb_light],

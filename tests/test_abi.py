@@ -120,6 +120,24 @@ def test_ssao_validation():
     assert call(c=c2) == E.EPB_ERR_PARAM
 
 
+def test_ssao_static_validation():
+    """The allocation-free SSAO call: missing pointers and images whose scratch
+    exceeds the library's own array fail before any device query; 3840x2160
+    fits."""
+    p = E.epb_ssao_params(16, FAKE, FAKE, 0.5, 0.025, 0.1, 1, E.EPB_F32)
+    call = lambda g, c, out=FAKE: E.lib.epb_ssao_static(C.byref(g), C.byref(c), C.byref(p), out, None)
+    assert E.lib.epb_ssao_static(None, C.byref(_cam()), C.byref(p), FAKE, None) == E.EPB_ERR_NULL
+    assert call(_gbuf(), _cam(), out=None) == E.EPB_ERR_NULL
+    assert call(_gbuf(0, 48), _cam(0, 48)) == E.EPB_ERR_SIZE
+    assert call(_gbuf(4096, 4096), _cam(4096, 4096)) == E.EPB_ERR_SIZE
+    cap = E.EPB_SSAO_STATIC_SCRATCH_BYTES
+    assert E.epb_scratch_bytes(E.EPB_OP_SSAO, 3840, 2160, None) <= cap
+    w = 3840
+    while E.epb_scratch_bytes(E.EPB_OP_SSAO, w, 2160, None) <= cap:
+        w += 2
+    assert call(_gbuf(w, 2160), _cam(w, 2160)) == E.EPB_ERR_SIZE
+
+
 def test_shade_validation():
     cam = _cam()
     cube = E.epb_cube(8, 1, FAKE)
