@@ -43,13 +43,13 @@ DEFAULT_TIE = Tie(16 * ULP32, 8 * ULP32, 4 * ULP32, 4 * ULP32, 1e-5)
 EXACT = Tie(0.0, 0.0, 0.0, 0.0, 0.0)  # every decision taken once, in float64
 
 
-def build() -> str:
+def build(src: str = _SRC, out: str = _LIB_PATH) -> str:
     """Compile the oracle with gcc (IEEE double, no fast-math, OpenMP)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
-           "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", "-o", _LIB_PATH + ".tmp", _SRC, "-lm"]
+           "-fno-fast-math", "-Wall", "-Wno-unknown-pragmas", "-I", _HERE, "-o", out + ".tmp", src, "-lm"]
     subprocess.run(cmd, check=True)
-    os.replace(_LIB_PATH + ".tmp", _LIB_PATH)
-    return _LIB_PATH
+    os.replace(out + ".tmp", out)
+    return out
 
 
 _lib = None
@@ -86,42 +86,47 @@ def lib():
     if _lib is None:
         if not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
             build()
-        L = C.CDLL(_LIB_PATH)
-        L.orc_cube_texel_dir.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _D]
-        L.orc_texel_solid_angle.argtypes = [C.c_int, C.c_int, C.c_int]
-        L.orc_texel_solid_angle.restype = C.c_double
-        L.orc_ggx_D.argtypes = [C.c_double, C.c_double]
-        L.orc_ggx_D.restype = C.c_double
-        L.orc_brdf_lut_point.argtypes = [C.c_double, C.c_double, C.c_int, _D]
-        L.orc_aces.argtypes = [C.c_double]
-        L.orc_aces.restype = C.c_double
-        L.orc_encode_u8.argtypes = [C.c_double, C.c_double, C.c_double]
-        L.orc_encode_u8.restype = C.c_int
-        L.orc_reinhard.argtypes = [C.c_double]
-        L.orc_reinhard.restype = C.c_double
-        L.orc_encode_u8_op.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
-        L.orc_encode_u8_op.restype = C.c_int
-        L.orc_env_downsample.argtypes = [_D, C.c_int, _D]
-        L.orc_irradiance.argtypes = [_D, C.c_int, _D, C.c_int]
-        L.orc_prefilter.argtypes = [_D, C.c_int, _D, _D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int]
-        L.orc_brdf_lut.argtypes = [_D, C.c_int, C.c_int]
-        L.orc_ssao_raw.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, C.c_int, _D, C.c_double,
-                                   C.c_double, C.POINTER(OrcTie), _D, _D]
-        L.orc_ssao_blur.argtypes = [_D, _D, _D, C.c_int, C.c_int, C.c_double, _D, _D]
-        L.orc_shade.argtypes = [_D, _D, _D, _D, _D, C.POINTER(OrcCamera), _D, _D,
-                                C.POINTER(OrcLight), C.c_int, _D, C.c_int, _D, _D, C.c_int, C.c_int,
-                                _D, C.c_int, _D, C.c_int, C.POINTER(OrcTie), _D, _D]
-        L.orc_normalize_gbuffer.argtypes = [_D, C.c_int, C.c_int, _D, _D, _D, _D]
-        L.orc_raycast.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcCamera), C.c_double, _D,
-                                  C.POINTER(C.c_int32), _D, _D, _D, _D, C.POINTER(C.c_uint8)]
-        L.orc_set_threads.argtypes = [C.c_int]
-        L.orc_edl_offsets.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
-        L.orc_edl.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, _D, C.c_int, C.c_int, C.c_double,
-                              C.c_double, _D, C.c_int, C.c_double, _D, _D]
-        L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
-                                        C.c_double, C.c_double, C.c_int, C.POINTER(C.c_uint8), _D, _D]
-        _lib = L
+        _lib = load(_LIB_PATH)
     return _lib
+
+
+def load(path: str):
+    """Load a build of the oracle's C source and declare its signatures."""
+    L = C.CDLL(path)
+    L.orc_cube_texel_dir.argtypes = [C.c_int, C.c_int, C.c_int, C.c_int, _D]
+    L.orc_texel_solid_angle.argtypes = [C.c_int, C.c_int, C.c_int]
+    L.orc_texel_solid_angle.restype = C.c_double
+    L.orc_ggx_D.argtypes = [C.c_double, C.c_double]
+    L.orc_ggx_D.restype = C.c_double
+    L.orc_brdf_lut_point.argtypes = [C.c_double, C.c_double, C.c_int, _D]
+    L.orc_aces.argtypes = [C.c_double]
+    L.orc_aces.restype = C.c_double
+    L.orc_encode_u8.argtypes = [C.c_double, C.c_double, C.c_double]
+    L.orc_encode_u8.restype = C.c_int
+    L.orc_reinhard.argtypes = [C.c_double]
+    L.orc_reinhard.restype = C.c_double
+    L.orc_encode_u8_op.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int]
+    L.orc_encode_u8_op.restype = C.c_int
+    L.orc_env_downsample.argtypes = [_D, C.c_int, _D]
+    L.orc_irradiance.argtypes = [_D, C.c_int, _D, C.c_int]
+    L.orc_prefilter.argtypes = [_D, C.c_int, _D, _D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_int]
+    L.orc_brdf_lut.argtypes = [_D, C.c_int, C.c_int]
+    L.orc_ssao_raw.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, C.c_int, _D, C.c_double,
+                               C.c_double, C.POINTER(OrcTie), _D, _D]
+    L.orc_ssao_blur.argtypes = [_D, _D, _D, C.c_int, C.c_int, C.c_double, _D, _D]
+    L.orc_shade.argtypes = [_D, _D, _D, _D, _D, C.POINTER(OrcCamera), _D, _D,
+                            C.POINTER(OrcLight), C.c_int, _D, C.c_int, _D, _D, C.c_int, C.c_int,
+                            _D, C.c_int, _D, C.c_int, C.POINTER(OrcTie), _D, _D]
+    L.orc_normalize_gbuffer.argtypes = [_D, C.c_int, C.c_int, _D, _D, _D, _D]
+    L.orc_raycast.argtypes = [C.POINTER(OrcScene), C.POINTER(OrcCamera), C.c_double, _D,
+                              C.POINTER(C.c_int32), _D, _D, _D, _D, C.POINTER(C.c_uint8)]
+    L.orc_set_threads.argtypes = [C.c_int]
+    L.orc_edl_offsets.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.orc_edl.argtypes = [_D, _D, C.POINTER(OrcCamera), _D, _D, C.c_int, C.c_int, C.c_double,
+                          C.c_double, _D, C.c_int, C.c_double, _D, _D]
+    L.orc_bloom_tonemap.argtypes = [_D, C.c_int, C.c_int, C.c_int, C.c_double, C.c_double,
+                                    C.c_double, C.c_double, C.c_int, C.POINTER(C.c_uint8), _D, _D]
+    return L
 
 
 def _d(a) -> np.ndarray:
