@@ -9,9 +9,11 @@ epb_precompute_ibl runs before the timed region and is timed on its own
 (``ibl_precompute_ms``); ``value_incl_ibl`` charges it to every frame.
 
 To keep the 256 MB last-level cache (MALL) from serving the per-frame buffers,
-the timed loop rotates over several full copies of the G-buffer and of every
-output and scratch buffer (the scene-static shadow maps and IBL tables are
-shared, as a renderer keeps them resident).  Each copy's frame (its seven
+the timed loop rotates over several full copies of the G-buffer, the four
+shadow maps and every output and scratch buffer (only the IBL tables, 2 MB,
+are shared).  The shading kernel is also timed with the maps shared by all
+copies (``shade_ms_shared_maps``: what a renderer that keeps its maps resident
+sees, the MALL serving the re-read texels).  Each copy's frame (its seven
 kernel launches) is captured once in a HIP graph; the timed steps replay the
 graphs with several frames in flight on as many streams (``frames_in_flight``;
 a copy always returns to the same stream).  Frames replayed one at a time give
@@ -37,6 +39,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "shaded Mpix/s (SSAO+PBR+IBL+tonemap) batched/FP16 vs plain; p99 request latency"
 HBM_PEAK_GBPS = 8000.0  # MI355X published HBM3E bandwidth
+# VALU issue peak: 256 CUs x 2.4 GHz x one wavefront instruction per clock per CU
+# (four SIMDs, each 16 lanes wide, take four clocks per 64-lane instruction)
+VALU_PEAK_GWINST = 256 * 2.4
 
 
 def log(msg):
@@ -75,6 +80,13 @@ def counted_shade_record():
 def counted_shade_traffic():
     rec = counted_shade_record()
     return rec.get("bytes_per_launch") if rec else None
+
+
+def counted_shade_valu_instructions():
+    """VALU wavefront instructions per launch of the FP32 shading kernel
+    (SQ_INSTS_VALU of the committed counter run), or None."""
+    rec = counted_shade_record()
+    return rec.get("valu_wave_instructions_per_launch") if rec else None
 
 
 def counted_shade_utilisation():
@@ -432,6 +444,79 @@ def bench_serving(args, torch, E, frame, synth, schedule=None) -> dict:
     return out
 
 
+def fp16_outputs_256(torch, E, frame, synth) -> dict:
+    """The precision form on the 256x256 view (FP16 G-buffer attributes, FP16
+    AO, HDR and bloom pyramid; the IBL tables in float32): every output, on
+    the host, for the error statement of the oracle leg."""
+    view = synth.config_small()
+    ibl = frame.DeviceIBL(view.env, **view.ibl)
+    ibl.precompute()
+    dv = frame.DeviceView(view, ibl, gdtype=E.EPB_F16, ao_dtype=E.EPB_F16, hdr_dtype=E.EPB_F16)
+    dv.render()
+    torch.cuda.synchronize()
+    return dict(view=view, irradiance=ibl.irr.cpu().numpy()[..., :3],
+                prefiltered=[m.cpu().numpy()[..., :3] for m in ibl.pref_levels()], lut=ibl.lut.cpu().numpy(),
+                ao=dv.ao.float().cpu().numpy(), hdr=dv.hdr.float().cpu().numpy(), ldr=dv.ldr.cpu().numpy())
+
+
+def _rel_outside(g, lo, hi, floor):
+    """Distance of g outside [lo, hi] relative to the interval's magnitude."""
+    g, lo, hi = (np.asarray(x, np.float64) for x in (g, lo, hi))
+    out = np.maximum(np.maximum(lo - g, g - hi), 0.0)
+    return out / np.maximum(np.maximum(np.abs(lo), np.abs(hi)), floor)
+
+
+def _stats(x):
+    x = np.asarray(x, np.float64).ravel()
+    return {"max": float(f"{x.max():.3e}"), "p99_9": float(f"{np.percentile(x, 99.9):.3e}")}
+
+
+def fp16_error_statement(orc, gpu) -> dict:
+    """Error of the FP16 form per output against the FP64 oracle, (i) on the
+    original FP32 inputs and (ii) on the FP16-rounded inputs: relative error
+    of the IBL tables and of linear HDR (distance outside the oracle's
+    interval over its magnitude), absolute error of AO, and the histogram of
+    8-bit distances (in codes) outside the oracle's interval."""
+    view = gpu["view"]
+    ref_ibl = orc.precompute_ibl(view.env, **view.ibl)
+    tables = {"irradiance": _stats(_rel_outside(gpu["irradiance"], ref_ibl["irradiance"][..., :3],
+                                                ref_ibl["irradiance"][..., :3], 1e-30)),
+              "prefiltered": _stats(np.concatenate([
+                  _rel_outside(g, lo[..., :3], hi[..., :3], 1e-30).ravel()
+                  for g, lo, hi in zip(gpu["prefiltered"], ref_ibl["prefiltered"], ref_ibl["prefiltered_hi"])])),
+              "brdf_lut": _stats(_rel_outside(gpu["lut"], ref_ibl["lut"], ref_ibl["lut"], 1e-30))}
+    out = {"workload": "plain-256x256 in the FP16 form (config small), IBL tables float32 with Kahan sums",
+           "ibl_tables_rel": tables}
+    import copy
+    for name, rounded in (("vs_fp32_inputs", False), ("vs_fp16_rounded_inputs", True)):
+        v = copy.deepcopy(view)
+        if rounded:
+            for k in ("normal", "albedo", "roughness", "metalness"):
+                v.gbuf[k] = v.gbuf[k].astype(np.float16).astype(np.float32)
+        ref = orc.render(v, ibl=ref_ibl)
+        hdr_lo, hdr_hi = (np.minimum(x, 65504.0) for x in ref["hdr"])
+        floor = 1e-6 * float(np.abs(hdr_hi).max())
+        ao_err = np.maximum(np.maximum(ref["ao"][0] - gpu["ao"], gpu["ao"] - ref["ao"][1]), 0.0)
+        g = gpu["ldr"][..., :3].astype(np.int32)
+        lo, hi = (x[..., :3].astype(np.int32) for x in ref["ldr"])
+        dist = np.maximum(np.maximum(g - hi, lo - g), 0).max(-1)
+        out[name] = {"hdr_rel": _stats(_rel_outside(gpu["hdr"], hdr_lo, hdr_hi, floor)),
+                     "ao_abs": _stats(ao_err),
+                     "ldr_lsb_histogram": np.bincount(dist.ravel(), minlength=3).tolist()}
+    return out
+
+
+def valu_entry(winst, launch_s):
+    """VALU issue roofline of the shading kernel: counted wavefront
+    instructions per launch over the launch time, against one wavefront
+    instruction per clock per CU."""
+    if not winst:
+        return None
+    achieved = winst / launch_s / 1e9
+    return {"wave_instructions_per_launch": int(winst), "achieved": round(achieved, 1),
+            "peak": VALU_PEAK_GWINST, "unit": "G wave-instr/s", "frac": round(achieved / VALU_PEAK_GWINST, 4)}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -443,12 +528,15 @@ def _cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(view, budget_s: float) -> dict:
-    """The FP64 oracle on the host cores: whole frames (SSAO, blur, shading,
-    bloom + tonemap, without the per-environment precompute) until the time
-    budget is used; Mpix/s over the frames completed.  Then the same on one
-    thread for a third of the budget."""
+def cpu_baseline(view, budget_s: float, fp16_gpu=None):
+    """The oracle leg.  The FP64 oracle on the host cores: whole frames (SSAO,
+    blur, shading, bloom + tonemap, without the per-environment precompute)
+    until the time budget is used; Mpix/s over the frames completed.  Then the
+    same on one thread for a third of the budget.  With ``fp16_gpu`` (the FP16
+    form's outputs on the 256x256 view) the same oracle also states that
+    form's error per output.  Returns (baseline, error statement or None)."""
     from oracle import oracle as orc
+    statement = fp16_error_statement(orc, fp16_gpu) if fp16_gpu is not None else None
     ibl = orc.precompute_ibl(view.env, **dict(view.ibl, pref_samples=64, lut_size=32,
                                               lut_samples=64))
     g = view.gbuf
@@ -478,7 +566,7 @@ def cpu_baseline(view, budget_s: float) -> dict:
             "single_thread_Mpix_s": round(frames1 * px / el1 / 1e6, 3),
             "sample": f"{frames} whole {view.width}x{view.height} frames of the FP64 oracle "
                       f"(SSAO+blur+shade+bloom/tonemap, IBL tables precomputed outside) in {el:.1f} s on "
-                      f"{threads} threads; {frames1} frames in {el1:.1f} s on one thread"}
+                      f"{threads} threads; {frames1} frames in {el1:.1f} s on one thread"}, statement
 
 
 def main():
@@ -499,6 +587,8 @@ def main():
     ap.add_argument("--serve-min-requests", type=int, default=200, help="requests per rate at least")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of request slots")
     ap.add_argument("--serve-saturation", type=int, default=1000, help="requests of the closed-loop run")
+    ap.add_argument("--shared-shadow-maps", action="store_true", help="time frames with one set of shadow maps "
+                    "shared by all copies (the default rotates them with the copies)")
     args = ap.parse_args()
     if args.frames_in_flight < 1 or args.copies % args.frames_in_flight:
         print("--copies must be a positive multiple of --frames-in-flight", file=sys.stderr)
@@ -537,9 +627,10 @@ def main():
         per-frame buffer; HIP events around epb_shade on the launch stream."""
         views = [frame.DeviceView(view, ibl, gdtype=dt, ao_dtype=dt, hdr_dtype=dt)
                  for _ in range(args.copies)]
-        for dv in views[1:]:  # the scene-static shadow maps are shared
-            dv.shadow_maps = views[0].shadow_maps
-            dv.lights = views[0].lights
+        if args.shared_shadow_maps:  # every copy reads the first copy's maps
+            for dv in views[1:]:
+                dv.shadow_maps = views[0].shadow_maps
+                dv.lights = views[0].lights
         for k in range(args.warmup):
             views[k % args.copies].render()
         torch.cuda.synchronize()
@@ -620,12 +711,25 @@ def main():
         e1.record(stream)
         torch.cuda.synchronize()
         launch_ms = e0.elapsed_time(e1) / KS
+        # the same with every copy reading the first copy's shadow maps
+        own = [(dv.shadow_maps, dv.lights) for dv in views]
+        for dv in views[1:]:
+            dv.shadow_maps, dv.lights = views[0].shadow_maps, views[0].lights
+        e0.record(stream)
+        for k in range(KS):
+            views[k % args.copies].shade()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        shared_ms = e0.elapsed_time(e1) / KS
+        for dv, (m, l) in zip(views, own):
+            dv.shadow_maps, dv.lights = m, l
         del views
         torch.cuda.empty_cache()
         return dict(ms_per_step=pipelined_ms, wall_ms=1e3 * wall / K, serial_ms_per_frame=serial_ms,
                     p50=float(np.percentile(step_ms, 50)), p99=float(np.percentile(step_ms, 99)),
                     eager_ms_per_step=eager_ms,
-                    shade_in_frame_ms=float(shade_ms.mean()), shade_ms=launch_ms, shade_launches=KS)
+                    shade_in_frame_ms=float(shade_ms.mean()), shade_ms=launch_ms, shade_launches=KS,
+                    shade_ms_shared_maps=shared_ms)
 
     K = args.steps
     px = view.width * view.height
@@ -690,6 +794,10 @@ def main():
             "frac": round(achieved / HBM_PEAK_GBPS, 4),
             "traffic": counted_shade_traffic(),
             "utilisation": counted_shade_utilisation(),
+            "valu": valu_entry(counted_shade_valu_instructions(), shade_avg_s),
+            "shadow_maps": ("shared by the rotated copies" if args.shared_shadow_maps else
+                            "rotated with the copies (each copy its own four maps)"),
+            "shade_ms_shared_maps": round(plain["shade_ms_shared_maps"], 5),
             "algorithmic_bytes_per_launch": acc["total"],
             "algorithmic_bytes_per_px": round(acc["per_px"], 2),
             "avg_launch_ms": round(1e3 * shade_avg_s, 5),
@@ -703,7 +811,7 @@ def main():
                    "eager_ms_per_step": round(m["eager_ms_per_step"], 5),
                    "eager_Mpix_s": round(px / (m["eager_ms_per_step"] / 1e3) / 1e6, 2),
                    "shade_ms": round(m["shade_ms"], 5), "shade_in_frame_ms": round(m["shade_in_frame_ms"], 5),
-                   "shade_GBps": round(m["shade_GBps"], 1),
+                   "shade_GBps": round(m["shade_GBps"], 1), "shade_ms_shared_maps": round(m["shade_ms_shared_maps"], 5),
                    "shade_bytes_per_px": round(m["shade_bytes_per_px"], 2)}
             for name, m in res.items()
         },
@@ -719,8 +827,10 @@ def main():
     if not args.no_serve:
         out["serving"] = bench_serving(args, torch, E, frame, synth, sched)
     if not args.no_cpu:
+        fp16_gpu = fp16_outputs_256(torch, E, frame, synth)
         log("timing the FP64 oracle on the host cores ...")
-        out["cpu_baseline"] = cpu_baseline(view, args.cpu_budget)
+        out["cpu_baseline"], statement = cpu_baseline(view, args.cpu_budget, fp16_gpu)
+        out["forms"]["fp16"]["error_vs_oracle"] = statement
     print(json.dumps(out), flush=True)
 
 

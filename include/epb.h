@@ -182,16 +182,19 @@ typedef struct {
  * reads a 3x3 texel patch around each shaded point's projection; neighbouring
  * pixels project onto a rotated strip of the map, so in row-major order one
  * wavefront's patch rows fall on many different cache lines.  The tiled form
- * cuts the map into tiles of 6x6 texels and stores each as an 8x8 block of
- * floats that repeats the next two columns and rows (clamped to the map's last
- * column and row): every 3x3 patch then lies inside one block, its three rows
- * 8 floats apart, and a strip of the map covers far fewer lines.
+ * pads the map with a one-texel apron of +inf (empty, so lit), cuts the padded
+ * map into tiles of 6x6 texels and stores each as an 8x8 block of floats that
+ * repeats the next two columns and rows: the patch of any point projecting
+ * inside the map then lies inside one block, its three rows 8 floats apart,
+ * with no border case, and a strip of the map covers far fewer lines.  One
+ * more block of +inf follows the tiles (points outside the map read it).
  *
- *   nx = ceil((w - 2) / 6) tiles across, ny = ceil((h - 2) / 6) down, tiles in
- *   row-major order; float (p nx + q) 64 + 8 j + i (0 <= i, j < 8) holds
- *   map[min(6 p + j, h - 1)][min(6 q + i, w - 1)].
+ *   nx = ceil(w / 6) tiles across, ny = ceil(h / 6) down, tiles in row-major
+ *   order; float (p nx + q) 64 + 8 j + i (0 <= i, j < 8) holds
+ *   map[6 p + j - 1][6 q + i - 1], +inf where that index is outside the map;
+ *   floats 64 nx ny .. 64 nx ny + 63 are +inf.
  *
- * epb_shadow_tiles_bytes(w, h) = 256 nx ny (0 unless 3 <= w, h <=
+ * epb_shadow_tiles_bytes(w, h) = 256 (nx ny + 1) (0 unless 3 <= w, h <=
  * EPB_MAX_IMAGE_SIZE).  epb_shadow_tiles copies the row-major [h][w] `map`
  * into `tiles` (>= epb_shadow_tiles_bytes bytes, not overlapping `map`) on
  * `stream`; a renderer calls it whenever it re-renders a map.  Statuses:

@@ -178,7 +178,9 @@ int build_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, 
             h.bias = L.shadow_bias;
             if (L.shadow_layout != EPB_MAP_ROWS && L.shadow_layout != EPB_MAP_TILES) return EPB_ERR_PARAM;
             h.tiles = L.shadow_layout == EPB_MAP_TILES;
-            h.tile_pitch = h.tiles ? epb::shadow_tiles_plan(h.w, h.h).pitch : 0u;
+            epb::ShadowTilesPlan tp = epb::shadow_tiles_plan(h.w, h.h);
+            h.tile_pitch = h.tiles ? tp.pitch : 0u;
+            h.sentinel = h.tiles ? tp.sentinel : 0u;
         }
     }
     a.irr = ibl->irradiance.data; a.irr_size = ibl->irradiance.size;
@@ -314,7 +316,7 @@ int epb_edl(const float *depth, const void *color, epb_dtype color_dtype, const 
     c.cx = hc.cx; c.cy = hc.cy; c.inv_fx = hc.inv_fx; c.inv_fy = hc.inv_fy;
     c.W = cam->width; c.H = cam->height; c.Wh = (c.W + 1) / 2; c.Hh = (c.H + 1) / 2;
     c.env_size = env ? env->size : 0;
-    c.f_env = (float)c.env_size;
+    c.env_dims = epb::face_dims(c.env_size);
     c.radius = params->radius;
     c.n_dirs = params->n_dirs;
     c.neg_strength_over_n = (float)(-(double)params->strength / params->n_dirs);

@@ -12,6 +12,18 @@
 
 namespace epb {
 
+// Sizes of a face of S x S texels as the bilinear lookups use them; all exact
+// in float.  Kernels take them precomputed (kernel arguments, scalar
+// registers) where S is the same for every lane.
+struct FaceDims {
+    int S;
+    float half, off, hi, hi1;  // S / 2, S / 2 - 1/2, S - 1, S - 2
+};
+__host__ __device__ inline FaceDims face_dims(int S) {
+    float fS = (float)S;
+    return FaceDims{S, 0.5f * fS, 0.5f * fS - 0.5f, fS - 1.0f, fS - 2.0f};
+}
+
 // Rigid camera with precomputed reciprocals.
 struct DevCam {
     float R[9];  // row-major rotation
@@ -33,8 +45,9 @@ struct DevLight {
     int w, h;
     float fw, fh;          // w, h as floats
     float bias;
-    int tiles;             // map in the tiled form (6x6 texels per 8x8 block)
+    int tiles;             // map in the tiled form (6x6 texels per 8x8 block, +inf apron)
     unsigned tile_pitch;   // byte step per row of tiles minus 6 block rows: 256 nx - 192
+    unsigned sentinel;     // byte offset of the tiled form's all-+inf tile
 };
 
 struct SsaoDesc {
@@ -64,7 +77,8 @@ struct ShadeDesc {
     float cx, cy, inv_fx, inv_fy;
     int W, H, Wh, Hh;
     int irr_size, pref_base, pref_levels, lut_size, env_size;
-    float f_irr, f_lut, f_env, f_levels1;  // sizes as floats; f_levels1 = levels - 1
+    FaceDims irr_dims, lut_dims, env_dims;  // sizes of the lookups (host-computed)
+    float f_levels1;                        // levels - 1
     int pref_off[8];                       // texel offset of each prefiltered level
     int n_lights;
     DevLight lights[EPB_MAX_LIGHTS];
@@ -93,7 +107,7 @@ struct EdlDesc {
     float cx, cy, inv_fx, inv_fy;
     int W, H, Wh, Hh;
     int env_size;
-    float f_env;
+    FaceDims env_dims;
     int radius, n_dirs;
     float neg_strength_over_n;  // -strength / n_dirs
     float far_depth;

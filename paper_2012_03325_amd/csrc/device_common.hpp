@@ -126,6 +126,9 @@ __device__ __forceinline__ int floor_to_int(float x) {
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ v3 normalize(v3 a) { return a * rsq(dot(a, a)); }
 __device__ __forceinline__ float clamp01(float x) { return fminf(fmaxf(x, 0.0f), 1.0f); }
+// x clamped to [0, hi] in one instruction (median of three; equal to the
+// min/max pair for every non-NaN x)
+__device__ __forceinline__ float clamp_to(float x, float hi) { return __builtin_amdgcn_fmed3f(x, 0.0f, hi); }
 __device__ __forceinline__ float pow5(float x) {
     float x2 = x * x;
     return x2 * x2 * x;
@@ -170,26 +173,25 @@ __device__ __forceinline__ float4 lerp4(float4 a, float4 b, float w) {
 // Bilinear, clamp-to-edge inside one face of one level (S >= 2).  Clamping
 // the coordinate to [0, S-1] and the left tap to S-2 gives the same result as
 // clamping both taps (at an edge one weight is 0 or 1), and keeps the second
-// column at a fixed +1 offset from the first.  `lvl` is wave-uniform and the
+// column at a fixed +1 offset from the first (taken from the base pointer, so
+// that it folds into the load instructions).  `lvl` is wave-uniform and the
 // texel index a 32-bit offset (24-bit multiplies; S <= 8192).
-__device__ __forceinline__ float4 face_bilinear(const float4 *__restrict__ lvl, unsigned off, int S, float fS,
+__device__ __forceinline__ float4 face_bilinear(const float4 *__restrict__ lvl, unsigned off, const FaceDims &g,
                                                 FaceST f) {
-    float half = 0.5f * fS;
-    float hi = fS - 1.0f;
-    float x = fminf(fmaxf(fmaf(f.s, half, half - 0.5f), 0.0f), hi);
-    float y = fminf(fmaxf(fmaf(f.t, half, half - 0.5f), 0.0f), hi);
-    float x0f = fminf(floorf(x), hi - 1.0f), y0f = fminf(floorf(y), hi - 1.0f);
+    float x = clamp_to(fmaf(f.s, g.half, g.off), g.hi);
+    float y = clamp_to(fmaf(f.t, g.half, g.off), g.hi);
+    float x0f = fminf(floorf(x), g.hi1), y0f = fminf(floorf(y), g.hi1);
     float wx = x - x0f, wy = y - y0f;
     // row of the texel in the level: face S + y0, exact in float (below 2^24)
-    unsigned idx = off + __umul24((unsigned)fmaf(f.face, fS, y0f), (unsigned)S) + (unsigned)x0f;
-    unsigned o0 = idx * 16u, o1 = o0 + (unsigned)S * 16u;
-    float4 a = ldo(lvl, o0), b = ldo(lvl, o0 + 16u);
-    float4 c = ldo(lvl, o1), d = ldo(lvl, o1 + 16u);
+    unsigned idx = off + __umul24((unsigned)fmaf(f.face, (float)g.S, y0f), (unsigned)g.S) + (unsigned)x0f;
+    unsigned o0 = idx * 16u, o1 = o0 + (unsigned)g.S * 16u;
+    float4 a = ldo(lvl, o0), b = ldo(lvl + 1, o0);
+    float4 c = ldo(lvl, o1), d = ldo(lvl + 1, o1);
     return lerp4(lerp4(a, b, wx), lerp4(c, d, wx), wy);
 }
 
-__device__ __forceinline__ float4 cube_bilinear(const float4 *__restrict__ lvl, int S, float fS, v3 d) {
-    return face_bilinear(lvl, 0u, S, fS, cube_face(d));
+__device__ __forceinline__ float4 cube_bilinear(const float4 *__restrict__ lvl, const FaceDims &g, v3 d) {
+    return face_bilinear(lvl, 0u, g, cube_face(d));
 }
 
 // Offset (in texels) of level m of a chain with base size `base`.

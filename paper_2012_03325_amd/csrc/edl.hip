@@ -130,7 +130,7 @@ __global__ void __launch_bounds__(kEdlThreads) k_edl(const EdlDesc c, int tiles)
                 float dvx = ((float)x + 0.5f - c.cx) * c.inv_fx;
                 float dvy = -((float)y + 0.5f - c.cy) * c.inv_fy;
                 v3 dw = mul_Rt(c.R, mk3(dvx, dvy, -1.0f));
-                float4 e = cube_bilinear(c.env, c.env_size, c.f_env, dw);
+                float4 e = cube_bilinear(c.env, c.env_dims, dw);
                 out[0] = shade * e.x; out[1] = shade * e.y; out[2] = shade * e.z;
             }
         } else {

@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(256) k_prefilter_mirror(const float4 *__restri
     if (o >= 6 * sm * sm) return;
     int f = o / (sm * sm), j = (o / sm) % sm, i = o % sm;
     v3 n = normalize(cube_texel_dir(f, i, j, sm));
-    out[o] = cube_bilinear(env, S, (float)S, n);
+    out[o] = cube_bilinear(env, face_dims(S), n);
 }
 
 // One wavefront per prefiltered texel of a level with roughness^2 = alpha > 0.
@@ -151,7 +151,7 @@ __global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ en
     tangent_frame(n, T, B);
     float a2 = alpha * alpha;
     float inv_n = 1.0f / (float)samples;
-    float fS = (float)S;
+    FaceDims dims = face_dims(S);
     Kahan r{0, 0}, g{0, 0}, b{0, 0}, w{0, 0};
     for (int k = lane; k < samples; k += 64) {
         v3 h = ggx_half((float)k * inv_n, radical_inverse2((uint32_t)k), a2, n, T, B);
@@ -159,7 +159,7 @@ __global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ en
         v3 l = h * (2.0f * vh) - n;
         float nl = dot(n, l);
         if (nl > 0.0f) {
-            float4 L = cube_bilinear(env, S, fS, l);
+            float4 L = cube_bilinear(env, dims, l);
             kahan_add(r, L.x * nl);
             kahan_add(g, L.y * nl);
             kahan_add(b, L.z * nl);
@@ -248,8 +248,8 @@ __global__ void __launch_bounds__(256) k_prefilter_fis(const float4 *__restrict_
             float fl = lod - (float)l0;
             FaceST fs = cube_face(l);
             int s0 = S >> l0, s1 = S >> l1;
-            float4 L0 = face_bilinear(chain, chain_offset_pow2(S, l0), s0, (float)s0, fs);
-            float4 L1 = face_bilinear(chain, chain_offset_pow2(S, l1), s1, (float)s1, fs);
+            float4 L0 = face_bilinear(chain, chain_offset_pow2(S, l0), face_dims(s0), fs);
+            float4 L1 = face_bilinear(chain, chain_offset_pow2(S, l1), face_dims(s1), fs);
             float4 L = lerp4(L0, L1, fl);
             kahan_add(r, L.x * nl);
             kahan_add(g, L.y * nl);

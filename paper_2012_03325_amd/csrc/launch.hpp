@@ -82,12 +82,13 @@ ShadeDesc shade_desc(const ShadeArgs &a);
 int shade_items(const ShadeDesc &c, int shade_tile);
 hipError_t launch_shade(const ShadeArgs &a, hipStream_t s);
 
-// Tiled form of a w x h shadow map (w, h >= 3): nx x ny tiles of 6x6 texels,
-// each stored as 8x8 floats; pitch is the DevLight::tile_pitch of the form.
+// Tiled form of a w x h shadow map (w, h >= 3) padded with a +inf apron:
+// nx x ny tiles of 6x6 texels, each stored as 8x8 floats, then one all-+inf
+// tile; pitch and sentinel are DevLight::tile_pitch and DevLight::sentinel.
 struct ShadowTilesPlan {
     int nx, ny;
     size_t bytes;
-    unsigned pitch;
+    unsigned pitch, sentinel;
 };
 ShadowTilesPlan shadow_tiles_plan(int w, int h);
 hipError_t launch_shadow_tiles(const float *map, int w, int h, float *tiles, hipStream_t s);

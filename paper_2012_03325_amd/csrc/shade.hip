@@ -28,29 +28,38 @@ struct Row3 {
     float v[3];
 };
 
-// Bilinear lookup of the (size >= 2) BRDF table, clamp to edge.
-__device__ __forceinline__ float2 lut_bilinear(const float2 *__restrict__ lut, int size, float fsize, float u,
-                                               float v) {
-    float hi = fsize - 1.0f;
-    float fx = fminf(fmaxf(fmaf(u, fsize, -0.5f), 0.0f), hi);
-    float fy = fminf(fmaxf(fmaf(v, fsize, -0.5f), 0.0f), hi);
-    float x0f = fminf(floorf(fx), hi - 1.0f), y0f = fminf(floorf(fy), hi - 1.0f);
+// Bilinear lookup of the (size >= 2) BRDF table, clamp to edge (sizes as for
+// a cube face: the table is one size x size face).
+__device__ __forceinline__ float2 lut_bilinear(const float2 *__restrict__ lut, const FaceDims &g, float u, float v) {
+    float fsize = (float)g.S;
+    float fx = clamp_to(fmaf(u, fsize, -0.5f), g.hi);
+    float fy = clamp_to(fmaf(v, fsize, -0.5f), g.hi);
+    float x0f = fminf(floorf(fx), g.hi1), y0f = fminf(floorf(fy), g.hi1);
     float wx = fx - x0f, wy = fy - y0f;
-    unsigned o0 = (__umul24((unsigned)y0f, (unsigned)size) + (unsigned)x0f) * 8u;
-    unsigned o1 = o0 + (unsigned)size * 8u;
-    float2 a = ldo(lut, o0), b = ldo(lut, o0 + 8u), c = ldo(lut, o1), d = ldo(lut, o1 + 8u);
+    unsigned o0 = (__umul24((unsigned)y0f, (unsigned)g.S) + (unsigned)x0f) * 8u;
+    unsigned o1 = o0 + (unsigned)g.S * 8u;
+    float2 a = ldo(lut, o0), b = ldo(lut + 1, o0), c = ldo(lut, o1), d = ldo(lut + 1, o1);
     float ax = fmaf(wx, b.x - a.x, a.x), ay = fmaf(wx, b.y - a.y, a.y);
     float cx = fmaf(wx, d.x - c.x, c.x), cy = fmaf(wx, d.y - c.y, c.y);
     return make_float2(fmaf(wy, cx - ax, ax), fmaf(wy, cy - ay, ay));
 }
 
 // Lit fraction of the 3x3 patch around the projection of view point Pv
-// (maps of at least 3x3).  One 3x3 block that lies wholly inside the map is
-// fetched through three row pointers (fixed +1/+2 column offsets, all nine
-// loads in flight together); when the true patch sticks out of the map the
-// block is shifted inwards by one texel and the columns/rows that do not belong
-// to the patch are dropped, the missing taps counting as lit.  Points outside
-// the light's frustum are lit.
+// (maps of at least 3x3); points outside the light's frustum are lit.
+//
+// Tiled form: the map is padded with a +inf (lit) apron, so the patch of any
+// point that projects inside the map, top-left texel (i0 - 1, j0 - 1), is the
+// block at padded coordinates (i0, j0) and lies inside one 8x8 stored block
+// (tile (j0 / 6, i0 / 6)); its rows sit at fixed +32/+64-byte offsets, taken
+// from the base pointer so that they fold into the load instructions.  A point
+// outside the map or behind the light reads the form's all-+inf tile: all nine
+// taps lit, no border case and no select of the result.
+//
+// Row-major form: one 3x3 block that lies wholly inside the map is fetched
+// through three row loads (fixed +1/+2 column offsets, all nine loads in
+// flight together); when the true patch sticks out of the map the block is
+// shifted inwards by one texel and the columns/rows that do not belong to the
+// patch are dropped, the missing taps counting as lit.
 __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, float d) {
     // M P_v + o = ((u - cx) d_l, (v - cy) d_l, -d_l) with P_v = d (dvx, dvy, -1)
     v3 Md = mk3(fmaf(L.M[0], dvx, fmaf(L.M[1], dvy, -L.M[2])), fmaf(L.M[3], dvx, fmaf(L.M[4], dvy, -L.M[5])),
@@ -60,30 +69,33 @@ __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, fl
     float idl = rcp(dl);
     float u = fmaf(Pl.x, idl, L.cx);
     float v = fmaf(Pl.y, idl, L.cy);
+    float ref = dl - L.bias;
+    const Row3 *map = reinterpret_cast<const Row3 *>(L.map);
+    if (L.tiles) {
+        // floor-convert: 0 <= u < w exactly when 0 <= floor(u) < w (one unsigned
+        // compare; +-inf saturate outside; u is finite whenever d_l > 0)
+        int i0 = floor_to_int(u), j0 = floor_to_int(v);
+        bool inside = dl > 0.0f && (unsigned)i0 < (unsigned)L.w && (unsigned)j0 < (unsigned)L.h;
+        unsigned x = (unsigned)i0, y = (unsigned)j0;
+        unsigned tq = __umulhi(x, 0x2AAAAAABu), tp = __umulhi(y, 0x2AAAAAABu);  // x / 6, y / 6 (exact below 2^31)
+        unsigned q0 = inside ? __umul24(tp, L.tile_pitch) + __umul24(tq, 232u) + y * 32u + x * 4u : L.sentinel;
+        const char *base = reinterpret_cast<const char *>(L.map);  // wave-uniform: the row offsets are scalar adds
+        Row3 a = ldo(map, q0), b = ldo(reinterpret_cast<const Row3 *>(base + 32), q0),
+             e = ldo(reinterpret_cast<const Row3 *>(base + 64), q0);
+        float t[9] = {a.v[0], a.v[1], a.v[2], b.v[0], b.v[1], b.v[2], e.v[0], e.v[1], e.v[2]};
+        int lit = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) lit += t[k] < ref ? 0 : 1;  // lit iff ref <= t
+        return (float)lit * (1.0f / 9.0f);
+    }
     bool inside = dl > 0.0f && u >= 0.0f && u < L.fw && v >= 0.0f && v < L.fh;
     int i0 = inside ? (int)u : 1, j0 = inside ? (int)v : 1;  // truncation == floor when inside
     int bi = min(max(i0, 1), L.w - 2), bj = min(max(j0, 1), L.h - 2);
     // three 12-byte row loads (dword aligned) cover the 3x3 block
-    const Row3 *map = reinterpret_cast<const Row3 *>(L.map);
-    Row3 a, b, e;
-    if (L.tiles) {
-        // tiled form: the block (x .. x+2, y .. y+2) lies inside tile (y / 6, x / 6),
-        // whose 8x8 floats repeat the next two columns and rows; its rows are 32 bytes apart
-        unsigned x = (unsigned)(bi - 1), y = (unsigned)(bj - 1);
-        unsigned tq = __umulhi(x, 0x2AAAAAABu), tp = __umulhi(y, 0x2AAAAAABu);  // x / 6, y / 6 (exact below 2^31)
-        unsigned q0 = __umul24(tp, L.tile_pitch) + __umul24(tq, 232u) + y * 32u + x * 4u;
-        a = ldo(map, q0);
-        b = ldo(map, q0 + 32u);
-        e = ldo(map, q0 + 64u);
-    } else {
-        unsigned q0 = (__umul24((unsigned)(bj - 1), (unsigned)L.w) + (unsigned)(bi - 1)) * 4u;
-        unsigned row = (unsigned)L.w * 4u;
-        a = ldo(map, q0);
-        b = ldo(map, q0 + row);
-        e = ldo(map, q0 + 2u * row);
-    }
+    unsigned q0 = (__umul24((unsigned)(bj - 1), (unsigned)L.w) + (unsigned)(bi - 1)) * 4u;
+    unsigned row = (unsigned)L.w * 4u;
+    Row3 a = ldo(map, q0), b = ldo(map, q0 + row), e = ldo(map, q0 + 2u * row);
     float t[9] = {a.v[0], a.v[1], a.v[2], b.v[0], b.v[1], b.v[2], e.v[0], e.v[1], e.v[2]};
-    float ref = dl - L.bias;
     int lit = 0;
 #pragma unroll
     for (int k = 0; k < 9; ++k) lit += ref <= t[k] ? 1 : 0;
@@ -114,7 +126,7 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
     float out[3];
     if (__builtin_isinf(d)) {
         v3 dw = mul_Rt(c.R, mk3(dvx, dvy, -1.0f));
-        float4 e = cube_bilinear(c.env, c.env_size, c.f_env, dw);
+        float4 e = cube_bilinear(c.env, c.env_dims, dw);
         out[0] = e.x; out[1] = e.y; out[2] = e.z;
     } else {
         const TG *nrm = (const TG *)c.normal, *alb = (const TG *)c.albedo;
@@ -136,7 +148,7 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
             }
         }
         float nv_raw = dot(n, V);
-        float NoV = fminf(fmaxf(nv_raw, 1e-4f), 1.0f);
+        float NoV = __builtin_amdgcn_fmed3f(nv_raw, 1e-4f, 1.0f);
         float F0[3], cd[3], omF0[3], cdpi[3];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
@@ -189,17 +201,17 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
         }
         // ambient inputs after the light loop: gathered before it, their taps would stay live
         // through the loop (123 VGPRs, 4 waves/SIMD); here the kernel needs 65 (7 waves/SIMD)
-        float2 AB = lut_bilinear(c.lut, c.lut_size, c.f_lut, NoV, r);
-        float4 E = cube_bilinear(c.irr, c.irr_size, c.f_irr, n);
+        float2 AB = lut_bilinear(c.lut, c.lut_dims, NoV, r);
+        float4 E = cube_bilinear(c.irr, c.irr_dims, n);
         v3 Rf = n * (2.0f * nv_raw) - V;
-        float lod = fminf(fmaxf(r * c.f_levels1, 0.0f), c.f_levels1);
+        float lod = clamp_to(r * c.f_levels1, c.f_levels1);
         int l0 = (int)lod;
         int l1 = min(l0 + 1, c.pref_levels - 1);
         float fl = lod - (float)l0;
         FaceST fs = cube_face(Rf);
         int s0 = c.pref_base >> l0, s1 = c.pref_base >> l1;
-        float4 P0 = face_bilinear(c.pref, c.pref_off[l0], s0, (float)s0, fs);
-        float4 P1 = face_bilinear(c.pref, c.pref_off[l1], s1, (float)s1, fs);
+        float4 P0 = face_bilinear(c.pref, c.pref_off[l0], face_dims(s0), fs);
+        float4 P1 = face_bilinear(c.pref, c.pref_off[l1], face_dims(s1), fs);
         float4 P = lerp4(P0, P1, fl);
         float fc5 = pow5(1.0f - NoV);
         float Pc[3] = {P.x, P.y, P.z}, Ec[3] = {E.x, E.y, E.z};
@@ -272,7 +284,7 @@ ShadeDesc shade_desc(const ShadeArgs &a) {
     k.W = a.W; k.H = a.H; k.Wh = (a.W + 1) / 2; k.Hh = (a.H + 1) / 2;
     k.irr_size = a.irr_size; k.pref_base = a.pref_base; k.pref_levels = a.pref_levels;
     k.lut_size = a.lut_size; k.env_size = a.env_size;
-    k.f_irr = (float)a.irr_size; k.f_lut = (float)a.lut_size; k.f_env = (float)a.env_size;
+    k.irr_dims = face_dims(a.irr_size); k.lut_dims = face_dims(a.lut_size); k.env_dims = face_dims(a.env_size);
     k.f_levels1 = (float)(a.pref_levels - 1);
     int off = 0;
     for (int m = 0; m < 8; ++m) {
@@ -332,30 +344,36 @@ hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
 }
 
 // Tiled form of a shadow map: one thread per stored float, one row of tiles per
-// blockIdx.y; consecutive threads write consecutive floats and read runs of 8
-// texels of a map row.
-__global__ void __launch_bounds__(256) k_shadow_tiles(const float *__restrict__ map, int w, int h, int nx,
+// blockIdx.y (the last row holds the all-+inf tile); consecutive threads write
+// consecutive floats and read runs of 8 texels of a map row.  Stored float
+// (p nx + q) 64 + 8 j + i is texel (6 q + i - 1, 6 p + j - 1) of the map, +inf
+// outside it.
+__global__ void __launch_bounds__(256) k_shadow_tiles(const float *__restrict__ map, int w, int h, int nx, int ny,
                                                       float *__restrict__ tiles) {
     unsigned t = blockIdx.x * 256u + threadIdx.x;  // float index inside this row of tiles
-    if (t >= (unsigned)nx * 64u) return;
-    unsigned p = blockIdx.y, q = t >> 6, j = (t >> 3) & 7u, i = t & 7u;
-    unsigned sx = min(6u * q + i, (unsigned)w - 1u), sy = min(6u * p + j, (unsigned)h - 1u);
-    tiles[(size_t)p * nx * 64u + t] = map[(size_t)sy * (unsigned)w + sx];
+    unsigned p = blockIdx.y;
+    if (t >= (p < (unsigned)ny ? (unsigned)nx * 64u : 64u)) return;
+    unsigned q = t >> 6, j = (t >> 3) & 7u, i = t & 7u;
+    int x = (int)(6u * q + i) - 1, y = (int)(6u * p + j) - 1;
+    float v = __builtin_inff();
+    if (p < (unsigned)ny && x >= 0 && x < w && y >= 0 && y < h) v = map[(size_t)y * (unsigned)w + (unsigned)x];
+    tiles[(size_t)p * nx * 64u + t] = v;
 }
 
 ShadowTilesPlan shadow_tiles_plan(int w, int h) {
     ShadowTilesPlan t{};
-    t.nx = ceil_div(w - 2, 6);
-    t.ny = ceil_div(h - 2, 6);
-    t.bytes = (size_t)t.nx * (size_t)t.ny * 256u;
+    t.nx = ceil_div(w, 6);
+    t.ny = ceil_div(h, 6);
+    t.bytes = ((size_t)t.nx * (size_t)t.ny + 1u) * 256u;
     t.pitch = 256u * (unsigned)t.nx - 192u;
+    t.sentinel = (unsigned)t.nx * (unsigned)t.ny * 256u;
     return t;
 }
 
 hipError_t launch_shadow_tiles(const float *map, int w, int h, float *tiles, hipStream_t s) {
     ShadowTilesPlan t = shadow_tiles_plan(w, h);
-    dim3 grid(ceil_div(t.nx * 64, 256), t.ny);
-    k_shadow_tiles<<<grid, 256, 0, s>>>(map, w, h, t.nx, tiles);
+    dim3 grid(ceil_div(t.nx * 64, 256), t.ny + 1);
+    k_shadow_tiles<<<grid, 256, 0, s>>>(map, w, h, t.nx, t.ny, tiles);
     return hipGetLastError();
 }
 

@@ -105,6 +105,8 @@ def test_ssao_validation():
     assert call(g=_gbuf(dt=7)) == E.EPB_ERR_DTYPE
     assert call(g=_gbuf(base=FAKE + 4)) == E.EPB_ERR_ALIGN
     assert call(out=FAKE + 8) == E.EPB_ERR_ALIGN
+    # 16-byte alignment is the rule (not 256): such planes pass on to the next check
+    assert call(g=_gbuf(base=FAKE + 16), out=FAKE + 48, sc=None) == E.EPB_ERR_SCRATCH
     assert call(sc=None) == E.EPB_ERR_SCRATCH
     assert call(n=16) == E.EPB_ERR_SCRATCH
     for bad in (dict(n_samples=0), dict(n_samples=257), dict(radius=0.0), dict(radius=float("nan")),
@@ -180,14 +182,14 @@ def test_shade_validation():
 
 
 def test_shadow_tiles_sizes_and_validation():
-    """Tiles of 6x6 texels stored as 8x8 floats: ceil((w - 2) / 6) x
-    ceil((h - 2) / 6) tiles of 256 bytes."""
+    """Tiles of 6x6 texels of the map padded by one texel of +inf, stored as
+    8x8 floats: ceil(w / 6) x ceil(h / 6) tiles of 256 bytes and one more."""
     nb = E.epb_shadow_tiles_bytes
-    assert nb(2048, 2048) == 341 * 341 * 256
-    assert nb(3, 3) == nb(8, 8) == 256
-    assert nb(9, 8) == 2 * 256 and nb(9, 9) == 4 * 256
-    assert nb(1920, 1080) == 320 * 180 * 256
-    assert nb(16384, 16384) == 2731 * 2731 * 256 < 2 ** 32
+    assert nb(2048, 2048) == (342 * 342 + 1) * 256
+    assert nb(3, 3) == nb(6, 6) == 2 * 256
+    assert nb(7, 6) == 3 * 256 and nb(7, 7) == 5 * 256
+    assert nb(1920, 1080) == (320 * 180 + 1) * 256
+    assert nb(16384, 16384) == (2731 * 2731 + 1) * 256 < 2 ** 32
     assert nb(2, 9) == nb(9, 2) == nb(16385, 9) == nb(-1, 9) == 0
     need = nb(64, 48)
 

@@ -30,14 +30,16 @@ def _gpu():
 
 def _tiles_by_definition(m: np.ndarray) -> np.ndarray:
     """Tile (p, q) element (j, i) at (p nx + q) 64 + 8 j + i holds
-    m[min(6 p + j, h - 1), min(6 q + i, w - 1)]."""
+    m[6 p + j - 1, 6 q + i - 1], +inf outside the map; then 64 floats of +inf."""
     h, w = m.shape
-    nx, ny = -(-(w - 2) // 6), -(-(h - 2) // 6)
+    nx, ny = -(-w // 6), -(-h // 6)
+    pad = np.full((6 * ny + 2, 6 * nx + 2), np.inf, np.float32)
+    pad[1:h + 1, 1:w + 1] = m
     p = np.arange(ny)[:, None, None, None]
     q = np.arange(nx)[None, :, None, None]
     j = np.arange(8)[None, None, :, None]
     i = np.arange(8)[None, None, None, :]
-    return m[np.minimum(6 * p + j, h - 1), np.minimum(6 * q + i, w - 1)].reshape(-1)
+    return np.concatenate([pad[6 * p + j, 6 * q + i].reshape(-1), np.full(64, np.inf, np.float32)])
 
 
 @pytest.mark.parametrize("w,h", [(3, 3), (8, 8), (9, 9), (7, 5), (13, 11), (64, 48), (1000, 3), (2048, 2048)])
