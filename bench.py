@@ -378,16 +378,20 @@ def bench_serving(args, torch, E, frame, synth, schedule=None) -> dict:
         return S.Server(ex, budget, max_batch_views=max_views, max_inflight=3)
 
     rates = []
-    for k, rate in enumerate((50, 100, 200, 500, 1000, 2000)):
+    # the paper-workload rates (50..2000 req/s) and on through the batched server's
+    # capacity (~30 Gpix/s over 2.685 Mpx per request: ~11,000 req/s), where requests
+    # queue, batches fill and the latency tail bends
+    for k, rate in enumerate(args.serve_rates):
         dur = min(10.0, max(args.serve_seconds, args.serve_min_requests / rate))
         reqs = S.poisson_arrivals(float(rate), 400 + k, 32, synth.SERVING_RESOLUTIONS, duration=dur)
         srv = server(rs.templates)
         st = srv.run(reqs, S.RealClock())
         srv.pool.clear()
+        offered = sum(r.px for r in reqs) / dur / 1e6
         rates.append(dict(rate=rate, duration_s=round(dur, 2), requests=st["requests"],
                           p50_ms=round(st["p50_ms"], 3), p99_ms=round(st["p99_ms"], 3),
                           mean_ms=round(st["mean_ms"], 3), Mpix_s=round(st["Mpix_s"], 1),
-                          offered_Mpix_s=round(sum(r.px for r in reqs) / dur / 1e6, 1),
+                          offered_Mpix_s=round(offered, 1), served_over_offered=round(st["Mpix_s"] / offered, 3),
                           mean_batch_views=round(st["mean_batch_views"], 2),
                           peak_reserved_GB=round(st["peak_reserved_bytes"] / 1e9, 3)))
         log(f"serving {rate} req/s: {rates[-1]}")
@@ -587,6 +591,9 @@ def main():
     ap.add_argument("--serve-min-requests", type=int, default=200, help="requests per rate at least")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of request slots")
     ap.add_argument("--serve-saturation", type=int, default=1000, help="requests of the closed-loop run")
+    ap.add_argument("--serve-rates", type=float, nargs="+",
+                    default=[50, 100, 200, 500, 1000, 2000, 4000, 6000, 8000, 10000, 12000, 16000],
+                    help="Poisson arrival rates (requests/s) of the serving sweep")
     ap.add_argument("--shared-shadow-maps", action="store_true", help="time frames with one set of shadow maps "
                     "shared by all copies (the default rotates them with the copies)")
     args = ap.parse_args()
