@@ -327,6 +327,8 @@ def bench_batched(args, torch, E, frame, synth) -> dict:
             "batched_ms": round(mean_ms, 4), "batched_p50_ms": round(med_ms, 4),
             "batched_default_schedule_ms": round(default_ms, 4),
             "schedule": tuned, "autotune_tried": len(trace),
+            "autotune_trials_ms": [[*(t["schedule"][k] for k in autotune.ORDER), round(t["ms"], 4)] for t in trace],
+            "autotune_trial_fields": [*autotune.ORDER, "ms"],
             "plain_eager_Mpix_s": round(px / (plain_ms / 1e3) / 1e6, 2), "plain_eager_ms": round(plain_ms, 4),
             "plain_graph_Mpix_s": round(px / (plain_graph_ms / 1e3) / 1e6, 2),
             "plain_graph_ms": round(plain_graph_ms, 4),

@@ -401,7 +401,9 @@ typedef struct {
  * output value is computed by the same arithmetic whatever the shape. */
 typedef struct {
     int32_t shade_tile;    /* shading pixel tile: 0 = 32x8, 1 = 64x4, 2 = 16x16 */
-    int32_t ssao_tile;     /* SSAO half-resolution tile: 0 = 16x8, 1 = 32x4     */
+    int32_t ssao_tile;     /* SSAO half-resolution tile: 0 = 16x8, 1 = 32x4,
+                              2 = 16x16, its depth and a 32-texel halo staged
+                              in LDS                                          */
     int32_t ssao_batch;    /* SSAO depth gathers in flight: 0 = 8, 1 = 16        */
     int32_t blocks_per_cu; /* 0: one workgroup per work item; k in 1..64: a
                               persistent grid of k workgroups per compute unit  */

@@ -27,7 +27,7 @@ from . import epb as E
 SPACE: Dict[str, Tuple[int, ...]] = {
     "blocks_per_cu": (0, 1, 2, 4, 8),
     "shade_tile": (0, 1, 2),
-    "ssao_tile": (0, 1),
+    "ssao_tile": (0, 1, 2),
     "ssao_batch": (0, 1),
 }
 ORDER = ("blocks_per_cu", "shade_tile", "ssao_tile", "ssao_batch")

@@ -260,7 +260,7 @@ int batch_scratch(const epb_view *views, int32_t n, size_t *bytes) {
 }
 
 int check_schedule(const epb_schedule &q) {
-    if (q.shade_tile < 0 || q.shade_tile > 2 || q.ssao_tile < 0 || q.ssao_tile > 1 || q.ssao_batch < 0 ||
+    if (q.shade_tile < 0 || q.shade_tile > 2 || q.ssao_tile < 0 || q.ssao_tile > 2 || q.ssao_batch < 0 ||
         q.ssao_batch > 1 || q.blocks_per_cu < 0 || q.blocks_per_cu > 64)
         return EPB_ERR_PARAM;
     return EPB_OK;

@@ -146,7 +146,9 @@ struct TileShape {
     int tx, ty;
 };
 constexpr TileShape kShadeTiles[3] = {{32, 8}, {64, 4}, {16, 16}};
-constexpr TileShape kSsaoTiles[2] = {{16, 8}, {32, 4}};
+constexpr TileShape kSsaoTiles[3] = {{16, 8}, {32, 4}, {16, 16}};  // the last one stages its window in LDS
+constexpr int kSsaoLdsTile = 16, kSsaoHalo = 32;                     // LDS variant: tile and halo
+constexpr int kSsaoLdsW = kSsaoLdsTile + 2 * kSsaoHalo;             // window side: 80 texels, 25.6 KB
 constexpr int kSsaoBatches[2] = {8, 16};
 
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

@@ -55,14 +55,26 @@ struct SsaoPix {
     float d, dpb, hx0, hy0;  // own depth, d + bias, own half-resolution coordinates + 1/2
 };
 
+// Half-resolution depth staged in LDS for a tile and its halo: lds[ly * kSsaoLdsW + lx]
+// holds texel (ox + lx, oy + ly) of the compact plane (clamped to the image:
+// entries outside it are never used, a sample landing there is discarded).
+struct LdsWindow {
+    const float *lds;
+    int ox, oy;
+};
+
 // KB samples of one pixel: all gathers issued before any is used.  `kern` points
 // at the batch's first kernel vector; with `ragged`, only the first `m` samples
-// exist (the others repeat the last one and are discarded).
-template <int KB, bool ragged>
+// exist (the others repeat the last one and are discarded).  With kLds, a sample
+// inside the LDS window reads it there; the lanes with a kept sample outside it
+// read all KB from the plane in L2 (the same texels, so the same values).
+template <int KB, bool ragged, bool kLds>
 __device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const ConstFloat *kern, int m, const SsaoPix &q,
-                                            __amdgpu_buffer_rsrc_t hdepth, float occ) {
+                                            __amdgpu_buffer_rsrc_t hdepth, LdsWindow win, float occ) {
     float ds[KB], es[KB];
     bool ok[KB];
+    unsigned off[KB];
+    bool miss = false;
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
         int k = ragged ? min(b, m - 1) : b;  // wave-uniform: scalar loads
@@ -79,8 +91,22 @@ __device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const ConstFloat 
         ok[b] = (!ragged || b < m) && zq > 0.0f && (unsigned)ix < (unsigned)c.Wh && (unsigned)iy < (unsigned)c.Hh;
         // unchecked offset: when !ok it may point anywhere (a load past the plane
         // reads 0, one inside it an unrelated texel) and the sample is discarded
-        ds[b] = buf_ldf(hdepth, (__umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix) * 4u);
+        off[b] = (__umul24((unsigned)iy, (unsigned)c.Wh) + (unsigned)ix) * 4u;
+        if constexpr (kLds) {
+            unsigned lx = (unsigned)(ix - win.ox), ly = (unsigned)(iy - win.oy);
+            bool in = max(lx, ly) < (unsigned)kSsaoLdsW;
+            ds[b] = win.lds[in ? __umul24(ly, (unsigned)kSsaoLdsW) + lx : 0u];
+            miss |= ok[b] && !in;
+        } else {
+            ds[b] = buf_ldf(hdepth, off[b]);
+        }
         es[b] = e;
+    }
+    if constexpr (kLds) {
+        if (miss) {
+#pragma unroll
+            for (int b = 0; b < KB; ++b) ds[b] = buf_ldf(hdepth, off[b]);
+        }
     }
 #pragma unroll
     for (int b = 0; b < KB; ++b) {
@@ -93,22 +119,11 @@ __device__ __forceinline__ float ssao_batch(const SsaoDesc &c, const ConstFloat 
     return occ;
 }
 
-template <int TX, int TY, int KB, typename TG, typename TA>
-__device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
-    int tiles_x = (c.Wh + TX - 1) / TX;
-    int ty = tile / tiles_x;
-    int i = (tile - ty * tiles_x) * TX + (int)(threadIdx.x % TX);
-    int j = ty * TY + (int)(threadIdx.x / TX);
-    if (i >= c.Wh || j >= c.Hh) return;
+// Raw AO of half-resolution texel (i, j), whose pixel (2i, 2j) at plane index p
+// has the finite depth d: the kernel's samples in batches of KB.
+template <int KB, bool kLds, typename TG>
+__device__ __forceinline__ float ssao_texel(const SsaoDesc &c, int i, int j, unsigned p, float d, LdsWindow win) {
     int x = 2 * i, y = 2 * j;
-    unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
-    float d = ldf(c.depth, p);
-    unsigned o = __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i;
-    TA *out = (TA *)c.raw;
-    if (__builtin_isinf(d)) {
-        stf(out, o, 1.0f);
-        return;
-    }
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
     const TG *normal = (const TG *)c.normal;
     // view-ray slopes of the pixel (its point is d (ax, ay, -1)) and view-space normal
@@ -139,10 +154,55 @@ __device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
     int nfull = c.n - c.n % KB;
     const ConstFloat *kern = as_constant(c.kernel);
     for (int k0 = 0; k0 < nfull; k0 += KB)
-        occ = ssao_batch<KB, false>(c, kern + 3 * k0, KB, q, hdepth, occ);
+        occ = ssao_batch<KB, false, kLds>(c, kern + 3 * k0, KB, q, hdepth, win, occ);
     if (nfull < c.n)
-        occ = ssao_batch<KB, true>(c, kern + 3 * nfull, c.n - nfull, q, hdepth, occ);
-    stf(out, o, 1.0f - occ * c.inv_n);
+        occ = ssao_batch<KB, true, kLds>(c, kern + 3 * nfull, c.n - nfull, q, hdepth, win, occ);
+    return 1.0f - occ * c.inv_n;
+}
+
+template <int TX, int TY, int KB, typename TG, typename TA>
+__device__ __forceinline__ void ssao_raw_tile(const SsaoDesc &c, int tile) {
+    int tiles_x = (c.Wh + TX - 1) / TX;
+    int ty = tile / tiles_x;
+    int i = (tile - ty * tiles_x) * TX + (int)(threadIdx.x % TX);
+    int j = ty * TY + (int)(threadIdx.x / TX);
+    if (i >= c.Wh || j >= c.Hh) return;
+    unsigned p = __umul24((unsigned)(2 * j), (unsigned)c.W) + (unsigned)(2 * i);
+    float d = ldf(c.depth, p);
+    unsigned o = __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i;
+    stf((TA *)c.raw, o, __builtin_isinf(d) ? 1.0f : ssao_texel<KB, false, TG>(c, i, j, p, d, LdsWindow{}));
+}
+
+// The LDS-staged variant: a kSsaoLdsTile^2 tile stages its footprint and a
+// kSsaoHalo-texel halo of the compact depth plane (kSsaoLdsW^2 floats), then
+// samples as above.  Every thread reaches both barriers; the first one also
+// keeps a persistent block from overwriting the window that the previous item
+// still reads.
+template <int KB, typename TG, typename TA>
+__device__ __forceinline__ void ssao_raw_tile_lds(const SsaoDesc &c, int tile, float *lds) {
+    constexpr int T = kSsaoLdsTile, NT = T * T, N = kSsaoLdsW * kSsaoLdsW, IT = N / NT;
+    static_assert(N % NT == 0, "the window is whole rounds of the block");
+    int tiles_x = (c.Wh + T - 1) / T;
+    int ty = tile / tiles_x;
+    LdsWindow win{lds, (tile - ty * tiles_x) * T - kSsaoHalo, ty * T - kSsaoHalo};
+    float st[IT];
+#pragma unroll
+    for (int k = 0; k < IT; ++k) {  // all loads in flight before the first store
+        int q = (int)threadIdx.x + NT * k;
+        int ly = q / kSsaoLdsW, lx = q - ly * kSsaoLdsW;
+        int gi = min(max(win.ox + lx, 0), c.Wh - 1), gj = min(max(win.oy + ly, 0), c.Hh - 1);
+        st[k] = ldf(c.hdepth, __umul24((unsigned)gj, (unsigned)c.Wh) + (unsigned)gi);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < IT; ++k) lds[(int)threadIdx.x + NT * k] = st[k];
+    __syncthreads();
+    int i = win.ox + kSsaoHalo + (int)(threadIdx.x % T), j = win.oy + kSsaoHalo + (int)(threadIdx.x / T);
+    if (i >= c.Wh || j >= c.Hh) return;
+    unsigned p = __umul24((unsigned)(2 * j), (unsigned)c.W) + (unsigned)(2 * i);
+    float d = ldf(c.depth, p);
+    unsigned o = __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i;
+    stf((TA *)c.raw, o, __builtin_isinf(d) ? 1.0f : ssao_texel<KB, true, TG>(c, i, j, p, d, win));
 }
 
 // LDS rows of the blur footprint (11 rows of 19) plus padding, so that every
@@ -247,6 +307,20 @@ __global__ void __launch_bounds__(TX *TY) k_ssao_raw_batch(const void *__restric
         int g = w.first + it;
         int v = find_view(start, h->n_views, g);
         ssao_raw_tile<TX, TY, KB, TG, TA>(views[v].ssao, g - start[v]);
+    }
+}
+
+template <int KB, typename TG, typename TA>
+__global__ void __launch_bounds__(kSsaoLdsTile *kSsaoLdsTile) k_ssao_raw_batch_lds(const void *__restrict__ table) {
+    __shared__ float lds[kSsaoLdsW * kSsaoLdsW];
+    const BatchHeader *h = (const BatchHeader *)table;
+    const int *start = batch_start(table, kStRaw);
+    const ViewDesc *views = batch_views(table);
+    XcdRange w = xcd_range(h->total[kStRaw]);
+    for (int it = w.lb; it < w.count; it += w.stride) {  // the bounds are block-uniform
+        int g = w.first + it;
+        int v = find_view(start, h->n_views, g);
+        ssao_raw_tile_lds<KB, TG, TA>(views[v].ssao, g - start[v], lds);
     }
 }
 
@@ -393,13 +467,22 @@ static void go_raw_batch(const BatchHeader &h, const void *table, hipStream_t s)
     hipLaunchKernelGGL((k_ssao_raw_batch<TX, TY, KB, TG, TA>), dim3(grid), dim3(TX * TY), 0, s, table);
 }
 
+template <int KB, typename TG, typename TA>
+static void go_raw_batch_lds(const BatchHeader &h, const void *table, hipStream_t s) {
+    int grid = batch_grid(h.total[kStRaw], h.blocks_per_cu);
+    hipLaunchKernelGGL((k_ssao_raw_batch_lds<KB, TG, TA>), dim3(grid), dim3(kSsaoLdsTile * kSsaoLdsTile), 0, s,
+                       table);
+}
+
 template <typename TG, typename TA>
 static void pick_raw_batch(const BatchHeader &h, const void *table, hipStream_t s) {
     int shape = h.ssao_tile, kb = h.ssao_batch;
     if (shape == 0 && kb == 0) go_raw_batch<16, 8, 8, TG, TA>(h, table, s);
     else if (shape == 0) go_raw_batch<16, 8, 16, TG, TA>(h, table, s);
-    else if (kb == 0) go_raw_batch<32, 4, 8, TG, TA>(h, table, s);
-    else go_raw_batch<32, 4, 16, TG, TA>(h, table, s);
+    else if (shape == 1 && kb == 0) go_raw_batch<32, 4, 8, TG, TA>(h, table, s);
+    else if (shape == 1) go_raw_batch<32, 4, 16, TG, TA>(h, table, s);
+    else if (kb == 0) go_raw_batch_lds<8, TG, TA>(h, table, s);
+    else go_raw_batch_lds<16, TG, TA>(h, table, s);
 }
 
 hipError_t launch_ssao_batch(const BatchHeader &h, const void *table, hipStream_t s) {

@@ -342,7 +342,7 @@ def test_batch_build_validation():
     assert b.build(sc_bytes=16) == E.EPB_ERR_SCRATCH
     assert b.build(sc=FAKE + 4) == E.EPB_ERR_ALIGN
     assert b.build(table_bytes=64) == E.EPB_ERR_SIZE
-    for bad in (E.epb_schedule(3, 0, 0, 0), E.epb_schedule(0, 2, 0, 0), E.epb_schedule(0, 0, 2, 0),
+    for bad in (E.epb_schedule(3, 0, 0, 0), E.epb_schedule(0, 3, 0, 0), E.epb_schedule(0, 0, 2, 0),
                 E.epb_schedule(0, 0, 0, 65), E.epb_schedule(-1, 0, 0, 0)):
         assert b.build(sched=bad) == E.EPB_ERR_PARAM
     assert b.build(sched=E.epb_schedule(2, 1, 1, 4)) == E.EPB_OK

@@ -42,6 +42,9 @@ def _views():
                  for w, h, s, n in SIZES]
         views[4] = synth.surfel_accumulate(views[4], seed=41)  # one surfel-splatted G-buffer
         views[1].tonemap = 1  # one view tone-mapped with Reinhard instead of ACES
+        # a wide SSAO radius: many samples land beyond the 32-texel halo of the LDS
+        # window (read from the plane in L2 instead)
+        views[0].ssao_radius = 2.5
         _cache["views"] = views
     return [copy.deepcopy(v) for v in _cache["views"]]
 
@@ -75,7 +78,9 @@ def _assert_same(a, b, what):
             assert torch.equal(p, q), f"{what}: view {k} ({SIZES[k][:2]}) {name} differs"
 
 
-SCHEDULES = [(0, 0, 0, 0), (1, 1, 1, 2), (2, 0, 1, 4), (0, 1, 0, 1), (1, 0, 0, 8)]
+# (shade tile, SSAO tile, SSAO gathers in flight, blocks per CU); SSAO tile 2 stages
+# its depth window in LDS
+SCHEDULES = [(0, 0, 0, 0), (1, 1, 1, 2), (2, 0, 1, 4), (0, 1, 0, 1), (1, 0, 0, 8), (0, 2, 0, 0), (2, 2, 1, 2)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "sched-" + "-".join(map(str, s)))
