@@ -631,9 +631,11 @@ def main():
     torch.cuda.synchronize()
     ibl_ms = ev[0].elapsed_time(ev[1]) / reps
 
-    def measure(dt):
+    def measure(dt, fused=False):
         """Time K frames of one storage form over rotated copies of every
-        per-frame buffer; HIP events around epb_shade on the launch stream."""
+        per-frame buffer; HIP events around epb_shade on the launch stream.
+        fused: the frame's shading and bloom through epb_shade_post (bloom level
+        1 formed in the shading pass; the same outputs bit for bit)."""
         views = [frame.DeviceView(view, ibl, gdtype=dt, ao_dtype=dt, hdr_dtype=dt)
                  for _ in range(args.copies)]
         if args.shared_shadow_maps:  # every copy reads the first copy's maps
@@ -641,7 +643,7 @@ def main():
                 dv.shadow_maps = views[0].shadow_maps
                 dv.lights = views[0].lights
         for k in range(args.warmup):
-            views[k % args.copies].render()
+            views[k % args.copies].render(fused=fused)
         torch.cuda.synchronize()
         K = args.steps
         # eager frames, with events around the shading call
@@ -654,9 +656,13 @@ def main():
             dv = views[k % args.copies]
             dv.ssao()
             sh0[k].record(stream)
-            dv.shade()
-            sh1[k].record(stream)
-            dv.bloom_tonemap()
+            if fused:
+                dv.shade_post()
+                sh1[k].record(stream)
+            else:
+                dv.shade()
+                sh1[k].record(stream)
+                dv.bloom_tonemap()
             marks[k + 1].record(stream)
         torch.cuda.synchronize()
         eager_ms = marks[0].elapsed_time(marks[K]) / K
@@ -668,12 +674,12 @@ def main():
         for dv in views:
             side.wait_stream(stream)
             with torch.cuda.stream(side):
-                dv.render()
+                dv.render(fused=fused)
             stream.wait_stream(side)
             torch.cuda.synchronize()
             g = torch.cuda.CUDAGraph()
             with torch.cuda.graph(g):
-                dv.render()
+                dv.render(fused=fused)
             graphs.append(g)
         for k in range(args.warmup):
             graphs[k % args.copies].replay()
@@ -744,8 +750,9 @@ def main():
     px = view.width * view.height
     shadow = shadow_texels_touched(view)
     res = {}
-    for name, dt in (("fp32", E.EPB_F32), ("fp16", E.EPB_F16)):
-        m = measure(dt)
+    for name, dt, fused in (("fp32", E.EPB_F32, False), ("fp16", E.EPB_F16, False),
+                            ("fp32_fused", E.EPB_F32, True), ("fp16_fused", E.EPB_F16, True)):
+        m = measure(dt, fused)
         acc = shade_algorithmic_bytes(view, ibl, half=(dt == E.EPB_F16), shadow=shadow)
         m["shade_GBps"] = acc["total"] / (m["shade_ms"] / 1e3) / 1e9
         m["shade_bytes"] = acc["total"]

@@ -16,6 +16,9 @@
  *   epb_bloom_tonemap   -- bright-map pyramid bloom, ACES, gamma, 8 bit
  *                          (Sec. 5.3, 5.4)
  *
+ * epb_shade_post runs the last two as one call, forming bloom level 1 inside
+ * the shading pass (bitwise the same results).
+ *
  * Beside them: a batched form of the per-frame calls, a device ray caster of
  * sphere fields (the G-buffer and shadow-map pass before shading) and
  * eye-dome lighting, the compositing step of depth-only point-cloud renders
@@ -346,7 +349,9 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao,
  *             return its first part holds the blurred levels 1 .. L-1, each
  *             [H_l][W_l][4] of params->pyr_dtype (RGB + unused), level after level
  *
- * Bright map b = c max(Y - threshold, 0) / Y (Rec. 709 luminance Y); level l
+ * Bright map b = c max(Y - threshold, 0) / Y (Rec. 709 luminance Y, the
+ * division as a float32 reciprocal; pixels with Y below 2^-126 add nothing);
+ * level 1 sums each 2x2 block as two horizontal pairs, then the rows; level l
  * of size ceil(W / 2^l) x ceil(H / 2^l) is the mean of the in-range children of
  * level l - 1; levels 1 .. L-1 are blurred with the separable [1 4 6 4 1] / 16
  * kernel (clamp to edge) and added, times strength, bilinearly upsampled; the
@@ -357,6 +362,21 @@ int epb_shade(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao,
 int epb_bloom_tonemap(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32_t height,
                       const epb_post_params *params, uint8_t *ldr_out, void *scratch,
                       size_t scratch_bytes, hipStream_t stream);
+
+/*
+ * epb_shade_post -- epb_shade followed by epb_bloom_tonemap in one call, with
+ * level 1 of the bloom pyramid (Sec. 5.3) formed in the shading pass: each
+ * 2x2 block of shaded pixels is bright-passed and averaged from the HDR values
+ * as stored while they are still in registers, so the bloom pass does not read
+ * the HDR image back to build it.  Arguments are those of the two calls (the
+ * bloom pass takes W, H from cam and its HDR input is hdr_out); the same
+ * validation and statuses.  hdr_out, ldr_out and scratch hold bitwise what
+ * epb_shade then epb_bloom_tonemap leave there.
+ */
+int epb_shade_post(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, epb_dtype ao_dtype,
+                   const epb_light *lights, int32_t n_lights, const epb_ibl_maps *ibl, const epb_cube *env,
+                   void *hdr_out, epb_dtype hdr_dtype, const epb_post_params *params, uint8_t *ldr_out,
+                   void *scratch, size_t scratch_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
  * Batched form: the whole pass (SSAO, shading, bloom and tone mapping) of many

@@ -440,6 +440,21 @@ int epb_bloom_tonemap(const void *hdr, epb_dtype hdr_dtype, int32_t width, int32
     return hip_status(epb::launch_bloom_tonemap(d, hdr_dtype, params->pyr_dtype, stream));
 }
 
+int epb_shade_post(const epb_gbuffer *gbuf, const epb_camera *cam, const void *ao, epb_dtype ao_dtype,
+                   const epb_light *lights, int32_t n_lights, const epb_ibl_maps *ibl, const epb_cube *env,
+                   void *hdr_out, epb_dtype hdr_dtype, const epb_post_params *params, uint8_t *ldr_out,
+                   void *scratch, size_t scratch_bytes, hipStream_t stream) {
+    epb::ShadeArgs a;
+    int st = build_shade(gbuf, cam, ao, ao_dtype, lights, n_lights, ibl, env, hdr_out, hdr_dtype, &a);
+    if (st) return st;
+    epb::PostDesc d;
+    if ((st = build_post(hdr_out, hdr_dtype, cam->width, cam->height, params, ldr_out, scratch, scratch_bytes, &d)))
+        return st;
+    hipError_t e = epb::launch_shade(a, stream, &d);
+    if (e != hipSuccess) return hip_status(e);
+    return hip_status(epb::launch_bloom_tonemap(d, hdr_dtype, params->pyr_dtype, stream, d.nl >= 1));
+}
+
 size_t epb_batch_table_bytes(int32_t n_views) {
     if (n_views < 1 || n_views > EPB_MAX_BATCH_VIEWS) return 0;
     return epb::batch_table_bytes(n_views);

@@ -82,10 +82,14 @@ struct ShadeDesc {
     int pref_off[8];                       // texel offset of each prefiltered level
     int n_lights;
     DevLight lights[EPB_MAX_LIGHTS];
+    void *bloom1;           // bloom level 1, written by the fused form; null otherwise
+    int bloom1_half;        // its texels are four halves (else float4)
+    float bloom_threshold;
 };
 
 struct PostDesc {
     int W, H, nl;  // nl = number of pyramid levels >= 1
+    int texel_half;  // pyramid texels are four halves (else float4)
     int lw[EPB_MAX_BLOOM_LEVELS], lh[EPB_MAX_BLOOM_LEVELS];
     void *raw[EPB_MAX_BLOOM_LEVELS];   // unblurred level texels (pyramid storage type)
     void *blur[EPB_MAX_BLOOM_LEVELS];  // blurred level texels

@@ -243,6 +243,73 @@ __device__ __forceinline__ float wave_sum_compensated(float v) {
 }
 
 // ---------------------------------------------------------------------------
+// bloom bright pass and the 2x2 sums of its first level
+// ---------------------------------------------------------------------------
+// Pyramid texel storage: float4, or four halves (saturating at 65504).
+struct alignas(8) Half4 {
+    __half x, y, z, w;
+};
+__device__ __forceinline__ float4 unpack(float4 v) { return v; }
+__device__ __forceinline__ float4 unpack(Half4 v) {
+    return make_float4(__half2float(v.x), __half2float(v.y), __half2float(v.z), 0.0f);
+}
+template <typename TP> __device__ __forceinline__ TP pack(float4 v);
+template <> __device__ __forceinline__ float4 pack<float4>(float4 v) { return v; }
+template <> __device__ __forceinline__ Half4 pack<Half4>(float4 v) {
+    Half4 h;
+    h.x = __float2half_rn(fminf(v.x, 65504.0f));
+    h.y = __float2half_rn(fminf(v.y, 65504.0f));
+    h.z = __float2half_rn(fminf(v.z, 65504.0f));
+    h.w = __float2half_rn(0.0f);
+    return h;
+}
+
+__device__ __forceinline__ Half4 pack_half4(float4 v) { return pack<Half4>(v); }
+
+// The value that storing v to a buffer of T leaves there, read back as float.
+__device__ __forceinline__ float stored_as(float v, const float *) { return v; }
+__device__ __forceinline__ float stored_as(float v, const __half *) {
+    return __half2float(__float2half_rn(fminf(v, 65504.0f)));
+}
+
+// Bright-pass weight max(Y - threshold, 0) / Y of a pixel (Rec. 709 luminance
+// Y), with a reciprocal; a luminance below the smallest normal float blooms
+// nothing (its reciprocal would overflow).
+__device__ __forceinline__ float bright_scale(float r, float g, float b, float threshold) {
+    float Y = fmaf(0.2126f, r, fmaf(0.7152f, g, 0.0722f * b));
+    float m = Y - threshold;
+    return m > 0.0f && Y >= 1.17549435e-38f ? m * rcp(Y) : 0.0f;
+}
+
+// v plus the value of the neighbouring lane (lanes 2k and 2k + 1 pair up);
+// both lanes get the same sum.
+__device__ __forceinline__ float add_lane_pair(float v) {
+    int n = __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, true);  // quad_perm 1,0,3,2
+    return v + __builtin_bit_cast(float, n);
+}
+
+// v plus the value of lane l ^ S, S = 16 or 32: the lane's row of S lanes and
+// the paired row (rows 2k and 2k + 1).  A permlane swap of v with itself puts
+// the even row's values in the first result and the odd row's in the second.
+// (The results are copied out before the bit casts: a bit cast of a vector
+// element reads element 0 with this compiler.)
+template <int S>
+__device__ __forceinline__ float add_row_pair(float v) {
+    static_assert(S == 16 || S == 32, "rows of 16 or 32 lanes");
+    unsigned u = __builtin_bit_cast(unsigned, v), even, odd;
+    if constexpr (S == 32) {
+        auto p = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+        even = p[0];
+        odd = p[1];
+    } else {
+        auto p = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+        even = p[0];
+        odd = p[1];
+    }
+    return __builtin_bit_cast(float, even) + __builtin_bit_cast(float, odd);
+}
+
+// ---------------------------------------------------------------------------
 // launch order: consecutive tiles go to the same XCD (own L2)
 // ---------------------------------------------------------------------------
 // The dispatcher hands workgroup b to XCD b % 8.  Remap so that XCD k

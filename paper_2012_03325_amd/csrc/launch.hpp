@@ -80,7 +80,8 @@ struct ShadeArgs {
 };
 ShadeDesc shade_desc(const ShadeArgs &a);
 int shade_items(const ShadeDesc &c, int shade_tile);
-hipError_t launch_shade(const ShadeArgs &a, hipStream_t s);
+// with `bloom` (the fused form), level 1 of its pyramid is written as well
+hipError_t launch_shade(const ShadeArgs &a, hipStream_t s, const PostDesc *bloom = nullptr);
 
 // Tiled form of a w x h shadow map (w, h >= 3) padded with a +inf apron:
 // nx x ny tiles of 6x6 texels, each stored as 8x8 floats, then one all-+inf
@@ -107,7 +108,9 @@ PostPlan post_plan(int W, int H, int levels, epb_dtype pyr_dtype);
 PostDesc post_desc(const PostPlan &q, const void *hdr, float threshold, float strength, float exposure,
                    float gamma, int tonemap, uint8_t *ldr, void *scratch);
 int post_items(const PostDesc &c, int stage);
-hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s);
+// level1_given: the shading pass has written pyramid level 1 (the fused form)
+hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s,
+                                bool level1_given = false);
 hipError_t launch_post_batch(const BatchHeader &h, const void *table, hipStream_t s);
 
 // ---- eye-dome lighting (edl.hip) ---------------------------------------------

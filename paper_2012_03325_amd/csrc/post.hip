@@ -28,25 +28,6 @@ __device__ __forceinline__ float4 add4(float4 a, float4 b) {
 }
 __device__ __forceinline__ float4 scale4(float4 a, float s) { return make_float4(a.x * s, a.y * s, a.z * s, 0.0f); }
 
-// Pyramid texel storage: float4, or four halves (saturating at 65504).
-struct alignas(8) Half4 {
-    __half x, y, z, w;
-};
-__device__ __forceinline__ float4 unpack(float4 v) { return v; }
-__device__ __forceinline__ float4 unpack(Half4 v) {
-    return make_float4(__half2float(v.x), __half2float(v.y), __half2float(v.z), 0.0f);
-}
-template <typename TP> __device__ __forceinline__ TP pack(float4 v);
-template <> __device__ __forceinline__ float4 pack<float4>(float4 v) { return v; }
-template <> __device__ __forceinline__ Half4 pack<Half4>(float4 v) {
-    Half4 h;
-    h.x = __float2half_rn(fminf(v.x, 65504.0f));
-    h.y = __float2half_rn(fminf(v.y, 65504.0f));
-    h.z = __float2half_rn(fminf(v.z, 65504.0f));
-    h.w = __float2half_rn(0.0f);
-    return h;
-}
-
 // ---------------------------------------------------------------------------
 // bloom_down: one 16x16 level-1 tile (32x32 pixels) -> levels 1..5 of that tile
 // ---------------------------------------------------------------------------
@@ -80,6 +61,27 @@ __device__ __forceinline__ void down_level(const PostDesc &c, int bx, int by, SR
     if (dst) dst[ly][lx] = v;
 }
 
+// Levels 2..5 of tile (bx, by) from its level-1 texels in sm.s1 (the level
+// count is uniform: barriers are safe).
+template <typename TP>
+__device__ __forceinline__ void down_levels_2_to_5(const PostDesc &c, int bx, int by, DownLds &sm) {
+    __syncthreads();
+    if (c.nl >= 2) {
+        down_level<2, 8, TP>(c, bx, by, sm.s1, sm.s2);
+        __syncthreads();
+    }
+    if (c.nl >= 3) {
+        down_level<3, 4, TP>(c, bx, by, sm.s2, sm.s3);
+        __syncthreads();
+    }
+    if (c.nl >= 4) {
+        down_level<4, 2, TP>(c, bx, by, sm.s3, sm.s4);
+        __syncthreads();
+    }
+    if (c.nl >= 5) down_level<5, 1, TP>(c, bx, by, sm.s4, (float4(*)[3]) nullptr);
+    __syncthreads();  // the next item of a batched launch refills the LDS
+}
+
 template <typename TH, typename TP>
 __device__ __forceinline__ void bloom_down_tile(const PostDesc &c, int tile, DownLds &sm) {
     int tiles_x = (c.lw[1] + kDownTile - 1) / kDownTile;
@@ -87,7 +89,9 @@ __device__ __forceinline__ void bloom_down_tile(const PostDesc &c, int tile, Dow
     int t = threadIdx.x;
     const TH *hdr = (const TH *)c.hdr;
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
-    // level 1, one texel per thread: the bright map averaged over its in-range 2x2 children
+    // level 1, one texel per thread: the bright map averaged over its in-range 2x2
+    // children, summed as horizontal pairs and then the two rows (the order the
+    // fused shading epilogue uses)
     int lx = t % kDownTile, ly = t / kDownTile;
     int X = bx * kDownTile + lx, Y = by * kDownTile + ly;
     float4 v = make_float4(0, 0, 0, 0);
@@ -103,37 +107,38 @@ __device__ __forceinline__ void bloom_down_tile(const PostDesc &c, int tile, Dow
             G[k] = ldf(hdr, plane + p);
             B[k] = ldf(hdr, 2 * plane + p);
         }
-        float n = 0.0f;
+        float cr[4], cg[4], cb[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            if (!in[k]) continue;
-            float Yl = fmaf(0.2126f, R[k], fmaf(0.7152f, G[k], 0.0722f * B[k]));
-            float sc = Yl > 0.0f ? fmaxf(Yl - c.threshold, 0.0f) / Yl : 0.0f;
-            v.x = fmaf(R[k], sc, v.x);
-            v.y = fmaf(G[k], sc, v.y);
-            v.z = fmaf(B[k], sc, v.z);
-            n += 1.0f;
+        for (int k = 0; k < 4; ++k) {  // an out-of-image child adds an exact zero
+            float sc = bright_scale(R[k], G[k], B[k], c.threshold);
+            cr[k] = in[k] ? R[k] * sc : 0.0f;
+            cg[k] = in[k] ? G[k] * sc : 0.0f;
+            cb[k] = in[k] ? B[k] * sc : 0.0f;
         }
-        v = scale4(v, 1.0f / n);
-        sto((TP *)c.raw[1], (unsigned)(Y * c.lw[1] + X) * (unsigned)sizeof(TP), pack<TP>(v));
+        float inv_n = (in[1] ? 0.5f : 1.0f) * (in[2] ? 0.5f : 1.0f);
+        v = make_float4(((cr[0] + cr[1]) + (cr[2] + cr[3])) * inv_n, ((cg[0] + cg[1]) + (cg[2] + cg[3])) * inv_n,
+                        ((cb[0] + cb[1]) + (cb[2] + cb[3])) * inv_n, 0.0f);
+        TP st = pack<TP>(v);
+        sto((TP *)c.raw[1], (unsigned)(Y * c.lw[1] + X) * (unsigned)sizeof(TP), st);
+        v = unpack(st);  // the next levels average what level 1 holds
     }
     sm.s1[ly][lx] = v;
-    __syncthreads();
-    // levels 2..5 inside the tile (the level count is uniform: barriers are safe)
-    if (c.nl >= 2) {
-        down_level<2, 8, TP>(c, bx, by, sm.s1, sm.s2);
-        __syncthreads();
-    }
-    if (c.nl >= 3) {
-        down_level<3, 4, TP>(c, bx, by, sm.s2, sm.s3);
-        __syncthreads();
-    }
-    if (c.nl >= 4) {
-        down_level<4, 2, TP>(c, bx, by, sm.s3, sm.s4);
-        __syncthreads();
-    }
-    if (c.nl >= 5) down_level<5, 1, TP>(c, bx, by, sm.s4, (float4(*)[3]) nullptr);
-    __syncthreads();  // the next item of a batched launch refills the LDS
+    down_levels_2_to_5<TP>(c, bx, by, sm);
+}
+
+// Levels 2..5 when the shading pass has written level 1 (the fused form).
+template <typename TP>
+__device__ __forceinline__ void bloom_down_from1_tile(const PostDesc &c, int tile, DownLds &sm) {
+    int tiles_x = (c.lw[1] + kDownTile - 1) / kDownTile;
+    int by = tile / tiles_x, bx = tile - by * tiles_x;
+    int t = threadIdx.x;
+    int lx = t % kDownTile, ly = t / kDownTile;
+    int X = bx * kDownTile + lx, Y = by * kDownTile + ly;
+    float4 v = make_float4(0, 0, 0, 0);
+    if (X < c.lw[1] && Y < c.lh[1])
+        v = unpack(ldo((const TP *)c.raw[1], (unsigned)(Y * c.lw[1] + X) * (unsigned)sizeof(TP)));
+    sm.s1[ly][lx] = v;
+    down_levels_2_to_5<TP>(c, bx, by, sm);
 }
 
 // ---------------------------------------------------------------------------
@@ -330,6 +335,12 @@ __global__ void __launch_bounds__(256) k_bloom_down(const PostDesc c, int tiles)
 }
 
 template <typename TP>
+__global__ void __launch_bounds__(256) k_bloom_down_from1(const PostDesc c, int tiles) {
+    __shared__ DownLds sm;
+    bloom_down_from1_tile<TP>(c, xcd_tile(blockIdx.x, tiles), sm);
+}
+
+template <typename TP>
 __global__ void __launch_bounds__(256) k_bloom_blur(const PostDesc c) {
     __shared__ BlurLds sm;
     bloom_blur_item<TP>(c, blockIdx.x, sm);
@@ -417,6 +428,7 @@ PostDesc post_desc(const PostPlan &q, const void *hdr, float threshold, float st
     c.W = q.W;
     c.H = q.H;
     c.nl = q.levels - 1;
+    c.texel_half = q.texel_bytes == 8;
     char *sc = (char *)scratch;
     for (int l = 0; l < q.levels; ++l) {
         c.lw[l] = q.lw[l];
@@ -449,10 +461,13 @@ int post_items(const PostDesc &c, int stage) {
 }
 
 template <typename TH, typename TP>
-static void launch_post(const PostDesc &c, hipStream_t s) {
+static void launch_post(const PostDesc &c, bool level1_given, hipStream_t s) {
     if (c.nl >= 1) {
         int tiles = post_items(c, kStDown);
-        hipLaunchKernelGGL((k_bloom_down<TH, TP>), dim3(tiles), dim3(256), 0, s, c, tiles);
+        if (!level1_given)
+            hipLaunchKernelGGL((k_bloom_down<TH, TP>), dim3(tiles), dim3(256), 0, s, c, tiles);
+        else if (c.nl >= 2)
+            hipLaunchKernelGGL(k_bloom_down_from1<TP>, dim3(tiles), dim3(256), 0, s, c, tiles);
         hipLaunchKernelGGL(k_bloom_blur<TP>, dim3(post_items(c, kStBloomBlur)), dim3(256), 0, s, c);
     }
     int tiles = post_items(c, kStComposite);
@@ -471,12 +486,13 @@ static void launch_post_batch_t(const BatchHeader &h, const void *table, hipStre
                        dim3(kPostTx), 0, s, table);
 }
 
-hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s) {
+hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtype pyr_dtype, hipStream_t s,
+                                bool level1_given) {
     bool h16 = hdr_dtype == EPB_F16, p16 = pyr_dtype == EPB_F16;
-    if (!h16 && !p16) launch_post<float, float4>(c, s);
-    else if (!h16 && p16) launch_post<float, Half4>(c, s);
-    else if (h16 && !p16) launch_post<__half, float4>(c, s);
-    else launch_post<__half, Half4>(c, s);
+    if (!h16 && !p16) launch_post<float, float4>(c, level1_given, s);
+    else if (!h16 && p16) launch_post<float, Half4>(c, level1_given, s);
+    else if (h16 && !p16) launch_post<__half, float4>(c, level1_given, s);
+    else launch_post<__half, Half4>(c, level1_given, s);
     return hipGetLastError();
 }
 

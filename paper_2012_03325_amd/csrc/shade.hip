@@ -111,19 +111,14 @@ __device__ __forceinline__ float pcf(const DevLight &L, float dvx, float dvy, fl
     return inside ? (float)lit * (1.0f / 9.0f) : 1.0f;
 }
 
-template <int TX, int TY, typename TG, typename TA, typename TH>
-__device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
-    int tiles_x = (c.W + TX - 1) / TX;
-    int ty = tile / tiles_x;
-    int x = (tile - ty * tiles_x) * TX + (int)(threadIdx.x % TX);
-    int y = ty * TY + (int)(threadIdx.x / TX);
-    if (x >= c.W || y >= c.H) return;
+// One pixel's radiance: shading of the surface, or the environment behind it.
+template <typename TG, typename TA, typename TH>
+__device__ __forceinline__ void shade_pixel(const ShadeDesc &c, int x, int y, float (&out)[3]) {
     unsigned p = __umul24((unsigned)y, (unsigned)c.W) + (unsigned)x;
     unsigned plane = (unsigned)c.W * (unsigned)c.H;
     float d = ldf(c.depth, p);
     float dvx = ((float)x + 0.5f - c.cx) * c.inv_fx;
     float dvy = -((float)y + 0.5f - c.cy) * c.inv_fy;
-    float out[3];
     if (__builtin_isinf(d)) {
         v3 dw = mul_Rt(c.R, mk3(dvx, dvy, -1.0f));
         float4 e = cube_bilinear(c.env, c.env_dims, dw);
@@ -234,24 +229,66 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
     stf(hdr, 2 * plane + p, out[2]);
 }
 
+// Level 1 of the bloom pyramid from the shaded pixels of this wave: the texel
+// (x / 2, y / 2) is the mean of the bright-pass values of its in-image 2x2
+// children, summed as horizontal pairs, then the two rows (the order of the
+// unfused bloom pass, so the two agree bitwise), from the HDR values as
+// stored.  A TX-wide tile (TX = 16 or 32) puts rows 2k and 2k + 1 of a tile in
+// one wave, at lanes l and l ^ TX; every lane of the wave takes part.
+template <int TX, typename TH>
+__device__ __forceinline__ void bloom1_epilogue(const ShadeDesc &c, int x, int y, bool in, const float (&o)[3]) {
+    float cr = 0.0f, cg = 0.0f, cb = 0.0f;
+    if (in) {
+        float r = stored_as(o[0], (const TH *)nullptr), g = stored_as(o[1], (const TH *)nullptr),
+              b = stored_as(o[2], (const TH *)nullptr);
+        float sc = bright_scale(r, g, b, c.bloom_threshold);
+        cr = r * sc;
+        cg = g * sc;
+        cb = b * sc;
+    }
+    cr = add_row_pair<TX>(add_lane_pair(cr));
+    cg = add_row_pair<TX>(add_lane_pair(cg));
+    cb = add_row_pair<TX>(add_lane_pair(cb));
+    if (in && !(x & 1) && !(y & 1)) {
+        float inv_n = (x + 1 < c.W ? 0.5f : 1.0f) * (y + 1 < c.H ? 0.5f : 1.0f);
+        unsigned t = __umul24((unsigned)(y >> 1), (unsigned)c.Wh) + (unsigned)(x >> 1);
+        float4 v = make_float4(cr * inv_n, cg * inv_n, cb * inv_n, 0.0f);
+        if (c.bloom1_half) sto((Half4 *)c.bloom1, t * 8u, pack_half4(v));
+        else sto((float4 *)c.bloom1, t * 16u, v);
+    }
+}
+
+template <int TX, int TY, bool kBloom1, typename TG, typename TA, typename TH>
+__device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
+    int tiles_x = (c.W + TX - 1) / TX;
+    int ty = tile / tiles_x;
+    int x = (tile - ty * tiles_x) * TX + (int)(threadIdx.x % TX);
+    int y = ty * TY + (int)(threadIdx.x / TX);
+    bool in = x < c.W && y < c.H;
+    float out[3] = {0.0f, 0.0f, 0.0f};
+    // (with kBloom1 every lane reaches the epilogue; otherwise out-of-image lanes leave here)
+    if (!kBloom1 && !in) return;
+    if (in) shade_pixel<TG, TA, TH>(c, x, y, out);
+    if constexpr (kBloom1) bloom1_epilogue<TX, TH>(c, x, y, in, out);
+}
+
 // ---------------------------------------------------------------------------
 // kernels
 // ---------------------------------------------------------------------------
-// Minimum waves per SIMD: 8 for the single-view kernel on an FP16 G-buffer (fewer
-// bytes per pixel, more issue-bound; 61 VGPRs), 7 otherwise (the FP32 kernel's
-// natural 65 VGPRs; the batched kernel, with the view lookup on top, would settle
-// at 6, and at 8 it would spill).
-template <typename TG>
-constexpr int shade_min_waves() { return sizeof(TG) == 2 ? 8 : 7; }
+// Minimum waves per SIMD: 7, the FP32 kernel's natural 65 VGPRs (69 with the
+// bloom epilogue).  At 8 (64 VGPRs) the FP16 kernel spills and runs 3 us
+// slower at 1080p; the batched kernel, with the view lookup on top, would
+// settle at 6.
+constexpr int kShadeMinWaves = 7;
 
-template <int TX, int TY, typename TG, typename TA, typename TH>
-__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(shade_min_waves<TG>())))
+template <int TX, int TY, bool kBloom1, typename TG, typename TA, typename TH>
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kShadeMinWaves)))
 k_shade(const ShadeDesc c, int tiles) {
-    shade_tile<TX, TY, TG, TA, TH>(c, xcd_tile(blockIdx.x, tiles));
+    shade_tile<TX, TY, kBloom1, TG, TA, TH>(c, xcd_tile(blockIdx.x, tiles));
 }
 
 template <int TX, int TY, typename TG, typename TA, typename TH>
-__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(7)))
+__global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kShadeMinWaves)))
 k_shade_batch(const void *__restrict__ table) {
     const BatchHeader *h = (const BatchHeader *)table;
     const int *start = batch_start(table, kStShade);
@@ -260,7 +297,7 @@ k_shade_batch(const void *__restrict__ table) {
     for (int it = w.lb; it < w.count; it += w.stride) {
         int g = w.first + it;
         int v = find_view(start, h->n_views, g);
-        shade_tile<TX, TY, TG, TA, TH>(views[v].shade, g - start[v]);
+        shade_tile<TX, TY, false, TG, TA, TH>(views[v].shade, g - start[v]);
     }
 }
 
@@ -305,7 +342,10 @@ int shade_items(const ShadeDesc &c, int shade_tile) {
 template <typename TG, typename TA, typename TH>
 static void go(const ShadeDesc &k, hipStream_t s) {
     int tiles = shade_items(k, 0);
-    hipLaunchKernelGGL((k_shade<32, 8, TG, TA, TH>), dim3(tiles), dim3(256), 0, s, k, tiles);
+    if (k.bloom1)
+        hipLaunchKernelGGL((k_shade<32, 8, true, TG, TA, TH>), dim3(tiles), dim3(256), 0, s, k, tiles);
+    else
+        hipLaunchKernelGGL((k_shade<32, 8, false, TG, TA, TH>), dim3(tiles), dim3(256), 0, s, k, tiles);
 }
 template <int TX, int TY, typename TG, typename TA, typename TH>
 static void go_batch(const BatchHeader &h, const void *table, hipStream_t s) {
@@ -336,8 +376,13 @@ static void go_a(const BatchHeader *h, const void *table, const ShadeDesc *k, ep
     else go_h<TG, __half>(h, table, k, hd, s);
 }
 
-hipError_t launch_shade(const ShadeArgs &a, hipStream_t s) {
+hipError_t launch_shade(const ShadeArgs &a, hipStream_t s, const PostDesc *bloom) {
     ShadeDesc k = shade_desc(a);
+    if (bloom && bloom->nl >= 1) {  // the fused form writes bloom level 1 as well
+        k.bloom1 = bloom->raw[1];
+        k.bloom1_half = bloom->texel_half;
+        k.bloom_threshold = bloom->threshold;
+    }
     if (a.gdtype == EPB_F32) go_a<float>(nullptr, nullptr, &k, a.ao_dtype, a.hdr_dtype, s);
     else go_a<__half>(nullptr, nullptr, &k, a.ao_dtype, a.hdr_dtype, s);
     return hipGetLastError();

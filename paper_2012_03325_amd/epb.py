@@ -46,6 +46,7 @@ EPB_MAP_TILES = 1
 EPB_SSAO_STATIC_SCRATCH_BYTES = 16 << 20
 
 ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_ssao_static", "epb_shade", "epb_bloom_tonemap",
+                "epb_shade_post",
                 "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
                 "epb_batch_table_bytes", "epb_view_scratch_bytes", "epb_batch_scratch_bytes",
                 "epb_batch_build",
@@ -157,6 +158,10 @@ def _load() -> C.CDLL:
                               C.POINTER(epb_cube), P, C.c_int, P]
     lib.epb_bloom_tonemap.argtypes = [P, C.c_int, C.c_int32, C.c_int32, C.POINTER(epb_post_params),
                                       P, P, C.c_size_t, P]
+    lib.epb_shade_post.argtypes = [C.POINTER(epb_gbuffer), C.POINTER(epb_camera), P, C.c_int,
+                                   C.POINTER(epb_light), C.c_int32, C.POINTER(epb_ibl_maps),
+                                   C.POINTER(epb_cube), P, C.c_int, C.POINTER(epb_post_params), P, P,
+                                   C.c_size_t, P]
     lib.epb_scratch_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32, P]
     lib.epb_scratch_bytes.restype = C.c_size_t
     lib.epb_status_str.argtypes = [C.c_int]
@@ -178,7 +183,7 @@ def _load() -> C.CDLL:
     lib.epb_shadow_tiles_bytes.restype = C.c_size_t
     lib.epb_shadow_tiles.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, P]
     for fn in ("epb_precompute_ibl", "epb_ssao", "epb_ssao_static", "epb_shade", "epb_bloom_tonemap",
-               "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast", "epb_edl",
+               "epb_shade_post", "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast", "epb_edl",
                "epb_shadow_tiles"):
         getattr(lib, fn).restype = C.c_int
     return lib
@@ -261,6 +266,17 @@ def epb_bloom_tonemap(hdr, hdr_dtype: int, width: int, height: int, params: epb_
     st = lib.epb_bloom_tonemap(_ptr(hdr), hdr_dtype, width, height, C.byref(params), _ptr(ldr_out),
                                _ptr(scratch), scratch_bytes, _stream(stream))
     return _check("epb_bloom_tonemap", st, check)
+
+
+def epb_shade_post(gbuf: epb_gbuffer, cam: epb_camera, ao, ao_dtype: int, lights: Sequence[epb_light],
+                   ibl: epb_ibl_maps, env: epb_cube, hdr_out, hdr_dtype: int, params: epb_post_params,
+                   ldr_out, scratch, scratch_bytes: int, stream=None, check: bool = True) -> int:
+    n = len(lights)
+    arr = (epb_light * max(1, n))(*lights)
+    st = lib.epb_shade_post(C.byref(gbuf), C.byref(cam), _ptr(ao), ao_dtype, arr if n else None, n,
+                            C.byref(ibl), C.byref(env), _ptr(hdr_out), hdr_dtype, C.byref(params),
+                            _ptr(ldr_out), _ptr(scratch), scratch_bytes, _stream(stream))
+    return _check("epb_shade_post", st, check)
 
 
 def epb_batch_table_bytes(n_views: int) -> int:

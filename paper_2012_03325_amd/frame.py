@@ -207,10 +207,21 @@ class DeviceView:
     def bloom_tonemap(self, stream=None, hdr: Optional[torch.Tensor] = None):
         self.postp.run(hdr if hdr is not None else self.hdr, stream)
 
-    def render(self, stream=None):
+    def shade_post(self, stream=None, ao: Optional[torch.Tensor] = None, use_ao: bool = True):
+        """shade() then bloom_tonemap() in one call, bloom level 1 formed while shading."""
+        a = (ao if ao is not None else self.ao) if use_ao else None
+        adt = E.EPB_F16 if (a is not None and a.dtype == torch.float16) else E.EPB_F32
+        pp = self.postp
+        E.epb_shade_post(self.gbuf, self.cam, a, adt, self.lights, self.ibl.maps, self.ibl.env_c, self.hdr,
+                         self.hdr_dtype, pp.post, pp.ldr, pp.scratch, pp.scratch_bytes, stream)
+
+    def render(self, stream=None, fused: bool = False):
         self.ssao(stream)
-        self.shade(stream)
-        self.bloom_tonemap(stream)
+        if fused:
+            self.shade_post(stream)
+        else:
+            self.shade(stream)
+            self.bloom_tonemap(stream)
 
     def pyramid(self) -> List[torch.Tensor]:
         return self.postp.pyramid()

@@ -227,6 +227,34 @@ def test_bloom_tonemap_validation():
     assert call(n=need - 1) == E.EPB_ERR_SCRATCH
 
 
+def test_shade_post_validation():
+    """The fused call validates both halves (shading, then bloom and tone
+    mapping) before it enqueues anything."""
+    cam = _cam()
+    cube = E.epb_cube(8, 1, FAKE)
+    maps = E.epb_ibl_maps(E.epb_cube(4, 1, FAKE), E.epb_cube(8, 3, FAKE), FAKE, 16)
+    lights = (E.epb_light * 1)()
+    p = E.epb_post_params(6, 1.0, 0.04, 1.0, 2.2)
+    need = E.epb_scratch_bytes(E.EPB_OP_BLOOM_TONEMAP, 64, 48, p)
+
+    def call(hdr=FAKE, hdt=E.EPB_F32, pp=p, out=FAKE, sc=FAKE, n=need, env=cube):
+        g = _gbuf()
+        return E.lib.epb_shade_post(C.byref(g), C.byref(cam), FAKE, E.EPB_F32, lights, 0, C.byref(maps),
+                                    C.byref(env), hdr, hdt, C.byref(pp), out, sc, n, None)
+
+    assert call(hdr=None) == E.EPB_ERR_NULL
+    assert call(hdt=5) == E.EPB_ERR_DTYPE
+    assert call(env=E.epb_cube(0, 1, FAKE)) == E.EPB_ERR_SIZE
+    assert call(out=None) == E.EPB_ERR_NULL
+    assert call(sc=None) == E.EPB_ERR_SCRATCH
+    assert call(n=need - 1) == E.EPB_ERR_SCRATCH
+    assert call(out=FAKE + 1) == E.EPB_ERR_ALIGN
+    assert call(pp=E.epb_post_params(0, 1.0, 0.04, 1.0, 2.2)) == E.EPB_ERR_PARAM
+    assert call(pp=E.epb_post_params(6, 1.0, 0.04, 1.0, 2.2, 7)) == E.EPB_ERR_DTYPE
+    assert E.lib.epb_shade_post(None, C.byref(cam), FAKE, E.EPB_F32, lights, 0, C.byref(maps), C.byref(cube),
+                                FAKE, E.EPB_F32, C.byref(p), FAKE, FAKE, need, None) == E.EPB_ERR_NULL
+
+
 def test_precompute_ibl_validation():
     ip = E.epb_ibl_params(8, 16, 16, 3, 64, 16, 64)
     need = E.epb_scratch_bytes(E.EPB_OP_PRECOMPUTE_IBL, 32, 32, ip)
