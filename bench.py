@@ -52,7 +52,8 @@ def log(msg):
 # (FETCH_SIZE, then WRITE_SIZE, scaled by what the counters read for a device
 # copy of known size), valid while the kernel's sources hash to the recorded value
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_shade_1080p_traffic.json")
-SHADE_SOURCES = ("paper_2012_03325_amd/csrc/shade.hip", "paper_2012_03325_amd/csrc/device_common.hpp",
+SHADE_SOURCES = ("paper_2012_03325_amd/csrc/shade.hip", "paper_2012_03325_amd/csrc/shade_tiles.hpp",
+                 "paper_2012_03325_amd/csrc/device_common.hpp",
                  "paper_2012_03325_amd/csrc/desc.hpp", "include/epb.h")
 
 
@@ -838,8 +839,9 @@ def main():
     if not args.no_batch:
         out["batched"] = bench_batched(args, torch, E, frame, synth)
         tuned = out["batched"]["fp16"]["schedule"]
+        # (the serving batches mix storage types per buffer: stage launches only)
         sched = E.epb_schedule(tuned["shade_tile"], tuned["ssao_tile"], tuned["ssao_batch"],
-                               tuned["blocks_per_cu"])
+                               tuned["blocks_per_cu"], 0, 0)
     if not args.no_serve:
         out["serving"] = bench_serving(args, torch, E, frame, synth, sched)
     if not args.no_cpu:

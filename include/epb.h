@@ -82,7 +82,8 @@ typedef enum {
     EPB_ERR_ALIGN = -4,   /* a device pointer is not 16-byte aligned          */
     EPB_ERR_SCRATCH = -5, /* scratch buffer missing or smaller than required  */
     EPB_ERR_PARAM = -6,   /* a scalar parameter is out of range               */
-    EPB_ERR_HIP = -7      /* a HIP launch failed; see epb_last_hip_error()    */
+    EPB_ERR_HIP = -7,     /* a HIP launch failed; see epb_last_hip_error()    */
+    EPB_ERR_TIMEOUT = -8  /* a wait of the persistent batch launch gave up    */
 } epb_status;
 
 /* Storage type of G-buffer attribute planes, AO and HDR images.  Arithmetic
@@ -381,7 +382,7 @@ int epb_shade_post(const epb_gbuffer *gbuf, const epb_camera *cam, const void *a
 /* ------------------------------------------------------------------------
  * Batched form: the whole pass (SSAO, shading, bloom and tone mapping) of many
  * views of any sizes with one launch per stage (seven launches per batch, not
- * seven per view).  Every stage walks the work items (tiles) of all views, so
+ * seven per view), or all of it in one persistent launch (epb_schedule).  Every stage walks the work items (tiles) of all views, so
  * small views do not leave the device idle and a batch is a fixed sequence of
  * launches that can be captured in a HIP graph and replayed.
  *
@@ -425,9 +426,22 @@ typedef struct {
                               2 = 16x16, its depth and a 32-texel halo staged
                               in LDS                                          */
     int32_t ssao_batch;    /* SSAO depth gathers in flight: 0 = 8, 1 = 16        */
-    int32_t blocks_per_cu; /* 0: one workgroup per work item; k in 1..64: a
-                              persistent grid of k workgroups per compute unit  */
+    int32_t blocks_per_cu; /* 0: one workgroup per work item (persistent
+                              launch: as many as fit); k in 1..64: a grid of k
+                              workgroups per compute unit that loops over the
+                              work                                             */
+    int32_t persistent;    /* 0: one launch per stage (seven per batch);
+                              k in 1..EPB_MAX_PERSISTENT_CHUNK: the whole batch
+                              in one launch whose work items are k tiles of one
+                              view and stage (requires one storage type for
+                              G-buffer, AO, HDR and pyramid; else EPB_ERR_DTYPE) */
+    int32_t wait_limit;    /* persistent: polls of a dependency before a
+                              workgroup gives up (0: 2^22, about seconds); a
+                              negative value -k makes every wait give up after k
+                              polls (for testing the error path)               */
 } epb_schedule;
+
+#define EPB_MAX_PERSISTENT_CHUNK 4096
 
 /* Bytes of the batch table for n_views views (0 if n_views is out of range). */
 size_t epb_batch_table_bytes(int32_t n_views);
@@ -467,8 +481,26 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
  * Launches exactly the kernels of one frame: no copies, allocations or
  * memsets, so the call may be captured into a HIP graph.  Returns
  * EPB_ERR_PARAM for a table that epb_batch_build did not write.
+ *
+ * With a persistent schedule the frame is one launch (after a one-block clear
+ * of the table's work counters): the device copy must then stay writable, as
+ * its last bytes hold the counters (the host copy is not changed), and two
+ * renders of one device table must not overlap.
+ * Work items are handed out in stage order, and an item waits, bounded by the
+ * schedule's wait_limit, until its view's previous stage is complete; a wait
+ * that gives up stops the launch early (its outputs are then incomplete) and
+ * is reported by epb_batch_status().
  */
 int epb_render_batch(const void *table, const void *table_dev, hipStream_t stream);
+
+/*
+ * epb_batch_status -- after epb_render_batch of a persistent table: waits for
+ * `stream` and returns EPB_ERR_TIMEOUT if a dependency wait of the last render
+ * of `table_dev` gave up, else EPB_OK (also for tables of stage launches,
+ * which never wait).  EPB_ERR_PARAM for a table epb_batch_build did not write;
+ * EPB_ERR_HIP if the copy of the status word fails.
+ */
+int epb_batch_status(const void *table, const void *table_dev, hipStream_t stream);
 
 /*
  * epb_raycast -- G-buffer (or depth map) of a sphere field seen by `cam`: the

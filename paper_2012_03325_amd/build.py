@@ -17,7 +17,8 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libepb.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-SOURCES = ["api.cpp", "ibl.hip", "ssao.hip", "shade.hip", "post.hip", "raycast.hip", "edl.hip"]
+SOURCES = ["api.cpp", "ibl.hip", "ssao.hip", "shade.hip", "post.hip", "raycast.hip", "edl.hip",
+           "persistent.hip"]
 ARCH = "gfx950"
 
 HIPCC = os.environ.get("HIPCC", shutil.which("hipcc") or "/opt/rocm/bin/hipcc")

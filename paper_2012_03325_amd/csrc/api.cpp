@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 
 #include "../../include/epb.h"
@@ -261,9 +262,23 @@ int batch_scratch(const epb_view *views, int32_t n, size_t *bytes) {
 
 int check_schedule(const epb_schedule &q) {
     if (q.shade_tile < 0 || q.shade_tile > 2 || q.ssao_tile < 0 || q.ssao_tile > 2 || q.ssao_batch < 0 ||
-        q.ssao_batch > 1 || q.blocks_per_cu < 0 || q.blocks_per_cu > 64)
+        q.ssao_batch > 1 || q.blocks_per_cu < 0 || q.blocks_per_cu > 64 || q.persistent < 0 ||
+        q.persistent > EPB_MAX_PERSISTENT_CHUNK || q.wait_limit < -(1 << 30))
         return EPB_ERR_PARAM;
     return EPB_OK;
+}
+
+// Work items of one view's stages in the persistent launch (256-thread tiles).
+void persistent_items(const epb::ViewDesc &d, int items[epb::kStages]) {
+    using namespace epb;
+    int st = kPersistSsaoT;
+    items[kStPrep] = ssao_items(d.ssao, kStPrep, 0);
+    items[kStRaw] = ceil_div(d.ssao.Wh, st) * ceil_div(d.ssao.Hh, st);
+    items[kStBlur] = d.ssao.blur ? items[kStRaw] : 0;
+    items[kStShade] = shade_items(d.shade, 0);
+    items[kStDown] = post_items(d.post, kStDown);
+    items[kStBloomBlur] = post_items(d.post, kStBloomBlur);
+    items[kStComposite] = ceil_div(post_items(d.post, kStComposite), kPersistCompositeTiles);
 }
 
 }  // namespace
@@ -280,6 +295,7 @@ const char *epb_status_str(int status) {
     case EPB_ERR_SCRATCH: return "scratch buffer missing or too small";
     case EPB_ERR_PARAM: return "parameter out of range";
     case EPB_ERR_HIP: return "HIP launch failed";
+    case EPB_ERR_TIMEOUT: return "a dependency wait of the persistent launch gave up";
     default: return "unknown status";
     }
 }
@@ -538,11 +554,16 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
             return EPB_ERR_DTYPE;
         if ((v.ssao->blur != 0) != (v0.ssao->blur != 0)) return EPB_ERR_PARAM;
     }
+    // the persistent launch is built for one storage type throughout
+    if (q.persistent && (v0.ssao->out_dtype != v0.gbuf.dtype || v0.hdr_dtype != v0.gbuf.dtype ||
+                         v0.post->pyr_dtype != v0.gbuf.dtype))
+        return EPB_ERR_DTYPE;
     // descriptors first (validating every view), then the header and item prefix sums
     epb::ViewDesc *vd = (epb::ViewDesc *)((char *)table + epb::batch_views_offset(n_views));
     char *sc = (char *)scratch;
-    long long total[epb::kStages] = {};
+    long long total[epb::kStages] = {}, chunks[epb::kStages] = {};
     int *start = (int *)((char *)table + epb::batch_start_offset());
+    int *cstart = (int *)((char *)table + epb::batch_cstart_offset(n_views));
     for (int i = 0; i < n_views; ++i) {
         const epb_view &v = views[i];
         ViewScratch vs;
@@ -564,17 +585,24 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
         if ((st = build_post(hdr, v.hdr_dtype, v.cam.width, v.cam.height, v.post, v.ldr, s_post, vs.post, &d.post)))
             return st;
         int items[epb::kStages];
-        items[epb::kStPrep] = epb::ssao_items(d.ssao, epb::kStPrep, q.ssao_tile);
-        items[epb::kStRaw] = epb::ssao_items(d.ssao, epb::kStRaw, q.ssao_tile);
-        items[epb::kStBlur] = d.ssao.blur ? epb::ssao_items(d.ssao, epb::kStBlur, q.ssao_tile) : 0;
-        items[epb::kStShade] = epb::shade_items(d.shade, q.shade_tile);
-        items[epb::kStDown] = epb::post_items(d.post, epb::kStDown);
-        items[epb::kStBloomBlur] = epb::post_items(d.post, epb::kStBloomBlur);
-        items[epb::kStComposite] = epb::post_items(d.post, epb::kStComposite);
+        if (q.persistent) {
+            persistent_items(d, items);
+        } else {
+            items[epb::kStPrep] = epb::ssao_items(d.ssao, epb::kStPrep, q.ssao_tile);
+            items[epb::kStRaw] = epb::ssao_items(d.ssao, epb::kStRaw, q.ssao_tile);
+            items[epb::kStBlur] = d.ssao.blur ? epb::ssao_items(d.ssao, epb::kStBlur, q.ssao_tile) : 0;
+            items[epb::kStShade] = epb::shade_items(d.shade, q.shade_tile);
+            items[epb::kStDown] = epb::post_items(d.post, epb::kStDown);
+            items[epb::kStBloomBlur] = epb::post_items(d.post, epb::kStBloomBlur);
+            items[epb::kStComposite] = epb::post_items(d.post, epb::kStComposite);
+        }
         for (int k = 0; k < epb::kStages; ++k) {
             if (total[k] + items[k] > 0x7fffffffLL) return EPB_ERR_SIZE;
             start[k * (n_views + 1) + i] = (int)total[k];
             total[k] += items[k];
+            long long nc = q.persistent ? (items[k] + q.persistent - 1) / q.persistent : 0;
+            cstart[k * (n_views + 1) + i] = (int)chunks[k];
+            chunks[k] += nc;
         }
         std::memcpy(&vd[i], &d, sizeof(d));
     }
@@ -594,7 +622,22 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
     for (int k = 0; k < epb::kStages; ++k) {
         h.total[k] = (int)total[k];
         start[k * (n_views + 1) + n_views] = (int)total[k];
+        cstart[k * (n_views + 1) + n_views] = (int)chunks[k];
     }
+    h.persistent = q.persistent ? 1 : 0;
+    h.chunk = q.persistent;
+    h.gate = q.wait_limit < 0 ? 0 : 1;
+    h.wait_limit = q.wait_limit < 0 ? -q.wait_limit : (q.wait_limit > 0 ? q.wait_limit : (1 << 22));
+    long long first = 0;
+    for (int k = 0; k < epb::kStages; ++k) {
+        h.chunk_first[k] = (int)first;
+        first += chunks[k];
+        if (first > 0x7fffffffLL) return EPB_ERR_SIZE;
+    }
+    h.chunk_first[epb::kStages] = (int)first;
+    h.total_chunks = (int)first;
+    std::memset((char *)table + epb::batch_state_offset(n_views), 0,
+                epb::batch_table_bytes(n_views) - epb::batch_state_offset(n_views));
     std::memset(table, 0, epb::batch_start_offset());
     std::memcpy(table, &h, sizeof(h));
     return EPB_OK;
@@ -606,10 +649,26 @@ int epb_render_batch(const void *table, const void *table_dev, hipStream_t strea
     epb::BatchHeader h;
     std::memcpy(&h, table, sizeof(h));
     if (h.magic != epb::kBatchMagic || h.n_views < 1 || h.n_views > EPB_MAX_BATCH_VIEWS) return EPB_ERR_PARAM;
+    if (h.persistent) return hip_status(epb::launch_persistent(h, table_dev, stream));
     hipError_t e = epb::launch_ssao_batch(h, table_dev, stream);
     if (e == hipSuccess) e = epb::launch_shade_batch(h, table_dev, stream);
     if (e == hipSuccess) e = epb::launch_post_batch(h, table_dev, stream);
     return hip_status(e);
+}
+
+int epb_batch_status(const void *table, const void *table_dev, hipStream_t stream) {
+    if (!table || !table_dev) return EPB_ERR_NULL;
+    if (!aligned16(table_dev)) return EPB_ERR_ALIGN;
+    epb::BatchHeader h;
+    std::memcpy(&h, table, sizeof(h));
+    if (h.magic != epb::kBatchMagic || h.n_views < 1 || h.n_views > EPB_MAX_BATCH_VIEWS) return EPB_ERR_PARAM;
+    if (!h.persistent) return EPB_OK;  // the stage launches have nothing that can give up
+    int err = 0;
+    const char *word = (const char *)table_dev + epb::batch_state_offset(h.n_views) + offsetof(epb::PersistState, error);
+    hipError_t e = hipMemcpyAsync(&err, word, sizeof(int), hipMemcpyDeviceToHost, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_status(e);
+    return err ? EPB_ERR_TIMEOUT : EPB_OK;
 }
 
 }  // extern "C"

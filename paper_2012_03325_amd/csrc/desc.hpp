@@ -158,7 +158,8 @@ constexpr int kSsaoBatches[2] = {8, 16};
 inline int ceil_div(int a, int b) { return (a + b - 1) / b; }
 
 // ---------------------------------------------------------------------------
-// batch table: [BatchHeader][int start[kStages][n + 1]][pad to 16][ViewDesc[n]]
+// batch table: [BatchHeader][int start[kStages][n + 1]][int cstart[kStages][n + 1]]
+// [pad to 16][ViewDesc[n]][pad to 256][PersistState][int done[n][kStages]]
 // ---------------------------------------------------------------------------
 enum Stage { kStPrep = 0, kStRaw, kStBlur, kStShade, kStDown, kStBloomBlur, kStComposite, kStages };
 
@@ -175,19 +176,56 @@ struct BatchHeader {
     int blur, has_ao;
     int shade_tile, ssao_tile, ssao_batch, blocks_per_cu;
     int total[kStages];  // work items of each stage over all views
+    // one persistent launch (persistent != 0): work items are chunks of `chunk`
+    // tiles of one view and stage, handed out in stage-major order
+    int persistent, chunk;
+    int wait_limit;                 // polls of a dependency before the block gives up
+    int gate;                       // 1; 0 makes every dependency wait give up (error-path tests)
+    int total_chunks;
+    int chunk_first[kStages + 1];   // first chunk of each stage
 };
 
-constexpr uint32_t kBatchMagic = 0x45504231u;  // "EPB1"
+// Work counters of the persistent launch, in the device copy of the table; the
+// launch clears them first.  done[v][s] (after this struct) counts the finished
+// chunks of view v's stage s.
+struct PersistState {
+    int head;                 // next chunk to hand out
+    int error;                // a dependency wait gave up
+    int stage_done[kStages];  // finished chunks of each stage over all views
+    int pad[16 - 2 - kStages];
+};
+static_assert(sizeof(PersistState) == 64, "one 64-byte block");
 
-__host__ __device__ inline size_t batch_start_offset() { return (sizeof(BatchHeader) + 15) & ~size_t(15); }
-__host__ __device__ inline size_t batch_views_offset(int n) {
-    return (batch_start_offset() + sizeof(int) * kStages * (size_t)(n + 1) + 15) & ~size_t(15);
+// Persistent launch: tile shapes of the stages whose single-view / batched tile
+// is not 256 threads (SSAO raw and blur: 16 x 16 texels; composite: 4 tiles of
+// 64 x 8 pixels, one per wavefront).
+constexpr int kPersistSsaoT = 16;
+constexpr int kPersistCompositeTiles = 4;
+
+constexpr uint32_t kBatchMagic = 0x45504232u;  // "EPB2"
+
+__host__ __device__ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+__host__ __device__ inline size_t batch_start_offset() { return align_up(sizeof(BatchHeader), 16); }
+__host__ __device__ inline size_t batch_cstart_offset(int n) {
+    return batch_start_offset() + sizeof(int) * kStages * (size_t)(n + 1);
 }
-__host__ __device__ inline size_t batch_table_bytes(int n) { return batch_views_offset(n) + sizeof(ViewDesc) * (size_t)n; }
+__host__ __device__ inline size_t batch_views_offset(int n) {
+    return align_up(batch_cstart_offset(n) + sizeof(int) * kStages * (size_t)(n + 1), 16);
+}
+__host__ __device__ inline size_t batch_state_offset(int n) {
+    return align_up(batch_views_offset(n) + sizeof(ViewDesc) * (size_t)n, 256);
+}
+__host__ __device__ inline size_t batch_table_bytes(int n) {
+    return batch_state_offset(n) + sizeof(PersistState) + sizeof(int) * kStages * (size_t)n;
+}
 
 __host__ __device__ inline const int *batch_start(const void *table, int stage) {
     const BatchHeader *h = (const BatchHeader *)table;
     return (const int *)((const char *)table + batch_start_offset()) + stage * (h->n_views + 1);
+}
+__host__ __device__ inline const int *batch_cstart(const void *table, int stage) {
+    const BatchHeader *h = (const BatchHeader *)table;
+    return (const int *)((const char *)table + batch_cstart_offset(h->n_views)) + stage * (h->n_views + 1);
 }
 __host__ __device__ inline const ViewDesc *batch_views(const void *table) {
     const BatchHeader *h = (const BatchHeader *)table;

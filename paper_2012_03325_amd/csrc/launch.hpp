@@ -113,6 +113,10 @@ hipError_t launch_bloom_tonemap(const PostDesc &c, epb_dtype hdr_dtype, epb_dtyp
                                 bool level1_given = false);
 hipError_t launch_post_batch(const BatchHeader &h, const void *table, hipStream_t s);
 
+// persistent.hip: the whole batch in one launch (the table's persistent schedule); the
+// table must be the device copy, whose work counters it clears and updates
+hipError_t launch_persistent(const BatchHeader &h, const void *table, hipStream_t s);
+
 // ---- eye-dome lighting (edl.hip) ---------------------------------------------
 hipError_t launch_edl(const EdlDesc &c, epb_dtype cdtype, epb_dtype ao_dtype, epb_dtype hdr_dtype, hipStream_t s);
 

@@ -23,6 +23,7 @@ EPB_ERR_ALIGN = -4
 EPB_ERR_SCRATCH = -5
 EPB_ERR_PARAM = -6
 EPB_ERR_HIP = -7
+EPB_ERR_TIMEOUT = -8
 
 EPB_F32 = 0
 EPB_F16 = 1
@@ -31,6 +32,7 @@ EPB_MAX_LIGHTS = 8
 EPB_MAX_SSAO_SAMPLES = 256
 EPB_MAX_BLOOM_LEVELS = 6
 EPB_MAX_BATCH_VIEWS = 4096
+EPB_MAX_PERSISTENT_CHUNK = 4096
 
 EPB_OP_PRECOMPUTE_IBL = 0
 EPB_OP_SSAO = 1
@@ -50,7 +52,7 @@ ENTRY_POINTS = ("epb_precompute_ibl", "epb_ssao", "epb_ssao_static", "epb_shade"
                 "epb_scratch_bytes", "epb_status_str", "epb_last_hip_error",
                 "epb_batch_table_bytes", "epb_view_scratch_bytes", "epb_batch_scratch_bytes",
                 "epb_batch_build",
-                "epb_render_batch", "epb_raycast", "epb_edl", "epb_shadow_tiles_bytes", "epb_shadow_tiles")
+                "epb_render_batch", "epb_batch_status", "epb_raycast", "epb_edl", "epb_shadow_tiles_bytes", "epb_shadow_tiles")
 
 
 class EpbError(RuntimeError):
@@ -127,7 +129,7 @@ class epb_edl_params(C.Structure):
 
 class epb_schedule(C.Structure):
     _fields_ = [("shade_tile", C.c_int32), ("ssao_tile", C.c_int32), ("ssao_batch", C.c_int32),
-                ("blocks_per_cu", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("persistent", C.c_int32), ("wait_limit", C.c_int32)]
 
 
 STRUCTS = dict(epb_camera=epb_camera, epb_gbuffer=epb_gbuffer, epb_cube=epb_cube,
@@ -175,6 +177,7 @@ def _load() -> C.CDLL:
     lib.epb_batch_scratch_bytes.restype = C.c_size_t
     lib.epb_batch_build.argtypes = [P, C.c_int32, P, P, C.c_size_t, P, C.c_size_t]
     lib.epb_render_batch.argtypes = [P, P, P]
+    lib.epb_batch_status.argtypes = [P, P, P]
     lib.epb_raycast.argtypes = [C.POINTER(epb_sphere_scene), C.POINTER(epb_camera), C.POINTER(epb_gbuffer), P,
                                 C.c_size_t, P]
     lib.epb_edl.argtypes = [P, P, C.c_int, C.POINTER(epb_camera), P, C.c_int, C.POINTER(epb_edl_params),
@@ -183,7 +186,8 @@ def _load() -> C.CDLL:
     lib.epb_shadow_tiles_bytes.restype = C.c_size_t
     lib.epb_shadow_tiles.argtypes = [P, C.c_int32, C.c_int32, P, C.c_size_t, P]
     for fn in ("epb_precompute_ibl", "epb_ssao", "epb_ssao_static", "epb_shade", "epb_bloom_tonemap",
-               "epb_shade_post", "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_raycast", "epb_edl",
+               "epb_shade_post", "epb_last_hip_error", "epb_batch_build", "epb_render_batch", "epb_batch_status",
+               "epb_raycast", "epb_edl",
                "epb_shadow_tiles"):
         getattr(lib, fn).restype = C.c_int
     return lib
@@ -311,6 +315,12 @@ def epb_render_batch(table, table_dev, stream=None, check: bool = True) -> int:
     tab = C.addressof(table) if isinstance(table, C.Array) else _ptr(table)
     st = lib.epb_render_batch(tab, _ptr(table_dev), _stream(stream))
     return _check("epb_render_batch", st, check)
+
+
+def epb_batch_status(table, table_dev, stream=None, check: bool = True) -> int:
+    tab = C.addressof(table) if isinstance(table, C.Array) else _ptr(table)
+    st = lib.epb_batch_status(tab, _ptr(table_dev), _stream(stream))
+    return _check("epb_batch_status", st, check)
 
 
 def epb_raycast(scene: epb_sphere_scene, cam: epb_camera, out: epb_gbuffer, scratch, scratch_bytes: int,

@@ -248,8 +248,9 @@ class DeviceView:
         return v
 
 
-def make_schedule(shade_tile=0, ssao_tile=0, ssao_batch=0, blocks_per_cu=0) -> E.epb_schedule:
-    return E.epb_schedule(shade_tile, ssao_tile, ssao_batch, blocks_per_cu)
+def make_schedule(shade_tile=0, ssao_tile=0, ssao_batch=0, blocks_per_cu=0, persistent=0,
+                  wait_limit=0) -> E.epb_schedule:
+    return E.epb_schedule(shade_tile, ssao_tile, ssao_batch, blocks_per_cu, persistent, wait_limit)
 
 
 class DeviceBatch:
@@ -283,6 +284,11 @@ class DeviceBatch:
 
     def render(self, stream=None):
         E.epb_render_batch(self.table_host.data_ptr(), self.table_dev, stream)
+
+    def status(self, stream=None, check: bool = False) -> int:
+        """EPB_OK, or EPB_ERR_TIMEOUT when a wait of the last persistent render
+        gave up (waits for the stream)."""
+        return E.epb_batch_status(self.table_host.data_ptr(), self.table_dev, stream, check=check)
 
 
 class DeviceScene:

@@ -356,11 +356,55 @@ def test_batch_build_table():
     sizes = [(64, 48), (33, 17), (3, 2), (1920, 1080)]
     b = _Batch(sizes)
     assert b.build() == E.EPB_OK
-    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 19)).contents)
-    assert words[0] == 0x45504231 and words[1] == len(sizes)
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 32)).contents)
+    assert words[0] == 0x45504232 and words[1] == len(sizes)
     totals = words[12:19]
     exp = [sum(col) for col in zip(*[_expected_items(w, h) for w, h in sizes])]
     assert totals == exp
+    assert words[19] == 0  # stage launches
+
+
+def _persistent_items(w, h, levels=6):
+    """Tiles of the persistent launch: SSAO raw and blur on 16x16 texels, the
+    composite as groups of four 64x8 tiles; the other stages as above."""
+    it = _expected_items(w, h, levels)
+    wh, hh = (w + 1) // 2, (h + 1) // 2
+    it[1] = it[2] = _cdiv(wh, 16) * _cdiv(hh, 16)
+    it[6] = _cdiv(it[6], 4)
+    return it
+
+
+@pytest.mark.parametrize("chunk", [1, 7, 64])
+def test_batch_build_persistent_table(chunk):
+    """Header of a persistent table: work items per stage, chunks of `chunk`
+    tiles per view and stage, the first chunk of each stage, the wait limit."""
+    sizes = [(64, 48), (33, 17), (3, 2), (1920, 1080)]
+    b = _Batch(sizes)
+    assert b.build(sched=E.epb_schedule(0, 0, 0, 0, chunk, 0)) == E.EPB_OK
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 32)).contents)
+    items = [_persistent_items(w, h) for w, h in sizes]
+    assert words[12:19] == [sum(col) for col in zip(*items)]
+    persistent, k, limit, gate, total = words[19:24]
+    assert (persistent, k, limit, gate) == (1, chunk, 1 << 22, 1)
+    per_stage = [sum(_cdiv(n, chunk) for n in col) for col in zip(*items)]
+    first = [sum(per_stage[:s]) for s in range(8)]
+    assert words[24:32] == first and total == sum(per_stage)
+    assert b.build(sched=E.epb_schedule(0, 0, 0, 0, chunk, -50)) == E.EPB_OK  # error-path test mode
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 32)).contents)
+    assert words[21:23] == [50, 0]
+
+
+def test_batch_status_validation():
+    junk = (C.c_uint8 * 4096)()
+    assert E.lib.epb_batch_status(C.addressof(junk), FAKE, None) == E.EPB_ERR_PARAM
+    assert E.lib.epb_batch_status(None, FAKE, None) == E.EPB_ERR_NULL
+    b = _Batch([(64, 48)])
+    assert b.build() == E.EPB_OK
+    assert E.lib.epb_batch_status(C.addressof(b.table), None, None) == E.EPB_ERR_NULL
+    assert E.lib.epb_batch_status(C.addressof(b.table), FAKE + 8, None) == E.EPB_ERR_ALIGN
+    # stage launches never wait: nothing to read back
+    assert E.lib.epb_batch_status(C.addressof(b.table), FAKE, None) == E.EPB_OK
+    assert E.epb_status_str(E.EPB_ERR_TIMEOUT).startswith("a dependency wait")
 
 
 def test_batch_build_validation():
@@ -371,10 +415,15 @@ def test_batch_build_validation():
     assert b.build(sc=FAKE + 4) == E.EPB_ERR_ALIGN
     assert b.build(table_bytes=64) == E.EPB_ERR_SIZE
     for bad in (E.epb_schedule(3, 0, 0, 0), E.epb_schedule(0, 3, 0, 0), E.epb_schedule(0, 0, 2, 0),
-                E.epb_schedule(0, 0, 0, 65), E.epb_schedule(-1, 0, 0, 0)):
+                E.epb_schedule(0, 0, 0, 65), E.epb_schedule(-1, 0, 0, 0), E.epb_schedule(0, 0, 0, 0, -1),
+                E.epb_schedule(0, 0, 0, 0, E.EPB_MAX_PERSISTENT_CHUNK + 1)):
         assert b.build(sched=bad) == E.EPB_ERR_PARAM
     assert b.build(sched=E.epb_schedule(2, 1, 1, 4)) == E.EPB_OK
     assert _Batch([(64, 48), (33, 17)], gdtypes=[E.EPB_F32, E.EPB_F16]).build() == E.EPB_ERR_DTYPE
+    # the persistent launch takes one storage type throughout (these views: FP16 G-buffer, FP32 rest)
+    mixed = _Batch([(64, 48), (33, 17)], gdtypes=[E.EPB_F16, E.EPB_F16])
+    assert mixed.build() == E.EPB_OK
+    assert mixed.build(sched=E.epb_schedule(0, 0, 0, 0, 16)) == E.EPB_ERR_DTYPE
     assert _Batch([(64, 48), (33, 17)], blurs=[1, 0]).build() == E.EPB_ERR_PARAM
     # a view failing the single-view checks fails the batch with the same status
     bad = _Batch([(64, 48), (33, 17)])

@@ -78,9 +78,11 @@ def _assert_same(a, b, what):
             assert torch.equal(p, q), f"{what}: view {k} ({SIZES[k][:2]}) {name} differs"
 
 
-# (shade tile, SSAO tile, SSAO gathers in flight, blocks per CU); SSAO tile 2 stages
-# its depth window in LDS
-SCHEDULES = [(0, 0, 0, 0), (1, 1, 1, 2), (2, 0, 1, 4), (0, 1, 0, 1), (1, 0, 0, 8), (0, 2, 0, 0), (2, 2, 1, 2)]
+# (shade tile, SSAO tile, SSAO gathers in flight, blocks per CU[, persistent chunk]);
+# SSAO tile 2 stages its depth window in LDS; a persistent chunk k > 0 renders the
+# whole batch in one launch, k tiles per work item (blocks per CU 0: as many as fit)
+SCHEDULES = [(0, 0, 0, 0), (1, 1, 1, 2), (2, 0, 1, 4), (0, 1, 0, 1), (1, 0, 0, 8), (0, 2, 0, 0), (2, 2, 1, 2),
+             (0, 0, 0, 0, 1), (0, 0, 0, 0, 16), (0, 0, 0, 2, 64), (0, 0, 0, 1, 4096)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "sched-" + "-".join(map(str, s)))
@@ -95,6 +97,7 @@ def test_batch_equals_solo(sched):
     b = fr.DeviceBatch(dvs, fr.make_schedule(*sched))
     log(f"[batch] schedule {sched}: batched render")
     b.render()
+    assert b.status() == 0  # no persistent wait gave up
     _assert_same(_outputs(dvs), solo, f"schedule {sched}")
 
 
@@ -103,11 +106,16 @@ def test_batch_fp16_and_unblurred_equal_solo():
     from paper_2012_03325_amd import frame as fr
     dvs = _device_views(_views(), gdtype=E.EPB_F16, ao_dtype=E.EPB_F16, hdr_dtype=E.EPB_F16)
     for blur in (True, False):
-        log(f"[batch] FP16 form, blur={blur}")
         solo = _solo(dvs, blur=blur)
-        b = fr.DeviceBatch(dvs, fr.make_schedule(1, 1, 1, 2), blur=blur)
-        b.render()
-        _assert_same(_outputs(dvs), solo, f"fp16 blur={blur}")
+        for sched in ((1, 1, 1, 2), (0, 0, 0, 0, 16)):
+            log(f"[batch] FP16 form, blur={blur}, schedule {sched}")
+            for dv in dvs:
+                for t in (dv.ao, dv.hdr, dv.ldr):
+                    t.zero_()
+            b = fr.DeviceBatch(dvs, fr.make_schedule(*sched), blur=blur)
+            b.render()
+            assert b.status() == E.EPB_OK
+            _assert_same(_outputs(dvs), solo, f"fp16 blur={blur} schedule {sched}")
 
 
 def test_batch_scratch_outputs():
@@ -127,10 +135,13 @@ def test_batch_scratch_outputs():
         assert (dv.hdr == -1.0).all(), k  # not written
 
 
-def test_batch_graph_replay_equals_eager():
+@pytest.mark.parametrize("sched", [(1, 1, 1, 4), (0, 0, 0, 0, 16)], ids=lambda s: "sched-" + "-".join(map(str, s)))
+def test_batch_graph_replay_equals_eager(sched):
+    """Graph replays (the persistent form's counter clear is a kernel in the
+    graph, not a memset) equal the eager render, with eager work in between."""
     from paper_2012_03325_amd import frame as fr
     dvs = _device_views(_views())
-    b = fr.DeviceBatch(dvs, fr.make_schedule(1, 1, 1, 4))
+    b = fr.DeviceBatch(dvs, fr.make_schedule(*sched))
     b.render()
     eager = _outputs(dvs)
     g = torch.cuda.CUDAGraph()
@@ -152,6 +163,28 @@ def test_batch_graph_replay_equals_eager():
         log(f"[graph] replay {rep}")
         g.replay()
         _assert_same(_outputs(dvs), eager, f"graph replay {rep}")
+
+
+def test_persistent_wait_that_gives_up_is_reported():
+    """The error path of the persistent launch, forced from the host: in test
+    mode (a negative wait limit) no dependency is ever seen complete, so the
+    first waiting work item gives up after 50 polls, sets the error word and
+    every block stops taking work; the launch ends normally and
+    epb_batch_status reports it.  The same table rebuilt with the normal
+    limit then renders every view as the solo calls do."""
+    from paper_2012_03325_amd import epb as E
+    from paper_2012_03325_amd import frame as fr
+    dvs = _device_views(_views())
+    solo = _solo(dvs)
+    b = fr.DeviceBatch(dvs, fr.make_schedule(0, 0, 0, 0, 16, -50))
+    log("[persistent] render with waits that give up")
+    b.render()
+    assert b.status() == E.EPB_ERR_TIMEOUT
+    b.build(fr.make_schedule(0, 0, 0, 0, 16))
+    log("[persistent] render again with the normal wait limit")
+    b.render()
+    assert b.status() == E.EPB_OK
+    _assert_same(_outputs(dvs), solo, "persistent after a failed render")
 
 
 @pytest.mark.parametrize("k", [2, 3, 6])
