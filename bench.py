@@ -328,7 +328,8 @@ def bench_batched(args, torch, E, frame, synth) -> dict:
             "batched_ms": round(mean_ms, 4), "batched_p50_ms": round(med_ms, 4),
             "batched_default_schedule_ms": round(default_ms, 4),
             "schedule": tuned, "autotune_tried": len(trace),
-            "autotune_trials_ms": [[*(t["schedule"][k] for k in autotune.ORDER), round(t["ms"], 4)] for t in trace],
+            "autotune_trials_ms": [[*(t["schedule"][k] for k in autotune.ORDER),
+                                    None if t["ms"] is None else round(t["ms"], 4)] for t in trace],
             "autotune_trial_fields": [*autotune.ORDER, "ms"],
             "plain_eager_Mpix_s": round(px / (plain_ms / 1e3) / 1e6, 2), "plain_eager_ms": round(plain_ms, 4),
             "plain_graph_Mpix_s": round(px / (plain_graph_ms / 1e3) / 1e6, 2),
@@ -846,7 +847,7 @@ def main():
         tuned = out["batched"]["fp16"]["schedule"]
         # (the serving batches mix storage types per buffer: stage launches only)
         sched = E.epb_schedule(tuned["shade_tile"], tuned["ssao_tile"], tuned["ssao_batch"],
-                               tuned["blocks_per_cu"], 0, 0)
+                               tuned["blocks_per_cu"], 0, 0, tuned.get("fuse_bloom", 0))
     if not args.no_serve:
         out["serving"] = bench_serving(args, torch, E, frame, synth, sched)
     if not args.no_cpu:

@@ -439,6 +439,9 @@ typedef struct {
                               workgroup gives up (0: 2^22, about seconds); a
                               negative value -k makes every wait give up after k
                               polls (for testing the error path)               */
+    int32_t fuse_bloom;    /* 1: the shading stage also forms bloom level 1, as
+                              epb_shade_post does (stage launches with shading
+                              tile 0 only; else EPB_ERR_PARAM)                  */
 } epb_schedule;
 
 #define EPB_MAX_PERSISTENT_CHUNK 4096

@@ -2,8 +2,8 @@
 
 A batch's schedule (shading tile, SSAO tile, SSAO gathers in flight,
 workgroups per CU, seven stage launches or one persistent launch and its work
-item size) changes only the speed of epb_render_batch, never its results, so
-it can be picked by measurement alone.  The tuner runs a
+item size, bloom level 1 in the shading stage or not) changes only the speed of
+epb_render_batch, never its results, so it can be picked by measurement alone.  The tuner runs a
 coordinate descent over the schedule space: starting from the current best,
 it tries every value of one parameter with the others held, keeps the fastest
 (median of HIP-event timings over a few renders) and moves to the next
@@ -31,8 +31,9 @@ SPACE: Dict[str, Tuple[int, ...]] = {
     "ssao_tile": (0, 1, 2),
     "ssao_batch": (0, 1),
     "persistent": (0, 16, 64, 256, 1024),
+    "fuse_bloom": (0, 1),
 }
-ORDER = ("blocks_per_cu", "shade_tile", "ssao_tile", "ssao_batch", "persistent")
+ORDER = ("blocks_per_cu", "shade_tile", "ssao_tile", "ssao_batch", "persistent", "fuse_bloom")
 
 _lock = threading.Lock()
 _cache: Dict[str, Dict[str, int]] = {}
@@ -44,7 +45,7 @@ def _as_dict(s: E.epb_schedule) -> Dict[str, int]:
 
 def _as_sched(d: Dict[str, int]) -> E.epb_schedule:
     return E.epb_schedule(d["shade_tile"], d["ssao_tile"], d["ssao_batch"], d["blocks_per_cu"],
-                          d.get("persistent", 0), 0)
+                          d.get("persistent", 0), 0, d.get("fuse_bloom", 0))
 
 
 def signature(batch, device: Optional[str] = None) -> str:
@@ -100,12 +101,15 @@ def tune(batch, reps: int = 3, passes: int = 2, cache_path: Optional[str] = None
         if key not in tried:
             try:
                 batch.build(_as_sched(d))
-            except E.EpbError:  # a schedule this batch cannot take (persistent with mixed storage)
+            except E.EpbError as e:  # a schedule this batch cannot take (e.g. persistent with mixed storage)
                 tried[key] = float("inf")
+                trace.append(dict(schedule=dict(d), ms=None, rejected=str(e)))
                 return tried[key]
             ms = timer(batch, reps)
             if d.get("persistent") and batch.status() != E.EPB_OK:  # a wait gave up: not a valid render
-                ms = float("inf")
+                tried[key] = float("inf")
+                trace.append(dict(schedule=dict(d), ms=None, rejected="a persistent wait gave up"))
+                return tried[key]
             tried[key] = ms
             trace.append(dict(schedule=dict(d), ms=ms))
         return tried[key]

@@ -263,8 +263,11 @@ int batch_scratch(const epb_view *views, int32_t n, size_t *bytes) {
 int check_schedule(const epb_schedule &q) {
     if (q.shade_tile < 0 || q.shade_tile > 2 || q.ssao_tile < 0 || q.ssao_tile > 2 || q.ssao_batch < 0 ||
         q.ssao_batch > 1 || q.blocks_per_cu < 0 || q.blocks_per_cu > 64 || q.persistent < 0 ||
-        q.persistent > EPB_MAX_PERSISTENT_CHUNK || q.wait_limit < -(1 << 30))
+        q.persistent > EPB_MAX_PERSISTENT_CHUNK || q.wait_limit < -(1 << 30) || q.fuse_bloom < 0 ||
+        q.fuse_bloom > 1)
         return EPB_ERR_PARAM;
+    // the fused bloom epilogue needs the 32 x 8 shading tile of the stage launches
+    if (q.fuse_bloom && (q.shade_tile != 0 || q.persistent)) return EPB_ERR_PARAM;
     return EPB_OK;
 }
 
@@ -584,6 +587,11 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
         d.shade = epb::shade_desc(a);
         if ((st = build_post(hdr, v.hdr_dtype, v.cam.width, v.cam.height, v.post, v.ldr, s_post, vs.post, &d.post)))
             return st;
+        if (q.fuse_bloom && d.post.nl >= 1) {  // the shading stage writes bloom level 1
+            d.shade.bloom1 = d.post.raw[1];
+            d.shade.bloom1_half = d.post.texel_half;
+            d.shade.bloom_threshold = d.post.threshold;
+        }
         int items[epb::kStages];
         if (q.persistent) {
             persistent_items(d, items);
@@ -619,6 +627,7 @@ int epb_batch_build(const epb_view *views, int32_t n_views, const epb_schedule *
     h.ssao_tile = q.ssao_tile;
     h.ssao_batch = q.ssao_batch;
     h.blocks_per_cu = q.blocks_per_cu;
+    h.fuse_bloom = q.fuse_bloom;
     for (int k = 0; k < epb::kStages; ++k) {
         h.total[k] = (int)total[k];
         start[k * (n_views + 1) + n_views] = (int)total[k];

@@ -175,6 +175,7 @@ struct BatchHeader {
     int gdtype, ao_dtype, hdr_dtype, pyr_dtype;
     int blur, has_ao;
     int shade_tile, ssao_tile, ssao_batch, blocks_per_cu;
+    int fuse_bloom;      // the shading stage writes bloom level 1; the down stage starts from it
     int total[kStages];  // work items of each stage over all views
     // one persistent launch (persistent != 0): work items are chunks of `chunk`
     // tiles of one view and stage, handed out in stage-major order

@@ -65,6 +65,20 @@ __global__ void __launch_bounds__(256) k_bloom_down_batch(const void *__restrict
 }
 
 template <typename TP>
+__global__ void __launch_bounds__(256) k_bloom_down_from1_batch(const void *__restrict__ table) {
+    __shared__ DownLds sm;
+    const BatchHeader *h = (const BatchHeader *)table;
+    const int *start = batch_start(table, kStDown);
+    const ViewDesc *views = batch_views(table);
+    XcdRange w = xcd_range(h->total[kStDown]);
+    for (int it = w.lb; it < w.count; it += w.stride) {
+        int g = w.first + it;
+        int v = find_view(start, h->n_views, g);
+        bloom_down_from1_tile<TP>(views[v].post, g - start[v], sm);
+    }
+}
+
+template <typename TP>
 __global__ void __launch_bounds__(256) k_bloom_blur_batch(const void *__restrict__ table) {
     __shared__ BlurLds sm;
     const BatchHeader *h = (const BatchHeader *)table;
@@ -175,7 +189,10 @@ static void launch_post(const PostDesc &c, bool level1_given, hipStream_t s) {
 
 template <typename TH, typename TP>
 static void launch_post_batch_t(const BatchHeader &h, const void *table, hipStream_t s) {
-    if (h.total[kStDown] > 0)
+    if (h.total[kStDown] > 0 && h.fuse_bloom)  // level 1 came from the shading stage
+        hipLaunchKernelGGL(k_bloom_down_from1_batch<TP>, dim3(batch_grid(h.total[kStDown], h.blocks_per_cu)),
+                           dim3(256), 0, s, table);
+    else if (h.total[kStDown] > 0)
         hipLaunchKernelGGL((k_bloom_down_batch<TH, TP>), dim3(batch_grid(h.total[kStDown], h.blocks_per_cu)),
                            dim3(256), 0, s, table);
     if (h.total[kStBloomBlur] > 0)

@@ -40,7 +40,7 @@ k_shade(const ShadeDesc c, int tiles) {
     shade_tile<TX, TY, kBloom1, TG, TA, TH>(c, xcd_tile(blockIdx.x, tiles));
 }
 
-template <int TX, int TY, typename TG, typename TA, typename TH>
+template <int TX, int TY, bool kBloom1, typename TG, typename TA, typename TH>
 __global__ void __launch_bounds__(TX *TY) __attribute__((amdgpu_waves_per_eu(kShadeMinWaves)))
 k_shade_batch(const void *__restrict__ table) {
     const BatchHeader *h = (const BatchHeader *)table;
@@ -50,7 +50,7 @@ k_shade_batch(const void *__restrict__ table) {
     for (int it = w.lb; it < w.count; it += w.stride) {
         int g = w.first + it;
         int v = find_view(start, h->n_views, g);
-        shade_tile<TX, TY, false, TG, TA, TH>(views[v].shade, g - start[v]);
+        shade_tile<TX, TY, kBloom1, TG, TA, TH>(views[v].shade, g - start[v]);
     }
 }
 
@@ -100,10 +100,10 @@ static void go(const ShadeDesc &k, hipStream_t s) {
     else
         hipLaunchKernelGGL((k_shade<32, 8, false, TG, TA, TH>), dim3(tiles), dim3(256), 0, s, k, tiles);
 }
-template <int TX, int TY, typename TG, typename TA, typename TH>
+template <int TX, int TY, bool kBloom1, typename TG, typename TA, typename TH>
 static void go_batch(const BatchHeader &h, const void *table, hipStream_t s) {
-    hipLaunchKernelGGL((k_shade_batch<TX, TY, TG, TA, TH>), dim3(batch_grid(h.total[kStShade], h.blocks_per_cu)),
-                       dim3(TX * TY), 0, s, table);
+    hipLaunchKernelGGL((k_shade_batch<TX, TY, kBloom1, TG, TA, TH>),
+                       dim3(batch_grid(h.total[kStShade], h.blocks_per_cu)), dim3(TX * TY), 0, s, table);
 }
 template <typename TG, typename TA, typename TH>
 static void go_shape(const BatchHeader *h, const void *table, const ShadeDesc *k, hipStream_t s) {
@@ -111,10 +111,14 @@ static void go_shape(const BatchHeader *h, const void *table, const ShadeDesc *k
         go<TG, TA, TH>(*k, s);
         return;
     }
+    if (h->fuse_bloom) {  // 32 x 8 tiles only (rows 2k, 2k + 1 in one wavefront; checked on the host)
+        go_batch<32, 8, true, TG, TA, TH>(*h, table, s);
+        return;
+    }
     switch (h->shade_tile) {
-    case 1: go_batch<64, 4, TG, TA, TH>(*h, table, s); break;
-    case 2: go_batch<16, 16, TG, TA, TH>(*h, table, s); break;
-    default: go_batch<32, 8, TG, TA, TH>(*h, table, s); break;
+    case 1: go_batch<64, 4, false, TG, TA, TH>(*h, table, s); break;
+    case 2: go_batch<16, 16, false, TG, TA, TH>(*h, table, s); break;
+    default: go_batch<32, 8, false, TG, TA, TH>(*h, table, s); break;
     }
 }
 template <typename TG, typename TA>

@@ -252,7 +252,9 @@ __device__ __forceinline__ void shade_tile(const ShadeDesc &c, int tile) {
     // (with kBloom1 every lane reaches the epilogue; otherwise out-of-image lanes leave here)
     if (!kBloom1 && !in) return;
     if (in) shade_pixel<TG, TA, TH>(c, x, y, out);
-    if constexpr (kBloom1) bloom1_epilogue<TX, TH>(c, x, y, in, out);
+    if constexpr (kBloom1) {
+        if (c.bloom1) bloom1_epilogue<TX, TH>(c, x, y, in, out);  // (uniform: null for a view without bloom)
+    }
 }
 
 }  // namespace epb

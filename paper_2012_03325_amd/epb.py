@@ -129,7 +129,8 @@ class epb_edl_params(C.Structure):
 
 class epb_schedule(C.Structure):
     _fields_ = [("shade_tile", C.c_int32), ("ssao_tile", C.c_int32), ("ssao_batch", C.c_int32),
-                ("blocks_per_cu", C.c_int32), ("persistent", C.c_int32), ("wait_limit", C.c_int32)]
+                ("blocks_per_cu", C.c_int32), ("persistent", C.c_int32), ("wait_limit", C.c_int32),
+                ("fuse_bloom", C.c_int32)]
 
 
 STRUCTS = dict(epb_camera=epb_camera, epb_gbuffer=epb_gbuffer, epb_cube=epb_cube,

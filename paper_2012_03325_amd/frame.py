@@ -249,8 +249,8 @@ class DeviceView:
 
 
 def make_schedule(shade_tile=0, ssao_tile=0, ssao_batch=0, blocks_per_cu=0, persistent=0,
-                  wait_limit=0) -> E.epb_schedule:
-    return E.epb_schedule(shade_tile, ssao_tile, ssao_batch, blocks_per_cu, persistent, wait_limit)
+                  wait_limit=0, fuse_bloom=0) -> E.epb_schedule:
+    return E.epb_schedule(shade_tile, ssao_tile, ssao_batch, blocks_per_cu, persistent, wait_limit, fuse_bloom)
 
 
 class DeviceBatch:

@@ -356,12 +356,15 @@ def test_batch_build_table():
     sizes = [(64, 48), (33, 17), (3, 2), (1920, 1080)]
     b = _Batch(sizes)
     assert b.build() == E.EPB_OK
-    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 32)).contents)
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 33)).contents)
     assert words[0] == 0x45504232 and words[1] == len(sizes)
-    totals = words[12:19]
+    totals = words[13:20]
     exp = [sum(col) for col in zip(*[_expected_items(w, h) for w, h in sizes])]
     assert totals == exp
-    assert words[19] == 0  # stage launches
+    assert words[12] == 0 and words[20] == 0  # no fused bloom, stage launches
+    assert b.build(sched=E.epb_schedule(0, 1, 1, 2, 0, 0, 1)) == E.EPB_OK
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 33)).contents)
+    assert words[12] == 1 and words[13:20] != [0] * 7
 
 
 def _persistent_items(w, h, levels=6):
@@ -381,17 +384,17 @@ def test_batch_build_persistent_table(chunk):
     sizes = [(64, 48), (33, 17), (3, 2), (1920, 1080)]
     b = _Batch(sizes)
     assert b.build(sched=E.epb_schedule(0, 0, 0, 0, chunk, 0)) == E.EPB_OK
-    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 32)).contents)
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 33)).contents)
     items = [_persistent_items(w, h) for w, h in sizes]
-    assert words[12:19] == [sum(col) for col in zip(*items)]
-    persistent, k, limit, gate, total = words[19:24]
+    assert words[13:20] == [sum(col) for col in zip(*items)]
+    persistent, k, limit, gate, total = words[20:25]
     assert (persistent, k, limit, gate) == (1, chunk, 1 << 22, 1)
     per_stage = [sum(_cdiv(n, chunk) for n in col) for col in zip(*items)]
     first = [sum(per_stage[:s]) for s in range(8)]
-    assert words[24:32] == first and total == sum(per_stage)
+    assert words[25:33] == first and total == sum(per_stage)
     assert b.build(sched=E.epb_schedule(0, 0, 0, 0, chunk, -50)) == E.EPB_OK  # error-path test mode
-    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 32)).contents)
-    assert words[21:23] == [50, 0]
+    words = list(C.cast(b.table, C.POINTER(C.c_int32 * 33)).contents)
+    assert words[22:24] == [50, 0]
 
 
 def test_batch_status_validation():
@@ -416,7 +419,9 @@ def test_batch_build_validation():
     assert b.build(table_bytes=64) == E.EPB_ERR_SIZE
     for bad in (E.epb_schedule(3, 0, 0, 0), E.epb_schedule(0, 3, 0, 0), E.epb_schedule(0, 0, 2, 0),
                 E.epb_schedule(0, 0, 0, 65), E.epb_schedule(-1, 0, 0, 0), E.epb_schedule(0, 0, 0, 0, -1),
-                E.epb_schedule(0, 0, 0, 0, E.EPB_MAX_PERSISTENT_CHUNK + 1)):
+                E.epb_schedule(0, 0, 0, 0, E.EPB_MAX_PERSISTENT_CHUNK + 1),
+                E.epb_schedule(0, 0, 0, 0, 0, 0, 2), E.epb_schedule(1, 0, 0, 0, 0, 0, 1),
+                E.epb_schedule(2, 0, 0, 0, 0, 0, 1), E.epb_schedule(0, 0, 0, 0, 16, 0, 1)):
         assert b.build(sched=bad) == E.EPB_ERR_PARAM
     assert b.build(sched=E.epb_schedule(2, 1, 1, 4)) == E.EPB_OK
     assert _Batch([(64, 48), (33, 17)], gdtypes=[E.EPB_F32, E.EPB_F16]).build() == E.EPB_ERR_DTYPE

@@ -44,32 +44,32 @@ class _FakeBatch:
 
 def test_coordinate_descent_finds_the_separable_minimum_and_leaves_it_built():
     A._cache.clear()
-    best = dict(blocks_per_cu=4, shade_tile=2, ssao_tile=1, ssao_batch=1, persistent=16)
+    best = dict(blocks_per_cu=4, shade_tile=2, ssao_tile=1, ssao_batch=1, persistent=16, fuse_bloom=1)
     b = _FakeBatch(best)
     sched, trace = A.tune(b, reps=1, passes=2, use_cache=False, timer=b.time, device="test")
     assert A._as_dict(sched) == best
     assert A._as_dict(b.schedule) == best  # the batch is left built with the pick
-    # no schedule is timed twice, and the search stays far below the full grid (5*3*3*2*5 = 450)
+    # no schedule is timed twice, and the search stays far below the full grid (5*3*3*2*5*2 = 900)
     keys = [tuple(t["schedule"][k] for k in A.ORDER) for t in trace]
-    assert len(keys) == len(set(keys)) and len(keys) < 25
+    assert len(keys) == len(set(keys)) and len(keys) < 30
 
 
 def test_schedules_a_batch_cannot_take_or_that_give_up_are_skipped():
     """A schedule the batch rejects (persistent with mixed storage) or whose
     persistent render reports a wait that gave up is never picked."""
     A._cache.clear()
-    best = dict(blocks_per_cu=0, shade_tile=0, ssao_tile=0, ssao_batch=0, persistent=64)
-    b = _FakeBatch(best, invalid={(0, 0, 0, 0, 64)}, gives_up={(0, 0, 0, 0, 16)})
+    best = dict(blocks_per_cu=0, shade_tile=0, ssao_tile=0, ssao_batch=0, persistent=64, fuse_bloom=0)
+    b = _FakeBatch(best, invalid={(0, 0, 0, 0, 64, 0)}, gives_up={(0, 0, 0, 0, 16, 0)})
     sched, trace = A.tune(b, reps=1, passes=2, use_cache=False, timer=b.time, device="test")
     assert A._as_dict(sched)["persistent"] not in (16, 64)
-    assert all(t["ms"] == float("inf") for t in trace if t["schedule"]["persistent"] == 16)
+    assert all(t["ms"] is None and t["rejected"] for t in trace if t["schedule"]["persistent"] in (16, 64))
 
 
 def test_second_pass_escapes_a_coupled_valley():
     """A slower cell on the first pass's path is avoided by the second pass."""
     A._cache.clear()
-    best = dict(blocks_per_cu=0, shade_tile=1, ssao_tile=1, ssao_batch=0, persistent=0)
-    b = _FakeBatch(best, extra={(0, 1, 0, 0, 0): 5.0})  # stepping to shade_tile 1 alone looks worse
+    best = dict(blocks_per_cu=0, shade_tile=1, ssao_tile=1, ssao_batch=0, persistent=0, fuse_bloom=0)
+    b = _FakeBatch(best, extra={(0, 1, 0, 0, 0, 0): 5.0})  # stepping to shade_tile 1 alone looks worse
     s1, _ = A.tune(b, reps=1, passes=1, use_cache=False, timer=b.time, device="test")
     s2, _ = A.tune(b, reps=1, passes=3, use_cache=False, timer=b.time, device="test")
     assert A._as_dict(s1) != best  # one pass stops short
@@ -80,7 +80,7 @@ def test_second_pass_escapes_a_coupled_valley():
 def test_cache_hit_skips_timing_and_survives_a_restart(tmp_path):
     A._cache.clear()
     path = str(tmp_path / "sched.json")
-    best = dict(blocks_per_cu=2, shade_tile=0, ssao_tile=1, ssao_batch=0, persistent=256)
+    best = dict(blocks_per_cu=2, shade_tile=0, ssao_tile=1, ssao_batch=0, persistent=256, fuse_bloom=1)
     b = _FakeBatch(best)
     A.tune(b, reps=1, use_cache=True, cache_path=path, timer=b.time, device="test")
     saved = json.load(open(path))

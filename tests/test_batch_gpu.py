@@ -78,11 +78,13 @@ def _assert_same(a, b, what):
             assert torch.equal(p, q), f"{what}: view {k} ({SIZES[k][:2]}) {name} differs"
 
 
-# (shade tile, SSAO tile, SSAO gathers in flight, blocks per CU[, persistent chunk]);
+# (shade tile, SSAO tile, SSAO gathers in flight, blocks per CU[, persistent chunk, wait
+# limit, bloom level 1 in the shading stage]);
 # SSAO tile 2 stages its depth window in LDS; a persistent chunk k > 0 renders the
 # whole batch in one launch, k tiles per work item (blocks per CU 0: as many as fit)
 SCHEDULES = [(0, 0, 0, 0), (1, 1, 1, 2), (2, 0, 1, 4), (0, 1, 0, 1), (1, 0, 0, 8), (0, 2, 0, 0), (2, 2, 1, 2),
-             (0, 0, 0, 0, 1), (0, 0, 0, 0, 16), (0, 0, 0, 2, 64), (0, 0, 0, 1, 4096)]
+             (0, 0, 0, 0, 1), (0, 0, 0, 0, 16), (0, 0, 0, 2, 64), (0, 0, 0, 1, 4096),
+             (0, 1, 1, 0, 0, 0, 1), (0, 0, 0, 4, 0, 0, 1)]
 
 
 @pytest.mark.parametrize("sched", SCHEDULES, ids=lambda s: "sched-" + "-".join(map(str, s)))
@@ -107,7 +109,7 @@ def test_batch_fp16_and_unblurred_equal_solo():
     dvs = _device_views(_views(), gdtype=E.EPB_F16, ao_dtype=E.EPB_F16, hdr_dtype=E.EPB_F16)
     for blur in (True, False):
         solo = _solo(dvs, blur=blur)
-        for sched in ((1, 1, 1, 2), (0, 0, 0, 0, 16)):
+        for sched in ((1, 1, 1, 2), (0, 0, 0, 0, 16), (0, 1, 0, 0, 0, 0, 1)):
             log(f"[batch] FP16 form, blur={blur}, schedule {sched}")
             for dv in dvs:
                 for t in (dv.ao, dv.hdr, dv.ldr):
