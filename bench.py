@@ -240,6 +240,69 @@ def bench_edl(args, torch, E, frame, synth) -> dict:
     return res
 
 
+def bench_small(args, torch, E, frame, synth) -> dict:
+    """The 256x256 view (64 spheres, one light without shadows, SSAO 16, a 64^2
+    sky gradient), which alone cannot fill the chip: single-view frames replayed
+    from graphs with frames in flight over 16 rotated copies, and 256 copies
+    rendered as one batch (tuned schedule), FP32 and FP16."""
+    from paper_2012_03325_amd import autotune
+    v = synth.config_small()
+    ibl = frame.DeviceIBL(v.env, **v.ibl)
+    ibl.precompute()
+    s = torch.cuda.current_stream()
+    px = v.width * v.height
+    res = {"workload": "plain-256x256: 64 seeded spheres, 1 light without a depth map, SSAO 16 + blur, "
+                       "6x64^2 sky gradient (5-mip prefilter at 1024 samples, 32^2 irradiance, 256^2 LUT), "
+                       "6-level bloom, ACES"}
+    for name, dt in (("fp32", E.EPB_F32), ("fp16", E.EPB_F16)):
+        copies, F = 16, 4
+        dvs = [frame.DeviceView(v, ibl, gdtype=dt, ao_dtype=dt, hdr_dtype=dt) for _ in range(copies)]
+        side = torch.cuda.Stream()
+        graphs = []
+        for dv in dvs:
+            side.wait_stream(s)
+            with torch.cuda.stream(side):
+                dv.render()
+            s.wait_stream(side)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                dv.render()
+            graphs.append(g)
+        streams = [torch.cuda.Stream() for _ in range(F)]
+        K = max(400, args.steps)
+        for rep in range(2):  # the first pass is untimed
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for st in streams:
+                st.wait_stream(s)
+            for k in range(K):
+                with torch.cuda.stream(streams[k % F]):
+                    graphs[k % copies].replay()
+            for st in streams:
+                s.wait_stream(st)
+            e1.record(s)
+            torch.cuda.synchronize()
+        plain_ms = e0.elapsed_time(e1) / K
+        del graphs
+        many = [frame.DeviceView(v, ibl, gdtype=dt, ao_dtype=dt, hdr_dtype=dt, solo_scratch=False,
+                                 src=dvs[0]) for _ in range(256)]
+        b = frame.DeviceBatch(many)
+        sched, trace = autotune.tune(b, reps=3, passes=1, use_cache=False)
+        b.render()
+        torch.cuda.synchronize()
+        batch_ms = autotune.time_render(b, 10)
+        res[name] = {"plain_ms_per_frame": round(plain_ms, 5), "plain_Mpix_s": round(px / (plain_ms / 1e3) / 1e6, 1),
+                     "batched_256_ms": round(batch_ms, 4),
+                     "batched_256_Mpix_s": round(256 * px / (batch_ms / 1e3) / 1e6, 1),
+                     "schedule": autotune._as_dict(sched)}
+        log(f"small {name}: {res[name]}")
+        del dvs, many, b
+        torch.cuda.empty_cache()
+    return res
+
+
 def bench_batched(args, torch, E, frame, synth) -> dict:
     """The batched form on 16 scenes / 256 views of uneven resolution: the plain
     single-view calls over every view (eager, and captured in one graph)
@@ -543,37 +606,44 @@ def cpu_baseline(view, budget_s: float, fp16_gpu=None):
     form's outputs on the 256x256 view) the same oracle also states that
     form's error per output.  Returns (baseline, error statement or None)."""
     from oracle import oracle as orc
+    from paper_2012_03325_amd import synth
     statement = fp16_error_statement(orc, fp16_gpu) if fp16_gpu is not None else None
-    ibl = orc.precompute_ibl(view.env, **dict(view.ibl, pref_samples=64, lut_size=32,
-                                              lut_samples=64))
-    g = view.gbuf
-    px = view.width * view.height
 
-    def run(budget):
+    def tables(v):
+        return orc.precompute_ibl(v.env, **dict(v.ibl, pref_samples=64, lut_size=32, lut_samples=64))
+
+    def run(v, ibl, budget):
+        g = v.gbuf
         frames, t0 = 0, time.perf_counter()
         while True:
-            raw = orc.ssao_raw(g["depth"], g["normal"], view.cam, view.ssao_kernel, view.ssao_noise,
-                               view.ssao_radius, view.ssao_bias)
-            ao = orc.ssao_blur(*raw, g["depth"], view.blur_tau)
-            lo, hi = orc.shade(g, view.cam, *ao, view.lights, ibl, view.env)
-            orc.bloom_tonemap(lo, exposure=view.exposure)
+            raw = orc.ssao_raw(g["depth"], g["normal"], v.cam, v.ssao_kernel, v.ssao_noise,
+                               v.ssao_radius, v.ssao_bias)
+            ao = orc.ssao_blur(*raw, g["depth"], v.blur_tau)
+            lo, hi = orc.shade(g, v.cam, *ao, v.lights, ibl, v.env)
+            orc.bloom_tonemap(lo, exposure=v.exposure)
             frames += 1
             el = time.perf_counter() - t0
             if el >= budget:
                 return frames, el
 
+    px = view.width * view.height
+    ibl = tables(view)
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     orc.set_threads(threads)
-    frames, el = run(budget_s)
+    frames, el = run(view, ibl, budget_s)
     orc.set_threads(1)
-    frames1, el1 = run(budget_s / 3.0)
+    frames1, el1 = run(view, ibl, budget_s / 3.0)
     orc.set_threads(threads)
+    small = synth.config_small()  # the 256x256 view, 2 s
+    fs, els = run(small, tables(small), 2.0)
     return {"value": round(frames * px / el / 1e6, 3), "unit": "Mpix/s", "cores": threads,
             "kind": "oracle", "cpu_model": _cpu_model(),
             "single_thread_Mpix_s": round(frames1 * px / el1 / 1e6, 3),
+            "small_256_Mpix_s": round(fs * small.width * small.height / els / 1e6, 3),
             "sample": f"{frames} whole {view.width}x{view.height} frames of the FP64 oracle "
                       f"(SSAO+blur+shade+bloom/tonemap, IBL tables precomputed outside) in {el:.1f} s on "
-                      f"{threads} threads; {frames1} frames in {el1:.1f} s on one thread"}, statement
+                      f"{threads} threads; {frames1} frames in {el1:.1f} s on one thread; {fs} frames of the "
+                      f"256x256 view in {els:.1f} s on {threads} threads"}, statement
 
 
 def main():
@@ -590,6 +660,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10, help="timed replays of the batched frame")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving form")
     ap.add_argument("--no-edl", action="store_true", help="skip the eye-dome lighting measurement")
+    ap.add_argument("--no-small", action="store_true", help="skip the 256x256 view (single frames and a batch)")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of arrivals per rate (max 10)")
     ap.add_argument("--serve-min-requests", type=int, default=200, help="requests per rate at least")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of request slots")
@@ -841,6 +912,8 @@ def main():
     }
     if not args.no_edl:
         out["edl"] = bench_edl(args, torch, E, frame, synth)
+    if not args.no_small:
+        out["small_256"] = bench_small(args, torch, E, frame, synth)
     sched = None
     if not args.no_batch:
         out["batched"] = bench_batched(args, torch, E, frame, synth)
