@@ -232,3 +232,34 @@ def test_autotuned_schedule_equals_default():
             assert torch.equal(p, q), k
     s2, t2 = autotune.tune(b)
     assert t2[0].get("cached") and autotune._as_dict(s2) == autotune._as_dict(sched)
+
+
+@pytest.mark.parametrize("sched", [(0, 0, 0, 0), (0, 0, 0, 0, 64)], ids=["stages", "persistent-64"])
+def test_batch_of_the_maximum_view_count(sched):
+    """EPB_MAX_BATCH_VIEWS views (two small sizes, one SSAO kernel length each)
+    in one batch: the table's prefix sums, chunk lists and per-view counters at
+    their largest; every sampled view equals its solo render bit for bit."""
+    from paper_2012_03325_amd import epb as E
+    from paper_2012_03325_amd import frame as fr
+    base = [synth.config_reduced(w, h, seed=50 + k, shadow_size=16, env_size=8, ssao_n=8, n_spheres=4, n_lights=1)
+            for k, (w, h) in enumerate(((5, 3), (19, 11)))]
+    ibls = []
+    for v in base:
+        ibl = fr.DeviceIBL(v.env, **v.ibl)
+        ibl.precompute()
+        ibls.append(ibl)
+    src = [fr.DeviceView(v, ibl) for v, ibl in zip(base, ibls)]
+    n = E.EPB_MAX_BATCH_VIEWS
+    log(f"[batch-max] {n} views, schedule {sched}")
+    dvs = [fr.DeviceView(base[k % 2], ibls[k % 2], solo_scratch=False, src=src[k % 2]) for k in range(n)]
+    b = fr.DeviceBatch(dvs, fr.make_schedule(*sched))
+    b.render()
+    assert b.status() == E.EPB_OK
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(7)
+    for k in sorted(set(rng.integers(0, n, 14).tolist()) | {0, 1, n - 2, n - 1}):
+        s = src[k % 2]
+        s.render()
+        torch.cuda.synchronize()
+        for name, p, q in zip(("AO", "HDR", "LDR"), (dvs[k].ao, dvs[k].hdr, dvs[k].ldr), (s.ao, s.hdr, s.ldr)):
+            assert torch.equal(p, q), f"view {k}: {name} differs"
