@@ -240,6 +240,40 @@ def bench_edl(args, torch, E, frame, synth) -> dict:
     return res
 
 
+def bench_raycast(args, torch, E, frame, synth, view) -> dict:
+    """The device ray caster (the pass that writes G-buffers and depth maps
+    before shading) on the 1080p scene: the 1920x1080 G-buffer (FP32 and FP16
+    attributes) and one 2048x2048 light depth map, back-to-back launches between
+    HIP events.  Every pixel is intersected in double precision against the
+    spheres whose screen boxes overlap its 16x16 tile."""
+    scene = synth.make_spheres(np.random.default_rng(2), 512, True)  # the scene of the 1080p view
+    ds = frame.DeviceScene(scene)
+    s = torch.cuda.current_stream()
+    res = {"workload": "512 seeded spheres + ground plane (the plain-1920x1080 scene): G-buffer of the "
+                       "1920x1080 camera, depth map of the first light's 2048x2048 camera"}
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        for _ in range(reps):
+            fn()
+        e1.record(s)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    cam, lc = view.cam, view.lights[0].shadow_cam
+    depth = torch.empty((lc.height, lc.width), device="cuda")
+    for name, dt in (("gbuffer_fp32", E.EPB_F32), ("gbuffer_fp16", E.EPB_F16)):
+        ms = timed(lambda: ds.render_gbuffer(cam, dt), 20)
+        res[name] = {"ms": round(ms, 4), "Mpix_s": round(cam.width * cam.height / (ms / 1e3) / 1e6, 1)}
+    ms = timed(lambda: ds.render_depth(lc, depth), 20)
+    res["depth_2048"] = {"ms": round(ms, 4), "Mpix_s": round(lc.width * lc.height / (ms / 1e3) / 1e6, 1)}
+    log(f"raycast: {res}")
+    return res
+
+
 def bench_small(args, torch, E, frame, synth) -> dict:
     """The 256x256 view (64 spheres, one light without shadows, SSAO 16, a 64^2
     sky gradient), which alone cannot fill the chip: single-view frames replayed
@@ -660,7 +694,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10, help="timed replays of the batched frame")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving form")
     ap.add_argument("--no-edl", action="store_true", help="skip the eye-dome lighting measurement")
-    ap.add_argument("--no-small", action="store_true", help="skip the 256x256 view (single frames and a batch)")
+    ap.add_argument("--no-small", action="store_true", help="skip the 256x256 view (single frames and a batch) "
+                    "and the ray-cast timing")
     ap.add_argument("--serve-seconds", type=float, default=2.0, help="seconds of arrivals per rate (max 10)")
     ap.add_argument("--serve-min-requests", type=int, default=200, help="requests per rate at least")
     ap.add_argument("--serve-budget-gb", type=float, default=16.0, help="HBM budget of request slots")
@@ -914,6 +949,7 @@ def main():
         out["edl"] = bench_edl(args, torch, E, frame, synth)
     if not args.no_small:
         out["small_256"] = bench_small(args, torch, E, frame, synth)
+        out["raycast"] = bench_raycast(args, torch, E, frame, synth, view)
     sched = None
     if not args.no_batch:
         out["batched"] = bench_batched(args, torch, E, frame, synth)
