@@ -126,3 +126,33 @@ def test_fused_pyramid_and_image_match_oracle(kind):
         assert_interval(f"fused bloom level {l + 1}", gg, r, r, rtol=1e-5)
     frac, exact = assert_ldr(f"fused {kind}", dv.ldr.cpu().numpy(), ref["ldr"], ref["ldr"], min_frac=1.0)
     log(f"[fused-oracle] {kind}: LDR exact {100 * exact:.3f}%")
+
+
+def test_fused_frame_in_a_graph_replays_equal_eager():
+    """A whole frame with the fused call (SSAO, epb_shade_post) captured in a
+    HIP graph, as the benchmark times it: every replay, with eager work in
+    between, equals the eager frame bit for bit."""
+    v = _view("ragged-201x137")
+    dv = _device_view(v, F32, F32, F32, 6)
+    dv.render(fused=True)
+    torch.cuda.synchronize()
+    eager = [t.clone() for t in (dv.ao, dv.hdr, dv.ldr)]
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        dv.render(fused=True)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    log("[fused-graph] capture")
+    with torch.cuda.graph(g):
+        dv.render(fused=True)
+    for rep in range(3):
+        dv.ao.fill_(-1.0)
+        dv.hdr.fill_(float(rep))
+        dv.ldr.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for name, a, b in zip(("AO", "HDR", "LDR"), (dv.ao, dv.hdr, dv.ldr), eager):
+            assert torch.equal(a, b), f"replay {rep}: {name} differs"
