@@ -57,12 +57,35 @@ SHADE_SOURCES = ("paper_2012_03325_amd/csrc/shade.hip", "paper_2012_03325_amd/cs
                  "paper_2012_03325_amd/csrc/desc.hpp", "include/epb.h")
 
 
-def shade_sources_sha256() -> str:
+FRAME_VALU_FILE = os.path.join(ROOT, "profiles", "frame_1080p_valu.json")
+FRAME_SOURCES = tuple("paper_2012_03325_amd/csrc/" + f for f in (
+    "ssao.hip", "ssao_tiles.hpp", "shade.hip", "shade_tiles.hpp", "post.hip", "post_tiles.hpp",
+    "device_common.hpp", "desc.hpp")) + ("include/epb.h",)
+
+
+def sources_sha256(files) -> str:
     h = hashlib.sha256()
-    for f in SHADE_SOURCES:
+    for f in files:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
+
+
+def shade_sources_sha256() -> str:
+    return sources_sha256(SHADE_SOURCES)
+
+
+def counted_frame_valu():
+    """VALU wavefront instructions of one FP32 1080p frame (separate calls) from
+    the committed counter record, or None when a frame kernel's sources changed."""
+    try:
+        with open(FRAME_VALU_FILE) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != sources_sha256(FRAME_SOURCES):
+        return None
+    return rec.get("wave_instructions_per_frame")
 
 
 def counted_shade_record():
@@ -621,6 +644,18 @@ def valu_entry(winst, launch_s):
             "peak": VALU_PEAK_GWINST, "unit": "G wave-instr/s", "frac": round(achieved / VALU_PEAK_GWINST, 4)}
 
 
+def frame_valu_entry(winst, step_s):
+    """VALU issue roofline of the whole frame: the counted wavefront
+    instructions of its seven kernels over the time per frame (frames in
+    flight), against one wavefront instruction per clock per CU."""
+    if not winst:
+        return None
+    achieved = winst / step_s / 1e9
+    return {"wave_instructions_per_frame": int(winst), "achieved": round(achieved, 1), "peak": VALU_PEAK_GWINST,
+            "unit": "G wave-instr/s", "frac": round(achieved / VALU_PEAK_GWINST, 4),
+            "issue_floor_ms": round(winst / (VALU_PEAK_GWINST * 1e9) * 1e3, 5)}
+
+
 def _cpu_model() -> str:
     try:
         with open("/proc/cpuinfo") as fh:
@@ -924,6 +959,7 @@ def main():
             "traffic": counted_shade_traffic(),
             "utilisation": counted_shade_utilisation(),
             "valu": valu_entry(counted_shade_valu_instructions(), shade_avg_s),
+            "frame_valu": frame_valu_entry(counted_frame_valu(), ms_per_step / 1e3),
             "shadow_maps": ("shared by the rotated copies" if args.shared_shadow_maps else
                             "rotated with the copies (each copy its own four maps)"),
             "shade_ms_shared_maps": round(plain["shade_ms_shared_maps"], 5),
