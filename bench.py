@@ -76,8 +76,9 @@ def shade_sources_sha256() -> str:
 
 
 def counted_frame_valu():
-    """VALU wavefront instructions of one FP32 1080p frame (separate calls) from
-    the committed counter record, or None when a frame kernel's sources changed."""
+    """VALU wavefront instructions of one FP32 1080p frame (separate calls) and
+    the transcendentals among them, from the committed counter record, as
+    (instructions, transcendentals), or None when a frame kernel's sources changed."""
     try:
         with open(FRAME_VALU_FILE) as fh:
             rec = json.load(fh)
@@ -85,7 +86,7 @@ def counted_frame_valu():
         return None
     if rec.get("source_sha256") != sources_sha256(FRAME_SOURCES):
         return None
-    return rec.get("wave_instructions_per_frame")
+    return rec.get("wave_instructions_per_frame"), rec.get("transcendental_per_frame")
 
 
 def counted_shade_record():
@@ -107,10 +108,13 @@ def counted_shade_traffic():
 
 
 def counted_shade_valu_instructions():
-    """VALU wavefront instructions per launch of the FP32 shading kernel
-    (SQ_INSTS_VALU of the committed counter run), or None."""
+    """VALU wavefront instructions per launch of the FP32 shading kernel and the
+    transcendentals among them (SQ_INSTS_VALU and SQ_INSTS_VALU_TRANS_F32 of the
+    committed counter runs), as (instructions, transcendentals), or None."""
     rec = counted_shade_record()
-    return rec.get("valu_wave_instructions_per_launch") if rec else None
+    if not rec:
+        return None
+    return rec.get("valu_wave_instructions_per_launch"), rec.get("valu_transcendental_per_launch")
 
 
 def counted_shade_utilisation():
@@ -633,27 +637,49 @@ def fp16_error_statement(orc, gpu) -> dict:
     return out
 
 
-def valu_entry(winst, launch_s):
+def _issue_slots(counted):
+    """(instructions, transcendentals, issue slots) from a counted pair; a
+    transcendental (rcp, rsq, sqrt, exp, log, ...) holds the issue port for
+    two slots, every other VALU instruction for one."""
+    winst, trans = counted
+    trans = int(trans) if trans is not None else None
+    return int(winst), trans, (int(winst) + trans if trans is not None else None)
+
+
+def valu_entry(counted, launch_s):
     """VALU issue roofline of the shading kernel: counted wavefront
     instructions per launch over the launch time, against one wavefront
-    instruction per clock per CU."""
-    if not winst:
+    instruction per clock per CU; `frac_issue_slots` counts each
+    transcendental twice."""
+    if not counted or not counted[0]:
         return None
+    winst, trans, slots = _issue_slots(counted)
     achieved = winst / launch_s / 1e9
-    return {"wave_instructions_per_launch": int(winst), "achieved": round(achieved, 1),
-            "peak": VALU_PEAK_GWINST, "unit": "G wave-instr/s", "frac": round(achieved / VALU_PEAK_GWINST, 4)}
+    out = {"wave_instructions_per_launch": winst, "achieved": round(achieved, 1),
+           "peak": VALU_PEAK_GWINST, "unit": "G wave-instr/s", "frac": round(achieved / VALU_PEAK_GWINST, 4)}
+    if slots is not None:
+        out.update(transcendental_per_launch=trans, issue_slots_per_launch=slots,
+                   frac_issue_slots=round(slots / launch_s / 1e9 / VALU_PEAK_GWINST, 4))
+    return out
 
 
-def frame_valu_entry(winst, step_s):
+def frame_valu_entry(counted, step_s):
     """VALU issue roofline of the whole frame: the counted wavefront
     instructions of its seven kernels over the time per frame (frames in
-    flight), against one wavefront instruction per clock per CU."""
-    if not winst:
+    flight), against one wavefront instruction per clock per CU; the
+    `_issue_slots` figures count each transcendental twice."""
+    if not counted or not counted[0]:
         return None
+    winst, trans, slots = _issue_slots(counted)
     achieved = winst / step_s / 1e9
-    return {"wave_instructions_per_frame": int(winst), "achieved": round(achieved, 1), "peak": VALU_PEAK_GWINST,
-            "unit": "G wave-instr/s", "frac": round(achieved / VALU_PEAK_GWINST, 4),
-            "issue_floor_ms": round(winst / (VALU_PEAK_GWINST * 1e9) * 1e3, 5)}
+    out = {"wave_instructions_per_frame": winst, "achieved": round(achieved, 1), "peak": VALU_PEAK_GWINST,
+           "unit": "G wave-instr/s", "frac": round(achieved / VALU_PEAK_GWINST, 4),
+           "issue_floor_ms": round(winst / (VALU_PEAK_GWINST * 1e9) * 1e3, 5)}
+    if slots is not None:
+        out.update(transcendental_per_frame=trans, issue_slots_per_frame=slots,
+                   frac_issue_slots=round(slots / step_s / 1e9 / VALU_PEAK_GWINST, 4),
+                   issue_floor_ms_slots=round(slots / (VALU_PEAK_GWINST * 1e9) * 1e3, 5))
+    return out
 
 
 def _cpu_model() -> str:
