@@ -423,9 +423,12 @@ def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, s
               n_lights: int, shadow_size: int, env_size: int, env_kind: str, ssao_n: int,
               ibl: Optional[dict] = None) -> ViewInputs:
     """One seeded view.  ``n_lights == 1`` puts a white light of intensity 40 at
-    (3, 5, 4); otherwise lights sit at azimuth 45 + 90 k degrees, radius 6,
-    height 6.  ``shadow_size > 0`` renders a square depth map per light with a
-    90 degree camera looking at the origin.
+    (3, 5, 4); otherwise the first four lights are white and sit at azimuth
+    45 + 90 k degrees, radius 6, height 6, and lights 4 .. 7 (up to the
+    C ABI's eight) on a lower ring at azimuth 90 (k - 4) degrees, radius 4.5,
+    height 3.5, each with its own tint (so that every colour channel of the
+    light radiance differs).  ``shadow_size > 0`` renders a square depth map
+    per light with a 90 degree camera looking at the origin.
 
     Under the HDR sky-and-sun environment (sky radiance up to 1e2, sun 1e4) the
     lights get intensity 1500 (about the sky's irradiance at the scene) and the
@@ -436,15 +439,20 @@ def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, s
     cam = look_at((0.0, 3.5, 8.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, width, height)
     gbuf = raycast(scene, cam)
     lights = []
+    tints = [(1.0, 0.6, 0.3), (0.3, 0.8, 1.0), (0.9, 1.0, 0.4), (0.6, 0.4, 1.0)]
     if n_lights == 1:
         positions = [np.array([3.0, 5.0, 4.0])]
+        colours = [(1.0, 1.0, 1.0)]
     else:
         positions = [np.array([6.0 * math.cos(math.radians(45 + 90 * k)), 6.0,
-                               6.0 * math.sin(math.radians(45 + 90 * k))])
+                               6.0 * math.sin(math.radians(45 + 90 * k))]) if k < 4 else
+                     np.array([4.5 * math.cos(math.radians(90 * (k - 4))), 3.5,
+                               4.5 * math.sin(math.radians(90 * (k - 4)))])
                      for k in range(n_lights)]
-    for p in positions:
+        colours = [(1.0, 1.0, 1.0) if k < 4 else tints[(k - 4) % 4] for k in range(n_lights)]
+    for p, col in zip(positions, colours):
         p = p.astype(np.float32).astype(np.float64)
-        light = Light(p, np.array([1.0, 1.0, 1.0]), 1500.0 if env_kind == "sun" else 40.0)
+        light = Light(p, np.array(col), 1500.0 if env_kind == "sun" else 40.0)
         if shadow_size > 0:
             lc = look_at(p, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 90.0, shadow_size, shadow_size)
             light.shadow_cam = lc

@@ -64,6 +64,15 @@ def _make_view(kind):
     if kind == "strip-16384x2":
         return synth.config_reduced(16384, 2, seed=10, shadow_size=64, env_size=8, ssao_n=8,
                                     n_spheres=8)
+    if kind == "max-lights-8":  # the C ABI's eight lights, four of them tinted, two without a depth map
+        v = synth.config_reduced(121, 83, seed=12, shadow_size=64, env_size=16, ssao_n=16, n_spheres=24,
+                                 n_lights=8)
+        for k in (5, 7):
+            v.lights[k].shadow_map = None
+            v.lights[k].shadow_cam = None
+        return v
+    if kind == "max-samples-256":  # the C ABI's largest SSAO kernel
+        return synth.config_reduced(75, 53, seed=13, shadow_size=32, env_size=8, ssao_n=256, n_spheres=16)
     if kind == "full-1080p":
         return synth.config_1080p()
     if kind == "auto-params-160x120":
@@ -163,7 +172,7 @@ def test_precompute_ibl_parity(case):
 # a2 / a3: SSAO
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "ragged-123x77-n13",
-                                  "tiny-3x2", "full-1080p"])
+                                  "tiny-3x2", "max-samples-256", "full-1080p"])
 def test_ssao_parity(kind):
     v = _view(kind)
     g = v.gbuf
@@ -188,7 +197,7 @@ def test_ssao_parity(kind):
 # a4: shading alone (oracle tables and AO as shared inputs)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "tiny-3x2",
-                                  "full-1080p"])
+                                  "max-lights-8", "full-1080p"])
 def test_shade_parity(kind):
     v = _view(kind)
     g = v.gbuf
@@ -293,7 +302,7 @@ def test_bloom_tonemap_reinhard_parity(shape):
 # the whole pass
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "tiny-3x2", "strip-16384x2",
-                                  "auto-params-160x120", "full-1080p"])
+                                  "auto-params-160x120", "max-lights-8", "max-samples-256", "full-1080p"])
 def test_end_to_end(kind):
     v = _view(kind)
     ref = O.render(v)
