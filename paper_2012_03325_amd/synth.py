@@ -421,14 +421,15 @@ def _f32(x) -> float:
 
 def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, seed: int,
               n_lights: int, shadow_size: int, env_size: int, env_kind: str, ssao_n: int,
-              ibl: Optional[dict] = None) -> ViewInputs:
+              ibl: Optional[dict] = None, eye=(0.0, 3.5, 8.5), up=(0.0, 1.0, 0.0)) -> ViewInputs:
     """One seeded view.  ``n_lights == 1`` puts a white light of intensity 40 at
     (3, 5, 4); otherwise the first four lights are white and sit at azimuth
     45 + 90 k degrees, radius 6, height 6, and lights 4 .. 7 (up to the
     C ABI's eight) on a lower ring at azimuth 90 (k - 4) degrees, radius 4.5,
     height 3.5, each with its own tint (so that every colour channel of the
     light radiance differs).  ``shadow_size > 0`` renders a square depth map
-    per light with a 90 degree camera looking at the origin.
+    per light with a 90 degree camera looking at the origin.  The view's
+    camera looks at the origin from ``eye`` with the given ``up`` direction.
 
     Under the HDR sky-and-sun environment (sky radiance up to 1e2, sun 1e4) the
     lights get intensity 1500 (about the sky's irradiance at the scene) and the
@@ -436,7 +437,7 @@ def make_view(name: str, width: int, height: int, n_spheres: int, plane: bool, s
     middle of the ACES curve; with exposure 1 that sky saturates every pixel."""
     rng = np.random.default_rng(seed)
     scene = make_spheres(rng, n_spheres, plane)
-    cam = look_at((0.0, 3.5, 8.5), (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 45.0, width, height)
+    cam = look_at(eye, (0.0, 0.0, 0.0), up, 45.0, width, height)
     gbuf = raycast(scene, cam)
     lights = []
     tints = [(1.0, 0.6, 0.3), (0.3, 0.8, 1.0), (0.9, 1.0, 0.4), (0.6, 0.4, 1.0)]
@@ -491,14 +492,14 @@ def config_1080p(seed: int = 2) -> ViewInputs:
 
 def config_reduced(width: int, height: int, seed: int = 5, shadow_size: int = 256,
                    env_size: int = 32, ssao_n: int = 16, n_spheres: int = 48,
-                   n_lights: int = 4) -> ViewInputs:
+                   n_lights: int = 4, eye=(0.0, 3.5, 8.5), up=(0.0, 1.0, 0.0)) -> ViewInputs:
     """A reduced copy of the 1080p workload (plane, shadowed lights, sun sky) at a
     size the FP64 oracle finishes in seconds; used for parity tests."""
     base = min(128, env_size)
     ibl = dict(irr_src_size=min(64, env_size), pref_size=base, pref_samples=256,
                pref_levels=min(5, base.bit_length() - 1), lut_size=32, lut_samples=256)
     return make_view(f"reduced-{width}x{height}", width, height, n_spheres, True, seed, n_lights,
-                     shadow_size, env_size, "sun", ssao_n, ibl)
+                     shadow_size, env_size, "sun", ssao_n, ibl, eye, up)
 
 
 # ----------------------------------------------------------------------------

@@ -73,6 +73,9 @@ def _make_view(kind):
         return v
     if kind == "max-samples-256":  # the C ABI's largest SSAO kernel
         return synth.config_reduced(75, 53, seed=13, shadow_size=32, env_size=8, ssao_n=256, n_spheres=16)
+    if kind == "yawed-131x91":  # a camera turned about every axis (yaw, pitch and a roll of ~8 degrees)
+        return synth.config_reduced(131, 91, seed=14, shadow_size=128, env_size=16, ssao_n=32, n_spheres=32,
+                                    eye=(5.5, 3.0, 6.0), up=(0.15, 1.0, 0.05))
     if kind == "full-1080p":
         return synth.config_1080p()
     if kind == "auto-params-160x120":
@@ -172,7 +175,7 @@ def test_precompute_ibl_parity(case):
 # a2 / a3: SSAO
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "ragged-123x77-n13",
-                                  "tiny-3x2", "max-samples-256", "full-1080p"])
+                                  "tiny-3x2", "max-samples-256", "yawed-131x91", "full-1080p"])
 def test_ssao_parity(kind):
     v = _view(kind)
     g = v.gbuf
@@ -197,7 +200,7 @@ def test_ssao_parity(kind):
 # a4: shading alone (oracle tables and AO as shared inputs)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "tiny-3x2",
-                                  "max-lights-8", "full-1080p"])
+                                  "max-lights-8", "yawed-131x91", "full-1080p"])
 def test_shade_parity(kind):
     v = _view(kind)
     g = v.gbuf
@@ -302,7 +305,8 @@ def test_bloom_tonemap_reinhard_parity(shape):
 # the whole pass
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "tiny-3x2", "strip-16384x2",
-                                  "auto-params-160x120", "max-lights-8", "max-samples-256", "full-1080p"])
+                                  "auto-params-160x120", "max-lights-8", "max-samples-256", "yawed-131x91",
+                                  "full-1080p"])
 def test_end_to_end(kind):
     v = _view(kind)
     ref = O.render(v)
