@@ -76,6 +76,13 @@ def _make_view(kind):
     if kind == "yawed-131x91":  # a camera turned about every axis (yaw, pitch and a roll of ~8 degrees)
         return synth.config_reduced(131, 91, seed=14, shadow_size=128, env_size=16, ssao_n=32, n_spheres=32,
                                     eye=(5.5, 3.0, 6.0), up=(0.15, 1.0, 0.05))
+    if kind == "odd-maps-201x137":  # depth maps of 3x3, 13x11, 37x29 and 130x97 texels (non-square, odd)
+        v = synth.config_reduced(201, 137, seed=7, shadow_size=0, env_size=16, ssao_n=16)
+        scene = synth.make_spheres(np.random.default_rng(7), 48, True)
+        for L, (w, h) in zip(v.lights, [(3, 3), (13, 11), (37, 29), (130, 97)]):
+            L.shadow_cam = synth.look_at(L.pos, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 90.0, w, h)
+            L.shadow_map = synth.raycast(scene, L.shadow_cam, depth_only=True)["depth"]
+        return v
     if kind == "full-1080p":
         return synth.config_1080p()
     if kind == "auto-params-160x120":
@@ -200,7 +207,7 @@ def test_ssao_parity(kind):
 # a4: shading alone (oracle tables and AO as shared inputs)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "tiny-3x2",
-                                  "max-lights-8", "yawed-131x91", "full-1080p"])
+                                  "max-lights-8", "yawed-131x91", "odd-maps-201x137", "full-1080p"])
 def test_shade_parity(kind):
     v = _view(kind)
     g = v.gbuf
@@ -306,7 +313,7 @@ def test_bloom_tonemap_reinhard_parity(shape):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "tiny-3x2", "strip-16384x2",
                                   "auto-params-160x120", "max-lights-8", "max-samples-256", "yawed-131x91",
-                                  "full-1080p"])
+                                  "odd-maps-201x137", "full-1080p"])
 def test_end_to_end(kind):
     v = _view(kind)
     ref = O.render(v)
