@@ -46,7 +46,7 @@ __global__ void __launch_bounds__(256) k_bloom_blur(const PostDesc c) {
 }
 
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(kPostTx) k_composite(const PostDesc c, int tiles) {
+__global__ void __launch_bounds__(kPostTx) __attribute__((amdgpu_waves_per_eu(5))) k_composite(const PostDesc c, int tiles) {
     composite_tile<TH, TP>(c, xcd_tile(blockIdx.x, tiles), (int)threadIdx.x);
 }
 
@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) k_bloom_blur_batch(const void *__restrict
 }
 
 template <typename TH, typename TP>
-__global__ void __launch_bounds__(kPostTx) k_composite_batch(const void *__restrict__ table) {
+__global__ void __launch_bounds__(kPostTx) __attribute__((amdgpu_waves_per_eu(5))) k_composite_batch(const void *__restrict__ table) {
     const BatchHeader *h = (const BatchHeader *)table;
     const int *start = batch_start(table, kStComposite);
     const ViewDesc *views = batch_views(table);

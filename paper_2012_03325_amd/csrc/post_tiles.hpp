@@ -195,9 +195,10 @@ __device__ __forceinline__ float aces(float x) {
 }
 // Reinhard's global operator on each channel (the paper's alternative curve).
 __device__ __forceinline__ float reinhard(float x) { return x * rcp(1.0f + x); }
-__device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_gamma, int tonemap) {
+template <bool kReinhard>
+__device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_gamma) {
     float e = exposure * x;
-    float y = clamp01(tonemap == EPB_TONEMAP_REINHARD ? reinhard(e) : aces(e));
+    float y = clamp01(kReinhard ? reinhard(e) : aces(e));
     float g = __builtin_amdgcn_exp2f(__builtin_amdgcn_logf(y) * inv_gamma);
     float q = floorf(fmaf(255.0f, g, 0.5f));
     return (uint32_t)fminf(fmaxf(q, 0.0f), 255.0f);
@@ -215,10 +216,10 @@ __device__ __forceinline__ uint32_t encode8(float x, float exposure, float inv_g
 // the column interpolates between two of those rows.  Because the strip starts
 // at a multiple of 8, which rows a pixel uses is fixed at compile time (levels
 // 1..3), or is the first pair for all eight pixels (levels 4 and 5, where the
-// strip lies inside one texel row pair); the weights of levels 1..3 are
-// compile-time constants as well.  Everything stays in registers: no LDS, no
-// barriers, and the strip's 24 HDR loads are in flight while the pyramid is
-// read.
+// strip lies inside one texel row pair and the remainder grows by 2 per pixel
+// without wrapping); the weights of levels 1..3 are compile-time constants as
+// well.  Everything stays in registers: no LDS, no barriers, and the strip's
+// 24 HDR loads are in flight while the pyramid is read.
 template <int L>
 struct LevelRows {
     static constexpr int sh = L + 1, o = 1 - (1 << L), m = (1 << sh) - 1;
@@ -226,10 +227,13 @@ struct LevelRows {
     static constexpr float inv = 1.0f / (float)(1 << sh);
     // first row (relative to the strip's first footprint row) of pixel j
     static constexpr int rel(int j) { return L <= 3 ? ((2 * j + o) >> sh) - (o >> sh) : 0; }
+    // weight of pixel j (levels 1..3)
+    static constexpr float wy(int j) { return (float)((2 * j + o) & m) * inv; }
 };
 
+// The level-L rows under the strip, interpolated at the thread's column.
 template <int L, typename TP>
-__device__ __forceinline__ void add_level(const PostDesc &c, int x, int Y0, float (&acc)[kPostTy][3]) {
+__device__ __forceinline__ void level_rows(const PostDesc &c, int x, int Y0, float (&rows)[LevelRows<L>::n][3]) {
     using LR = LevelRows<L>;
     const int w = c.lw[L], h = c.lh[L];
     const TP *lvl = (const TP *)c.blur[L];
@@ -248,7 +252,6 @@ __device__ __forceinline__ void add_level(const PostDesc &c, int x, int Y0, floa
         tb[r] = ldo(lvl, (base + c1) * (unsigned)sizeof(TP));
     }
     __builtin_amdgcn_sched_barrier(0);  // keep the scheduler from interleaving the loads with their uses
-    float rows[LR::n][3];
 #pragma unroll
     for (int r = 0; r < LR::n; ++r) {
         float4 a = unpack(ta[r]), b = unpack(tb[r]);
@@ -256,14 +259,75 @@ __device__ __forceinline__ void add_level(const PostDesc &c, int x, int Y0, floa
         rows[r][1] = fmaf(wx, b.y - a.y, a.y);
         rows[r][2] = fmaf(wx, b.z - a.z, a.z);
     }
+}
+
+// Levels 4 and 5, which start the strip's sums: each pixel of the strip adds
+// a_L + w_L(j) (b_L - a_L) for the one row pair (a_L, b_L) under the strip, with
+// w_L(j) = w_L(0) + 2 j / 2^(L+1); the two a_L are summed once per thread and
+// enter as the first addend, so a pixel spends one FMA per level and channel.
+// Absent levels contribute nothing (their difference and weight are 0).
+template <typename TP>
+__device__ __forceinline__ void init_coarse(const PostDesc &c, int x, int Y0, float (&acc)[kPostTy][3]) {
+    float base[3] = {0.0f, 0.0f, 0.0f}, d4[3] = {0.0f, 0.0f, 0.0f}, d5[3] = {0.0f, 0.0f, 0.0f};
+    float w4 = 0.0f, w5 = 0.0f;
+    if (c.nl >= 4) {
+        float rows[2][3];
+        level_rows<4, TP>(c, x, Y0, rows);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            base[ch] = rows[0][ch];
+            d4[ch] = rows[1][ch] - rows[0][ch];
+        }
+        w4 = (float)((2 * Y0 + LevelRows<4>::o) & LevelRows<4>::m) * LevelRows<4>::inv;
+    }
+    if (c.nl >= 5) {
+        float rows[2][3];
+        level_rows<5, TP>(c, x, Y0, rows);
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            base[ch] += rows[0][ch];
+            d5[ch] = rows[1][ch] - rows[0][ch];
+        }
+        w5 = (float)((2 * Y0 + LevelRows<5>::o) & LevelRows<5>::m) * LevelRows<5>::inv;
+    }
+#pragma unroll
+    for (int j = 0; j < kPostTy; ++j) {
+        float wj4 = w4 + (float)(2 * j) * LevelRows<4>::inv, wj5 = w5 + (float)(2 * j) * LevelRows<5>::inv;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) acc[j][ch] = fmaf(wj5, d5[ch], fmaf(wj4, d4[ch], base[ch]));
+    }
+}
+
+// Levels 1..3: (1 - w) a + w b for the pixel's row pair, two FMAs per channel.
+template <int L, typename TP>
+__device__ __forceinline__ void add_fine(const PostDesc &c, int x, int Y0, float (&acc)[kPostTy][3]) {
+    using LR = LevelRows<L>;
+    float rows[LR::n][3];
+    level_rows<L, TP>(c, x, Y0, rows);
 #pragma unroll
     for (int j = 0; j < kPostTy; ++j) {
         const int r0 = LR::rel(j);
-        float wy = L <= 3 ? (float)((2 * j + LR::o) & LR::m) * LR::inv
-                          : (float)((2 * (Y0 + j) + LR::o) & LR::m) * LR::inv;
+        const float w = LR::wy(j);
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch)
-            acc[j][ch] += fmaf(wy, rows[r0 + 1][ch] - rows[r0][ch], rows[r0][ch]);
+        for (int ch = 0; ch < 3; ++ch) acc[j][ch] = fmaf(w, rows[r0 + 1][ch], fmaf(1.0f - w, rows[r0][ch], acc[j][ch]));
+    }
+}
+
+// Bloom added to the strip's HDR, tone mapped and stored as RGBA8.
+template <bool kReinhard>
+__device__ __forceinline__ void store_strip(const PostDesc &c, int x, int Y0, const float (&px)[kPostTy][3],
+                                            const float (&acc)[kPostTy][3]) {
+#pragma unroll
+    for (int j = 0; j < kPostTy; ++j) {
+        if (Y0 + j >= c.H) break;
+        float R = fmaf(c.strength, acc[j][0], px[j][0]);
+        float G = fmaf(c.strength, acc[j][1], px[j][1]);
+        float Bc = fmaf(c.strength, acc[j][2], px[j][2]);
+        uint32_t word = encode8<kReinhard>(R, c.exposure, c.inv_gamma) |
+                        (encode8<kReinhard>(G, c.exposure, c.inv_gamma) << 8) |
+                        (encode8<kReinhard>(Bc, c.exposure, c.inv_gamma) << 16) | (255u << 24);
+        unsigned p = __umul24((unsigned)(Y0 + j), (unsigned)c.W) + (unsigned)x;
+        sto(c.ldr, p * 4u, word);
     }
 }
 
@@ -286,27 +350,15 @@ __device__ __forceinline__ void composite_tile(const PostDesc &c, int tile, int 
         px[j][1] = ldf(hdr, plane + p);
         px[j][2] = ldf(hdr, 2 * plane + p);
     }
+    // the bloom sum of levels 5, 4 (one row pair for the whole strip), then 1 .. 3
+    // (nl is uniform)
     float acc[kPostTy][3];
-#pragma unroll
-    for (int j = 0; j < kPostTy; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.0f;
-    // levels 1 .. nl (nl is uniform)
-    if (c.nl >= 1) add_level<1, TP>(c, x, Y0, acc);
-    if (c.nl >= 2) add_level<2, TP>(c, x, Y0, acc);
-    if (c.nl >= 3) add_level<3, TP>(c, x, Y0, acc);
-    if (c.nl >= 4) add_level<4, TP>(c, x, Y0, acc);
-    if (c.nl >= 5) add_level<5, TP>(c, x, Y0, acc);
-#pragma unroll
-    for (int j = 0; j < kPostTy; ++j) {
-        if (Y0 + j >= c.H) break;
-        float R = fmaf(c.strength, acc[j][0], px[j][0]);
-        float G = fmaf(c.strength, acc[j][1], px[j][1]);
-        float Bc = fmaf(c.strength, acc[j][2], px[j][2]);
-        uint32_t word = encode8(R, c.exposure, c.inv_gamma, c.tonemap) |
-                        (encode8(G, c.exposure, c.inv_gamma, c.tonemap) << 8) |
-                        (encode8(Bc, c.exposure, c.inv_gamma, c.tonemap) << 16) | (255u << 24);
-        unsigned p = __umul24((unsigned)(Y0 + j), (unsigned)c.W) + (unsigned)x;
-        sto(c.ldr, p * 4u, word);
-    }
+    init_coarse<TP>(c, x, Y0, acc);
+    if (c.nl >= 1) add_fine<1, TP>(c, x, Y0, acc);
+    if (c.nl >= 2) add_fine<2, TP>(c, x, Y0, acc);
+    if (c.nl >= 3) add_fine<3, TP>(c, x, Y0, acc);
+    if (c.tonemap == EPB_TONEMAP_REINHARD) store_strip<true>(c, x, Y0, px, acc);
+    else store_strip<false>(c, x, Y0, px, acc);
 }
 
 }  // namespace epb
