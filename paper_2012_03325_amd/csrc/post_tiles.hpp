@@ -31,14 +31,14 @@ __device__ __forceinline__ void down_level(const PostDesc &c, int bx, int by, SR
     int X = bx * N + lx, Y = by * N + ly;
     float4 v = make_float4(0, 0, 0, 0);
     if (X < c.lw[L] && Y < c.lh[L]) {
-        float n = 0.0f;
-        for (int b = 0; b < 2; ++b)
-            for (int a = 0; a < 2; ++a)
-                if (2 * X + a < c.lw[L - 1] && 2 * Y + b < c.lh[L - 1]) {
-                    v = add4(v, src[2 * ly + b][2 * lx + a]);
-                    n += 1.0f;
-                }
-        v = scale4(v, 1.0f / n);
+        // child (2X, 2Y) is always in range (each level is the previous one halved,
+        // rounded up); 1 / n for n = 1, 2 or 4 children is a product of halves, exact
+        bool x1 = 2 * X + 1 < c.lw[L - 1], y1 = 2 * Y + 1 < c.lh[L - 1];
+        v = add4(v, src[2 * ly][2 * lx]);
+        if (x1) v = add4(v, src[2 * ly][2 * lx + 1]);
+        if (y1) v = add4(v, src[2 * ly + 1][2 * lx]);
+        if (x1 && y1) v = add4(v, src[2 * ly + 1][2 * lx + 1]);
+        v = scale4(v, (x1 ? 0.5f : 1.0f) * (y1 ? 0.5f : 1.0f));
         sto((TP *)c.raw[L], (unsigned)(Y * c.lw[L] + X) * (unsigned)sizeof(TP), pack<TP>(v));
     }
     if (dst) dst[ly][lx] = v;

@@ -129,7 +129,7 @@ __device__ __forceinline__ float ssao_texel(const SsaoDesc &c, int i, int j, uns
         occ = ssao_batch<KB, false, kLds>(c, kern + 3 * k0, KB, q, hdepth, win, occ);
     if (nfull < c.n)
         occ = ssao_batch<KB, true, kLds>(c, kern + 3 * nfull, c.n - nfull, q, hdepth, win, occ);
-    return 1.0f - occ * c.inv_n;
+    return clamp01(1.0f - occ * c.inv_n);  // (1/n rounded up could take a fully occluded texel below 0)
 }
 
 template <int TX, int TY, int KB, typename TG, typename TA>
@@ -221,18 +221,23 @@ __device__ __forceinline__ void ssao_blur_tile(const SsaoDesc &c, int tile, floa
         float dp = sd[tj + 2][ti + 2];
         float v = 1.0f;
         if (!__builtin_isinf(dp)) {
-            float inv = 1.0f / (c.tau * dp);  // weight 1 - |d_q - d_p| / (tau d_p)
+            float inv = rcp(c.tau * dp);  // weight 1 - |d_q - d_p| / (tau d_p)
             float s = 0.0f, sw = 0.0f;
 #pragma unroll
             for (int dy = 0; dy < 4; ++dy)
 #pragma unroll
                 for (int dx = 0; dx < 4; ++dx) {
+                    // a background or out-of-range neighbour (+inf) gets max(0, -inf) = 0
                     float dq = sd[tj + dy][ti + dx];
-                    float w = __builtin_isinf(dq) ? 0.0f : fmaxf(0.0f, 1.0f - fabsf(dq - dp) * inv);
+                    float w = fmaxf(0.0f, 1.0f - fabsf(dq - dp) * inv);
                     s = fmaf(w, sa[tj + dy][ti + dx], s);
                     sw += w;
                 }
-            v = s / sw;
+            // s / sw (sw >= 1: the centre's own weight) from the reciprocal and one
+            // correction with the exact residual s - sw q: exactly 1 where s == sw, and
+            // kept in [0, 1] (a weighted mean of values in [0, 1]) by the free clamp
+            float r = rcp(sw), q = s * r;
+            v = clamp01(fmaf(fmaf(-sw, q, s), r, q));
         }
         stf((TA *)c.out, __umul24((unsigned)j, (unsigned)c.Wh) + (unsigned)i, v);
     }

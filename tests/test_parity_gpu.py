@@ -195,11 +195,13 @@ def test_ssao_parity(kind):
     dv.ssao(blur=False)
     torch.cuda.synchronize()
     raw = dv.ao.cpu().numpy()
+    assert (raw >= 0).all() and (raw <= 1).all(), f"{kind}: raw AO outside [0, 1]"
     f = assert_interval(f"{kind} raw AO", raw, raw_lo, raw_hi, rtol=0.0, atol=AO_ATOL)
     log(f"[ssao] {kind}: raw within {100 * f:.3f}%; ambiguous {100 * (raw_hi > raw_lo).mean():.2f}%; blurred")
     dv.ssao(blur=True)
     torch.cuda.synchronize()
     ao = dv.ao.cpu().numpy()
+    assert (ao >= 0).all() and (ao <= 1).all(), f"{kind}: blurred AO outside [0, 1]"
     assert_interval(f"{kind} blurred AO", ao, blur_lo, blur_hi, rtol=0.0, atol=AO_ATOL)
 
 
