@@ -100,9 +100,10 @@ __device__ __forceinline__ void publish(PersistState *st, int *done, Pending &pd
     np = 0;
 }
 
-// Every stage's code in one kernel: it needs the largest register count of any
-// stage (the composite's 94; at 5 waves per SIMD and 96 registers the combined
-// kernel spills), so it runs at 4 waves per SIMD with 128 registers.
+// Every stage's code in one kernel: it needs at least the largest register
+// count of any stage (the composite's 91-96), and the combined kernel spills
+// heavily at 5 waves per SIMD (96 registers), so it runs at 4 waves per SIMD
+// with 128 registers (a few registers still spill).
 //
 // A block publishes its finished chunks lazily: when it moves to another stage,
 // before it waits for anything, when its pending list is full and when it
