@@ -103,6 +103,40 @@ def test_batch_equals_solo(sched):
     _assert_same(_outputs(dvs), solo, f"schedule {sched}")
 
 
+def _limit_views():
+    """Views at the C ABI's limits: eight lights (four tinted, two without a depth
+    map), a 256-sample SSAO kernel, and a camera turned about every axis."""
+    v8 = synth.config_reduced(121, 83, seed=12, shadow_size=64, env_size=16, ssao_n=16, n_spheres=24, n_lights=8)
+    for k in (5, 7):
+        v8.lights[k].shadow_map = None
+        v8.lights[k].shadow_cam = None
+    v256 = synth.config_reduced(75, 53, seed=13, shadow_size=32, env_size=8, ssao_n=256, n_spheres=16)
+    vyaw = synth.config_reduced(131, 91, seed=14, shadow_size=128, env_size=16, ssao_n=32, n_spheres=32,
+                                eye=(5.5, 3.0, 6.0), up=(0.15, 1.0, 0.05))
+    return [v8, v256, vyaw]
+
+
+@pytest.mark.parametrize("sched", [(0, 0, 0, 0), (0, 2, 1, 0), (0, 0, 0, 0, 16), (0, 1, 1, 0, 0, 0, 1)],
+                         ids=lambda s: "sched-" + "-".join(map(str, s)))
+def test_batch_at_the_abi_limits_equals_solo(sched):
+    """Per-view light counts up to eight and SSAO kernels up to 256 samples in one batch."""
+    from paper_2012_03325_amd import frame as fr
+    views = _limit_views()
+    dvs = _device_views(views)
+    log(f"[batch-limits] {[(v.width, v.height, len(v.lights), v.ssao_kernel.shape[0]) for v in views]}, "
+        f"schedule {sched}: solo renders")
+    solo = _solo(dvs)
+    for dv in dvs:
+        for t in (dv.ao, dv.hdr, dv.ldr):
+            t.zero_()
+    b = fr.DeviceBatch(dvs, fr.make_schedule(*sched))
+    b.render()
+    assert b.status() == 0
+    for k, (x, y) in enumerate(zip(_outputs(dvs), solo)):
+        for name, p, q in zip(("AO", "HDR", "LDR"), x, y):
+            assert torch.equal(p, q), f"schedule {sched}: limit view {k} {name} differs"
+
+
 def test_batch_fp16_and_unblurred_equal_solo():
     from paper_2012_03325_amd import epb as E
     from paper_2012_03325_amd import frame as fr
