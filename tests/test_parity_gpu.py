@@ -83,6 +83,9 @@ def _make_view(kind):
             L.shadow_cam = synth.look_at(L.pos, (0.0, 0.0, 0.0), (0.0, 1.0, 0.0), 90.0, w, h)
             L.shadow_map = synth.raycast(scene, L.shadow_cam, depth_only=True)["depth"]
         return v
+    if kind in ("column-1x97", "row-97x1", "pixel-1x1"):  # one-texel-wide half-resolution planes
+        w, h = {"column-1x97": (1, 97), "row-97x1": (97, 1), "pixel-1x1": (1, 1)}[kind]
+        return synth.config_reduced(w, h, seed=15, shadow_size=32, env_size=8, ssao_n=16, n_spheres=16)
     if kind == "full-1080p":
         return synth.config_1080p()
     if kind == "auto-params-160x120":
@@ -182,7 +185,8 @@ def test_precompute_ibl_parity(case):
 # a2 / a3: SSAO
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "ragged-123x77-n13",
-                                  "tiny-3x2", "max-samples-256", "yawed-131x91", "full-1080p"])
+                                  "tiny-3x2", "column-1x97", "row-97x1", "pixel-1x1", "max-samples-256",
+                                  "yawed-131x91", "full-1080p"])
 def test_ssao_parity(kind):
     v = _view(kind)
     g = v.gbuf
@@ -209,7 +213,8 @@ def test_ssao_parity(kind):
 # a4: shading alone (oracle tables and AO as shared inputs)
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "ragged-97x61-n64", "tiny-3x2",
-                                  "max-lights-8", "yawed-131x91", "odd-maps-201x137", "full-1080p"])
+                                  "column-1x97", "row-97x1", "pixel-1x1", "max-lights-8", "yawed-131x91",
+                                  "odd-maps-201x137", "full-1080p"])
 def test_shade_parity(kind):
     v = _view(kind)
     g = v.gbuf
@@ -314,8 +319,8 @@ def test_bloom_tonemap_reinhard_parity(shape):
 # the whole pass
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "tiny-3x2", "strip-16384x2",
-                                  "auto-params-160x120", "max-lights-8", "max-samples-256", "yawed-131x91",
-                                  "odd-maps-201x137", "full-1080p"])
+                                  "column-1x97", "row-97x1", "pixel-1x1", "auto-params-160x120", "max-lights-8",
+                                  "max-samples-256", "yawed-131x91", "odd-maps-201x137", "full-1080p"])
 def test_end_to_end(kind):
     v = _view(kind)
     ref = O.render(v)
