@@ -353,7 +353,11 @@ __device__ __forceinline__ int find_view(const int *start, int n, int g) {
 // GGX half vector for the point (u1, u2) around normal n with tangent frame
 // (T, B): phi = 2 pi u1, cos^2 = (1 - u2) / den, sin^2 = alpha^2 u2 / den,
 // den = (1 - u2) + alpha^2 u2 (both fractions without cancellation).
-__device__ __forceinline__ v3 ggx_half(float u1, float u2, float a2, v3 n, v3 T, v3 B) {
+// The GGX half vector of sample (u1, u2) in the tangent frame: (sin t cos p,
+// sin t sin p, cos t) with p = 2 pi u1 and cos^2 t = (1 - u2) / (1 + (a2 - 1) u2).
+// It depends on the sample and the roughness only, so kernels that reuse one
+// sample set for many texels take it from a table made by this function.
+__device__ __forceinline__ float4 ggx_tangent(float u1, float u2, float a2) {
     float om = 1.0f - u2;
     float den = fmaf(a2, u2, om);
     float inv = rcp(den);
@@ -361,9 +365,15 @@ __device__ __forceinline__ v3 ggx_half(float u1, float u2, float a2, v3 n, v3 T,
     float st = sqrtf(a2 * u2 * inv);
     float sp, cp;
     sincospif(2.0f * u1, &sp, &cp);
-    float hx = st * cp, hy = st * sp;
-    return mk3(fmaf(T.x, hx, fmaf(B.x, hy, n.x * ct)), fmaf(T.y, hx, fmaf(B.y, hy, n.y * ct)),
-               fmaf(T.z, hx, fmaf(B.z, hy, n.z * ct)));
+    return make_float4(st * cp, st * sp, ct, 0.0f);
+}
+// A tangent-frame half vector t (x, y, z) in the frame (T, B, n).
+__device__ __forceinline__ v3 ggx_to_world(float4 t, v3 n, v3 T, v3 B) {
+    return mk3(fmaf(T.x, t.x, fmaf(B.x, t.y, n.x * t.z)), fmaf(T.y, t.x, fmaf(B.y, t.y, n.y * t.z)),
+               fmaf(T.z, t.x, fmaf(B.z, t.y, n.z * t.z)));
+}
+__device__ __forceinline__ v3 ggx_half(float u1, float u2, float a2, v3 n, v3 T, v3 B) {
+    return ggx_to_world(ggx_tangent(u1, u2, a2), n, T, B);
 }
 
 // Tangent frame: up = +z unless |n.z| >= 0.999, then +x; T = norm(up x n), B = n x T.

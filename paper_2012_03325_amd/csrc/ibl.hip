@@ -8,9 +8,25 @@
 //    to all lanes; the source range is split across workgroups so that the
 //    grid fills all 256 CUs, and the per-split Kahan partials are combined in
 //    a fixed order by a second kernel (deterministic, no atomics).
-//  * prefilter and BRDF table: one wavefront per output texel, the 64 lanes
-//    split the Hammersley samples, per-lane Kahan sums, compensated wave
-//    reduction through cross-lane shuffles.
+//  * a GGX sample's tangent-frame half vector depends on the sample and the
+//    roughness only, and its square roots, reciprocal and sine/cosine are most
+//    of a sample's instructions, so it is made once per level (prefilter) or
+//    per table row (BRDF table) and only turned into each texel's frame.
+//  * prefilter from the full-resolution environment: one wavefront per output
+//    texel, the 64 lanes split the samples, whose taps then stay within the
+//    texel's GGX lobe (a few cache lines at the rough levels' narrow lobes);
+//    per-lane Kahan sums, compensated wave reduction through cross-lane
+//    shuffles; each lane loads its next sample's half vector from the level's
+//    table one iteration ahead (in flight with the current sample's taps).
+//  * prefilter with filtered importance sampling (taps on the mip level that
+//    matches each sample's footprint): one wavefront per 8x8 tile of output
+//    texels and chunk of the samples; all lanes take the same sample at once,
+//    so its half vector is a uniform (scalar) table load and neighbouring
+//    texels' taps share cache lines; per-lane Kahan sums per chunk, the chunks
+//    added in a fixed order by a second kernel (deterministic, no atomics).
+//  * BRDF table: one wavefront per entry, the 64 lanes split the Hammersley
+//    samples (per-lane Kahan sums, compensated wave reduction through
+//    cross-lane shuffles); a block makes its row's half vectors into LDS.
 //  * roughness-0 prefilter level: every GGX half vector equals the normal, so
 //    the N.L-weighted mean is the environment along the texel direction; one
 //    bilinear lookup per texel.
@@ -139,43 +155,6 @@ __global__ void __launch_bounds__(256) k_prefilter_mirror(const float4 *__restri
     out[o] = cube_bilinear(env, face_dims(S), n);
 }
 
-// One wavefront per prefiltered texel of a level with roughness^2 = alpha > 0.
-__global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ env, int S, int sm, float alpha,
-                                                   int samples, float4 *__restrict__ out) {
-    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int o = blockIdx.x * 4 + wave;
-    if (o >= 6 * sm * sm) return;  // whole wavefront leaves together
-    int f = o / (sm * sm), j = (o / sm) % sm, i = o % sm;
-    v3 n = normalize(cube_texel_dir(f, i, j, sm));
-    v3 T, B;
-    tangent_frame(n, T, B);
-    float a2 = alpha * alpha;
-    float inv_n = 1.0f / (float)samples;
-    FaceDims dims = face_dims(S);
-    Kahan r{0, 0}, g{0, 0}, b{0, 0}, w{0, 0};
-    for (int k = lane; k < samples; k += 64) {
-        v3 h = ggx_half((float)k * inv_n, radical_inverse2((uint32_t)k), a2, n, T, B);
-        float vh = dot(n, h);
-        v3 l = h * (2.0f * vh) - n;
-        float nl = dot(n, l);
-        if (nl > 0.0f) {
-            float4 L = cube_bilinear(env, dims, l);
-            kahan_add(r, L.x * nl);
-            kahan_add(g, L.y * nl);
-            kahan_add(b, L.z * nl);
-            kahan_add(w, nl);
-        }
-    }
-    float R = wave_sum_compensated(kahan_value(r));
-    float G = wave_sum_compensated(kahan_value(g));
-    float Bv = wave_sum_compensated(kahan_value(b));
-    float W = wave_sum_compensated(kahan_value(w));
-    if (lane == 0) {
-        float iw = 1.0f / W;
-        out[o] = make_float4(R * iw, G * iw, Bv * iw, 0.0f);
-    }
-}
-
 // Environment mip chain for filtered importance sampling.  Level 0 is a copy
 // of the environment so that every level sits at a closed-form offset of one
 // buffer: level k (faces S >> k, S a power of two) starts at texel
@@ -214,15 +193,37 @@ __global__ void __launch_bounds__(256) k_env_down(const float4 *__restrict__ src
     dst[o] = make_float4(r * iw, g * iw, b * iw, 0.0f);
 }
 
-// Filtered importance sampling: as k_prefilter, but sample l reads the chain
-// trilinearly at lod = lod0 - log2(den) clamped to [0, last], where den =
+// The GGX samples of one prefiltered level (roughness^2 = alpha > 0): entry k
+// is the tangent-frame half vector of Hammersley sample k and, for filtered
+// importance sampling, the environment chain level that sample reads (w; 0
+// otherwise).  That level is lod0 - log2(den) clamped to [0, last], where den =
 // (1 - u2) + alpha^2 u2 is the GGX sampling denominator: for V = N the pdf of l
 // is D / 4 = den^2 / (4 pi alpha^2), so 1/2 log2(omega_s / omega_p) + 1 =
 // 1/2 log2(6 S^2 alpha^2 / N) + 1 - log2(den) (lod0 is that constant part,
 // computed on the host in double precision).
-__global__ void __launch_bounds__(256) k_prefilter_fis(const float4 *__restrict__ chain, int S, int last,
-                                                       int sm, float alpha, int samples, float lod0,
-                                                       float4 *__restrict__ out) {
+__global__ void __launch_bounds__(256) k_ggx_table(float alpha, int samples, int fis, float lod0, int last,
+                                                   float4 *__restrict__ table) {
+    int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
+    if (k >= samples) return;
+    float a2 = alpha * alpha;
+    float inv_n = 1.0f / (float)samples;
+    float u2 = radical_inverse2((uint32_t)k);
+    float4 t = ggx_tangent((float)k * inv_n, u2, a2);
+    if (fis) {
+        float den = fmaf(a2, u2, 1.0f - u2);
+        t.w = fminf(fmaxf(lod0 - __log2f(den), 0.0f), (float)last);
+    }
+    table[k] = t;
+}
+
+// One wavefront per prefiltered texel of a level (roughness > 0), from level 0
+// of the environment: sample k's half vector from the table (each lane loads
+// its next sample's entry one iteration ahead, so the load travels with the
+// current sample's taps), its direction l the half vector reflected about the
+// texel normal n; with N.L > 0 it adds L(l) N.L and N.L.
+__global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ env, int S, int sm,
+                                                   const float4 *__restrict__ table, int samples,
+                                                   float4 *__restrict__ out) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     int o = blockIdx.x * 4 + wave;
     if (o >= 6 * sm * sm) return;  // whole wavefront leaves together
@@ -230,27 +231,18 @@ __global__ void __launch_bounds__(256) k_prefilter_fis(const float4 *__restrict_
     v3 n = normalize(cube_texel_dir(f, i, j, sm));
     v3 T, B;
     tangent_frame(n, T, B);
-    float a2 = alpha * alpha;
-    float inv_n = 1.0f / (float)samples;
-    float flast = (float)last;
+    FaceDims dims = face_dims(S);
     Kahan r{0, 0}, g{0, 0}, b{0, 0}, w{0, 0};
+    float4 next = lane < samples ? table[lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (int k = lane; k < samples; k += 64) {
-        float u2 = radical_inverse2((uint32_t)k);
-        v3 h = ggx_half((float)k * inv_n, u2, a2, n, T, B);
+        float4 t = next;
+        if (k + 64 < samples) next = table[k + 64];
+        v3 h = ggx_to_world(t, n, T, B);
         float vh = dot(n, h);
         v3 l = h * (2.0f * vh) - n;
         float nl = dot(n, l);
         if (nl > 0.0f) {
-            float den = fmaf(a2, u2, 1.0f - u2);
-            float lod = fminf(fmaxf(lod0 - __log2f(den), 0.0f), flast);
-            int l0 = (int)lod;
-            int l1 = min(l0 + 1, last);
-            float fl = lod - (float)l0;
-            FaceST fs = cube_face(l);
-            int s0 = S >> l0, s1 = S >> l1;
-            float4 L0 = face_bilinear(chain, chain_offset_pow2(S, l0), face_dims(s0), fs);
-            float4 L1 = face_bilinear(chain, chain_offset_pow2(S, l1), face_dims(s1), fs);
-            float4 L = lerp4(L0, L1, fl);
+            float4 L = cube_bilinear(env, dims, l);
             kahan_add(r, L.x * nl);
             kahan_add(g, L.y * nl);
             kahan_add(b, L.z * nl);
@@ -264,6 +256,63 @@ __global__ void __launch_bounds__(256) k_prefilter_fis(const float4 *__restrict_
     if (lane == 0) {
         float iw = 1.0f / W;
         out[o] = make_float4(R * iw, G * iw, Bv * iw, 0.0f);
+    }
+}
+
+// Partial sums of a prefiltered level (roughness > 0) with filtered importance
+// sampling.  Wavefront w of the grid takes tile w / chunks (8x8 texels of one
+// face) and chunk w % chunks of the samples; its lanes are the tile's texels (a
+// lane past the face edge computes a clamped texel and writes nothing).  Sample
+// k's direction l is its half vector reflected about the texel normal n; with
+// N.L > 0 it adds L(l) N.L and N.L, L read trilinearly from the environment
+// chain at the sample's level.  part: [chunk][texel][8] = Kahan (s, c) of R,
+// G, B and the weight, as k_irradiance_final sums them.
+__global__ void __launch_bounds__(256) k_prefilter_fis(const float4 *__restrict__ chain, int S, int last, int sm,
+                                                       const float4 *__restrict__ table, int samples, int chunks,
+                                                       float *__restrict__ part) {
+    // wave-uniform by construction; readfirstlane tells the compiler, so the
+    // sample loop and its table loads are scalar
+    int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+    int lane = threadIdx.x & 63;
+    int tpf = (sm + 7) >> 3;
+    if (w >= 6 * tpf * tpf * chunks) return;  // whole wavefront leaves together
+    int tile = w / chunks, chunk = w - tile * chunks;
+    int f = tile / (tpf * tpf), t = tile - f * (tpf * tpf);
+    int i = (t % tpf) * 8 + (lane & 7), j = (t / tpf) * 8 + (lane >> 3);
+    v3 n = normalize(cube_texel_dir(f, min(i, sm - 1), min(j, sm - 1), sm));
+    v3 T, B;
+    tangent_frame(n, T, B);
+    Kahan r{0, 0}, g{0, 0}, b{0, 0}, wt{0, 0};
+    // (samples <= 2^20 and chunks <= 16: the products fit in 32 bits)
+    int k0 = chunk * samples / chunks, k1 = (chunk + 1) * samples / chunks;
+    for (int k = k0; k < k1; ++k) {
+        float4 tk = table[k];
+        v3 h = ggx_to_world(tk, n, T, B);
+        float vh = dot(n, h);
+        v3 l = h * (2.0f * vh) - n;
+        float nl = dot(n, l);
+        if (nl > 0.0f) {
+            float lod = tk.w;
+            int l0 = (int)lod;
+            int l1 = min(l0 + 1, last);
+            float fl = lod - (float)l0;
+            FaceST fs = cube_face(l);
+            int s0 = S >> l0, s1 = S >> l1;
+            float4 L0 = face_bilinear(chain, chain_offset_pow2(S, l0), face_dims(s0), fs);
+            float4 L1 = face_bilinear(chain, chain_offset_pow2(S, l1), face_dims(s1), fs);
+            float4 L = lerp4(L0, L1, fl);
+            kahan_add(r, L.x * nl);
+            kahan_add(g, L.y * nl);
+            kahan_add(b, L.z * nl);
+            kahan_add(wt, nl);
+        }
+    }
+    if (i < sm && j < sm) {
+        int nout = 6 * sm * sm;
+        int o = f * sm * sm + j * sm + i;
+        float *p = part + ((size_t)chunk * nout + o) * 8;
+        p[0] = r.s; p[1] = g.s; p[2] = b.s; p[3] = wt.s;
+        p[4] = r.c; p[5] = g.c; p[6] = b.c; p[7] = wt.c;
     }
 }
 
@@ -300,6 +349,58 @@ __global__ void __launch_bounds__(256) k_brdf_lut(int size, int samples, float2 
     if (lane == 0) out[o] = make_float2(a * inv_n, b * inv_n);
 }
 
+// The same entries with the row's GGX half vectors made once into LDS (for up
+// to kLutLdsSamples samples): block b takes kLutRowSlice entries of one row (one
+// roughness), each wavefront a quarter of them in turn, its lanes splitting
+// the samples as in k_brdf_lut (the same order, so the same sums).
+constexpr int kLutLdsSamples = 2048, kLutRowSlice = 32;
+__global__ void __launch_bounds__(256) k_brdf_lut_rows(int size, int samples, float2 *__restrict__ out) {
+    extern __shared__ float4 tab[];  // samples entries (launched with samples * 16 bytes)
+    int slices = (size + kLutRowSlice - 1) / kLutRowSlice;
+    int j = (int)blockIdx.x / slices, i0 = ((int)blockIdx.x - j * slices) * kLutRowSlice;
+    float rough = ((float)j + 0.5f) / (float)size;
+    float alpha = rough * rough, a2 = alpha * alpha, k = 0.5f * alpha;
+    float inv_n = 1.0f / (float)samples;
+    for (int s = (int)threadIdx.x; s < samples; s += 256)
+        tab[s] = ggx_tangent((float)s * inv_n, radical_inverse2((uint32_t)s), a2);
+    __syncthreads();
+    int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    v3 n = mk3(0.0f, 0.0f, 1.0f), T, B;
+    tangent_frame(n, T, B);
+    for (int q = wave; q < kLutRowSlice; q += 4) {
+        int i = i0 + q;
+        if (i >= size) break;  // wave-uniform
+        float NoV = ((float)i + 0.5f) / (float)size;
+        v3 V = mk3(sqrtf(fmaxf(0.0f, 1.0f - NoV * NoV)), 0.0f, NoV);
+        float gv = fmaf(NoV, 1.0f - k, k);
+        Kahan A{0, 0}, Bs{0, 0};
+        for (int s = lane; s < samples; s += 64) {
+            v3 h = ggx_to_world(tab[s], n, T, B);
+            float vh = dot(V, h);
+            float nl = fmaf(2.0f * vh, h.z, -V.z);
+            if (nl > 0.0f) {
+                float gvis = nl * vh / (h.z * fmaf(nl, 1.0f - k, k) * gv);
+                float fc = pow5(1.0f - vh);
+                kahan_add(A, (1.0f - fc) * gvis);
+                kahan_add(Bs, fc * gvis);
+            }
+        }
+        float a = wave_sum_compensated(kahan_value(A));
+        float b = wave_sum_compensated(kahan_value(Bs));
+        if (lane == 0) out[j * size + i] = make_float2(a * inv_n, b * inv_n);
+    }
+}
+
+// Sample chunks of a prefiltered level of face size sm: enough wavefronts to
+// fill the chip (about 8192, 32 per CU) without splitting a tile's samples
+// more than 16 ways.
+static int prefilter_chunks(int sm) {
+    int tpf = (sm + 7) / 8;
+    int tiles = 6 * tpf * tpf;
+    int c = (8192 + tiles - 1) / tiles;
+    return c < 1 ? 1 : (c > 16 ? 16 : c);
+}
+
 IblPlan ibl_plan(int S, const epb_ibl_params &p) {
     IblPlan q{};
     q.S = S;
@@ -334,6 +435,15 @@ IblPlan ibl_plan(int S, const epb_ibl_params &p) {
     // environment mip chain for filtered importance sampling: levels 0 .. last
     // contiguous, level k at texel offset 8 (S^2 - (S >> k)^2)
     q.off_chain = take(q.fis ? (size_t)8 * S * S * 16 : 0);
+    // the prefilter's GGX sample table and partial sums, one level at a time
+    size_t part = 0;
+    for (int m = 0; q.fis && m < q.pref_levels; ++m) {
+        int sm = q.pref_base >> m;
+        size_t need = (size_t)prefilter_chunks(sm) * 6 * sm * sm * 8 * 4;
+        if (need > part) part = need;
+    }
+    q.off_ggx = take((size_t)q.pref_samples * 16);
+    q.off_ppart = take(part);
     q.bytes = off;
     return q;
 }
@@ -354,6 +464,8 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
     hipLaunchKernelGGL(k_irradiance_final, dim3((nout + 255) / 256), dim3(256), 0, s, part, q.chunks, q.irr,
                        (float4 *)irr);
     float4 *chain = (float4 *)(sc + q.off_chain);
+    float4 *ggx = (float4 *)(sc + q.off_ggx);
+    float *ppart = (float *)(sc + q.off_ppart);
     if (q.fis) {
         int n0 = 6 * q.S * q.S;
         hipLaunchKernelGGL(k_env_copy, dim3((n0 + 255) / 256), dim3(256), 0, s, env4, n0, chain);
@@ -373,18 +485,37 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
         float4 *dst = (float4 *)pref + off;
         if (alpha == 0.0f) {
             hipLaunchKernelGGL(k_prefilter_mirror, dim3((n + 255) / 256), dim3(256), 0, s, env4, q.S, sm, dst);
-        } else if (q.fis) {
-            double a2 = (double)alpha * alpha;
-            float lod0 = (float)(0.5 * std::log2(6.0 * q.S * q.S * a2 / q.pref_samples) + 1.0);
-            hipLaunchKernelGGL(k_prefilter_fis, dim3((n + 3) / 4), dim3(256), 0, s, chain, q.S, q.chain_last, sm,
-                               alpha, q.pref_samples, lod0, dst);
-        } else
-            hipLaunchKernelGGL(k_prefilter, dim3((n + 3) / 4), dim3(256), 0, s, env4, q.S, sm, alpha,
-                               q.pref_samples, dst);
+        } else {
+            float lod0 = 0.0f;
+            if (q.fis) {
+                double a2 = (double)alpha * alpha;
+                lod0 = (float)(0.5 * std::log2(6.0 * q.S * q.S * a2 / q.pref_samples) + 1.0);
+            }
+            // (stream order: the previous level's kernels are done with the table and the partials)
+            hipLaunchKernelGGL(k_ggx_table, dim3((q.pref_samples + 255) / 256), dim3(256), 0, s, alpha,
+                               q.pref_samples, q.fis, lod0, q.chain_last, ggx);
+            if (q.fis) {
+                int chunks = prefilter_chunks(sm), tpf = (sm + 7) / 8;
+                int waves = 6 * tpf * tpf * chunks;
+                hipLaunchKernelGGL(k_prefilter_fis, dim3((waves + 3) / 4), dim3(256), 0, s, chain, q.S,
+                                   q.chain_last, sm, (const float4 *)ggx, q.pref_samples, chunks, ppart);
+                hipLaunchKernelGGL(k_irradiance_final, dim3((n + 255) / 256), dim3(256), 0, s, ppart, chunks, sm,
+                                   dst);
+            } else {
+                hipLaunchKernelGGL(k_prefilter, dim3((n + 3) / 4), dim3(256), 0, s, env4, q.S, sm,
+                                   (const float4 *)ggx, q.pref_samples, dst);
+            }
+        }
         off += (size_t)n;
     }
-    int nl = q.lut * q.lut;
-    hipLaunchKernelGGL(k_brdf_lut, dim3((nl + 3) / 4), dim3(256), 0, s, q.lut, q.lut_samples, (float2 *)lut);
+    if (q.lut_samples <= kLutLdsSamples) {
+        int slices = (q.lut + kLutRowSlice - 1) / kLutRowSlice;
+        hipLaunchKernelGGL(k_brdf_lut_rows, dim3(q.lut * slices), dim3(256), (size_t)q.lut_samples * sizeof(float4), s,
+                           q.lut, q.lut_samples, (float2 *)lut);
+    } else {
+        int nl = q.lut * q.lut;
+        hipLaunchKernelGGL(k_brdf_lut, dim3((nl + 3) / 4), dim3(256), 0, s, q.lut, q.lut_samples, (float2 *)lut);
+    }
     return hipGetLastError();
 }
 
