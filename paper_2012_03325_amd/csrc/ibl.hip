@@ -225,7 +225,9 @@ __global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ en
                                                    const float4 *__restrict__ table, int samples,
                                                    float4 *__restrict__ out) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    int o = blockIdx.x * 4 + wave;
+    // XCD-aware: each XCD's blocks take a contiguous run of texels, whose lobes
+    // cover a fraction of the environment that its own L2 can hold
+    int o = xcd_tile((int)blockIdx.x, (int)gridDim.x) * 4 + wave;
     if (o >= 6 * sm * sm) return;  // whole wavefront leaves together
     int f = o / (sm * sm), j = (o / sm) % sm, i = o % sm;
     v3 n = normalize(cube_texel_dir(f, i, j, sm));
@@ -272,6 +274,8 @@ __global__ void __launch_bounds__(256) k_prefilter_fis(const float4 *__restrict_
                                                        float *__restrict__ part) {
     // wave-uniform by construction; readfirstlane tells the compiler, so the
     // sample loop and its table loads are scalar
+    // (not XCD-aware: the matched mip levels are small enough for every L2,
+    // and the XCD-contiguous order measured slower here)
     int w = __builtin_amdgcn_readfirstlane((int)blockIdx.x * 4 + (int)(threadIdx.x >> 6));
     int lane = threadIdx.x & 63;
     int tpf = (sm + 7) >> 3;
