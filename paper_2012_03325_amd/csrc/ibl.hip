@@ -61,28 +61,56 @@ __device__ float texel_solid_angle(int i, int j, int S) {
 // of the k x k environment texels it covers (k = S / Ss).  Because solid angles
 // add, this equals repeated 2x2 weighted halving.  Also writes the source
 // table entry (unit direction, solid angle at size Ss).
-__global__ void __launch_bounds__(256) k_ibl_source(const float4 *__restrict__ env, int S, int Ss,
+// Compensated sum over aligned segments of `width` lanes (a power of two <= 64):
+// Knuth two-sums down a butterfly, the rounding errors carried beside.
+__device__ __forceinline__ float segment_sum_compensated(float v, int width) {
+    float comp = 0.0f;
+    for (int off = width >> 1; off >= 1; off >>= 1) {
+        float o = __shfl_xor(v, off, 64);
+        float oc = __shfl_xor(comp, off, 64);
+        float s, e;
+        two_sum(v, o, s, e);
+        v = s;
+        comp = comp + oc + e;
+    }
+    return v + comp;
+}
+
+// A segment of lpt lanes (the k x k block rounded up to a power of two, at most
+// 64) per source texel: each lane sums its share of the block with Kahan, the
+// segment adds the lanes' sums compensated.  lpt is uniform.
+__global__ void __launch_bounds__(256) k_ibl_source(const float4 *__restrict__ env, int S, int Ss, int lpt,
                                                     float4 *__restrict__ src, float4 *__restrict__ tab) {
-    int o = blockIdx.x * blockDim.x + threadIdx.x;
-    if (o >= 6 * Ss * Ss) return;
-    int f = o / (Ss * Ss), j = (o / Ss) % Ss, i = o % Ss;
+    int t = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+    int o = t / lpt, sub = t - o * lpt;
+    int nsrc = 6 * Ss * Ss;
+    // (the segment stays together: nsrc * lpt threads fill whole segments)
+    bool live = o < nsrc;
+    int oc = live ? o : nsrc - 1;
+    int f = oc / (Ss * Ss), j = (oc / Ss) % Ss, i = oc % Ss;
     int k = S / Ss;
     Kahan r{0, 0}, g{0, 0}, b{0, 0}, w{0, 0};
     const float4 *face = env + (size_t)f * S * S;
-    for (int bj = 0; bj < k; ++bj)
-        for (int bi = 0; bi < k; ++bi) {
-            int ci = i * k + bi, cj = j * k + bj;
-            float dw = k == 1 ? 1.0f : texel_solid_angle(ci, cj, S);
-            float4 L = face[(size_t)cj * S + ci];
-            kahan_add(r, L.x * dw);
-            kahan_add(g, L.y * dw);
-            kahan_add(b, L.z * dw);
-            kahan_add(w, dw);
-        }
-    float iw = 1.0f / kahan_value(w);
-    src[o] = make_float4(kahan_value(r) * iw, kahan_value(g) * iw, kahan_value(b) * iw, 0.0f);
-    v3 d = normalize(cube_texel_dir(f, i, j, Ss));
-    tab[o] = make_float4(d.x, d.y, d.z, texel_solid_angle(i, j, Ss));
+    for (int q = sub; q < k * k; q += lpt) {
+        int bj = q / k, bi = q - bj * k;
+        int ci = i * k + bi, cj = j * k + bj;
+        float dw = k == 1 ? 1.0f : texel_solid_angle(ci, cj, S);
+        float4 L = face[(size_t)cj * S + ci];
+        kahan_add(r, L.x * dw);
+        kahan_add(g, L.y * dw);
+        kahan_add(b, L.z * dw);
+        kahan_add(w, dw);
+    }
+    float R = segment_sum_compensated(kahan_value(r), lpt);
+    float G = segment_sum_compensated(kahan_value(g), lpt);
+    float Bv = segment_sum_compensated(kahan_value(b), lpt);
+    float W = segment_sum_compensated(kahan_value(w), lpt);
+    if (live && sub == 0) {
+        float iw = 1.0f / W;
+        src[o] = make_float4(R * iw, G * iw, Bv * iw, 0.0f);
+        v3 d = normalize(cube_texel_dir(f, i, j, Ss));
+        tab[o] = make_float4(d.x, d.y, d.z, texel_solid_angle(i, j, Ss));
+    }
 }
 
 // Partial irradiance sums over source chunk blockIdx.y for 256 outputs.
@@ -461,7 +489,11 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
     const float4 *env4 = (const float4 *)env;
     int nsrc = 6 * q.src * q.src;
     int nout = 6 * q.irr * q.irr;
-    hipLaunchKernelGGL(k_ibl_source, dim3((nsrc + 255) / 256), dim3(256), 0, s, env4, q.S, q.src, src, tab);
+    int kk = (q.S / q.src) * (q.S / q.src), lpt = 1;
+    while (lpt < kk && lpt < 64) lpt *= 2;
+    long long threads = (long long)nsrc * lpt;
+    hipLaunchKernelGGL(k_ibl_source, dim3((unsigned)((threads + 255) / 256)), dim3(256), 0, s, env4, q.S, q.src,
+                       lpt, src, tab);
     int chunk_len = (nsrc + q.chunks - 1) / q.chunks;
     hipLaunchKernelGGL(k_irradiance_partial, dim3((nout + 255) / 256, q.chunks), dim3(256), 0, s, src, tab,
                        nsrc, chunk_len, q.irr, part);
