@@ -469,12 +469,12 @@ IblPlan ibl_plan(int S, const epb_ibl_params &p) {
     q.off_chain = take(q.fis ? (size_t)8 * S * S * 16 : 0);
     // the prefilter's GGX sample table and partial sums, one level at a time
     size_t part = 0;
-    for (int m = 0; q.fis && m < q.pref_levels; ++m) {
+    for (int m = 1; q.fis && m < q.pref_levels; ++m) {  // (level 0 has roughness 0: no samples)
         int sm = q.pref_base >> m;
         size_t need = (size_t)prefilter_chunks(sm) * 6 * sm * sm * 8 * 4;
         if (need > part) part = need;
     }
-    q.off_ggx = take((size_t)q.pref_samples * 16);
+    q.off_ggx = take(q.pref_levels > 1 ? (size_t)q.pref_samples * 16 : 0);
     q.off_ppart = take(part);
     q.bytes = off;
     return q;
