@@ -155,6 +155,10 @@ IBL_CASES = {
     "gradient-16-fis-7": (lambda: synth.env_sky_gradient(16),
                           dict(irr_size=4, irr_src_size=16, pref_size=16, pref_levels=4, pref_samples=7,
                                lut_size=8, lut_samples=16, pref_fis=1)),
+    # more BRDF-table samples than the per-row LDS table holds (the one-wavefront-per-entry kernel)
+    "gradient-16-lut4096": (lambda: synth.env_sky_gradient(16),
+                            dict(irr_size=4, irr_src_size=16, pref_size=16, pref_levels=3, pref_samples=4096,
+                                 lut_size=24, lut_samples=4096)),
     "sun-512-fis-256": (lambda: synth.env_sky_sun(512),
                         dict(irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=256,
                              lut_size=64, lut_samples=64, pref_fis=1)),
