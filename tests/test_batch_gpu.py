@@ -118,13 +118,16 @@ def _limit_views():
 
 @pytest.mark.parametrize("sched", [(0, 0, 0, 0), (0, 2, 1, 0), (0, 0, 0, 0, 16), (0, 1, 1, 0, 0, 0, 1)],
                          ids=lambda s: "sched-" + "-".join(map(str, s)))
-def test_batch_at_the_abi_limits_equals_solo(sched):
+@pytest.mark.parametrize("half", [False, True], ids=["fp32", "fp16"])
+def test_batch_at_the_abi_limits_equals_solo(sched, half):
     """Per-view light counts up to eight and SSAO kernels up to 256 samples in one batch."""
+    from paper_2012_03325_amd import epb as E
     from paper_2012_03325_amd import frame as fr
     views = _limit_views()
-    dvs = _device_views(views)
+    dt = E.EPB_F16 if half else E.EPB_F32
+    dvs = _device_views(views, gdtype=dt, ao_dtype=dt, hdr_dtype=dt)
     log(f"[batch-limits] {[(v.width, v.height, len(v.lights), v.ssao_kernel.shape[0]) for v in views]}, "
-        f"schedule {sched}: solo renders")
+        f"{'FP16' if half else 'FP32'}, schedule {sched}: solo renders")
     solo = _solo(dvs)
     for dv in dvs:
         for t in (dv.ao, dv.hdr, dv.ldr):

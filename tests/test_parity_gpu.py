@@ -468,7 +468,7 @@ def _round_gbuffer_f16(view):
     return view
 
 
-@pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "full-1080p"])
+@pytest.mark.parametrize("kind", ["plain-256", "ragged-201x137", "max-lights-8", "yawed-131x91", "full-1080p"])
 def test_fp16_form_arithmetic_parity(kind):
     """FP16 storage against the oracle fed the same FP16-rounded G-buffer: only
     the arithmetic and the half storage of AO and HDR differ."""
