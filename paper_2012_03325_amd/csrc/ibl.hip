@@ -57,10 +57,6 @@ __device__ float texel_solid_angle(int i, int j, int S) {
     return 2.0f * (atan2f(num, den1) + atan2f(num, den2));
 }
 
-// Irradiance source: texel (f, i, j) of size Ss is the solid-angle-weighted mean
-// of the k x k environment texels it covers (k = S / Ss).  Because solid angles
-// add, this equals repeated 2x2 weighted halving.  Also writes the source
-// table entry (unit direction, solid angle at size Ss).
 // Compensated sum over aligned segments of `width` lanes (a power of two <= 64):
 // Knuth two-sums down a butterfly, the rounding errors carried beside.
 __device__ __forceinline__ float segment_sum_compensated(float v, int width) {
@@ -76,6 +72,10 @@ __device__ __forceinline__ float segment_sum_compensated(float v, int width) {
     return v + comp;
 }
 
+// Irradiance source: texel (f, i, j) of size Ss is the solid-angle-weighted mean
+// of the k x k environment texels it covers (k = S / Ss).  Because solid angles
+// add, this equals repeated 2x2 weighted halving.  Also writes the source
+// table entry (unit direction, solid angle at size Ss).
 // A segment of lpt lanes (the k x k block rounded up to a power of two, at most
 // 64) per source texel: each lane sums its share of the block with Kahan, the
 // segment adds the lanes' sums compensated.  lpt is uniform.
