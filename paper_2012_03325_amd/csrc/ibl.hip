@@ -384,7 +384,7 @@ __global__ void __launch_bounds__(256) k_brdf_lut(int size, int samples, float2 
 // The same entries with the row's GGX half vectors made once into LDS (for up
 // to kLutLdsSamples samples): block b takes kLutRowSlice entries of one row (one
 // roughness), each wavefront a quarter of them in turn, its lanes splitting
-// the samples as in k_brdf_lut (the same order, so the same sums).
+// the samples as in k_brdf_lut (the same order); G_vis from a reciprocal.
 constexpr int kLutLdsSamples = 2048, kLutRowSlice = 32;
 __global__ void __launch_bounds__(256) k_brdf_lut_rows(int size, int samples, float2 *__restrict__ out) {
     extern __shared__ float4 tab[];  // samples entries (launched with samples * 16 bytes)
@@ -411,7 +411,7 @@ __global__ void __launch_bounds__(256) k_brdf_lut_rows(int size, int samples, fl
             float vh = dot(V, h);
             float nl = fmaf(2.0f * vh, h.z, -V.z);
             if (nl > 0.0f) {
-                float gvis = nl * vh / (h.z * fmaf(nl, 1.0f - k, k) * gv);
+                float gvis = nl * vh * rcp(h.z * fmaf(nl, 1.0f - k, k) * gv);
                 float fc = pow5(1.0f - vh);
                 kahan_add(A, (1.0f - fc) * gvis);
                 kahan_add(Bs, fc * gvis);
