@@ -138,7 +138,28 @@ __global__ void __launch_bounds__(256) k_irradiance_partial(const float4 *__rest
         }
         __syncthreads();
         int cnt = min(256, end - base);
-        for (int q = 0; q < cnt; ++q) {
+        // Every term is >= 0, so a group of four summed in plain float and then
+        // Kahan-added keeps the whole sum within about 3 units of rounding of
+        // its value (each group's error is bounded by its own terms), as with
+        // a Kahan add per term, at a quarter of the compensation work.
+        int q = 0;
+        for (; q + 4 <= cnt; q += 4) {
+            float c[4], lr[4], lg[4], lb[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                float4 T = sT[q + u];
+                c[u] = fmaxf(0.0f, fmaf(n.x, T.x, fmaf(n.y, T.y, n.z * T.z))) * T.w;
+                float4 L = sL[q + u];
+                lr[u] = L.x;
+                lg[u] = L.y;
+                lb[u] = L.z;
+            }
+            kahan_add(r, fmaf(lr[3], c[3], fmaf(lr[2], c[2], fmaf(lr[1], c[1], lr[0] * c[0]))));
+            kahan_add(g, fmaf(lg[3], c[3], fmaf(lg[2], c[2], fmaf(lg[1], c[1], lg[0] * c[0]))));
+            kahan_add(b, fmaf(lb[3], c[3], fmaf(lb[2], c[2], fmaf(lb[1], c[1], lb[0] * c[0]))));
+            kahan_add(w, ((c[0] + c[1]) + c[2]) + c[3]);
+        }
+        for (; q < cnt; ++q) {
             float4 T = sT[q];
             float c = fmaxf(0.0f, fmaf(n.x, T.x, fmaf(n.y, T.y, n.z * T.z))) * T.w;
             float4 L = sL[q];
