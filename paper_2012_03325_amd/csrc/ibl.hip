@@ -242,27 +242,32 @@ __global__ void __launch_bounds__(256) k_env_down(const float4 *__restrict__ src
     dst[o] = make_float4(r * iw, g * iw, b * iw, 0.0f);
 }
 
-// The GGX samples of one prefiltered level (roughness^2 = alpha > 0): entry k
-// is the tangent-frame half vector of Hammersley sample k and, for filtered
-// importance sampling, the environment chain level that sample reads (w; 0
-// otherwise).  That level is lod0 - log2(den) clamped to [0, last], where den =
-// (1 - u2) + alpha^2 u2 is the GGX sampling denominator: for V = N the pdf of l
-// is D / 4 = den^2 / (4 pi alpha^2), so 1/2 log2(omega_s / omega_p) + 1 =
-// 1/2 log2(6 S^2 alpha^2 / N) + 1 - log2(den) (lod0 is that constant part,
-// computed on the host in double precision).
-__global__ void __launch_bounds__(256) k_ggx_table(float alpha, int samples, int fis, float lod0, int last,
-                                                   float4 *__restrict__ table) {
-    int k = (int)blockIdx.x * 256 + (int)threadIdx.x;
-    if (k >= samples) return;
+// The GGX samples of the prefiltered levels (one launch, blockIdx.y = level):
+// entry k of level m is the tangent-frame half vector of Hammersley sample k for
+// roughness^2 = alpha_m and, for filtered importance sampling, the environment
+// chain level that sample reads (w; 0 otherwise).  That level is lod0 - log2(den)
+// clamped to [0, last], where den = (1 - u2) + alpha^2 u2 is the GGX sampling
+// denominator: for V = N the pdf of l is D / 4 = den^2 / (4 pi alpha^2), so
+// 1/2 log2(omega_s / omega_p) + 1 = 1/2 log2(6 S^2 alpha^2 / N) + 1 - log2(den)
+// (lod0 is that constant part, computed on the host in double precision).
+// Levels with alpha = 0 (the mirror level) have no table.
+struct GgxLevels {
+    float alpha[8], lod0[8];
+};
+__global__ void __launch_bounds__(256) k_ggx_table(GgxLevels lv, int samples, int fis, int last,
+                                                   float4 *__restrict__ tables) {
+    int k = (int)blockIdx.x * 256 + (int)threadIdx.x, m = (int)blockIdx.y;
+    float alpha = lv.alpha[m];
+    if (k >= samples || alpha == 0.0f) return;
     float a2 = alpha * alpha;
     float inv_n = 1.0f / (float)samples;
     float u2 = radical_inverse2((uint32_t)k);
     float4 t = ggx_tangent((float)k * inv_n, u2, a2);
     if (fis) {
         float den = fmaf(a2, u2, 1.0f - u2);
-        t.w = fminf(fmaxf(lod0 - __log2f(den), 0.0f), (float)last);
+        t.w = fminf(fmaxf(lv.lod0[m] - __log2f(den), 0.0f), (float)last);
     }
-    table[k] = t;
+    tables[(size_t)m * samples + k] = t;
 }
 
 // One wavefront per prefiltered texel of a level (roughness > 0), from level 0
@@ -495,7 +500,7 @@ IblPlan ibl_plan(int S, const epb_ibl_params &p) {
         size_t need = (size_t)prefilter_chunks(sm) * 6 * sm * sm * 8 * 4;
         if (need > part) part = need;
     }
-    q.off_ggx = take(q.pref_levels > 1 ? (size_t)q.pref_samples * 16 : 0);
+    q.off_ggx = take(q.pref_levels > 1 ? (size_t)q.pref_levels * q.pref_samples * 16 : 0);  // a table per level
     q.off_ppart = take(part);
     q.bytes = off;
     return q;
@@ -533,34 +538,39 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
                                2 * Sd, chain + 8u * ((unsigned)q.S * q.S - (unsigned)Sd * Sd));
         }
     }
+    GgxLevels lv{};
+    for (int m = 0; m < q.pref_levels; ++m) {
+        float rough = q.pref_levels > 1 ? (float)m / (float)(q.pref_levels - 1) : 0.0f;
+        lv.alpha[m] = rough * rough;
+        if (q.fis && lv.alpha[m] != 0.0f) {
+            double a2 = (double)lv.alpha[m] * lv.alpha[m];
+            lv.lod0[m] = (float)(0.5 * std::log2(6.0 * q.S * q.S * a2 / q.pref_samples) + 1.0);
+        }
+    }
+    if (q.pref_levels > 1)
+        hipLaunchKernelGGL(k_ggx_table, dim3((q.pref_samples + 255) / 256, q.pref_levels), dim3(256), 0, s, lv,
+                           q.pref_samples, q.fis, q.chain_last, ggx);
     size_t off = 0;
     for (int m = 0; m < q.pref_levels; ++m) {
         int sm = q.pref_base >> m;
-        float rough = q.pref_levels > 1 ? (float)m / (float)(q.pref_levels - 1) : 0.0f;
-        float alpha = rough * rough;
+        float alpha = lv.alpha[m];
+        const float4 *table = ggx + (size_t)m * q.pref_samples;
         int n = 6 * sm * sm;
         float4 *dst = (float4 *)pref + off;
         if (alpha == 0.0f) {
             hipLaunchKernelGGL(k_prefilter_mirror, dim3((n + 255) / 256), dim3(256), 0, s, env4, q.S, sm, dst);
         } else {
-            float lod0 = 0.0f;
-            if (q.fis) {
-                double a2 = (double)alpha * alpha;
-                lod0 = (float)(0.5 * std::log2(6.0 * q.S * q.S * a2 / q.pref_samples) + 1.0);
-            }
-            // (stream order: the previous level's kernels are done with the table and the partials)
-            hipLaunchKernelGGL(k_ggx_table, dim3((q.pref_samples + 255) / 256), dim3(256), 0, s, alpha,
-                               q.pref_samples, q.fis, lod0, q.chain_last, ggx);
+            // (stream order: the previous level's kernels are done with the partials)
             if (q.fis) {
                 int chunks = prefilter_chunks(sm), tpf = (sm + 7) / 8;
                 int waves = 6 * tpf * tpf * chunks;
                 hipLaunchKernelGGL(k_prefilter_fis, dim3((waves + 3) / 4), dim3(256), 0, s, chain, q.S,
-                                   q.chain_last, sm, (const float4 *)ggx, q.pref_samples, chunks, ppart);
+                                   q.chain_last, sm, table, q.pref_samples, chunks, ppart);
                 hipLaunchKernelGGL(k_irradiance_final, dim3((n + 255) / 256), dim3(256), 0, s, ppart, chunks, sm,
                                    dst);
             } else {
-                hipLaunchKernelGGL(k_prefilter, dim3((n + 3) / 4), dim3(256), 0, s, env4, q.S, sm,
-                                   (const float4 *)ggx, q.pref_samples, dst);
+                hipLaunchKernelGGL(k_prefilter, dim3((n + 3) / 4), dim3(256), 0, s, env4, q.S, sm, table,
+                                   q.pref_samples, dst);
             }
         }
         off += (size_t)n;
