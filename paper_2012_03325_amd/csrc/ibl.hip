@@ -218,6 +218,48 @@ __global__ void __launch_bounds__(256) k_env_copy(const float4 *__restrict__ env
     if (o < n) dst[o] = env[o];
 }
 
+// Level 0 of the environment as packed RGB texels (12 bytes) for the
+// prefilter, whose taps use only the colour: each tap then moves three quarters
+// of the bytes through the texture data path, the unit that bounds it.
+struct Rgb {
+    float r, g, b;
+};
+__global__ void __launch_bounds__(256) k_env_rgb(const float4 *__restrict__ env, int n, Rgb *__restrict__ dst) {
+    int o = blockIdx.x * blockDim.x + threadIdx.x;
+    if (o < n) {
+        float4 v = env[o];
+        sto(dst, (unsigned)o * 12u, Rgb{v.x, v.y, v.z});
+    }
+}
+
+// face_bilinear over packed RGB texels, split into its loads and its
+// interpolation (so that a caller can have several lookups' loads in flight):
+// the same coordinates, taps and interpolation, so the same values.
+struct RgbTaps {
+    Rgb a, b, c, d;
+    float wx, wy;
+};
+__device__ __forceinline__ RgbTaps rgb_taps(const Rgb *__restrict__ lvl, const FaceDims &g, FaceST f) {
+    RgbTaps q;
+    float x = clamp_to(fmaf(f.s, g.half, g.off), g.hi);
+    float y = clamp_to(fmaf(f.t, g.half, g.off), g.hi);
+    float x0f = fminf(floorf(x), g.hi1), y0f = fminf(floorf(y), g.hi1);
+    q.wx = x - x0f;
+    q.wy = y - y0f;
+    unsigned idx = __umul24((unsigned)fmaf(f.face, (float)g.S, y0f), (unsigned)g.S) + (unsigned)x0f;
+    unsigned o0 = idx * 12u, o1 = o0 + (unsigned)g.S * 12u;
+    q.a = ldo(lvl, o0);
+    q.b = ldo(lvl + 1, o0);
+    q.c = ldo(lvl, o1);
+    q.d = ldo(lvl + 1, o1);
+    return q;
+}
+__device__ __forceinline__ float4 rgb_bilinear(const RgbTaps &q) {
+    float4 A = make_float4(q.a.r, q.a.g, q.a.b, 0.0f), B = make_float4(q.b.r, q.b.g, q.b.b, 0.0f);
+    float4 C = make_float4(q.c.r, q.c.g, q.c.b, 0.0f), D = make_float4(q.d.r, q.d.g, q.d.b, 0.0f);
+    return lerp4(lerp4(A, B, q.wx), lerp4(C, D, q.wx), q.wy);
+}
+
 // Level k from level k - 1 (face size Sp = 2 Sd): solid-angle-weighted mean of
 // the 2x2 children, as the irradiance source is built.
 __global__ void __launch_bounds__(256) k_env_down(const float4 *__restrict__ src, int Sp,
@@ -271,11 +313,13 @@ __global__ void __launch_bounds__(256) k_ggx_table(GgxLevels lv, int samples, in
 }
 
 // One wavefront per prefiltered texel of a level (roughness > 0), from level 0
-// of the environment: sample k's half vector from the table (each lane loads
-// its next sample's entry one iteration ahead, so the load travels with the
-// current sample's taps), its direction l the half vector reflected about the
-// texel normal n; with N.L > 0 it adds L(l) N.L and N.L.
-__global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ env, int S, int sm,
+// of the environment (its packed RGB copy): sample k's half vector from the table, its direction l
+// the half vector reflected about the texel normal n; with N.L > 0 it adds
+// L(l) N.L and N.L.  A lane takes its samples k and k + 64 together: both
+// lookups' taps are in flight before either is added (the adds keep the order
+// k, k + 64, k + 128, ...), and the next pair's table entries load one
+// iteration ahead, with the current pair's taps.
+__global__ void __launch_bounds__(256) k_prefilter(const Rgb *__restrict__ env, int S, int sm,
                                                    const float4 *__restrict__ table, int samples,
                                                    float4 *__restrict__ out) {
     int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -289,20 +333,34 @@ __global__ void __launch_bounds__(256) k_prefilter(const float4 *__restrict__ en
     tangent_frame(n, T, B);
     FaceDims dims = face_dims(S);
     Kahan r{0, 0}, g{0, 0}, b{0, 0}, w{0, 0};
-    float4 next = lane < samples ? table[lane] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int k = lane; k < samples; k += 64) {
-        float4 t = next;
-        if (k + 64 < samples) next = table[k + 64];
-        v3 h = ggx_to_world(t, n, T, B);
-        float vh = dot(n, h);
-        v3 l = h * (2.0f * vh) - n;
-        float nl = dot(n, l);
-        if (nl > 0.0f) {
-            float4 L = cube_bilinear(env, dims, l);
-            kahan_add(r, L.x * nl);
-            kahan_add(g, L.y * nl);
-            kahan_add(b, L.z * nl);
-            kahan_add(w, nl);
+    int last = samples - 1;
+    float4 na = table[min(lane, last)], nb = table[min(lane + 64, last)];
+    for (int k = lane; k < samples; k += 128) {
+        float4 ta = na, tb = nb;
+        if (k + 128 < samples) {
+            na = table[k + 128];
+            nb = table[min(k + 192, last)];
+        }
+        v3 ha = ggx_to_world(ta, n, T, B), hb = ggx_to_world(tb, n, T, B);
+        float vha = dot(n, ha), vhb = dot(n, hb);
+        v3 la = ha * (2.0f * vha) - n, lb = hb * (2.0f * vhb) - n;
+        float nla = dot(n, la), nlb = dot(n, lb);
+        bool ua = nla > 0.0f, ub = k + 64 < samples && nlb > 0.0f;
+        RgbTaps qa{}, qb{};
+        if (ua) qa = rgb_taps(env, dims, cube_face(la));
+        if (ub) qb = rgb_taps(env, dims, cube_face(lb));
+        float4 La = rgb_bilinear(qa), Lb = rgb_bilinear(qb);
+        if (ua) {
+            kahan_add(r, La.x * nla);
+            kahan_add(g, La.y * nla);
+            kahan_add(b, La.z * nla);
+            kahan_add(w, nla);
+        }
+        if (ub) {
+            kahan_add(r, Lb.x * nlb);
+            kahan_add(g, Lb.y * nlb);
+            kahan_add(b, Lb.z * nlb);
+            kahan_add(w, nlb);
         }
     }
     float R = wave_sum_compensated(kahan_value(r));
@@ -501,6 +559,7 @@ IblPlan ibl_plan(int S, const epb_ibl_params &p) {
         if (need > part) part = need;
     }
     q.off_ggx = take(q.pref_levels > 1 ? (size_t)q.pref_levels * q.pref_samples * 16 : 0);  // a table per level
+    q.off_rgb = take(!q.fis && q.pref_levels > 1 ? (size_t)6 * S * S * 12 : 0);  // level 0 as packed RGB
     q.off_ppart = take(part);
     q.bytes = off;
     return q;
@@ -547,6 +606,11 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
             lv.lod0[m] = (float)(0.5 * std::log2(6.0 * q.S * q.S * a2 / q.pref_samples) + 1.0);
         }
     }
+    Rgb *rgb = (Rgb *)(sc + q.off_rgb);
+    if (!q.fis && q.pref_levels > 1) {
+        int n0 = 6 * q.S * q.S;
+        hipLaunchKernelGGL(k_env_rgb, dim3((n0 + 255) / 256), dim3(256), 0, s, env4, n0, rgb);
+    }
     if (q.pref_levels > 1)
         hipLaunchKernelGGL(k_ggx_table, dim3((q.pref_samples + 255) / 256, q.pref_levels), dim3(256), 0, s, lv,
                            q.pref_samples, q.fis, q.chain_last, ggx);
@@ -569,8 +633,8 @@ hipError_t launch_precompute_ibl(const IblPlan &q, const float *env, float *irr,
                 hipLaunchKernelGGL(k_irradiance_final, dim3((n + 255) / 256), dim3(256), 0, s, ppart, chunks, sm,
                                    dst);
             } else {
-                hipLaunchKernelGGL(k_prefilter, dim3((n + 3) / 4), dim3(256), 0, s, env4, q.S, sm, table,
-                                   q.pref_samples, dst);
+                hipLaunchKernelGGL(k_prefilter, dim3((n + 3) / 4), dim3(256), 0, s, (const Rgb *)rgb, q.S, sm,
+                                   table, q.pref_samples, dst);
             }
         }
         off += (size_t)n;

@@ -32,7 +32,7 @@ struct IblPlan {
     int chunks;     // split of the irradiance source sum
     int fis;        // filtered importance sampling of the prefilter
     int chain_last; // last level of the environment mip chain (faces >= 2x2)
-    size_t off_src, off_tab, off_part, off_chain, off_ggx, off_ppart, bytes;  // scratch layout
+    size_t off_src, off_tab, off_part, off_chain, off_ggx, off_rgb, off_ppart, bytes;  // scratch layout
 };
 IblPlan ibl_plan(int S, const epb_ibl_params &p);
 hipError_t launch_precompute_ibl(const IblPlan &plan, const float *env, float *irr, float *pref,
