@@ -468,7 +468,8 @@ __global__ void __launch_bounds__(256) k_brdf_lut(int size, int samples, float2 
 // The same entries with the row's GGX half vectors made once into LDS (for up
 // to kLutLdsSamples samples): block b takes kLutRowSlice entries of one row (one
 // roughness), each wavefront a quarter of them in turn, its lanes splitting
-// the samples as in k_brdf_lut (the same order); G_vis from a reciprocal.
+// the samples as in k_brdf_lut (the same order); G_vis from a reciprocal, the
+// compensated sums over groups of four samples.
 constexpr int kLutLdsSamples = 2048, kLutRowSlice = 32;
 __global__ void __launch_bounds__(256) k_brdf_lut_rows(int size, int samples, float2 *__restrict__ out) {
     extern __shared__ float4 tab[];  // samples entries (launched with samples * 16 bytes)
@@ -489,17 +490,37 @@ __global__ void __launch_bounds__(256) k_brdf_lut_rows(int size, int samples, fl
         float NoV = ((float)i + 0.5f) / (float)size;
         v3 V = mk3(sqrtf(fmaxf(0.0f, 1.0f - NoV * NoV)), 0.0f, NoV);
         float gv = fmaf(NoV, 1.0f - k, k);
-        Kahan A{0, 0}, Bs{0, 0};
-        for (int s = lane; s < samples; s += 64) {
+        // Sample s's two terms, both >= 0: with N.L clamped at 0, a sample
+        // below the horizon gets G_vis = 0 (N.L is a factor, the denominator
+        // stays positive: h.z > 0, k > 0) and adds nothing, as if skipped.
+        auto terms = [&](int s, float &ta, float &tb) {
             v3 h = ggx_to_world(tab[s], n, T, B);
             float vh = dot(V, h);
-            float nl = fmaf(2.0f * vh, h.z, -V.z);
-            if (nl > 0.0f) {
-                float gvis = nl * vh * rcp(h.z * fmaf(nl, 1.0f - k, k) * gv);
-                float fc = pow5(1.0f - vh);
-                kahan_add(A, (1.0f - fc) * gvis);
-                kahan_add(Bs, fc * gvis);
-            }
+            float nl = fmaxf(fmaf(2.0f * vh, h.z, -V.z), 0.0f);
+            float gvis = nl * vh * rcp(h.z * fmaf(nl, 1.0f - k, k) * gv);
+            float fc = pow5(1.0f - vh);
+            ta = (1.0f - fc) * gvis;
+            tb = fc * gvis;
+        };
+        // a lane's samples in groups of four summed in plain float, each group
+        // Kahan-added (the whole sum stays within a few units of rounding, as
+        // for the irradiance), then the ones left over one by one
+        Kahan A{0, 0}, Bs{0, 0};
+        int s = lane;
+        for (; s + 192 < samples; s += 256) {
+            float a0, b0, a1, b1, a2, b2, a3, b3;
+            terms(s, a0, b0);
+            terms(s + 64, a1, b1);
+            terms(s + 128, a2, b2);
+            terms(s + 192, a3, b3);
+            kahan_add(A, ((a0 + a1) + a2) + a3);
+            kahan_add(Bs, ((b0 + b1) + b2) + b3);
+        }
+        for (; s < samples; s += 64) {
+            float ta, tb;
+            terms(s, ta, tb);
+            kahan_add(A, ta);
+            kahan_add(Bs, tb);
         }
         float a = wave_sum_compensated(kahan_value(A));
         float b = wave_sum_compensated(kahan_value(Bs));
@@ -533,8 +554,9 @@ IblPlan ibl_plan(int S, const epb_ibl_params &p) {
     int nsrc = 6 * q.src * q.src;
     int nout = 6 * q.irr * q.irr;
     int out_blocks = (nout + 255) / 256;
-    // enough workgroups to cover the 256 CUs at least twice, chunks of >= 256 sources
-    int chunks = (512 + out_blocks - 1) / out_blocks;
+    // about four workgroups per CU (one per SIMD is too few to hide the serial
+    // Kahan chains; eight gain nothing more), chunks of >= 256 sources
+    int chunks = (1024 + out_blocks - 1) / out_blocks;
     int max_chunks = (nsrc + 255) / 256;
     if (chunks > max_chunks) chunks = max_chunks;
     if (chunks < 1) chunks = 1;
