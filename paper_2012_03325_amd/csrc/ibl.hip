@@ -16,8 +16,10 @@
 //    texel, the 64 lanes split the samples, whose taps then stay within the
 //    texel's GGX lobe (a few cache lines at the rough levels' narrow lobes);
 //    per-lane Kahan sums, compensated wave reduction through cross-lane
-//    shuffles; each lane loads its next sample's half vector from the level's
-//    table one iteration ahead (in flight with the current sample's taps).
+//    shuffles; a lane takes two samples at a time (both lookups' taps in
+//    flight), their half vectors from the level's table one iteration ahead,
+//    the taps from a packed RGB copy of the environment (the texture data path
+//    bounds this kernel, and the fourth channel is never used).
 //  * prefilter with filtered importance sampling (taps on the mip level that
 //    matches each sample's footprint): one wavefront per 8x8 tile of output
 //    texels and chunk of the samples; all lanes take the same sample at once,
