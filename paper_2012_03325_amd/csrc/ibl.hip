@@ -185,6 +185,8 @@ __global__ void __launch_bounds__(256) k_irradiance_final(const float *__restric
     int o = blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= nout) return;
     Kahan acc[4] = {{0, 0}, {0, 0}, {0, 0}, {0, 0}};
+    // (unrolled: several chunks' loads in flight ahead of the serial adds)
+#pragma unroll 8
     for (int c = 0; c < chunks; ++c) {
         const float *p = part + ((size_t)c * nout + o) * 8;
         for (int q = 0; q < 4; ++q) {
