@@ -162,6 +162,15 @@ IBL_CASES = {
     "sun-512-fis-256": (lambda: synth.env_sky_sun(512),
                         dict(irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=256,
                              lut_size=64, lut_samples=64, pref_fis=1)),
+    # the largest cube the C ABI takes (6 x 4096^2): 64 x 64 environment texels per irradiance source, the
+    # prefilter's packed RGB copy (1.2 GB) and, with filtered importance sampling, the 13-level mip chain
+    # (2.1 GB) at byte offsets near the top of their 32-bit range
+    "sun-4096-limit": (lambda: synth.env_sky_sun(4096),
+                       dict(irr_size=32, irr_src_size=64, pref_size=128, pref_levels=5, pref_samples=1024,
+                            lut_size=32, lut_samples=256)),
+    "sun-4096-fis-limit": (lambda: synth.env_sky_sun(4096),
+                           dict(irr_size=16, irr_src_size=32, pref_size=256, pref_levels=6, pref_samples=256,
+                                lut_size=32, lut_samples=256, pref_fis=1)),
 }
 
 
