@@ -161,14 +161,19 @@ __device__ __forceinline__ void shade_pixel(const ShadeDesc &c, int x, int y, fl
             float NoL = dot(n, l);
             if (!(NoL > 0.0f)) continue;
             float sh = L.map ? pcf(L, dvx, dvy, d) : 1.0f;
-            v3 h = normalize(V + l);
-            float NoH = dot(n, h);
-            float VoH = fmaxf(dot(V, h), 0.0f);
-            v3 hp = mk3(fmaf(-NoH, n.x, h.x), fmaf(-NoH, n.y, h.y), fmaf(-NoH, n.z, h.z));  // h minus its n part
-            float q = fmaf(NoH * NoH, a2, dot(hp, hp));
+            // The half vector h = s / |s| is never formed: with s = V + l (both unit
+            // vectors) N.H = (N.V + N.L) / |s|, 1 - (N.H)^2 = |s - (n.s) n|^2 / |s|^2
+            // (the part of s off the normal, no cancellation at the peak) and
+            // V.H = |s| / 2, so the GGX denominator q = (N.H)^2 alpha^2 + 1 - (N.H)^2
+            // is qs / |s|^2 with qs = (n.s)^2 alpha^2 + |s - (n.s) n|^2.
+            v3 sv = V + l;
+            float s2 = dot(sv, sv);
+            float ns = nv_raw + NoL;
+            v3 sp = mk3(fmaf(-ns, n.x, sv.x), fmaf(-ns, n.y, sv.y), fmaf(-ns, n.z, sv.z));
+            float qs = fmaf(ns * ns, a2, dot(sp, sp));
             // D * G / (4 NoL NoV) = alpha^2 / (pi q^2) * 1 / (4 (NoL(1-k)+k)(NoV(1-k)+k))
-            float spec = (0.25f / kPi) * a2 * rcp(q * q * fmaf(NoL, 1.0f - kd, kd) * gv);
-            float fc = pow5(1.0f - VoH);
+            float spec = (0.25f / kPi) * a2 * (s2 * s2) * rcp(qs * qs * fmaf(NoL, 1.0f - kd, kd) * gv);
+            float fc = pow5(fmaf(-0.5f, __builtin_amdgcn_sqrtf(s2), 1.0f));  // (1 - V.H)^5
             float e = il * il * NoL * sh;
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
