@@ -157,8 +157,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeDesc &c, int x, int y, fl
             v3 lv = mk3(L.pos[0], L.pos[1], L.pos[2]) - Pw;
             float dist2 = dot(lv, lv);
             float il = rsq(dist2);
-            v3 l = lv * il;
-            float NoL = dot(n, l);
+            float NoL = dot(n, lv) * il;  // (l = lv il is never formed)
             if (!(NoL > 0.0f)) continue;
             float sh = L.map ? pcf(L, dvx, dvy, d) : 1.0f;
             // The half vector h = s / |s| is never formed: with s = V + l (both unit
@@ -166,7 +165,7 @@ __device__ __forceinline__ void shade_pixel(const ShadeDesc &c, int x, int y, fl
             // (the part of s off the normal, no cancellation at the peak) and
             // V.H = |s| / 2, so the GGX denominator q = (N.H)^2 alpha^2 + 1 - (N.H)^2
             // is qs / |s|^2 with qs = (n.s)^2 alpha^2 + |s - (n.s) n|^2.
-            v3 sv = V + l;
+            v3 sv = mk3(fmaf(lv.x, il, V.x), fmaf(lv.y, il, V.y), fmaf(lv.z, il, V.z));
             float s2 = dot(sv, sv);
             float ns = nv_raw + NoL;
             v3 sp = mk3(fmaf(-ns, n.x, sv.x), fmaf(-ns, n.y, sv.y), fmaf(-ns, n.z, sv.z));
