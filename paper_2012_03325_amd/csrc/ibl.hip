@@ -6,7 +6,7 @@
 //  * irradiance: 6*32^2 outputs x 6*64^2 source texels.  One thread per
 //    output, source texels staged through LDS in blocks of 256 and broadcast
 //    to all lanes; the source range is split across workgroups so that the
-//    grid fills all 256 CUs, and the per-split Kahan partials are combined in
+//    grid gives every CU about four, and the per-split Kahan partials are combined in
 //    a fixed order by a second kernel (deterministic, no atomics).
 //  * a GGX sample's tangent-frame half vector depends on the sample and the
 //    roughness only, and its square roots, reciprocal and sine/cosine are most
@@ -28,7 +28,8 @@
 //    added in a fixed order by a second kernel (deterministic, no atomics).
 //  * BRDF table: one wavefront per entry, the 64 lanes split the Hammersley
 //    samples (per-lane Kahan sums, compensated wave reduction through
-//    cross-lane shuffles); a block makes its row's half vectors into LDS.
+//    cross-lane shuffles); a block makes its row's half vectors into LDS, and
+//    a lane Kahan-adds its (non-negative) terms four at a time.
 //  * roughness-0 prefilter level: every GGX half vector equals the normal, so
 //    the N.L-weighted mean is the environment along the texel direction; one
 //    bilinear lookup per texel.
