@@ -43,13 +43,15 @@ def _case(name):
         return sc, synth.look_at((0, 3.5, 8.5), (0, 0, 0), (0, 1, 0), 45, 64, 48)
     if name == "no-spheres-plane":
         return synth.make_spheres(rng, 0, True), synth.look_at((0, 2, 6), (0, 0, 0), (0, 1, 0), 60, 33, 17)
+    if name == "65536-spheres-256x192":  # the largest scene the C ABI takes: 256 chunks of 256 spheres per tile
+        return synth.make_spheres(rng, 65536, True), synth.orbit_camera(rng, 256, 192)
     if name == "1-sphere-no-plane-3x2":
         return synth.make_spheres(rng, 1, False), synth.look_at((0, 0.5, 3), (0, 0, 0), (0, 1, 0), 60, 3, 2)
     raise KeyError(name)
 
 
 CASES = ["64-spheres-201x137", "512-spheres-1080p", "orbit-300-97x61", "inside-and-behind", "no-spheres-plane",
-         "1-sphere-no-plane-3x2"]
+         "1-sphere-no-plane-3x2", "65536-spheres-256x192"]
 
 
 def _ulps(a, b):
