@@ -513,6 +513,11 @@ def bench_serving(args, torch, E, frame, synth, schedule=None) -> dict:
         dur = min(10.0, max(args.serve_seconds, args.serve_min_requests / rate))
         reqs = S.poisson_arrivals(float(rate), 400 + k, 32, synth.SERVING_RESOLUTIONS, duration=dur)
         srv = server(rs.templates)
+        # untimed warm-up on the same server: two requests per resolution, so that the
+        # first slots and launches (milliseconds on a new server) stay out of the tail
+        warm = [S.Request(-1 - i, i % 32, w, h, 0.0) for i, (w, h) in enumerate(synth.SERVING_RESOLUTIONS * 2)]
+        srv.run(warm, S.RealClock(poll=args.serve_poll_us * 1e-6))
+        srv.reset_stats()
         st = srv.run(reqs, S.RealClock(poll=args.serve_poll_us * 1e-6))
         srv.pool.clear()
         offered = sum(r.px for r in reqs) / dur / 1e6

@@ -276,6 +276,12 @@ class Server:
                 clock.wait(pending[0].arrival if pending else None, self.ex.next_event())
         return self.stats()
 
+    def reset_stats(self):
+        """Forget finished requests and batch counts (after an untimed warm-up
+        pass); idle slots stay in the pool for the requests that follow."""
+        self.finished, self.rejected, self.batch_views = [], [], []
+        self.n_batches = 0
+
     def stats(self) -> dict:
         done = self.finished
         if not done:

@@ -145,3 +145,20 @@ def test_idle_slots_of_other_resolutions_are_released():
     st = srv.run(reqs, clock)
     assert st["requests"] == 12
     assert ex.live_slots <= 4 and srv.pool.reserved <= fp((3840, 2160))
+
+
+def test_warm_up_then_reset_keeps_slots_and_drops_stats():
+    """An untimed warm-up pass leaves idle slots that the timed requests reuse;
+    reset_stats makes the statistics cover the timed requests only."""
+    srv, ex, clock = _server(1 << 40, s_per_px=2e-10)
+    warm = [S.Request(-1 - i, i, *RES[i % 4], arrival=0.0) for i in range(8)]
+    srv.run(warm, clock)
+    allocs = srv.pool.allocs
+    assert allocs > 0
+    srv.reset_stats()
+    assert srv.stats()["requests"] == 0
+    reqs = [S.Request(k, k % 32, *RES[k % 4], arrival=1.0 + 0.01 * k) for k in range(12)]
+    st = srv.run(reqs, clock)
+    assert st["requests"] == 12 and st["batches"] == 12
+    assert sorted(r.rid for r in srv.finished) == list(range(12))
+    assert srv.pool.allocs == allocs  # every timed request found an idle slot of its size
