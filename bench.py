@@ -701,8 +701,9 @@ def _cpu_model() -> str:
 def cpu_baseline(view, budget_s: float, fp16_gpu=None):
     """The oracle leg.  The FP64 oracle on the host cores: whole frames (SSAO,
     blur, shading, bloom + tonemap, without the per-environment precompute)
-    until the time budget is used; Mpix/s over the frames completed.  Then the
-    same on one thread for a third of the budget.  With ``fp16_gpu`` (the FP16
+    until the time budget is used; Mpix/s over the frames completed, and each
+    stage's share per frame.  Then the same on one thread for a third of the
+    budget, and the per-environment precompute at the view's settings once.  With ``fp16_gpu`` (the FP16
     form's outputs on the 256x256 view) the same oracle also states that
     form's error per output.  Returns (baseline, error statement or None)."""
     from oracle import oracle as orc
@@ -715,35 +716,49 @@ def cpu_baseline(view, budget_s: float, fp16_gpu=None):
     def run(v, ibl, budget):
         g = v.gbuf
         frames, t0 = 0, time.perf_counter()
+        stage = dict(ssao_raw=0.0, ssao_blur=0.0, shade=0.0, bloom_tonemap=0.0)
         while True:
+            a = time.perf_counter()
             raw = orc.ssao_raw(g["depth"], g["normal"], v.cam, v.ssao_kernel, v.ssao_noise,
                                v.ssao_radius, v.ssao_bias)
+            b = time.perf_counter()
             ao = orc.ssao_blur(*raw, g["depth"], v.blur_tau)
+            c = time.perf_counter()
             lo, hi = orc.shade(g, v.cam, *ao, v.lights, ibl, v.env)
+            d = time.perf_counter()
             orc.bloom_tonemap(lo, exposure=v.exposure)
+            e = time.perf_counter()
+            for k, dt in zip(stage, (b - a, c - b, d - c, e - d)):
+                stage[k] += dt
             frames += 1
-            el = time.perf_counter() - t0
+            el = e - t0
             if el >= budget:
-                return frames, el
+                return frames, el, stage
 
     px = view.width * view.height
     ibl = tables(view)
     threads = int(os.environ.get("OMP_NUM_THREADS", len(os.sched_getaffinity(0))))
     orc.set_threads(threads)
-    frames, el = run(view, ibl, budget_s)
+    frames, el, stage = run(view, ibl, budget_s)
     orc.set_threads(1)
-    frames1, el1 = run(view, ibl, budget_s / 3.0)
+    frames1, el1, _ = run(view, ibl, budget_s / 3.0)
     orc.set_threads(threads)
     small = synth.config_small()  # the 256x256 view, 2 s
-    fs, els = run(small, tables(small), 2.0)
+    fs, els, _ = run(small, tables(small), 2.0)
+    t = time.perf_counter()  # the per-environment precompute at the view's own settings, once
+    orc.precompute_ibl(view.env, **dict(view.ibl))
+    ibl_s = time.perf_counter() - t
     return {"value": round(frames * px / el / 1e6, 3), "unit": "Mpix/s", "cores": threads,
             "kind": "oracle", "cpu_model": _cpu_model(),
             "single_thread_Mpix_s": round(frames1 * px / el1 / 1e6, 3),
             "small_256_Mpix_s": round(fs * small.width * small.height / els / 1e6, 3),
+            "stage_ms_per_frame": {k: round(1e3 * v / frames, 2) for k, v in stage.items()},
+            "ibl_precompute_s": round(ibl_s, 3),
             "sample": f"{frames} whole {view.width}x{view.height} frames of the FP64 oracle "
                       f"(SSAO+blur+shade+bloom/tonemap, IBL tables precomputed outside) in {el:.1f} s on "
                       f"{threads} threads; {frames1} frames in {el1:.1f} s on one thread; {fs} frames of the "
-                      f"256x256 view in {els:.1f} s on {threads} threads"}, statement
+                      f"256x256 view in {els:.1f} s on {threads} threads; the 1080p view's IBL tables at its own "
+                      f"settings once in {ibl_s:.1f} s on {threads} threads"}, statement
 
 
 def main():
