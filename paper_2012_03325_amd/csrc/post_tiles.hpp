@@ -65,6 +65,22 @@ __device__ __forceinline__ void down_levels_2_to_5(const PostDesc &c, int bx, in
     __syncthreads();  // the next item of a batched launch refills the LDS
 }
 
+// Two horizontally adjacent pixels of a plane (index p even, so the pair is
+// 8-byte aligned in float32 and 4-byte aligned in half): one load.
+__device__ __forceinline__ void ld_pair(const float *b, unsigned p, float &u, float &v) {
+    float2 q = ldo((const float2 *)b, p * 4u);
+    u = q.x;
+    v = q.y;
+}
+struct alignas(4) HalfPair {
+    __half a, b;
+};
+__device__ __forceinline__ void ld_pair(const __half *b, unsigned p, float &u, float &v) {
+    HalfPair q = ldo((const HalfPair *)b, p * 2u);
+    u = __half2float(q.a);
+    v = __half2float(q.b);
+}
+
 template <typename TH, typename TP>
 __device__ __forceinline__ void bloom_down_tile(const PostDesc &c, int tile, DownLds &sm) {
     int tiles_x = (c.lw[1] + kDownTile - 1) / kDownTile;
@@ -81,14 +97,26 @@ __device__ __forceinline__ void bloom_down_tile(const PostDesc &c, int tile, Dow
     if (X < c.lw[1] && Y < c.lh[1]) {
         float R[4], G[4], B[4];
         bool in[4];
+        if (!(c.W & 1)) {  // even width: a row's two children are one pair (six loads in flight)
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {  // all twelve loads in flight together
-            int px = 2 * X + (k & 1), py = 2 * Y + (k >> 1);
-            in[k] = px < c.W && py < c.H;
-            unsigned p = in[k] ? __umul24((unsigned)py, (unsigned)c.W) + (unsigned)px : 0u;
-            R[k] = ldf(hdr, p);
-            G[k] = ldf(hdr, plane + p);
-            B[k] = ldf(hdr, 2 * plane + p);
+            for (int r = 0; r < 2; ++r) {
+                int py = 2 * Y + r;
+                in[2 * r] = in[2 * r + 1] = py < c.H;
+                unsigned p = in[2 * r] ? __umul24((unsigned)py, (unsigned)c.W) + (unsigned)(2 * X) : 0u;
+                ld_pair(hdr, p, R[2 * r], R[2 * r + 1]);
+                ld_pair(hdr, plane + p, G[2 * r], G[2 * r + 1]);
+                ld_pair(hdr, 2 * plane + p, B[2 * r], B[2 * r + 1]);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {  // all twelve loads in flight together
+                int px = 2 * X + (k & 1), py = 2 * Y + (k >> 1);
+                in[k] = px < c.W && py < c.H;
+                unsigned p = in[k] ? __umul24((unsigned)py, (unsigned)c.W) + (unsigned)px : 0u;
+                R[k] = ldf(hdr, p);
+                G[k] = ldf(hdr, plane + p);
+                B[k] = ldf(hdr, 2 * plane + p);
+            }
         }
         float cr[4], cg[4], cb[4];
 #pragma unroll
